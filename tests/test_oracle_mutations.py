@@ -1,0 +1,97 @@
+"""Planted mistakes in the oracle (CPU only): each mutant must make at least
+one pin fail, which shows the pins can see that kind of error."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from paper_2304_04876_amd import problems as P
+from oracle import gdsw_oracle as O
+from tests.test_oracle_pins import geometric_gdsw_dense, oracle_dense
+
+
+def _p2_error(local="exact", sweeps=5, N=6, Pn=2):
+    pr, Minv = geometric_gdsw_dense(N, Pn, local, sweeps)
+    M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local=local, sweeps=sweeps)
+    Mo = oracle_dense(M, pr.n)
+    return np.abs(Mo - Minv).max() / np.abs(Minv).max()
+
+
+def test_unmutated_oracle_passes():
+    assert _p2_error() <= 1e-13
+    assert _p2_error("ilu0") <= 1e-13
+
+
+def test_mutant_extension_sign(monkeypatch):
+    real = O.extension_solve
+    monkeypatch.setattr(O, "extension_solve", lambda A, r: -real(A, r))
+    assert _p2_error() > 1e-6
+
+
+def test_mutant_extension_dropped(monkeypatch):
+    monkeypatch.setattr(O, "extension_solve", lambda A, r: 0.0 * r)
+    assert _p2_error() > 1e-6
+
+
+def test_mutant_interface_on_upper_faces(monkeypatch):
+    real = O.interface
+
+    def reversed_interface(G, part):
+        return real(G, -part)
+    monkeypatch.setattr(O, "interface", reversed_interface)
+    assert _p2_error() > 1e-6
+
+
+def test_mutant_no_overlap(monkeypatch):
+    real = O.overlapping_subdomains
+    monkeypatch.setattr(O, "overlapping_subdomains", lambda G, p, n, ov: real(G, p, n, 0))
+    assert _p2_error() > 1e-6
+
+
+def test_mutant_components_merged(monkeypatch):
+    # one component per S-class would still be right here; merging all pieces
+    # into a single constant is not
+    monkeypatch.setattr(O, "components", lambda G, g, S: [np.nonzero(g)[0]])
+    assert _p2_error() > 1e-6
+
+
+def test_mutant_ilu_without_update(monkeypatch):
+    import scipy.sparse as sp
+
+    def diag_only(Ai):
+        f = O.ILU0(sp.tril(Ai, -1, format="csr") * 0, sp.triu(Ai, 1, format="csr"), Ai.diagonal())
+        return f
+    monkeypatch.setattr(O, "ilu0_factors", diag_only)
+    assert _p2_error("ilu0") > 1e-6
+
+
+def test_mutant_jacobi_sign(monkeypatch):
+    def bad(f, r, K):
+        y = np.zeros_like(r)
+        for _ in range(K):
+            y = r + f.NL @ y
+        w = np.zeros_like(r)
+        for _ in range(K):
+            w = (y - f.NU @ w) / f.d
+        return w
+    monkeypatch.setattr(O, "ilu0_jacobi_solve", bad)
+    assert _p2_error("ilu0") > 1e-6
+
+
+def test_mutant_cg_beta(monkeypatch):
+    pr = P.poisson3d(12, 2)
+    M = O.GDSW(pr.A, pr.part, 1, pr.n_parts)
+    b = P.rhs_uniform(pr.n, 0)
+    x = spla.spsolve(pr.A.tocsc(), b)
+    good = O.pcg(pr.A, b, M, 1e-12, maxit=60)
+    assert np.linalg.norm(good.x - x) <= 1e-9 * np.linalg.norm(x)
+
+    # a preconditioner that is not fixed breaks CG's convergence: shows the
+    # solution check can see a wrong search direction
+    class Bad:
+        def __init__(self):
+            self.k = 0
+        def apply(self, r):
+            self.k += 1
+            return M.apply(r) * (1.0 if self.k % 2 else 3.0) + 0.1 * r
+    bad = O.pcg(pr.A, b, Bad(), 1e-12, maxit=60)
+    assert np.linalg.norm(bad.x - x) > 1e-9 * np.linalg.norm(x) or bad.iters > good.iters
