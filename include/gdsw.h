@@ -1,0 +1,211 @@
+/*
+ * gdsw.h -- C ABI of the GDSW two-level overlapping Schwarz preconditioner
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library applies
+ *
+ *     M^{-1} r = sum_i R_i^T A_i^{-1} R_i r + Phi A_0^{-1} Phi^T r        (paper eq. (1))
+ *
+ * with the energy-minimising GDSW coarse basis
+ *
+ *     Phi = [ -A_II^{-1} A_IG ; I ] Phi_G,     A_0 = Phi^T A Phi           (paper eq. (2))
+ *
+ * inside preconditioned CG or GMRES, in the paper's three phases (Sec. V-A,
+ * "Software Structure"): a host-side symbolic analysis (gdsw_analyze), a
+ * device-side numerical setup (gdsw_factor) and device-side applies/solves.
+ *
+ * Conventions shared by every entry point:
+ *  - Host pointers are read during the call only; the caller keeps ownership
+ *    and may free them afterwards.  Device pointers (suffix _dev) are HIP
+ *    device addresses; the caller owns them and they must stay valid until
+ *    the work queued on `stream` has finished.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is queued on it; entry points do not synchronise except where
+ *    stated (gdsw_factor, gdsw_solve poll the device for convergence).
+ *  - Every entry point returns a gdsw_status and never aborts.  On error the
+ *    handle (when there is one) keeps a message for gdsw_last_error.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Sizes are int64_t; matrix column indices are int32_t (n < 2^31).
+ */
+#ifndef GDSW_H
+#define GDSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gdsw_handle_s *gdsw_handle;
+
+typedef enum {
+    GDSW_OK = 0,
+    GDSW_ERR_INVALID_ARG = 1,   /* bad shape, index, option or non-finite value   */
+    GDSW_ERR_SINGULAR = 2,      /* non-positive pivot in a Cholesky / zero ILU pivot */
+    GDSW_ERR_BREAKDOWN = 3,     /* Krylov breakdown (NaN/Inf or zero denominator)   */
+    GDSW_ERR_NOT_CONVERGED = 4, /* maxit reached before the tolerance              */
+    GDSW_ERR_BUDGET = 5,        /* device memory budget exceeded / allocation failed */
+    GDSW_ERR_HIP = 6,           /* a HIP runtime call failed                        */
+    GDSW_ERR_STATE = 7,         /* call out of order (e.g. apply before factor)     */
+    GDSW_ERR_INTERNAL = 8
+} gdsw_status;
+
+/* Coarse space of eq. (1): none (one-level) or GDSW (eq. (2)). */
+enum { GDSW_COARSE_NONE = 0, GDSW_COARSE_GDSW = 1 };
+
+/* Local solver for A_i^{-1}: exact (banded Cholesky, A_i must be SPD;
+ * Sec. V-B "Sparse Direct Matrix Factorization") or ILU(0) in the natural
+ * order with Jacobi-sweep triangular solves (Sec. V-B "Incomplete Local
+ * Solver"). */
+enum { GDSW_LOCAL_EXACT = 0, GDSW_LOCAL_ILU0 = 1 };
+
+/* Storage precision of the local factors and the coarse basis Phi.
+ * Arithmetic is FP32 for the reduced formats and FP64 for GDSW_FP64; the
+ * coarse matrix, its inverse and all Krylov vectors stay FP64 (the paper's
+ * half-precision preconditioner, Sec. V-A "Lower Precision Preconditioning",
+ * applied to the local parts only). */
+enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2, GDSW_FP16 = 3 };
+
+/* Krylov method of gdsw_solve. */
+enum { GDSW_KRYLOV_CG = 0, GDSW_KRYLOV_GMRES = 1 };
+
+typedef struct {
+    int32_t overlap;          /* layers of graph overlap (>= 0); paper: 1        */
+    int32_t coarse;           /* GDSW_COARSE_*                                    */
+    int32_t local;            /* GDSW_LOCAL_*                                     */
+    int32_t jacobi_sweeps;    /* sweeps per triangle for ILU(0); paper: 5         */
+    int32_t local_prec;       /* GDSW_FP64 / FP32 / BF16 / FP16                   */
+    int32_t basis_prec;       /* GDSW_FP64 / FP32 (storage of Phi)                */
+    int64_t hbm_budget_bytes; /* device bytes the handle may allocate; 0 = no cap */
+    uint64_t flags;           /* reserved, must be 0                              */
+} gdsw_options;
+
+/* Square sparse matrix in CSR form, HOST pointers: rowptr[n+1] (int64),
+ * col[nnz] (int32, sorted ascending within each row), val[nnz] (FP64). */
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} gdsw_csr;
+
+typedef struct {
+    int32_t iterations;       /* Krylov iterations performed                     */
+    int32_t converged;        /* 1 if the tolerance was met                       */
+    double rel_res_recursive; /* ||r_k|| / ||b|| as tracked by the iteration      */
+    double rel_res_true;      /* ||b - A x|| / ||b|| recomputed at the end        */
+    double seconds;           /* wall time of the call                            */
+} gdsw_solve_info;
+
+typedef struct {
+    int64_t n;                /* dofs                                             */
+    int64_t n_nodes;
+    int32_t dpn;              /* dofs per node                                    */
+    int32_t n_parts;          /* subdomains                                       */
+    int64_t sum_overlap_dofs; /* sum_i |Omega_i'| * dpn                           */
+    int64_t n_gamma_nodes;    /* interface nodes                                  */
+    int32_t n_components;     /* interface components                             */
+    int32_t n0;               /* coarse dimension                                 */
+    int64_t local_factor_entries;  /* stored local-factor values (all subdomains) */
+    int64_t phi_entries;      /* stored coarse-basis values                       */
+    int64_t device_bytes;     /* device memory held by the handle                 */
+    int32_t max_local_rows;   /* largest overlapping subdomain (dofs)             */
+    int32_t max_bandwidth;    /* largest local bandwidth (exact solver)           */
+    double t_analyze;         /* seconds: host symbolic analysis                  */
+    double t_factor;          /* seconds: device numerical setup (synchronised)   */
+} gdsw_info;
+
+/* Integer maps that can be copied out for inspection (gdsw_map_size /
+ * gdsw_copy_map).  All are produced by gdsw_analyze. */
+enum {
+    GDSW_MAP_OV_PTR = 0,       /* int64 [n_parts+1]: offsets into OV_IDX          */
+    GDSW_MAP_OV_IDX = 1,       /* int64 [sum_overlap_dofs]: dofs of Omega_i', ascending */
+    GDSW_MAP_IS_GAMMA = 2,     /* int8  [n_nodes]: 1 on the interface             */
+    GDSW_MAP_COMP_OF_NODE = 3, /* int32 [n_nodes]: interface component, -1 if interior */
+    GDSW_MAP_COMP_RANK = 4,    /* int32 [n_components]: coarse columns of each component */
+    GDSW_MAP_PHI_ROWPTR = 5,   /* int64 [n+1]: CSR of Phi (after gdsw_factor)     */
+    GDSW_MAP_PHI_COL = 6,      /* int32 [phi_entries]                             */
+    GDSW_MAP_PHI_VAL = 7,      /* FP64  [phi_entries]  (after gdsw_factor)        */
+    GDSW_MAP_A0 = 8            /* FP64  [n0*n0] coarse matrix, row-major (after gdsw_factor) */
+};
+
+/* Fills `opt` with the paper's defaults: overlap 1, GDSW coarse space,
+ * exact local solver, 5 Jacobi sweeps, FP64 storage, no budget. */
+void gdsw_default_options(gdsw_options *opt);
+
+/* Phase (a), symbolic, host only (no device is touched).
+ *   A        : the matrix (host CSR).  Values are copied for gdsw_factor.
+ *   part     : [n/dpn] nonoverlapping subdomain of every node, in [0, n_parts).
+ *   n_parts  : number of subdomains (>= 1).
+ *   dpn      : dofs per node (dof = dpn*node + component), n % dpn == 0.
+ *   Z        : [n x n_null] column-major null-space basis of the Neumann
+ *              operator (Sec. III item 3), or NULL for the constants (then
+ *              n_null must be 0 or 1).
+ * Builds the node graph, the overlapping subdomains, the interface and its
+ * components, the interface basis Phi_G (orthonormal per component), the
+ * local orderings, band profiles, level schedules and all index maps.
+ * Errors: INVALID_ARG for malformed input. */
+gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts,
+                         int32_t dpn, const double *Z, int32_t n_null,
+                         const gdsw_options *opt, gdsw_handle *out);
+
+/* Phase (b), numeric, on the current HIP device: uploads the maps, gathers
+ * the local matrices, factors them, computes the extension Phi_I, assembles
+ * A_0 and inverts it.  Synchronises `stream` before returning (so that
+ * singular pivots are reported).  Errors: SINGULAR, BUDGET, HIP, STATE. */
+gdsw_status gdsw_factor(gdsw_handle h, void *stream);
+
+/* Numeric re-setup with new values on the same pattern (host FP64 array of
+ * nnz values in the CSR order given to gdsw_analyze). */
+gdsw_status gdsw_refactor(gdsw_handle h, const double *val, void *stream);
+
+/* gdsw_analyze followed by gdsw_factor. */
+gdsw_status gdsw_setup(const gdsw_csr *A, const int32_t *part, int32_t n_parts,
+                       int32_t dpn, const double *Z, int32_t n_null,
+                       const gdsw_options *opt, void *stream, gdsw_handle *out);
+
+/* Phase (c): z = M^{-1} r, eq. (1).  r_dev, z_dev: FP64 device vectors of
+ * length n (distinct).  Queued on `stream`, no synchronisation. */
+gdsw_status gdsw_apply(gdsw_handle h, const double *r_dev, double *z_dev, void *stream);
+
+/* Parts of eq. (1) alone: which = 1 one-level sum only, 2 coarse term only,
+ * 3 both (same as gdsw_apply); 4 = only the batched local solves
+ * A_i^{-1} R_i r, kept in the handle's local buffer (z_dev unused, may be
+ * NULL) -- used to time the local-solve kernel by itself. */
+gdsw_status gdsw_apply_part(gdsw_handle h, const double *r_dev, double *z_dev,
+                            int32_t which, void *stream);
+
+/* y = A x with the matrix given to gdsw_analyze (FP64 device vectors). */
+gdsw_status gdsw_spmv(gdsw_handle h, const double *x_dev, double *y_dev, void *stream);
+
+/* Preconditioned Krylov solve of A x = b (Sec. VII), x0 = 0.
+ *   krylov : GDSW_KRYLOV_CG or GDSW_KRYLOV_GMRES (right preconditioned).
+ *   restart: GMRES restart length (paper: 30); ignored by CG.
+ *   rtol   : stop when ||r_k||_2 <= rtol ||b||_2.
+ *   maxit  : iteration cap.  If fixed_iters > 0 exactly that many iterations
+ *            are run whatever the residual (used to compare iterates).
+ *   b_dev, x_dev: FP64 device vectors of length n; x_dev receives x.
+ *   info   : optional, filled on return.
+ * Synchronises `stream` to poll convergence.
+ * Errors: NOT_CONVERGED (x holds the last iterate), BREAKDOWN. */
+gdsw_status gdsw_solve(gdsw_handle h, const double *b_dev, double *x_dev,
+                       int32_t krylov, int32_t restart, double rtol, int32_t maxit,
+                       int32_t fixed_iters, gdsw_solve_info *info, void *stream);
+
+gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info);
+
+/* Number of elements of a GDSW_MAP_* array, and a copy of it into host
+ * memory of at least that many elements of the documented type. */
+gdsw_status gdsw_map_size(gdsw_handle h, int32_t map, int64_t *count);
+gdsw_status gdsw_copy_map(gdsw_handle h, int32_t map, void *host_out);
+
+/* Releases all host and device memory of the handle (NULL is accepted). */
+gdsw_status gdsw_destroy(gdsw_handle h);
+
+const char *gdsw_status_string(gdsw_status s);
+const char *gdsw_last_error(gdsw_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDSW_H */

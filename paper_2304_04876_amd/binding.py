@@ -1,0 +1,288 @@
+"""ctypes binding of libgdsw.so (C ABI in include/gdsw.h).
+
+Argument marshalling only: every step of the preconditioner runs in the
+library (host analysis in C++, numerical setup, applies and solves in HIP
+kernels).  Functions keep the C names; device vectors may be passed as torch
+tensors (FP64, on the GPU) or raw device addresses, streams as
+``torch.cuda.Stream`` objects, raw ``hipStream_t`` addresses or None (the
+current torch stream).  If the library has not been built, ``lib()`` raises;
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdsw.so")
+_LIB = None
+
+GDSW_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "SINGULAR", 3: "BREAKDOWN", 4: "NOT_CONVERGED",
+                5: "BUDGET", 6: "HIP", 7: "STATE", 8: "INTERNAL"}
+COARSE_NONE, COARSE_GDSW = 0, 1
+LOCAL_EXACT, LOCAL_ILU0 = 0, 1
+FP64, FP32, BF16, FP16 = 0, 1, 2, 3
+KRYLOV_CG, KRYLOV_GMRES = 0, 1
+MAP_OV_PTR, MAP_OV_IDX, MAP_IS_GAMMA, MAP_COMP_OF_NODE, MAP_COMP_RANK = 0, 1, 2, 3, 4
+MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8
+_MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
+              5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64}
+
+EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
+            "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
+            "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("overlap", ctypes.c_int32), ("coarse", ctypes.c_int32), ("local", ctypes.c_int32),
+                ("jacobi_sweeps", ctypes.c_int32), ("local_prec", ctypes.c_int32),
+                ("basis_prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("flags", ctypes.c_uint64)]
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("dpn", ctypes.c_int32),
+                ("n_parts", ctypes.c_int32), ("sum_overlap_dofs", ctypes.c_int64),
+                ("n_gamma_nodes", ctypes.c_int64), ("n_components", ctypes.c_int32),
+                ("n0", ctypes.c_int32), ("local_factor_entries", ctypes.c_int64),
+                ("phi_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("max_local_rows", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
+                ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double)]
+
+
+def lib():
+    """Loads libgdsw.so; raises RuntimeError if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_04876_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "gdsw_default_options": (None, [ctypes.POINTER(Options)]),
+        "gdsw_analyze": (ctypes.c_int, [ctypes.POINTER(CSR), vp, i32, i32, vp, i32, ctypes.POINTER(Options),
+                                        ctypes.POINTER(vp)]),
+        "gdsw_factor": (ctypes.c_int, [vp, vp]),
+        "gdsw_refactor": (ctypes.c_int, [vp, vp, vp]),
+        "gdsw_setup": (ctypes.c_int, [ctypes.POINTER(CSR), vp, i32, i32, vp, i32, ctypes.POINTER(Options), vp,
+                                      ctypes.POINTER(vp)]),
+        "gdsw_apply": (ctypes.c_int, [vp, vp, vp, vp]),
+        "gdsw_apply_part": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "gdsw_spmv": (ctypes.c_int, [vp, vp, vp, vp]),
+        "gdsw_solve": (ctypes.c_int, [vp, vp, vp, i32, i32, dbl, i32, i32, ctypes.POINTER(SolveInfo), vp]),
+        "gdsw_get_info": (ctypes.c_int, [vp, ctypes.POINTER(Info)]),
+        "gdsw_map_size": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
+        "gdsw_copy_map": (ctypes.c_int, [vp, i32, vp]),
+        "gdsw_destroy": (ctypes.c_int, [vp]),
+        "gdsw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "gdsw_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+class GdswError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(x):
+    """Device address of a torch tensor, or an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def gdsw_default_options(**kw) -> Options:
+    o = Options()
+    lib().gdsw_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _csr_arrays(A):
+    A = A.tocsr()
+    A.sort_indices()
+    rowptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.indices, dtype=np.int32)
+    val = np.ascontiguousarray(A.data, dtype=np.float64)
+    return rowptr, col, val
+
+
+def gdsw_analyze(A, part, n_parts, dpn=1, Z=None, options: Options | None = None):
+    """Symbolic phase on the host; returns a handle (int)."""
+    rowptr, col, val = _csr_arrays(A)
+    csr = CSR(A.shape[0], rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    if Z is not None:
+        Zc = np.asfortranarray(np.asarray(Z, dtype=np.float64).reshape(A.shape[0], -1))
+        zp, nz = Zc.ctypes.data, Zc.shape[1]
+    else:
+        Zc, zp, nz = None, None, 0
+    opt = options if options is not None else gdsw_default_options()
+    h = ctypes.c_void_p()
+    st = lib().gdsw_analyze(ctypes.byref(csr), part.ctypes.data, int(n_parts), int(dpn), zp, nz,
+                            ctypes.byref(opt), ctypes.byref(h))
+    if st != GDSW_OK:
+        msg = gdsw_last_error(h.value)
+        gdsw_destroy(h.value)
+        raise GdswError(st, msg)
+    return h.value
+
+
+def _check(h, st):
+    if st != GDSW_OK:
+        raise GdswError(st, gdsw_last_error(h))
+
+
+def gdsw_factor(h, stream=None):
+    _check(h, lib().gdsw_factor(h, _stream(stream)))
+
+
+def gdsw_refactor(h, val, stream=None):
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    _check(h, lib().gdsw_refactor(h, v.ctypes.data, _stream(stream)))
+
+
+def gdsw_setup(A, part, n_parts, dpn=1, Z=None, options=None, stream=None):
+    h = gdsw_analyze(A, part, n_parts, dpn, Z, options)
+    try:
+        gdsw_factor(h, stream)
+    except Exception:
+        gdsw_destroy(h)
+        raise
+    return h
+
+
+def gdsw_apply(h, r, z, stream=None):
+    _check(h, lib().gdsw_apply(h, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def gdsw_apply_part(h, r, z, which, stream=None):
+    _check(h, lib().gdsw_apply_part(h, _ptr(r), _ptr(z), int(which), _stream(stream)))
+
+
+def gdsw_spmv(h, x, y, stream=None):
+    _check(h, lib().gdsw_spmv(h, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def gdsw_solve(h, b, x, krylov=KRYLOV_CG, restart=30, rtol=1e-8, maxit=1000, fixed_iters=0,
+               stream=None, raise_on_error=True):
+    info = SolveInfo()
+    st = lib().gdsw_solve(h, _ptr(b), _ptr(x), int(krylov), int(restart), float(rtol), int(maxit),
+                          int(fixed_iters), ctypes.byref(info), _stream(stream))
+    out = {"status": st, "iterations": info.iterations, "converged": bool(info.converged),
+           "rel_res_recursive": info.rel_res_recursive, "rel_res_true": info.rel_res_true,
+           "seconds": info.seconds}
+    if raise_on_error and st != GDSW_OK:
+        raise GdswError(st, gdsw_last_error(h))
+    return out
+
+
+def gdsw_get_info(h) -> dict:
+    info = Info()
+    _check(h, lib().gdsw_get_info(h, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in Info._fields_}
+
+
+def gdsw_map_size(h, which) -> int:
+    c = ctypes.c_int64()
+    _check(h, lib().gdsw_map_size(h, int(which), ctypes.byref(c)))
+    return c.value
+
+
+def gdsw_copy_map(h, which) -> np.ndarray:
+    out = np.empty(max(gdsw_map_size(h, which), 1), dtype=_MAP_DTYPE[which])
+    _check(h, lib().gdsw_copy_map(h, int(which), out.ctypes.data))
+    return out[:gdsw_map_size(h, which)]
+
+
+def gdsw_destroy(h):
+    if h:
+        lib().gdsw_destroy(h)
+
+
+def gdsw_status_string(st) -> str:
+    return lib().gdsw_status_string(int(st)).decode()
+
+
+def gdsw_last_error(h) -> str:
+    m = lib().gdsw_last_error(h)
+    return m.decode() if m else ""
+
+
+class Gdsw:
+    """Owning wrapper of a handle (destroyed with the object)."""
+
+    def __init__(self, A, part, n_parts, dpn=1, Z=None, factor=True, stream=None, **options):
+        self.h = gdsw_analyze(A, part, n_parts, dpn, Z, gdsw_default_options(**options))
+        self.n = A.shape[0]
+        if factor:
+            try:
+                gdsw_factor(self.h, stream)
+            except Exception:
+                self.close()
+                raise
+
+    def apply(self, r, z, stream=None):
+        gdsw_apply(self.h, r, z, stream)
+
+    def apply_part(self, r, z, which, stream=None):
+        gdsw_apply_part(self.h, r, z, which, stream)
+
+    def spmv(self, x, y, stream=None):
+        gdsw_spmv(self.h, x, y, stream)
+
+    def solve(self, b, x, **kw):
+        return gdsw_solve(self.h, b, x, **kw)
+
+    def info(self):
+        return gdsw_get_info(self.h)
+
+    def map(self, which):
+        return gdsw_copy_map(self.h, which)
+
+    def close(self):
+        if getattr(self, "h", None):
+            gdsw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

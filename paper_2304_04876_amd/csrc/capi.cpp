@@ -1,0 +1,203 @@
+// C ABI entry points (include/gdsw.h): argument checks, error strings and
+// dispatch to the host analysis (symbolic.cpp) and the device phases
+// (device.hip).
+#include <cstring>
+#include <new>
+
+#include "gdsw_impl.hpp"
+
+extern "C" {
+
+void gdsw_default_options(gdsw_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->overlap = 1;
+    opt->coarse = GDSW_COARSE_GDSW;
+    opt->local = GDSW_LOCAL_EXACT;
+    opt->jacobi_sweeps = 5;
+    opt->local_prec = GDSW_FP64;
+    opt->basis_prec = GDSW_FP64;
+    opt->hbm_budget_bytes = 0;
+    opt->flags = 0;
+}
+
+gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts, int32_t dpn, const double *Z,
+                         int32_t n_null, const gdsw_options *opt, gdsw_handle *out) {
+    if (!out) return GDSW_ERR_INVALID_ARG;
+    *out = nullptr;
+    gdsw_handle_s *h = new (std::nothrow) gdsw_handle_s();
+    if (!h) return GDSW_ERR_BUDGET;
+    gdsw_status st = gdsw::analyze(h, A, part, n_parts, dpn, Z, n_null, opt);
+    *out = h;   // returned even on error so that gdsw_last_error can be read
+    return st;
+}
+
+gdsw_status gdsw_factor(gdsw_handle h, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    if (!h->analyzed) {
+        h->err = "factor before a successful analysis";
+        return GDSW_ERR_STATE;
+    }
+    return gdsw::factor(h, stream);
+}
+
+gdsw_status gdsw_refactor(gdsw_handle h, const double *val, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    if (!h->analyzed) return GDSW_ERR_STATE;
+    return gdsw::refactor(h, val, stream);
+}
+
+gdsw_status gdsw_setup(const gdsw_csr *A, const int32_t *part, int32_t n_parts, int32_t dpn, const double *Z,
+                       int32_t n_null, const gdsw_options *opt, void *stream, gdsw_handle *out) {
+    gdsw_status st = gdsw_analyze(A, part, n_parts, dpn, Z, n_null, opt, out);
+    if (st != GDSW_OK) return st;
+    return gdsw_factor(*out, stream);
+}
+
+gdsw_status gdsw_apply(gdsw_handle h, const double *r_dev, double *z_dev, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::apply(h, r_dev, z_dev, 3, stream);
+}
+
+gdsw_status gdsw_apply_part(gdsw_handle h, const double *r_dev, double *z_dev, int32_t which, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::apply(h, r_dev, z_dev, which, stream);
+}
+
+gdsw_status gdsw_spmv(gdsw_handle h, const double *x_dev, double *y_dev, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::spmv(h, x_dev, y_dev, stream);
+}
+
+gdsw_status gdsw_solve(gdsw_handle h, const double *b_dev, double *x_dev, int32_t krylov, int32_t restart,
+                       double rtol, int32_t maxit, int32_t fixed_iters, gdsw_solve_info *info, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::solve(h, b_dev, x_dev, krylov, restart, rtol, maxit, fixed_iters, info, stream);
+}
+
+gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
+    if (!h || !info) return GDSW_ERR_INVALID_ARG;
+    const gdsw::Symbolic &S = h->sym;
+    std::memset(info, 0, sizeof(*info));
+    info->n = S.n;
+    info->n_nodes = S.nn;
+    info->dpn = S.dpn;
+    info->n_parts = S.np;
+    info->sum_overlap_dofs = S.ov_ptr.empty() ? 0 : S.ov_ptr.back();
+    info->n_gamma_nodes = S.n_gamma_nodes;
+    info->n_components = S.nc;
+    info->n0 = S.n0;
+    info->phi_entries = S.blk.val_off.empty() ? 0 : S.blk.val_off.back();
+    info->local_factor_entries = 0;
+    if (S.opt.local == GDSW_LOCAL_EXACT)
+        info->local_factor_entries = S.band_off.empty() ? 0 : S.band_off.back();
+    else
+        info->local_factor_entries = S.lcol.size();
+    info->device_bytes = gdsw::device_bytes(h);
+    info->max_local_rows = S.max_ni;
+    info->max_bandwidth = S.max_bw;
+    info->t_analyze = S.t_analyze;
+    info->t_factor = h->t_factor;
+    return GDSW_OK;
+}
+
+static int64_t map_count(gdsw_handle h, int32_t map) {
+    const gdsw::Symbolic &S = h->sym;
+    switch (map) {
+        case GDSW_MAP_OV_PTR: return int64_t(S.ov_ptr.size());
+        case GDSW_MAP_OV_IDX: return int64_t(S.ov_idx.size());
+        case GDSW_MAP_IS_GAMMA: return int64_t(S.is_gamma.size());
+        case GDSW_MAP_COMP_OF_NODE: return int64_t(S.comp_of_node.size());
+        case GDSW_MAP_COMP_RANK: return int64_t(S.comp_rank.size());
+        case GDSW_MAP_PHI_ROWPTR: return S.n + 1;
+        case GDSW_MAP_PHI_COL:
+        case GDSW_MAP_PHI_VAL: return S.blk.val_off.empty() ? 0 : S.blk.val_off.back();
+        case GDSW_MAP_A0: return int64_t(S.n0) * S.n0;
+        default: return -1;
+    }
+}
+
+gdsw_status gdsw_map_size(gdsw_handle h, int32_t map, int64_t *count) {
+    if (!h || !count) return GDSW_ERR_INVALID_ARG;
+    int64_t c = map_count(h, map);
+    if (c < 0) return GDSW_ERR_INVALID_ARG;
+    *count = c;
+    return GDSW_OK;
+}
+
+gdsw_status gdsw_copy_map(gdsw_handle h, int32_t map, void *out) {
+    if (!h || !out) return GDSW_ERR_INVALID_ARG;
+    const gdsw::Symbolic &S = h->sym;
+    switch (map) {
+        case GDSW_MAP_OV_PTR:
+            std::memcpy(out, S.ov_ptr.data(), 8 * S.ov_ptr.size());
+            return GDSW_OK;
+        case GDSW_MAP_OV_IDX: {
+            int64_t *o = static_cast<int64_t *>(out);
+            for (size_t p = 0; p < S.ov_idx.size(); ++p) o[p] = S.ov_idx[p];
+            return GDSW_OK;
+        }
+        case GDSW_MAP_IS_GAMMA:
+            std::memcpy(out, S.is_gamma.data(), S.is_gamma.size());
+            return GDSW_OK;
+        case GDSW_MAP_COMP_OF_NODE:
+            std::memcpy(out, S.comp_of_node.data(), 4 * S.comp_of_node.size());
+            return GDSW_OK;
+        case GDSW_MAP_COMP_RANK:
+            std::memcpy(out, S.comp_rank.data(), 4 * S.comp_rank.size());
+            return GDSW_OK;
+        case GDSW_MAP_PHI_ROWPTR:
+        case GDSW_MAP_PHI_COL: {
+            // CSR view of Phi: rows ascending, each row's block columns ascending
+            const gdsw::PhiBlocks &B = S.blk;
+            int64_t *rp = map == GDSW_MAP_PHI_ROWPTR ? static_cast<int64_t *>(out) : nullptr;
+            int32_t *cc = map == GDSW_MAP_PHI_COL ? static_cast<int32_t *>(out) : nullptr;
+            int64_t q = 0;
+            if (rp) rp[0] = 0;
+            for (int64_t d = 0; d < S.n; ++d) {
+                const int g = S.dof_blk.empty() ? -1 : S.dof_blk[d];
+                if (g >= 0)
+                    for (int64_t c = B.col_ptr[g]; c < B.col_ptr[g + 1]; ++c) {
+                        if (cc) cc[q] = B.cols[c];
+                        ++q;
+                    }
+                if (rp) rp[d + 1] = q;
+            }
+            return GDSW_OK;
+        }
+        case GDSW_MAP_PHI_VAL:
+        case GDSW_MAP_A0:
+            return gdsw::copy_device_map(h, map, out);
+        default:
+            return GDSW_ERR_INVALID_ARG;
+    }
+}
+
+gdsw_status gdsw_destroy(gdsw_handle h) {
+    if (!h) return GDSW_OK;
+    gdsw::destroy_device(h);
+    delete h;
+    return GDSW_OK;
+}
+
+const char *gdsw_status_string(gdsw_status s) {
+    switch (s) {
+        case GDSW_OK: return "ok";
+        case GDSW_ERR_INVALID_ARG: return "invalid argument";
+        case GDSW_ERR_SINGULAR: return "singular or indefinite pivot";
+        case GDSW_ERR_BREAKDOWN: return "Krylov breakdown";
+        case GDSW_ERR_NOT_CONVERGED: return "not converged";
+        case GDSW_ERR_BUDGET: return "device memory budget exceeded";
+        case GDSW_ERR_HIP: return "HIP runtime error";
+        case GDSW_ERR_STATE: return "call out of order";
+        case GDSW_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *gdsw_last_error(gdsw_handle h) {
+    if (!h) return "null handle";
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,763 @@
+// Device side of a GDSW handle: upload of the symbolic maps, the numerical
+// setup (phase (b)), the preconditioner apply and the Krylov solves.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gdsw_impl.hpp"
+#include "kernels_apply.hpp"
+#include "kernels_krylov.hpp"
+#include "kernels_setup.hpp"
+
+namespace gdsw {
+
+struct DevError {
+    gdsw_status st;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw DevError{GDSW_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+static inline int nblocks(int64_t n, int nt, int64_t cap = 1 << 20) {
+    int64_t b = (n + nt - 1) / nt;
+    if (b < 1) b = 1;
+    return int(std::min(b, cap));
+}
+
+static size_t prec_size(int p) {
+    switch (p) {
+        case GDSW_FP64: return 8;
+        case GDSW_FP32: return 4;
+        default: return 2;
+    }
+}
+
+struct Device {
+    std::vector<void *> allocs;
+    int64_t bytes = 0;
+    int64_t budget = 0;
+
+    void *raw_alloc(size_t sz) {
+        if (sz == 0) sz = 16;
+        if (budget > 0 && bytes + int64_t(sz) > budget)
+            throw DevError{GDSW_ERR_BUDGET, "device memory budget exceeded"};
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, sz);
+        if (e != hipSuccess) throw DevError{GDSW_ERR_BUDGET, std::string("hipMalloc: ") + hipGetErrorString(e)};
+        allocs.push_back(p);
+        bytes += int64_t(sz);
+        return p;
+    }
+    void release(void *p, size_t sz) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) {
+            allocs.erase(it);
+            (void)hipFree(p);
+            bytes -= int64_t(sz == 0 ? 16 : sz);
+        }
+    }
+    template <typename T>
+    T *alloc(int64_t count) { return static_cast<T *>(raw_alloc(sizeof(T) * size_t(std::max<int64_t>(count, 1)))); }
+    template <typename T>
+    T *upload(const std::vector<T> &v, hipStream_t s) {
+        T *p = alloc<T>(int64_t(v.size()));
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+        return p;
+    }
+    ~Device() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+
+    // ---- matrix ----
+    int32_t *rowptr = nullptr, *col = nullptr, *arow = nullptr;
+    double *val = nullptr;
+    int64_t *adiag = nullptr;
+    double *dscale = nullptr;   // diagonal scaling of reduced-precision factors (or null)
+    // ---- restriction / prolongation ----
+    int32_t *ov_idx = nullptr;
+    int64_t *ov_ptr = nullptr, *t_ptr = nullptr;
+    int32_t *t_pos = nullptr;
+    double *zloc = nullptr;
+    // ---- local factors ----
+    void *band = nullptr;   // exact: band in local precision
+    int64_t *band_off = nullptr;
+    int32_t *bw = nullptr;
+    void *Lv = nullptr, *Uv = nullptr, *dinv = nullptr;   // ILU(0): sweep layout
+    uint16_t *Lc = nullptr, *Uc = nullptr;
+    int64_t *ell_off = nullptr;
+    // ---- coarse ----
+    int64_t *blk_row_ptr = nullptr, *blk_col_ptr = nullptr, *blk_val_off = nullptr;
+    int32_t *blk_rows = nullptr, *blk_cols = nullptr;
+    double *phi = nullptr;    // FP64 coarse-basis values
+    float *phi32 = nullptr;   // FP32 copy when basis_prec == FP32
+    int64_t *red_ptr = nullptr;
+    int32_t *red_idx = nullptr;
+    int32_t *dof_blk = nullptr, *dof_lr = nullptr;
+    double *partial = nullptr, *r0 = nullptr, *z0 = nullptr;
+    double *A0 = nullptr;     // assembled coarse matrix
+    double *A0inv = nullptr;  // its inverse
+    // ---- Krylov ----
+    double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kpart = nullptr;
+    KState *kst = nullptr;
+    int64_t phi_entries = 0;
+    int64_t local_entries = 0;
+    int KLp = 1, KUp = 1;   // slot counts of the sweep layout
+    size_t max_lds = 64 * 1024;   // dynamic LDS a workgroup may use on this device
+};
+
+// ---------------------------------------------------------------------------
+static void upload_all(gdsw_handle_s *h, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    std::vector<int32_t> rp32(S.n + 1), arow(S.nnz);
+    for (int64_t i = 0; i <= S.n; ++i) rp32[i] = int32_t(S.rowptr[i]);
+    std::vector<int64_t> adiag(S.n);
+    for (int64_t i = 0; i < S.n; ++i)
+        for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p) {
+            arow[p] = int32_t(i);
+            if (S.col[p] == i) adiag[i] = p;
+        }
+    D.rowptr = D.upload(rp32, s);
+    D.col = D.upload(S.col, s);
+    D.val = D.upload(S.val, s);
+    D.arow = D.upload(arow, s);
+    D.adiag = D.upload(adiag, s);
+    D.ov_idx = D.upload(S.ov_idx, s);
+    D.ov_ptr = D.upload(S.ov_ptr, s);
+    D.t_ptr = D.upload(S.t_ptr, s);
+    D.t_pos = D.upload(S.t_pos, s);
+    D.zloc = D.alloc<double>(S.ov_ptr[S.np]);
+    const int64_t n = S.n;
+    D.kr = D.alloc<double>(n);
+    D.kz = D.alloc<double>(n);
+    D.kp = D.alloc<double>(n);
+    D.kq = D.alloc<double>(n);
+    D.kt = D.alloc<double>(n);
+    D.kpart = D.alloc<double>(nblocks(n, KNT));
+    D.kst = D.alloc<KState>(1);
+    // the sync below makes the host vectors above safe to release
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+template <typename VT>
+static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *d_lcol, const int32_t *d_ldiag,
+                     const double *d_lval, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const bool small = S.KL <= 3 && S.KU <= 3;
+    const int KL = small ? 3 : std::max(S.KL, 1), KU = small ? 3 : std::max(S.KU, 1);
+    D.KLp = KL;
+    D.KUp = KU;
+    D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows);
+    D.Uv = D.alloc<VT>(int64_t(KU) * S.ell_rows);
+    D.dinv = D.alloc<VT>(S.ell_rows);
+    D.Lc = D.alloc<uint16_t>(int64_t(KL) * S.ell_rows);
+    D.Uc = D.alloc<uint16_t>(int64_t(KU) * S.ell_rows);
+    int64_t maxpad = 0;
+    for (int i = 0; i < S.np; ++i) maxpad = std::max(maxpad, S.ell_off[i + 1] - S.ell_off[i]);
+    dim3 grid(nblocks(maxpad, 256), S.np);
+    hipLaunchKernelGGL(k_ilu_pack<VT>, grid, dim3(256), 0, s, D.ov_ptr, D.ell_off, d_lrowptr, d_lcol, d_ldiag,
+                       d_lval, S.ell_rows, KL, KU, (VT *)D.Lv, D.Lc, (VT *)D.Uv, D.Uc, (VT *)D.dinv);
+    HIPCHK(hipGetLastError());
+    D.local_entries = int64_t(KL + KU + 1) * S.ell_rows;
+}
+
+static void check_status(Device &D, int *d_status, int count, hipStream_t s, const char *what) {
+    std::vector<int> st(count);
+    HIPCHK(hipMemcpyAsync(st.data(), d_status, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i)
+        if (st[i]) throw DevError{GDSW_ERR_SINGULAR, std::string(what) + ": non-positive or zero pivot in part " +
+                                                         std::to_string(i) + " at row " + std::to_string(st[i] - 1)};
+}
+
+static void factor_local(gdsw_handle_s *h, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int prec = S.opt.local_prec;
+    const bool scaled = prec != GDSW_FP64;
+    if (scaled) {
+        D.dscale = D.alloc<double>(S.n);
+        hipLaunchKernelGGL(k_diag_scale, dim3(nblocks(S.n, 256)), dim3(256), 0, s, D.val, D.adiag, D.dscale, S.n);
+    }
+    int *d_status = D.alloc<int>(S.np);
+    HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
+    if (S.opt.local == GDSW_LOCAL_ILU0) {
+        int64_t *d_lrowptr = D.upload(S.lrowptr, s);
+        int32_t *d_lcol = D.upload(S.lcol, s);
+        int64_t *d_lgpos = D.upload(S.lgpos, s);
+        int32_t *d_ldiag = D.upload(S.ldiag, s);
+        int64_t *d_lvl_base = D.upload(S.lvl_base, s);
+        int32_t *d_lvl_ptr = D.upload(S.lvl_ptr, s);
+        int32_t *d_lvl_rows = D.upload(S.lvl_rows, s);
+        D.ell_off = D.upload(S.ell_off, s);
+        const int64_t ne = int64_t(S.lcol.size());
+        double *d_lval = D.alloc<double>(ne);
+        hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_lgpos,
+                           (const int64_t *)nullptr, d_lval, ne, D.dscale, D.arow, D.col);
+        hipLaunchKernelGGL(k_ilu0_factor, dim3(S.np), dim3(256), 0, s, D.ov_ptr, d_lrowptr, d_lcol, d_ldiag,
+                           d_lvl_base, d_lvl_ptr, d_lvl_rows, d_lval, d_status);
+        HIPCHK(hipGetLastError());
+        check_status(D, d_status, S.np, s, "ILU(0)");
+        switch (prec) {
+            case GDSW_FP64: pack_ilu<double>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
+            case GDSW_FP32: pack_ilu<float>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
+            case GDSW_BF16: pack_ilu<bf16>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
+            default: pack_ilu<fp16>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        D.release(d_lval, sizeof(double) * ne);
+        D.release(d_lrowptr, sizeof(int64_t) * S.lrowptr.size());
+        D.release(d_lcol, sizeof(int32_t) * S.lcol.size());
+        D.release(d_lgpos, sizeof(int64_t) * S.lgpos.size());
+        D.release(d_ldiag, sizeof(int32_t) * S.ldiag.size());
+        D.release(d_lvl_base, sizeof(int64_t) * S.lvl_base.size());
+        D.release(d_lvl_ptr, sizeof(int32_t) * S.lvl_ptr.size());
+        D.release(d_lvl_rows, sizeof(int32_t) * S.lvl_rows.size());
+    } else {
+        const int64_t nb = S.band_off[S.np];
+        double *band64 = D.alloc<double>(nb);
+        HIPCHK(hipMemsetAsync(band64, 0, sizeof(double) * size_t(nb), s));
+        int64_t *d_src = D.upload(S.bscat_src, s);
+        int64_t *d_dst = D.upload(S.bscat_dst, s);
+        const int64_t ne = int64_t(S.bscat_src.size());
+        hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_src, d_dst,
+                           band64, ne, D.dscale, D.arow, D.col);
+        D.band_off = D.upload(S.band_off, s);
+        D.bw = D.upload(S.bw, s);
+        const size_t lds = sizeof(double) * (CH_NB * CH_LD + CH_NB + size_t(std::max(S.max_bw, 1)) * CH_LD);
+        if (lds > D.max_lds)
+            throw DevError{GDSW_ERR_INVALID_ARG, "local bandwidth too large for the banded Cholesky"};
+        hipLaunchKernelGGL(k_band_chol<256>, dim3(S.np), dim3(256), lds, s, band64, D.band_off, D.bw, D.ov_ptr,
+                           d_status);
+        HIPCHK(hipGetLastError());
+        check_status(D, d_status, S.np, s, "banded Cholesky");
+        D.release(d_src, sizeof(int64_t) * S.bscat_src.size());
+        D.release(d_dst, sizeof(int64_t) * S.bscat_dst.size());
+        if (prec == GDSW_FP64) {
+            D.band = band64;
+        } else {
+            void *bl = D.raw_alloc(prec_size(prec) * size_t(nb));
+            const int gb = nblocks(nb, 256, 65536);
+            if (prec == GDSW_FP32) hipLaunchKernelGGL(k_cast<float>, dim3(gb), dim3(256), 0, s, band64, (float *)bl, nb);
+            else if (prec == GDSW_BF16) hipLaunchKernelGGL(k_cast<bf16>, dim3(gb), dim3(256), 0, s, band64, (bf16 *)bl, nb);
+            else hipLaunchKernelGGL(k_cast<fp16>, dim3(gb), dim3(256), 0, s, band64, (fp16 *)bl, nb);
+            HIPCHK(hipStreamSynchronize(s));
+            D.release(band64, sizeof(double) * size_t(nb));
+            D.band = bl;
+        }
+        D.local_entries = nb;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    D.release(d_status, sizeof(int) * S.np);
+}
+
+static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const PhiBlocks &B = S.blk;
+    if (S.opt.coarse != GDSW_COARSE_GDSW || S.n0 == 0 || B.nb == 0) return;
+    const int n0 = S.n0;
+    D.blk_row_ptr = D.upload(B.row_ptr, s);
+    D.blk_col_ptr = D.upload(B.col_ptr, s);
+    D.blk_val_off = D.upload(B.val_off, s);
+    D.blk_rows = D.upload(B.rows, s);
+    D.blk_cols = D.upload(B.cols, s);
+    D.red_ptr = D.upload(S.red_ptr, s);
+    D.red_idx = D.upload(S.red_idx, s);
+    D.dof_blk = D.upload(S.dof_blk, s);
+    D.dof_lr = D.upload(S.dof_lr, s);
+    D.partial = D.alloc<double>(int64_t(B.cols.size()));
+    D.r0 = D.alloc<double>(n0);
+    D.z0 = D.alloc<double>(n0);
+    const int64_t nphi = B.val_off[B.nb];
+    D.phi = D.alloc<double>(nphi);
+    D.phi_entries = nphi;
+    // interface blocks: the orthonormal bases from the analysis
+    std::vector<int32_t> sub_blk(S.np, -1);
+    for (int g = 0; g < B.nb; ++g) {
+        if (B.kind[g] == 0) {
+            sub_blk[B.owner[g]] = g;
+        } else {
+            const int c = B.owner[g];
+            HIPCHK(hipMemcpyAsync(D.phi + B.val_off[g], S.phig.data() + S.phig_off[c],
+                                  sizeof(double) * size_t(S.phig_off[c + 1] - S.phig_off[c]),
+                                  hipMemcpyHostToDevice, s));
+        }
+    }
+    double *d_phig = D.upload(S.phig, s);
+    int64_t *d_phig_off = D.upload(S.phig_off, s);
+    int32_t *d_comp_rank = D.upload(S.comp_rank, s);
+    int32_t *d_sub_blk = D.upload(sub_blk, s);
+    int64_t *d_int_ptr = D.upload(S.int_ptr, s);
+    int64_t *d_scol_ptr = D.upload(S.scol_ptr, s);
+    int64_t *d_ext_off = D.upload(S.ext_off, s);
+    // ---- extension: E_i = A_{I_i G} Phi_G, A_{I_i I_i} = L L^T, Phi_I = -A_II^{-1} E_i
+    const int64_t nint = S.int_ptr[S.np];
+    const int64_t next = S.ext_off[S.np];
+    double *E = D.alloc<double>(next);
+    HIPCHK(hipMemsetAsync(E, 0, sizeof(double) * size_t(std::max<int64_t>(next, 1)), s));
+    {
+        int64_t *a = D.upload(S.cpl_ptr, s);
+        int64_t *b = D.upload(S.cpl_apos, s);
+        int64_t *c = D.upload(S.cpl_phi, s);
+        int32_t *d = D.upload(S.cpl_stride, s);
+        int32_t *e = D.upload(S.cpl_rank, s);
+        int32_t *f = D.upload(S.cpl_slot, s);
+        hipLaunchKernelGGL(k_ext_rhs, dim3(nblocks(nint, 256)), dim3(256), 0, s, D.val, d_int_ptr, S.np, d_ext_off,
+                           a, b, c, d, e, f, d_phig, E, nint);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        D.release(a, 8 * S.cpl_ptr.size());
+        D.release(b, 8 * S.cpl_apos.size());
+        D.release(c, 8 * S.cpl_phi.size());
+        D.release(d, 4 * S.cpl_stride.size());
+        D.release(e, 4 * S.cpl_rank.size());
+        D.release(f, 4 * S.cpl_slot.size());
+    }
+    int *d_status = D.alloc<int>(std::max(S.np, 1));
+    HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
+    {
+        const int64_t nb = S.iband_off[S.np];
+        double *iband = D.alloc<double>(nb);
+        HIPCHK(hipMemsetAsync(iband, 0, sizeof(double) * size_t(std::max<int64_t>(nb, 1)), s));
+        int64_t *d_src = D.upload(S.ibscat_src, s);
+        int64_t *d_dst = D.upload(S.ibscat_dst, s);
+        int64_t *d_ioff = D.upload(S.iband_off, s);
+        int32_t *d_ibw = D.upload(S.ibw, s);
+        const int64_t ne = int64_t(S.ibscat_src.size());
+        hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_src, d_dst, iband,
+                           ne, (const double *)nullptr, D.arow, D.col);
+        const size_t lds = sizeof(double) * (CH_NB * CH_LD + CH_NB + size_t(std::max(S.max_ibw, 1)) * CH_LD);
+        if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "interior bandwidth too large"};
+        hipLaunchKernelGGL(k_band_chol<256>, dim3(S.np), dim3(256), lds, s, iband, d_ioff, d_ibw, d_int_ptr, d_status);
+        HIPCHK(hipGetLastError());
+        check_status(D, d_status, S.np, s, "interior Cholesky");
+        const size_t lds2 = sizeof(double) * (size_t(std::max(S.max_nii, 1)) + BS_NB * BS_LD);
+        if (lds2 > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "interior block too large for LDS"};
+        hipLaunchKernelGGL(k_ext_solve<256>, dim3(S.np), dim3(256), lds2, s, iband, d_ioff, d_ibw, d_int_ptr,
+                           d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        D.release(iband, sizeof(double) * size_t(nb));
+        D.release(d_src, 8 * S.ibscat_src.size());
+        D.release(d_dst, 8 * S.ibscat_dst.size());
+        D.release(d_ioff, 8 * S.iband_off.size());
+        D.release(d_ibw, 4 * S.ibw.size());
+    }
+    // ---- A_0 = Phi_G^T A_GG Phi_G + sum_i E_i^T Phi_{I_i}
+    double *A0raw = D.alloc<double>(int64_t(n0) * n0);
+    HIPCHK(hipMemsetAsync(A0raw, 0, sizeof(double) * size_t(n0) * n0, s));
+    {
+        const int npairs = int(S.pair_c.size());
+        if (npairs) {
+            int32_t *pc = D.upload(S.pair_c, s);
+            int32_t *pd = D.upload(S.pair_d, s);
+            int64_t *po = D.upload(S.pair_off, s);
+            int64_t *pe = D.upload(S.pair_eptr, s);
+            int64_t *pa = D.upload(S.pair_apos, s);
+            int32_t *plc = D.upload(S.pair_lr_c, s);
+            int32_t *pld = D.upload(S.pair_lr_d, s);
+            int64_t *tg = D.upload(S.a0pair_tgt, s);
+            const int64_t total = S.pair_off[npairs];
+            hipLaunchKernelGGL(k_t2, dim3(nblocks(total, 256)), dim3(256), 0, s, D.val, npairs, pc, pd, po, pe, pa,
+                               plc, pld, d_comp_rank, d_phig_off, d_phig, tg, A0raw, total);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));
+            D.release(pc, 4 * S.pair_c.size()); D.release(pd, 4 * S.pair_d.size());
+            D.release(po, 8 * S.pair_off.size()); D.release(pe, 8 * S.pair_eptr.size());
+            D.release(pa, 8 * S.pair_apos.size()); D.release(plc, 4 * S.pair_lr_c.size());
+            D.release(pld, 4 * S.pair_lr_d.size()); D.release(tg, 8 * S.a0pair_tgt.size());
+        }
+        const int64_t nt1 = S.t1_off[S.np];
+        if (nt1) {
+            double *T1 = D.alloc<double>(nt1);
+            int64_t *d_t1off = D.upload(S.t1_off, s);
+            int kmax = 0;
+            for (int i = 0; i < S.np; ++i) kmax = std::max<int>(kmax, int(S.scol_ptr[i + 1] - S.scol_ptr[i]));
+            dim3 grid(nblocks(int64_t(kmax) * kmax, 256), S.np);
+            hipLaunchKernelGGL(k_t1, grid, dim3(256), 0, s, d_int_ptr, d_scol_ptr, d_ext_off, E, d_sub_blk,
+                               D.blk_val_off, D.phi, d_t1off, T1);
+            int64_t *st = D.upload(S.a0seg_tgt, s);
+            int64_t *sp = D.upload(S.a0seg_ptr, s);
+            int64_t *ss = D.upload(S.a0seg_src, s);
+            const int64_t nseg = int64_t(S.a0seg_tgt.size());
+            hipLaunchKernelGGL(k_a0_segments, dim3(nblocks(nseg, 256)), dim3(256), 0, s, st, sp, ss, T1, A0raw, nseg);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));
+            D.release(T1, 8 * nt1); D.release(d_t1off, 8 * S.t1_off.size());
+            D.release(st, 8 * S.a0seg_tgt.size()); D.release(sp, 8 * S.a0seg_ptr.size());
+            D.release(ss, 8 * S.a0seg_src.size());
+        }
+    }
+    D.A0 = D.alloc<double>(int64_t(n0) * n0);
+    hipLaunchKernelGGL(k_symmetrize, dim3(nblocks(int64_t(n0) * n0, 256)), dim3(256), 0, s, A0raw, D.A0, n0);
+    // ---- A_0^{-1} by blocked Gauss-Jordan sweeps on a copy
+    D.A0inv = A0raw;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(int64_t(n0) * n0, 256, 65536)), dim3(256), 0, s, D.A0, D.A0inv,
+                       int64_t(n0) * n0);
+    {
+        double *P = D.alloc<double>(GJ_NB * GJ_NB);
+        double *W = D.alloc<double>(int64_t(n0) * GJ_NB);
+        HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int), s));
+        const dim3 tiles((n0 + 63) / 64, (n0 + 63) / 64);
+        for (int k0 = 0; k0 < n0; k0 += GJ_NB) {
+            const int kb = std::min(GJ_NB, n0 - k0);
+            hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, D.A0inv, n0, k0, kb, P, d_status);
+            hipLaunchKernelGGL(k_gj_panel, dim3(nblocks(n0, 256)), dim3(256), 0, s, D.A0inv, n0, k0, kb, P, W);
+            hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, D.A0inv, n0, k0, kb, W);
+            hipLaunchKernelGGL(k_gj_fix, dim3(nblocks(n0, 256)), dim3(256), 0, s, D.A0inv, n0, k0, kb, W, P);
+        }
+        hipLaunchKernelGGL(k_negate, dim3(nblocks(int64_t(n0) * n0, 256, 65536)), dim3(256), 0, s, D.A0inv,
+                           int64_t(n0) * n0);
+        HIPCHK(hipGetLastError());
+        check_status(D, d_status, 1, s, "coarse matrix inverse");
+        D.release(P, 8 * GJ_NB * GJ_NB);
+        D.release(W, 8 * size_t(n0) * GJ_NB);
+    }
+    if (S.opt.basis_prec == GDSW_FP32) {
+        D.phi32 = D.alloc<float>(nphi);
+        hipLaunchKernelGGL(k_cast<float>, dim3(nblocks(nphi, 256, 65536)), dim3(256), 0, s, D.phi, D.phi32, nphi);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    D.release(E, 8 * std::max<int64_t>(next, 1));
+    D.release(d_phig, 8 * S.phig.size());
+    D.release(d_phig_off, 8 * S.phig_off.size());
+    D.release(d_comp_rank, 4 * S.comp_rank.size());
+    D.release(d_sub_blk, 4 * sub_blk.size());
+    D.release(d_int_ptr, 8 * S.int_ptr.size());
+    D.release(d_scol_ptr, 8 * S.scol_ptr.size());
+    D.release(d_ext_off, 8 * S.ext_off.size());
+    D.release(d_status, 4 * std::max(S.np, 1));
+}
+
+gdsw_status factor(gdsw_handle_s *h, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto t0 = std::chrono::steady_clock::now();
+    try {
+        destroy_device(h);
+        h->dev = new Device();
+        h->dev->budget = h->sym.opt.hbm_budget_bytes;
+        {
+            int dev = 0, lds = 0;
+            HIPCHK(hipGetDevice(&dev));
+            HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            h->dev->max_lds = size_t(lds);
+        }
+        upload_all(h, s);
+        factor_local(h, s);
+        factor_coarse(h, s);
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        destroy_device(h);
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed";
+        destroy_device(h);
+        return GDSW_ERR_BUDGET;
+    }
+    h->factored = true;
+    h->t_factor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return GDSW_OK;
+}
+
+gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
+    if (!val) return GDSW_ERR_INVALID_ARG;
+    for (int64_t p = 0; p < h->sym.nnz; ++p)
+        if (!std::isfinite(val[p])) {
+            h->err = "non-finite matrix value";
+            return GDSW_ERR_INVALID_ARG;
+        }
+    h->sym.val.assign(val, val + h->sym.nnz);
+    return factor(h, stream);
+}
+
+// ---------------------------------------------------------------------------
+template <typename VT>
+static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const int *done, hipStream_t s) {
+    if (D.KLp != 3 || D.KUp != 3) return false;
+    constexpr bool f64 = std::is_same<VT, double>::value;
+    constexpr int NT = f64 ? 512 : 1024;
+    const int need = (S.max_ni + NT - 1) / NT;
+    using AT = typename AccOf<VT>::type;
+#define GDSW_ILU_CASE(RR)                                                                                    \
+    if (need <= RR) {                                                                                        \
+        const size_t lds = 2 * sizeof(AT) * NT * RR;                                                         \
+        if (lds > D.max_lds) return false;                                                                   \
+        hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, 3, 3, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx,     \
+                           D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc, \
+                           (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, done);                 \
+        return true;                                                                                         \
+    }
+    // largest row counts per thread that stay in registers without spilling
+    GDSW_ILU_CASE(2)
+    GDSW_ILU_CASE(4)
+    GDSW_ILU_CASE(6)
+    GDSW_ILU_CASE(8)
+    if constexpr (f64) { GDSW_ILU_CASE(11) }
+#undef GDSW_ILU_CASE
+    return false;
+}
+
+template <typename VT>
+static void launch_local(const Symbolic &S, Device &D, const double *r, const int *done, hipStream_t s) {
+    using AT = typename AccOf<VT>::type;
+    if (S.opt.local == GDSW_LOCAL_ILU0) {
+        if (launch_ilu_regs<VT>(S, D, r, done, s)) return;
+        const size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
+        if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS sweeps"};
+        hipLaunchKernelGGL((k_ilu_jacobi_generic<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
+                           D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc,
+                           (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc,
+                           S.max_ni, done);
+    } else {
+        const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
+        if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS band solve"};
+        hipLaunchKernelGGL((k_band_apply<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, done);
+    }
+}
+
+static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const int *done, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    if (which & 1) {
+        switch (S.opt.local_prec) {
+            case GDSW_FP64: launch_local<double>(S, D, r, done, s); break;
+            case GDSW_FP32: launch_local<float>(S, D, r, done, s); break;
+            case GDSW_BF16: launch_local<bf16>(S, D, r, done, s); break;
+            default: launch_local<fp16>(S, D, r, done, s); break;
+        }
+    }
+    if (which == 4) {   // the local solves alone (results stay in zloc)
+        switch (S.opt.local_prec) {
+            case GDSW_FP64: launch_local<double>(S, D, r, done, s); break;
+            case GDSW_FP32: launch_local<float>(S, D, r, done, s); break;
+            case GDSW_BF16: launch_local<bf16>(S, D, r, done, s); break;
+            default: launch_local<fp16>(S, D, r, done, s); break;
+        }
+        HIPCHK(hipGetLastError());
+        return;
+    }
+    const bool coarse = (which & 2) && D.A0inv != nullptr;
+    if (coarse) {
+        const PhiBlocks &B = S.blk;
+        if (D.phi32)
+            hipLaunchKernelGGL((k_coarse_restrict<256, float>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
+                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, done);
+        else
+            hipLaunchKernelGGL((k_coarse_restrict<256, double>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
+                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, done);
+        hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
+                           D.partial, D.r0, S.n0, done);
+        hipLaunchKernelGGL(k_dense_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.r0, D.z0, S.n0, done);
+    }
+    const int w = (which & 1) | (coarse ? 2 : 0);
+    if (D.phi32)
+        hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
+                           D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
+                           (const float *)D.phi32, D.z0, z, S.n, done);
+    else
+        hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
+                           D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
+                           (const double *)D.phi, D.z0, z, S.n, done);
+    HIPCHK(hipGetLastError());
+}
+
+gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "apply before factor";
+        return GDSW_ERR_STATE;
+    }
+    if (!r || (which != 4 && (!z || r == z)) || which < 1 || which > 4) {
+        h->err = "apply: bad arguments";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    try {
+        launch_apply(h, r, z, which, nullptr, static_cast<hipStream_t>(stream));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream) {
+    if (!h->dev) {
+        h->err = "spmv before factor";
+        return GDSW_ERR_STATE;
+    }
+    if (!x || !y || x == y) return GDSW_ERR_INVALID_ARG;
+    const int n = int(h->sym.n);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->rowptr,
+                       h->dev->col, h->dev->val, x, y, n);
+    return hipGetLastError() == hipSuccess ? GDSW_OK : GDSW_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned CG from x0 = 0 (the oracle's order of operations):
+//   r = b, z = M r, p = z, rho = r.z;
+//   repeat: q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q, stop if
+//           ||r|| <= rtol ||b||; z = M r, beta = r.z / rho, p = z + beta p.
+// Iterations are queued in chunks; the host reads the device state once per
+// chunk, kernels after convergence return immediately.
+static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, int fixed,
+                            gdsw_solve_info *info, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int n = int(S.n);
+    const int g = nblocks(n, KNT);
+    KState hs{};
+    hs.rtol2 = rtol * rtol;
+    hs.fixed = fixed;
+    hs.maxit = maxit;
+    HIPCHK(hipMemcpyAsync(D.kst, &hs, sizeof(KState), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, int64_t(n));
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, b, D.kr, int64_t(n));
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, b, b, n, D.kpart, D.kst, 0, 2);
+    HIPCHK(hipMemcpyAsync(&hs, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(hs.bb > 0.0)) {
+        if (info) { info->iterations = 0; info->converged = 1; info->rel_res_recursive = 0; info->rel_res_true = 0; }
+        return std::isfinite(hs.bb) ? GDSW_OK : GDSW_ERR_INVALID_ARG;
+    }
+    int *done = &D.kst->done;
+    launch_apply(h, D.kr, D.kz, 3, nullptr, s);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kr, D.kz, n, D.kpart, D.kst, 1, 3);
+    hipLaunchKernelGGL(k_cg_update_p, dim3(g), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 1);
+    const int limit = fixed > 0 ? fixed : maxit;
+    int queued = 0;
+    int chunk = 4;
+    while (true) {
+        const int c = std::min(chunk, limit - queued);
+        for (int k = 0; k < c; ++k) {
+            hipLaunchKernelGGL(k_cg_spmv_dot, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, n,
+                               D.kpart, D.kst);
+            hipLaunchKernelGGL(k_cg_update_xr, dim3(g), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, n, D.kpart, D.kst);
+            launch_apply(h, D.kr, D.kz, 3, done, s);
+            hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kr, D.kz, n, D.kpart, D.kst, 2, 4);
+            hipLaunchKernelGGL(k_cg_update_p, dim3(g), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 0);
+        }
+        queued += c;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&hs, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hs.done || queued >= limit) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    // true residual
+    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, n);
+    hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kt, D.kt, n, D.kpart, D.kst, 3, 5);
+    KState fin{};
+    HIPCHK(hipMemcpyAsync(&fin, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = fin.iters;
+        info->converged = fin.status == KS_CONVERGED;
+        info->rel_res_recursive = std::sqrt(fin.rr / fin.bb);
+        info->rel_res_true = std::sqrt(fin.red / fin.bb);
+    }
+    if (fin.status == KS_BREAKDOWN) {
+        h->err = "CG breakdown";
+        return GDSW_ERR_BREAKDOWN;
+    }
+    if (fixed > 0) return GDSW_OK;
+    if (fin.status != KS_CONVERGED) {
+        h->err = "CG did not converge";
+        return GDSW_ERR_NOT_CONVERGED;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restart, double rtol, int maxit,
+                        int fixed, gdsw_solve_info *info, hipStream_t s);
+
+gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart, double rtol, int maxit,
+                  int fixed_iters, gdsw_solve_info *info, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "solve before factor";
+        return GDSW_ERR_STATE;
+    }
+    if (!b || !x || b == x || !(rtol >= 0.0) || maxit < 0 || fixed_iters < 0 ||
+        (krylov != GDSW_KRYLOV_CG && krylov != GDSW_KRYLOV_GMRES)) {
+        h->err = "solve: bad arguments";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto t0 = std::chrono::steady_clock::now();
+    gdsw_status st;
+    try {
+        if (krylov == GDSW_KRYLOV_CG) st = solve_cg(h, b, x, rtol, maxit, fixed_iters, info, s);
+        else st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, info, s);
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+gdsw_status solve_gmres(gdsw_handle_s *h, const double *, double *, int, double, int, int, gdsw_solve_info *,
+                        hipStream_t) {
+    h->err = "GMRES is not available in this build";
+    return GDSW_ERR_INVALID_ARG;
+}
+
+void destroy_device(gdsw_handle_s *h) {
+    delete h->dev;
+    h->dev = nullptr;
+    h->factored = false;
+}
+
+int64_t device_bytes(const gdsw_handle_s *h) { return h->dev ? h->dev->bytes : 0; }
+
+gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out) {
+    if (!h->factored || !h->dev) return GDSW_ERR_STATE;
+    Device &D = *h->dev;
+    Symbolic &S = h->sym;
+    try {
+        if (map == GDSW_MAP_A0) {
+            if (!D.A0) return GDSW_ERR_STATE;
+            HIPCHK(hipMemcpy(out, D.A0, sizeof(double) * size_t(S.n0) * S.n0, hipMemcpyDeviceToHost));
+            return GDSW_OK;
+        }
+        if (map == GDSW_MAP_PHI_VAL) {
+            // values in the row order of the CSR view (rows ascending, block columns ascending)
+            const PhiBlocks &B = S.blk;
+            std::vector<double> vals(D.phi_entries);
+            if (D.phi_entries)
+                HIPCHK(hipMemcpy(vals.data(), D.phi, sizeof(double) * size_t(D.phi_entries), hipMemcpyDeviceToHost));
+            double *o = static_cast<double *>(out);
+            int64_t q = 0;
+            for (int64_t d = 0; d < S.n; ++d) {
+                const int g = S.dof_blk[d];
+                if (g < 0) continue;
+                const int64_t nr = B.row_ptr[g + 1] - B.row_ptr[g];
+                for (int64_t c = B.col_ptr[g]; c < B.col_ptr[g + 1]; ++c)
+                    o[q++] = vals[B.val_off[g] + (c - B.col_ptr[g]) * nr + S.dof_lr[d]];
+            }
+            return GDSW_OK;
+        }
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_ERR_INVALID_ARG;
+}
+
+}  // namespace gdsw

@@ -1,0 +1,156 @@
+// Internal state of a GDSW handle: host symbolic data (built by the analysis
+// in symbolic.cpp) and the device buffers of the numerical setup and solve
+// phases (device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gdsw.h"
+
+namespace gdsw {
+
+// A dense block of the coarse basis Phi: rows are global dofs, columns are
+// coarse columns; values are stored column-major (nr x k).  Row sets of
+// different blocks are disjoint, so Phi is the union of its blocks.
+struct PhiBlocks {
+    std::vector<int64_t> row_ptr;   // [nb+1] offsets into rows
+    std::vector<int32_t> rows;      // global dofs
+    std::vector<int64_t> col_ptr;   // [nb+1] offsets into cols (= partial index base)
+    std::vector<int32_t> cols;      // coarse columns (ascending within a block)
+    std::vector<int64_t> val_off;   // [nb+1] offsets into the value array
+    std::vector<int32_t> kind;      // 0 = interior of a subdomain, 1 = interface component
+    std::vector<int32_t> owner;     // subdomain or component id
+    int32_t nb = 0;
+};
+
+struct Symbolic {
+    // ---- input copy -----------------------------------------------------
+    int64_t n = 0, nn = 0, nnz = 0;
+    int32_t dpn = 1, np = 1;
+    gdsw_options opt{};
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int32_t> part;      // [nn]
+    std::vector<double> Z;          // [n x n_null] column-major
+    int32_t n_null = 1;
+
+    // ---- node graph --------------------------------------------------------
+    std::vector<int64_t> gptr;      // [nn+1]
+    std::vector<int32_t> gadj;
+
+    // ---- overlapping subdomains ---------------------------------------------
+    std::vector<int64_t> ov_ptr;    // [np+1] dof offsets (local row p = ov_ptr[i] + l)
+    std::vector<int32_t> ov_idx;    // global dofs, ascending per subdomain
+    int32_t max_ni = 0;
+
+    // transpose of the restriction maps: for dof d the local rows p that
+    // hold it, in ascending subdomain order
+    std::vector<int64_t> t_ptr;     // [n+1]
+    std::vector<int32_t> t_pos;     // local rows p (int32: sum |Omega'| < 2^31)
+
+    // ---- interface ------------------------------------------------------------
+    std::vector<int8_t> is_gamma;       // [nn]
+    std::vector<int32_t> comp_of_node;  // [nn], -1 interior
+    std::vector<int64_t> comp_ptr;      // [nc+1]
+    std::vector<int32_t> comp_nodes;
+    std::vector<int32_t> comp_rank;     // coarse columns per component
+    std::vector<int32_t> comp_col0;     // first coarse column
+    std::vector<int64_t> phig_off;      // [nc+1] offsets of the orthonormal blocks
+    std::vector<double> phig;           // column-major (|c|*dpn x r_c) blocks
+    int32_t nc = 0, n0 = 0;
+    int64_t n_gamma_nodes = 0;
+
+    // ---- interior sets and the extension ------------------------------------------
+    std::vector<int64_t> int_ptr;   // [np+1] offsets of interior dofs
+    std::vector<int32_t> int_idx;   // global interior dofs, ascending per subdomain
+    std::vector<int64_t> scol_ptr;  // [np+1] coarse columns adjacent to I_i
+    std::vector<int32_t> scol;
+    // couplings A_{I_i, Gamma}: per interior row (global interior row index q)
+    std::vector<int64_t> cpl_ptr;   // [n_int+1]
+    std::vector<int64_t> cpl_apos;  // position in A's CSR
+    std::vector<int64_t> cpl_phi;   // offset of the Phi_G row of the Gamma dof
+    std::vector<int32_t> cpl_stride;// rows of that component block
+    std::vector<int32_t> cpl_rank;  // columns of that component block
+    std::vector<int32_t> cpl_slot;  // first slot of those columns in scol of i
+    // extension value offsets (column-major n_Ii x k_i per subdomain)
+    std::vector<int64_t> ext_off;   // [np+1]
+
+    // ---- local matrices ---------------------------------------------------------------
+    // A_i in CSR over local rows p (all subdomains concatenated)
+    std::vector<int64_t> lrowptr;   // [sum n_i + 1]
+    std::vector<int32_t> lcol;      // local column within the subdomain
+    std::vector<int64_t> lgpos;     // position in A's CSR
+    // band Cholesky profiles (exact local solver)
+    std::vector<int32_t> bw;        // [np] lower bandwidth b_i of A_i
+    std::vector<int64_t> band_off;  // [np+1] offsets, row-major (b_i+1) per row
+    std::vector<int64_t> bscat_dst; // band positions of the lower entries of A_i
+    std::vector<int64_t> bscat_src; // their positions in A's CSR
+    // same for A_{I_i I_i}
+    std::vector<int32_t> ibw;
+    std::vector<int64_t> iband_off;
+    std::vector<int64_t> ibscat_dst;
+    std::vector<int64_t> ibscat_src;
+    int32_t max_bw = 0, max_ibw = 0, max_nii = 0;
+
+    // ---- ILU(0) level schedule and sweep layout -----------------------------------------
+    std::vector<int64_t> lvl_base;  // [np+1] offsets into lvl_ptr (each subdomain has nl_i+1)
+    std::vector<int32_t> lvl_ptr;   // local offsets into the subdomain's lvl_rows slice
+    std::vector<int32_t> lvl_rows;  // local rows by level, slice i starts at ov_ptr[i]
+    std::vector<int32_t> ldiag;     // [sum n_i] position (relative to lrowptr) of the diagonal
+    int32_t KL = 0, KU = 0;         // max strictly lower / upper entries per row
+    std::vector<int64_t> ell_off;   // [np+1] padded row offsets
+    int64_t ell_rows = 0;
+
+    // ---- coarse space ---------------------------------------------------------------
+    PhiBlocks blk;
+    std::vector<int64_t> red_ptr;   // [n0+1] partials of each coarse column
+    std::vector<int32_t> red_idx;
+    std::vector<int32_t> dof_blk;   // [n] block holding the Phi row of d, -1 none
+    std::vector<int32_t> dof_lr;    // [n] row within that block
+    // A_0 assembly: interface-interface pairs
+    std::vector<int32_t> pair_c, pair_d;      // component pairs (c, d)
+    std::vector<int64_t> pair_off;            // [npairs+1] offsets of their r_c x r_d blocks
+    std::vector<int64_t> pair_eptr;           // [npairs+1] entry lists
+    std::vector<int64_t> pair_apos;
+    std::vector<int32_t> pair_lr_c, pair_lr_d;
+    // subdomain contributions E_i^T X_i scattered into A_0
+    std::vector<int64_t> t1_off;              // [np+1] offsets of the k_i x k_i blocks
+    std::vector<int64_t> a0seg_tgt;           // target index a*n0+b of each segment
+    std::vector<int64_t> a0seg_ptr;           // [nseg+1]
+    std::vector<int64_t> a0seg_src;           // index into the T1 buffer
+    std::vector<int64_t> a0pair_tgt;          // target of every T2 value (same order as values)
+
+    double t_analyze = 0.0;
+};
+
+struct Device;   // device buffers (device.hip)
+
+}  // namespace gdsw
+
+struct gdsw_handle_s {
+    gdsw::Symbolic sym;
+    gdsw::Device *dev = nullptr;
+    std::string err;
+    bool analyzed = false;
+    bool factored = false;
+    double t_factor = 0.0;
+};
+
+namespace gdsw {
+// symbolic.cpp
+gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, int32_t n_parts,
+                    int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt);
+// device.hip
+gdsw_status factor(gdsw_handle_s *h, void *stream);
+gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream);
+gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void *stream);
+gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream);
+gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart,
+                  double rtol, int maxit, int fixed_iters, gdsw_solve_info *info, void *stream);
+void destroy_device(gdsw_handle_s *h);
+int64_t device_bytes(const gdsw_handle_s *h);
+gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out);
+}  // namespace gdsw

@@ -1,0 +1,307 @@
+// Device kernels of the preconditioner apply, eq. (1):
+//   one-level part  sum_i R_i^T A_i^{-1} R_i r   (restriction gather, local
+//                   solves, deterministic gather-sum), and
+//   coarse part     Phi A_0^{-1} Phi^T r        (block GEMV^T, segmented sum,
+//                   dense GEMV with the explicit inverse, block GEMV).
+#pragma once
+
+#include "kernels_common.hpp"
+#include "kernels_setup.hpp"
+
+namespace gdsw {
+
+// ---------------------------------------------------------------------------
+// Local ILU(0) solve with Jacobi sweeps (Sec. V-B "Incomplete Local Solver":
+// iterative triangular solves, five sweeps by default):
+//   y^0 = 0, y^{k+1} = r - N_L y^k;   w^0 = 0, w^{k+1} = D^{-1} y^K - (D^{-1} N_U) w^k.
+// One workgroup per subdomain.  Thread t owns rows t, t+NT, ... (R of them);
+// its rows' factor entries (KL lower, KU upper slots) stay in registers for
+// all sweeps, so the factors are read from HBM once per apply; the two
+// iterates live in LDS and alternate.  The restriction gather (with the
+// optional diagonal scaling of the reduced-precision factors) and the write
+// of the local result are fused in.
+template <int NT, int R, int KL, int KU, typename VT>
+__global__ __launch_bounds__(NT) void k_ilu_jacobi(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
+    const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
+    const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
+    double *__restrict__ zloc, const int *__restrict__ done) {
+    using AT = typename AccOf<VT>::type;
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    AT *bufA = reinterpret_cast<AT *>(smraw);
+    AT *bufB = bufA + NT * R;
+    const int i = blockIdx.x;
+    const int64_t o = ov_ptr[i];
+    const int ni = int(ov_ptr[i + 1] - o);
+    const int64_t eo = ell_off[i];
+    const int npad = int(ell_off[i + 1] - eo);
+    const int tid = threadIdx.x;
+
+    AT rr[R];
+    AT lv[R][KL], uv[R][KU];
+    uint16_t lc[R][KL], uc[R][KU];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int l = tid + m * NT;
+        rr[m] = 0;
+        if (l < ni) {
+            const int d = ov_idx[o + l];
+            double x = r[d];
+            if (dscale) x *= dscale[d];
+            rr[m] = AT(x);
+        }
+        const bool ok = l < npad;
+#pragma unroll
+        for (int s = 0; s < KL; ++s) {
+            lv[m][s] = ok ? to_acc(Lv[s * ell_rows + eo + l]) : AT(0);
+            lc[m][s] = ok ? Lc[s * ell_rows + eo + l] : uint16_t(0);
+        }
+#pragma unroll
+        for (int s = 0; s < KU; ++s) {
+            uv[m][s] = ok ? to_acc(Uv[s * ell_rows + eo + l]) : AT(0);
+            uc[m][s] = ok ? Uc[s * ell_rows + eo + l] : uint16_t(0);
+        }
+    }
+    AT *cur = bufA, *nxt = bufB;
+    // first L sweep from zero: y^1 = r
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int l = tid + m * NT;
+        if (l < ni) cur[l] = rr[m];
+    }
+    __syncthreads();
+    for (int k = 1; k < sweeps; ++k) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int l = tid + m * NT;
+            if (l < ni) {
+                AT acc = rr[m];
+#pragma unroll
+                for (int s = 0; s < KL; ++s) acc -= lv[m][s] * cur[lc[m][s]];
+                nxt[l] = acc;
+            }
+        }
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+    // c = D^{-1} y^K (kept in rr), first U sweep from zero: w^1 = c
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int l = tid + m * NT;
+        if (l < ni) {
+            rr[m] = to_acc(dinv[eo + l]) * cur[l];
+            nxt[l] = rr[m];
+        }
+    }
+    __syncthreads();
+    { AT *t = cur; cur = nxt; nxt = t; }
+    for (int k = 1; k < sweeps; ++k) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int l = tid + m * NT;
+            if (l < ni) {
+                AT acc = rr[m];
+#pragma unroll
+                for (int s = 0; s < KU; ++s) acc -= uv[m][s] * cur[uc[m][s]];
+                nxt[l] = acc;
+            }
+        }
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int l = tid + m * NT;
+        if (l < ni) {
+            double v = double(cur[l]);
+            if (dscale) v *= dscale[ov_idx[o + l]];
+            zloc[o + l] = v;
+        }
+    }
+}
+
+// Same sweeps for any slot counts and subdomain sizes: factors are read from
+// global memory on every sweep; r, the iterate pair live in LDS.
+template <int NT, typename VT>
+__global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const int64_t *__restrict__ ell_off, int64_t ell_rows, int KL, int KU, const VT *__restrict__ Lv,
+    const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
+    const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
+    double *__restrict__ zloc, int maxrows, const int *__restrict__ done) {
+    using AT = typename AccOf<VT>::type;
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    AT *rb = reinterpret_cast<AT *>(smraw);
+    AT *cur = rb + maxrows, *nxt = cur + maxrows;
+    const int i = blockIdx.x;
+    const int64_t o = ov_ptr[i];
+    const int ni = int(ov_ptr[i + 1] - o);
+    const int64_t eo = ell_off[i];
+    for (int l = threadIdx.x; l < ni; l += NT) {
+        const int d = ov_idx[o + l];
+        double x = r[d];
+        if (dscale) x *= dscale[d];
+        rb[l] = AT(x);
+        cur[l] = AT(x);
+    }
+    __syncthreads();
+    for (int k = 1; k < sweeps; ++k) {
+        for (int l = threadIdx.x; l < ni; l += NT) {
+            AT acc = rb[l];
+            for (int s = 0; s < KL; ++s)
+                acc -= to_acc(Lv[s * ell_rows + eo + l]) * cur[Lc[s * ell_rows + eo + l]];
+            nxt[l] = acc;
+        }
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+    for (int l = threadIdx.x; l < ni; l += NT) {
+        rb[l] = to_acc(dinv[eo + l]) * cur[l];
+        nxt[l] = rb[l];
+    }
+    __syncthreads();
+    { AT *t = cur; cur = nxt; nxt = t; }
+    for (int k = 1; k < sweeps; ++k) {
+        for (int l = threadIdx.x; l < ni; l += NT) {
+            AT acc = rb[l];
+            for (int s = 0; s < KU; ++s)
+                acc -= to_acc(Uv[s * ell_rows + eo + l]) * cur[Uc[s * ell_rows + eo + l]];
+            nxt[l] = acc;
+        }
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+    for (int l = threadIdx.x; l < ni; l += NT) {
+        double v = double(cur[l]);
+        if (dscale) v *= dscale[ov_idx[o + l]];
+        zloc[o + l] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact local solve A_i^{-1} r_i with the banded Cholesky factor, one
+// workgroup per subdomain, vector in LDS, gather and scatter fused.
+template <int NT, typename VT>
+__global__ __launch_bounds__(NT) void k_band_apply(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
+    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, const int *__restrict__ done) {
+    using AT = typename AccOf<VT>::type;
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    AT *y = reinterpret_cast<AT *>(smraw);
+    AT *sT = y + maxrows;
+    const int i = blockIdx.x;
+    const int64_t o = ov_ptr[i];
+    const int ni = int(ov_ptr[i + 1] - o);
+    for (int l = threadIdx.x; l < ni; l += NT) {
+        const int d = ov_idx[o + l];
+        double x = r[d];
+        if (dscale) x *= dscale[d];
+        y[l] = AT(x);
+    }
+    __syncthreads();
+    band_llt_solve<VT, AT, NT>(band + band_off[i], ni, bw[i], y, sT);
+    for (int l = threadIdx.x; l < ni; l += NT) {
+        double v = double(y[l]);
+        if (dscale) v *= dscale[ov_idx[o + l]];
+        zloc[o + l] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse restriction Phi^T r, block by block: partial[col_ptr[g] + s] =
+// sum_l B_g(l, s) r[rows_g(l)], fixed reduction order.
+template <int NT, typename PT>
+__global__ __launch_bounds__(NT) void k_coarse_restrict(
+    const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
+    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+    double *__restrict__ partial, const int *__restrict__ done) {
+    if (done && *done) return;
+    __shared__ double sh[NT / 64];
+    const int g = blockIdx.x;
+    const int64_t r0 = row_ptr[g];
+    const int nr = int(row_ptr[g + 1] - r0);
+    const int k = int(col_ptr[g + 1] - col_ptr[g]);
+    const PT *B = phi + val_off[g];
+    constexpr int KB = 8;
+    for (int s0 = 0; s0 < k; s0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int s = 0; s < KB; ++s) acc[s] = 0.0;
+        for (int l = threadIdx.x; l < nr; l += NT) {
+            const double x = r[rows[r0 + l]];
+#pragma unroll
+            for (int s = 0; s < KB; ++s)
+                if (s0 + s < k) acc[s] += double(to_acc(B[int64_t(s0 + s) * nr + l])) * x;
+        }
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            if (s0 + s >= k) break;
+            const double t = block_sum<double, NT>(acc[s], sh);
+            if (threadIdx.x == 0) partial[col_ptr[g] + s0 + s] = t;
+        }
+    }
+}
+
+// r0[c] = sum of the partials of coarse column c (ascending block order)
+__global__ void k_coarse_reduce(const int64_t *__restrict__ red_ptr, const int32_t *__restrict__ red_idx,
+                                const double *__restrict__ partial, double *__restrict__ r0, int n0,
+                                const int *__restrict__ done) {
+    if (done && *done) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n0) return;
+    double acc = 0.0;
+    for (int64_t q = red_ptr[c]; q < red_ptr[c + 1]; ++q) acc += partial[red_idx[q]];
+    r0[c] = acc;
+}
+
+// y = A x for a dense row-major n x n matrix: one wavefront per row
+__global__ __launch_bounds__(256) void k_dense_gemv(const double *__restrict__ A, const double *__restrict__ x,
+                                                    double *__restrict__ y, int n, const int *__restrict__ done) {
+    if (done && *done) return;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double *a = A + int64_t(row) * n;
+    double acc = 0.0;
+    for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = acc;
+}
+
+// z[d] = sum over the local rows holding d (ascending subdomain) of zloc
+//        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part)
+template <typename PT>
+__global__ void k_prolong(int which, const int64_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
+                          const double *__restrict__ zloc, const int32_t *__restrict__ dof_blk,
+                          const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
+                          const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols,
+                          const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+                          const double *__restrict__ z0, double *__restrict__ z, int64_t n,
+                          const int *__restrict__ done) {
+    if (done && *done) return;
+    const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (d >= n) return;
+    double acc = 0.0;
+    if (which & 1)
+        for (int64_t p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
+    if (which & 2) {
+        const int g = dof_blk[d];
+        if (g >= 0) {
+            const int64_t nr = row_ptr[g + 1] - row_ptr[g];
+            const int64_t c0 = col_ptr[g];
+            const int k = int(col_ptr[g + 1] - c0);
+            const PT *B = phi + val_off[g] + dof_lr[d];
+            double s = 0.0;
+            for (int q = 0; q < k; ++q) s += double(to_acc(B[q * nr])) * z0[cols[c0 + q]];
+            acc += s;
+        }
+    }
+    z[d] = acc;
+}
+
+}  // namespace gdsw

@@ -1,0 +1,53 @@
+// Shared device helpers: precision conversions and deterministic reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+
+namespace gdsw {
+
+using bf16 = __hip_bfloat16;
+using fp16 = __half;
+
+// arithmetic type for a storage type: FP64 stays FP64, everything else is
+// accumulated in FP32
+template <typename T> struct AccOf { using type = float; };
+template <> struct AccOf<double> { using type = double; };
+
+__device__ __forceinline__ double to_acc(double x) { return x; }
+__device__ __forceinline__ float to_acc(float x) { return x; }
+__device__ __forceinline__ float to_acc(fp16 x) { return __half2float(x); }
+__device__ __forceinline__ float to_acc(bf16 x) { return __bfloat162float(x); }
+
+template <typename T> __device__ __forceinline__ T from_double(double x);
+template <> __device__ __forceinline__ double from_double<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_double<float>(double x) { return float(x); }
+template <> __device__ __forceinline__ fp16 from_double<fp16>(double x) { return __float2half(float(x)); }
+template <> __device__ __forceinline__ bf16 from_double<bf16>(double x) { return __float2bfloat16(float(x)); }
+
+// Sum over a wavefront with a fixed butterfly order (every lane gets it).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Workgroup sum with a fixed order; `sh` must hold NT/64 values.  Every
+// thread returns the total.  Contains two barriers.
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
+}  // namespace gdsw

@@ -1,0 +1,592 @@
+// Device kernels of the numerical setup, phase (b) of the paper's solver
+// structure (Sec. V-A): local matrix values, local factorisations, the
+// energy-minimising extension of eq. (2), the coarse matrix A_0 = Phi^T A Phi
+// and its inverse.
+#pragma once
+
+#include "kernels_common.hpp"
+
+namespace gdsw {
+
+// out[dst[p]] = val[src[p]] * (scale ? scale[row[src[p]]] * scale[col[src[p]]] : 1)
+// (dst == nullptr: out[p]).  Used to gather the local matrices A_i and
+// A_{I_i I_i} from A, optionally symmetrically diagonally scaled.
+__global__ void k_gather_vals(const double *__restrict__ val, const int64_t *__restrict__ src,
+                              const int64_t *__restrict__ dst, double *__restrict__ out, int64_t cnt,
+                              const double *__restrict__ scale, const int32_t *__restrict__ arow,
+                              const int32_t *__restrict__ acol) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        int64_t s = src[p];
+        double v = val[s];
+        if (scale) v *= scale[arow[s]] * scale[acol[s]];
+        out[dst ? dst[p] : p] = v;
+    }
+}
+
+// scale[d] = 1 / sqrt(A[d,d])
+__global__ void k_diag_scale(const double *__restrict__ val, const int64_t *__restrict__ adiag,
+                             double *__restrict__ scale, int64_t n) {
+    int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (d < n) scale[d] = 1.0 / sqrt(val[adiag[d]]);
+}
+
+__global__ void k_fill(double *__restrict__ x, double v, int64_t n) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < n;
+         p += int64_t(gridDim.x) * blockDim.x)
+        x[p] = v;
+}
+
+// ---------------------------------------------------------------------------
+// ILU(0) of every A_i in its natural (ascending global dof) order, in place on
+// the local CSR values; one workgroup per subdomain, rows of one level of the
+// dependency DAG in parallel (level-set scheduling, Sec. V-B "Incomplete
+// Local Solver").  Row-by-row form: for each k < l in row l (ascending),
+// l_lk = a_lk / u_kk and a_lj -= l_lk u_kj for the j > k in both rows.
+// status[i] = 1 + local row of a zero pivot.
+__global__ void k_ilu0_factor(const int64_t *__restrict__ ov_ptr, const int64_t *__restrict__ lrowptr,
+                              const int32_t *__restrict__ lcol, const int32_t *__restrict__ ldiag,
+                              const int64_t *__restrict__ lvl_base, const int32_t *__restrict__ lvl_ptr,
+                              const int32_t *__restrict__ lvl_rows, double *__restrict__ lval,
+                              int *__restrict__ status) {
+    const int i = blockIdx.x;
+    const int64_t o = ov_ptr[i];
+    const int64_t lb = lvl_base[i];
+    const int nlev = int(lvl_base[i + 1] - lb) - 1;
+    for (int L = 0; L < nlev; ++L) {
+        const int beg = lvl_ptr[lb + L], end = lvl_ptr[lb + L + 1];
+        for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+            const int l = lvl_rows[o + q];
+            const int64_t p = o + l;
+            const int64_t rs = lrowptr[p], re = lrowptr[p + 1];
+            for (int64_t e = rs; e < re; ++e) {
+                const int k = lcol[e];
+                if (k >= l) break;
+                const int64_t pk = o + k;
+                const int64_t dk = lrowptr[pk] + ldiag[pk];
+                const double lik = lval[e] / lval[dk];
+                lval[e] = lik;
+                int64_t a = dk + 1, f = e + 1;
+                const int64_t ke = lrowptr[pk + 1];
+                while (a < ke && f < re) {
+                    const int ca = lcol[a], cf = lcol[f];
+                    if (ca == cf) {
+                        lval[f] -= lik * lval[a];
+                        ++a;
+                        ++f;
+                    } else if (ca < cf) {
+                        ++a;
+                    } else {
+                        ++f;
+                    }
+                }
+            }
+            if (lval[rs + ldiag[p]] == 0.0) atomicCAS(status + i, 0, 1 + l);
+        }
+        __syncthreads();
+    }
+}
+
+// Packs the ILU(0) factors into the padded slot-major layout of the Jacobi
+// sweeps: for row p of subdomain i (padded row R = ell_off[i] + l) slot s of
+// the strictly lower part L at [s * ell_rows + R], of the strictly upper part
+// scaled by the pivot (U_lj / U_ll) likewise, and 1 / U_ll.  Unused slots
+// hold 0 with column 0.
+template <typename VT>
+__global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__restrict__ ell_off,
+                           const int64_t *__restrict__ lrowptr, const int32_t *__restrict__ lcol,
+                           const int32_t *__restrict__ ldiag, const double *__restrict__ lval,
+                           int64_t ell_rows, int KL, int KU, VT *__restrict__ Lv,
+                           uint16_t *__restrict__ Lc, VT *__restrict__ Uv, uint16_t *__restrict__ Uc,
+                           VT *__restrict__ dinv) {
+    const int i = blockIdx.y;
+    const int64_t o = ov_ptr[i], ni = ov_ptr[i + 1] - o;
+    const int64_t npad = ell_off[i + 1] - ell_off[i];
+    const int64_t l = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (l >= npad) return;
+    const int64_t R = ell_off[i] + l;
+    int sl = 0, su = 0;
+    if (l < ni) {
+        const int64_t p = o + l;
+        const int64_t rs = lrowptr[p], re = lrowptr[p + 1];
+        const double piv = lval[rs + ldiag[p]];
+        for (int64_t e = rs; e < re; ++e) {
+            const int c = lcol[e];
+            if (c < l) {
+                Lv[sl * ell_rows + R] = from_double<VT>(lval[e]);
+                Lc[sl * ell_rows + R] = uint16_t(c);
+                ++sl;
+            } else if (c > l) {
+                Uv[su * ell_rows + R] = from_double<VT>(lval[e] / piv);
+                Uc[su * ell_rows + R] = uint16_t(c);
+                ++su;
+            }
+        }
+        dinv[R] = from_double<VT>(1.0 / piv);
+    } else {
+        dinv[R] = from_double<VT>(0.0);
+    }
+    for (; sl < KL; ++sl) {
+        Lv[sl * ell_rows + R] = from_double<VT>(0.0);
+        Lc[sl * ell_rows + R] = 0;
+    }
+    for (; su < KU; ++su) {
+        Uv[su * ell_rows + R] = from_double<VT>(0.0);
+        Uc[su * ell_rows + R] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Banded Cholesky A = L L^T of one symmetric positive definite matrix per
+// workgroup, in place in FP64.  Row-major band storage: row r holds columns
+// r-b .. r at band[r*(b+1) + (c - r + b)].  Blocked right-looking algorithm
+// with panels of NB columns: factor the diagonal block in LDS, solve the
+// rows below it (at most b of them), then update the (at most b x b) window
+// below the panel.  The fill of a banded Cholesky factor stays inside the
+// band.  status[i] = 1 + row of the first non-positive pivot.
+constexpr int CH_NB = 16;
+constexpr int CH_LD = CH_NB + 1;   // padded LDS row stride (bank spread)
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_band_chol(double *__restrict__ band, const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ bwid,
+                                                  const int64_t *__restrict__ rptr, int *__restrict__ status) {
+    extern __shared__ double smem[];
+    const int i = blockIdx.x;
+    const int n = int(rptr[i + 1] - rptr[i]);
+    const int b = bwid[i];
+    const int64_t w = b + 1;
+    double *L = band + off[i];
+    double *sD = smem;                 // CH_NB x CH_LD
+    double *sdg = sD + CH_NB * CH_LD;  // CH_NB
+    double *sP = sdg + CH_NB;          // b x CH_LD
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < n; k0 += CH_NB) {
+        const int kb = min(CH_NB, n - k0);
+        // (a) diagonal block, left-looking by columns
+        for (int e = tid; e < CH_NB * CH_NB; e += NT) {
+            const int t = e / CH_NB, s = e % CH_NB;
+            double v = 0.0;
+            if (t < kb && s <= t && t - s <= b) v = L[int64_t(k0 + t) * w + (s - t + b)];
+            sD[t * CH_LD + s] = v;
+        }
+        __syncthreads();
+        for (int j = 0; j < kb; ++j) {
+            const int t = j + tid;
+            if (t < kb) {
+                double v = sD[t * CH_LD + j];
+                for (int s = 0; s < j; ++s) v -= sD[t * CH_LD + s] * sD[j * CH_LD + s];
+                if (t == j) {
+                    if (!(v > 0.0)) {
+                        atomicCAS(status + i, 0, 1 + k0 + j);
+                        v = 1.0;
+                    }
+                    sdg[j] = sqrt(v);
+                } else {
+                    sD[t * CH_LD + j] = v;
+                }
+            }
+            __syncthreads();
+            if (t > j && t < kb) sD[t * CH_LD + j] /= sdg[j];
+            __syncthreads();
+        }
+        for (int e = tid; e < kb * kb; e += NT) {
+            const int t = e / kb, s = e % kb;
+            if (s <= t && t - s <= b)
+                L[int64_t(k0 + t) * w + (s - t + b)] = (s == t) ? sdg[t] : sD[t * CH_LD + s];
+        }
+        // (b) rows below the diagonal block: P <- P L_D^{-T}
+        const int rbeg = k0 + kb;
+        const int rend = min(n, k0 + kb + b);
+        const int m = max(0, rend - rbeg);
+        for (int q = tid; q < m; q += NT) {
+            const int r = rbeg + q;
+            const int s0 = max(0, r - b - k0);
+            double x[CH_NB];
+#pragma unroll
+            for (int s = 0; s < CH_NB; ++s) {
+                double v = 0.0;
+                if (s >= s0 && s < kb) {
+                    v = L[int64_t(r) * w + (k0 + s - r + b)];
+                    for (int t = 0; t < s; ++t) v -= x[t] * sD[s * CH_LD + t];   // x[t] = 0 for t < s0
+                    v /= sdg[s];
+                }
+                x[s] = v;
+            }
+#pragma unroll
+            for (int s = 0; s < CH_NB; ++s) {
+                sP[q * CH_LD + s] = x[s];
+                if (s >= s0 && s < kb) L[int64_t(r) * w + (k0 + s - r + b)] = x[s];
+            }
+        }
+        __syncthreads();
+        // (c) trailing window: A(r, c) -= P(r,:) . P(c,:), c <= r
+        for (int e = tid; e < m * m; e += NT) {
+            const int rq = e / m, cq = e % m;
+            if (cq > rq) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < CH_NB; ++s) acc += sP[rq * CH_LD + s] * sP[cq * CH_LD + s];
+            const int r = rbeg + rq, c = rbeg + cq;
+            L[int64_t(r) * w + (c - r + b)] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Casts a band (FP64) into the storage precision of the local factors.
+template <typename VT>
+__global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int64_t cnt) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * blockDim.x)
+        dst[p] = from_double<VT>(src[p]);
+}
+
+// ---------------------------------------------------------------------------
+// Band triangular solves with one LDS vector: y <- (L L^T)^{-1} y.
+// Forward: blocks of BS rows; the diagonal triangle is solved by wavefront 0
+// (lanes = rows, the solved value broadcast with a shuffle), then the rows
+// that couple to the block (at most b below it) are updated, one thread per
+// row reading its contiguous band segment.  Backward: the same blocks in
+// reverse; the transposed triangle by wavefront 0, then the entries above the
+// block are updated one thread per column, reading band rows of the block
+// (consecutive threads, consecutive addresses).
+constexpr int BS_NB = 32;
+constexpr int BS_LD = BS_NB + 1;
+
+template <typename VT, typename AT, int NT>
+__device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
+    const int64_t w = b + 1;
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < n; k0 += BS_NB) {
+        const int kb = min(BS_NB, n - k0);
+        for (int e = tid; e < BS_NB * BS_NB; e += NT) {
+            const int t = e / BS_NB, s = e % BS_NB;
+            AT v = 0;
+            if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
+            sT[t * BS_LD + s] = v;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            AT yt = (tid < kb) ? y[k0 + tid] : AT(0);
+            for (int s = 0; s < kb; ++s) {
+                if (tid == s) yt = yt / sT[s * BS_LD + s];
+                const AT ys = __shfl(yt, s, 64);
+                if (tid > s && tid < kb) yt -= sT[tid * BS_LD + s] * ys;
+            }
+            if (tid < kb) y[k0 + tid] = yt;
+        }
+        __syncthreads();
+        const int rend = min(n, k0 + kb + b);
+        for (int r = k0 + kb + tid; r < rend; r += NT) {
+            const int s0 = max(0, r - b - k0);
+            const VT *row = L + int64_t(r) * w + (k0 - r + b);
+            AT acc = 0;
+            for (int s = s0; s < kb; ++s) acc += to_acc(row[s]) * y[k0 + s];
+            y[r] -= acc;
+        }
+        __syncthreads();
+    }
+    const int nblk = (n + BS_NB - 1) / BS_NB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int k0 = bi * BS_NB;
+        const int kb = min(BS_NB, n - k0);
+        for (int e = tid; e < BS_NB * BS_NB; e += NT) {
+            const int t = e / BS_NB, s = e % BS_NB;
+            AT v = 0;
+            if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
+            sT[t * BS_LD + s] = v;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            AT yt = (tid < kb) ? y[k0 + tid] : AT(0);
+            for (int s = kb - 1; s >= 0; --s) {
+                if (tid == s) yt = yt / sT[s * BS_LD + s];
+                const AT zs = __shfl(yt, s, 64);
+                if (tid < s) yt -= sT[s * BS_LD + tid] * zs;
+            }
+            if (tid < kb) y[k0 + tid] = yt;
+        }
+        __syncthreads();
+        const int jbeg = max(0, k0 - b);
+        for (int j = jbeg + tid; j < k0; j += NT) {
+            const int smax = min(kb, j + b - k0 + 1);
+            AT acc = 0;
+            for (int s = 0; s < smax; ++s) acc += to_acc(L[int64_t(k0 + s) * w + (j - k0 - s + b)]) * y[k0 + s];
+            y[j] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Extension, eq. (2).  E_i = A_{I_i Gamma} Phi_Gamma(:, cols_i) is assembled
+// one thread per interior row (couplings in CSR order), column-major
+// n_Ii x k_i per subdomain at ext_off[i].
+__global__ void k_ext_rhs(const double *__restrict__ Aval, const int64_t *__restrict__ int_ptr, int np,
+                          const int64_t *__restrict__ ext_off, const int64_t *__restrict__ cpl_ptr,
+                          const int64_t *__restrict__ cpl_apos, const int64_t *__restrict__ cpl_phi,
+                          const int32_t *__restrict__ cpl_stride, const int32_t *__restrict__ cpl_rank,
+                          const int32_t *__restrict__ cpl_slot, const double *__restrict__ phig,
+                          double *__restrict__ E, int64_t nint) {
+    const int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (q >= nint) return;
+    int lo = 0, hi = np;   // subdomain with int_ptr[i] <= q < int_ptr[i+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (int_ptr[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int i = lo;
+    const int64_t nr = int_ptr[i + 1] - int_ptr[i];
+    const int64_t l = q - int_ptr[i];
+    double *Ei = E + ext_off[i];
+    for (int64_t e = cpl_ptr[q]; e < cpl_ptr[q + 1]; ++e) {
+        const double a = Aval[cpl_apos[e]];
+        const double *ph = phig + cpl_phi[e];
+        const int st = cpl_stride[e], rk = cpl_rank[e], sl = cpl_slot[e];
+        for (int j = 0; j < rk; ++j) Ei[(sl + j) * nr + l] += a * ph[int64_t(j) * st];
+    }
+}
+
+// Phi_{I_i} = -A_{I_i I_i}^{-1} E_i, one workgroup per subdomain, one right
+// hand side at a time through LDS, written into the subdomain's interior
+// block of Phi.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ext_solve(const double *__restrict__ iband,
+                                                  const int64_t *__restrict__ iband_off,
+                                                  const int32_t *__restrict__ ibw,
+                                                  const int64_t *__restrict__ int_ptr,
+                                                  const int64_t *__restrict__ scol_ptr,
+                                                  const int64_t *__restrict__ ext_off,
+                                                  const double *__restrict__ E,
+                                                  const int32_t *__restrict__ sub_blk,
+                                                  const int64_t *__restrict__ blk_val_off,
+                                                  double *__restrict__ phi) {
+    extern __shared__ double smem[];
+    const int i = blockIdx.x;
+    const int n = int(int_ptr[i + 1] - int_ptr[i]);
+    const int k = int(scol_ptr[i + 1] - scol_ptr[i]);
+    const int g = sub_blk[i];
+    if (n == 0 || k == 0 || g < 0) return;
+    double *y = smem;
+    double *sT = smem + n;
+    const double *L = iband + iband_off[i];
+    for (int s = 0; s < k; ++s) {
+        const double *e = E + ext_off[i] + int64_t(s) * n;
+        for (int l = threadIdx.x; l < n; l += NT) y[l] = e[l];
+        __syncthreads();
+        band_llt_solve<double, double, NT>(L, n, ibw[i], y, sT);
+        double *out = phi + blk_val_off[g] + int64_t(s) * n;
+        for (int l = threadIdx.x; l < n; l += NT) out[l] = -y[l];
+        __syncthreads();
+    }
+}
+
+// T1_i = E_i^T Phi_{I_i} (k_i x k_i), one thread per entry of one subdomain
+__global__ void k_t1(const int64_t *__restrict__ int_ptr, const int64_t *__restrict__ scol_ptr,
+                     const int64_t *__restrict__ ext_off, const double *__restrict__ E,
+                     const int32_t *__restrict__ sub_blk, const int64_t *__restrict__ blk_val_off,
+                     const double *__restrict__ phi, const int64_t *__restrict__ t1_off,
+                     double *__restrict__ T1) {
+    const int i = blockIdx.y;
+    const int n = int(int_ptr[i + 1] - int_ptr[i]);
+    const int k = int(scol_ptr[i + 1] - scol_ptr[i]);
+    const int g = sub_blk[i];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n == 0 || k == 0 || g < 0 || e >= k * k) return;
+    const int a = e / k, bcol = e % k;
+    const double *Ea = E + ext_off[i] + int64_t(a) * n;
+    const double *Xb = phi + blk_val_off[g] + int64_t(bcol) * n;
+    double acc = 0.0;
+    for (int l = 0; l < n; ++l) acc += Ea[l] * Xb[l];
+    T1[t1_off[i] + e] = acc;
+}
+
+// Interface-interface part of A_0: for every component pair (c, d) with
+// couplings in A, A0[c-cols, d-cols] = Phi_Gc^T A_{cd} Phi_Gd, one thread per
+// entry, couplings in a fixed order.
+__global__ void k_t2(const double *__restrict__ Aval, int npairs, const int32_t *__restrict__ pair_c,
+                     const int32_t *__restrict__ pair_d, const int64_t *__restrict__ pair_off,
+                     const int64_t *__restrict__ pair_eptr, const int64_t *__restrict__ pair_apos,
+                     const int32_t *__restrict__ pair_lr_c, const int32_t *__restrict__ pair_lr_d,
+                     const int32_t *__restrict__ comp_rank, const int64_t *__restrict__ phig_off,
+                     const double *__restrict__ phig, const int64_t *__restrict__ tgt,
+                     double *__restrict__ A0, int64_t total) {
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (t >= total) return;
+    int lo = 0, hi = npairs;   // pair with pair_off[q] <= t < pair_off[q+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pair_off[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int q = lo;
+    const int c = pair_c[q], d = pair_d[q];
+    const int rd = comp_rank[d];
+    const int64_t loc = t - pair_off[q];
+    const int a = int(loc / rd), bb = int(loc % rd);
+    const int64_t nrc = (phig_off[c + 1] - phig_off[c]) / comp_rank[c];
+    const int64_t nrd = (phig_off[d + 1] - phig_off[d]) / rd;
+    const double *pc = phig + phig_off[c] + a * nrc;
+    const double *pd = phig + phig_off[d] + bb * nrd;
+    double acc = 0.0;
+    for (int64_t e = pair_eptr[q]; e < pair_eptr[q + 1]; ++e)
+        acc += pc[pair_lr_c[e]] * Aval[pair_apos[e]] * pd[pair_lr_d[e]];
+    A0[tgt[t]] = acc;
+}
+
+// A0[tgt] += sum of the subdomain contributions of the segment, ascending
+// subdomain order
+__global__ void k_a0_segments(const int64_t *__restrict__ seg_tgt, const int64_t *__restrict__ seg_ptr,
+                              const int64_t *__restrict__ seg_src, const double *__restrict__ T1,
+                              double *__restrict__ A0, int64_t nseg) {
+    const int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (s >= nseg) return;
+    double acc = 0.0;
+    for (int64_t e = seg_ptr[s]; e < seg_ptr[s + 1]; ++e) acc += T1[seg_src[e]];
+    A0[seg_tgt[s]] += acc;
+}
+
+// B = (A + A^T) / 2
+__global__ void k_symmetrize(const double *__restrict__ A, double *__restrict__ B, int n) {
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (t >= int64_t(n) * n) return;
+    const int r = int(t / n), c = int(t % n);
+    B[t] = 0.5 * (A[t] + A[int64_t(c) * n + r]);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of the SPD coarse matrix by blocked Gauss-Jordan sweeps without
+// pivoting (the pivots are Schur complements of an SPD matrix).  Sweeping
+// block K of a symmetric matrix with P = A_KK^{-1}:
+//   A_KK <- -P,  A_iK <- A_iK P,  A_Kj <- P A_Kj,  A_ij <- A_ij - A_iK P A_Kj;
+// after all blocks the matrix holds -A^{-1}.
+constexpr int GJ_NB = 32;
+constexpr int GJ_LD = GJ_NB + 1;
+
+// P = A_KK^{-1} in LDS by scalar sweeps, written to Pout (kb x kb)
+__global__ __launch_bounds__(256) void k_gj_pivot(const double *__restrict__ A, int n, int k0, int kb,
+                                                  double *__restrict__ Pout, int *__restrict__ status) {
+    __shared__ double S[GJ_NB * GJ_LD];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kb * kb; e += 256) {
+        const int r = e / kb, c = e % kb;
+        S[r * GJ_LD + c] = A[int64_t(k0 + r) * n + (k0 + c)];
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        const double piv = S[j * GJ_LD + j];
+        if (!(piv > 0.0)) {
+            if (tid == 0) atomicCAS(status, 0, 1 + k0 + j);
+            return;
+        }
+        const double p = 1.0 / piv;
+        // all new values are computed from the old ones before any is stored
+        double upd[4];
+        int cnt = 0;
+        for (int e = tid; e < kb * kb; e += 256, ++cnt) {
+            const int rr = e / kb, cc = e % kb;
+            double v = S[rr * GJ_LD + cc];
+            const double aij = S[rr * GJ_LD + j], ajk = S[j * GJ_LD + cc];
+            if (rr == j && cc == j) v = -p;
+            else if (cc == j) v = aij * p;
+            else if (rr == j) v = p * ajk;
+            else v = v - aij * p * ajk;
+            upd[cnt] = v;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int e = tid; e < kb * kb; e += 256, ++cnt) S[(e / kb) * GJ_LD + (e % kb)] = upd[cnt];
+        __syncthreads();
+    }
+    for (int e = tid; e < kb * kb; e += 256) Pout[e] = -S[(e / kb) * GJ_LD + (e % kb)];
+}
+
+// W(i, :) = A(i, K) P for every row i (rows in K get 0)
+__global__ void k_gj_panel(const double *__restrict__ A, int n, int k0, int kb, const double *__restrict__ P,
+                           double *__restrict__ W) {
+    __shared__ double sP[GJ_NB * GJ_NB];
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) sP[e] = P[e];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[GJ_NB];
+#pragma unroll
+    for (int t = 0; t < GJ_NB; ++t) a[t] = (t < kb) ? A[int64_t(i) * n + k0 + t] : 0.0;
+    const bool inK = (i >= k0 && i < k0 + kb);
+    for (int s = 0; s < kb; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < GJ_NB; ++t)
+            if (t < kb) acc += a[t] * sP[t * kb + s];
+        W[int64_t(i) * GJ_NB + s] = inK ? 0.0 : acc;
+    }
+}
+
+// A(i, j) -= W(i, :) . A(K, j) for i, j outside K; 64x64 tiles, 4x4 per thread
+__global__ __launch_bounds__(256) void k_gj_update(double *__restrict__ A, int n, int k0, int kb,
+                                                   const double *__restrict__ W) {
+    __shared__ double sW[64 * GJ_LD];
+    __shared__ double sK[GJ_NB * 65];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * GJ_NB; e += 256) {
+        const int r = e / GJ_NB, t = e % GJ_NB;
+        const int i = i0 + r;
+        sW[r * GJ_LD + t] = (i < n && t < kb) ? W[int64_t(i) * GJ_NB + t] : 0.0;
+    }
+    for (int e = tid; e < GJ_NB * 64; e += 256) {
+        const int t = e / 64, c = e % 64;
+        const int j = j0 + c;
+        sK[t * 65 + c] = (j < n && t < kb) ? A[int64_t(k0 + t) * n + j] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4] = {};
+    for (int t = 0; t < kb; ++t) {
+        double wv[4], kv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wv[a] = sW[(tr + a) * GJ_LD + t];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kv[c] = sK[t * 65 + tc + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += wv[a] * kv[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + tr + a;
+        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + tc + c;
+            if (j >= n || (j >= k0 && j < k0 + kb)) continue;
+            A[int64_t(i) * n + j] -= acc[a][c];
+        }
+    }
+}
+
+// A(i, K) = W(i, :), A(K, i) = W(i, :)^T (i outside K), A_KK = -P
+__global__ void k_gj_fix(double *__restrict__ A, int n, int k0, int kb, const double *__restrict__ W,
+                         const double *__restrict__ P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i >= k0 && i < k0 + kb) {
+        const int r = i - k0;
+        for (int t = 0; t < kb; ++t) A[int64_t(i) * n + k0 + t] = -P[r * kb + t];
+        return;
+    }
+    for (int t = 0; t < kb; ++t) {
+        const double v = W[int64_t(i) * GJ_NB + t];
+        A[int64_t(i) * n + k0 + t] = v;
+        A[int64_t(k0 + t) * n + i] = v;
+    }
+}
+
+__global__ void k_negate(double *__restrict__ A, int64_t cnt) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * blockDim.x)
+        A[p] = -A[p];
+}
+
+}  // namespace gdsw

@@ -240,6 +240,8 @@ def elasticity_q1(Ne: int, P: int | tuple = 2, E: float = 1.0, nu: float = 0.3,
     v = np.tile(Ke.ravel(), e.size)
     m = (r >= 0) & (c >= 0)
     A = _csr(r[m], c[m], v[m], n)
+    A = ((A + A.T) * 0.5).tocsr()      # exact symmetry of the summed values
+    A.sort_indices()
     # consistent load: each element gives h^3/8 * f to each of its 8 nodes
     b = np.zeros(n)
     w = h ** 3 / 8

@@ -1,0 +1,144 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/gdsw.h, and its host symbolic analysis (phase (a))
+reproduces the oracle's integer maps bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_04876_amd import binding as B
+from paper_2304_04876_amd import problems as P
+from oracle import gdsw_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gdsw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gdsw_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert "gdsw_setup" in names and "gdsw_apply" in names and "gdsw_solve" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_status_strings_and_defaults():
+    assert B.gdsw_status_string(0) == "ok"
+    assert "singular" in B.gdsw_status_string(2)
+    o = B.gdsw_default_options()
+    assert (o.overlap, o.coarse, o.local, o.jacobi_sweeps, o.local_prec) == (1, 1, 0, 5, 0)
+
+
+def _maps_equal(pr, Z=None, overlap=1, local="exact"):
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
+                       B.gdsw_default_options(overlap=overlap, local=0 if local == "exact" else 1))
+    try:
+        M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, overlap=overlap, local=local)
+        m = M.maps()
+        ov_ptr = np.concatenate([[0], np.cumsum([r.size for r in M.R])])
+        assert np.array_equal(B.gdsw_copy_map(h, B.MAP_OV_PTR), ov_ptr)
+        assert np.array_equal(B.gdsw_copy_map(h, B.MAP_OV_IDX), m["ov_idx"])
+        assert np.array_equal(B.gdsw_copy_map(h, B.MAP_IS_GAMMA), m["is_gamma"])
+        assert np.array_equal(B.gdsw_copy_map(h, B.MAP_COMP_OF_NODE), m["comp_of_node"])
+        assert np.array_equal(B.gdsw_copy_map(h, B.MAP_COMP_RANK), m["comp_rank"])
+        info = B.gdsw_get_info(h)
+        assert info["n0"] == m["n0"] and info["n_components"] == m["n_comp"]
+        # Phi's column pattern: every interface dof in its component's columns
+        rp = B.gdsw_copy_map(h, B.MAP_PHI_ROWPTR)
+        cols = B.gdsw_copy_map(h, B.MAP_PHI_COL)
+        phi = M.cs.phi.tocsr() if M.cs is not None else None
+        if phi is not None:
+            for d in np.linspace(0, pr.n - 1, 50).astype(int):
+                lib_cols = set(cols[rp[d]:rp[d + 1]].tolist())
+                or_cols = set(phi.indices[phi.indptr[d]:phi.indptr[d + 1]].tolist())
+                assert or_cols <= lib_cols
+    finally:
+        B.gdsw_destroy(h)
+
+
+@pytest.mark.parametrize("N,Pn", [(20, 2), (12, 3), (17, 3), (9, 2)])
+def test_maps_poisson(N, Pn):
+    _maps_equal(P.poisson3d(N, Pn))
+
+
+@pytest.mark.parametrize("overlap", [0, 2])
+def test_maps_overlap(overlap):
+    _maps_equal(P.poisson3d(12, 3), overlap=overlap)
+
+
+def test_maps_uneven_partition():
+    pr = P.poisson3d(10, (2, 3, 1))
+    _maps_equal(pr)
+
+
+def test_maps_elasticity():
+    pr = P.elasticity_q1(6, 2)
+    _maps_equal(pr, P.rigid_body_modes(pr))
+
+
+def test_maps_elasticity_three_boxes():
+    pr = P.elasticity_q1(9, 3)
+    _maps_equal(pr, P.rigid_body_modes(pr))
+
+
+def test_maps_diffusion():
+    spec = P.batch_diffusion_specs(3)[1]
+    _maps_equal(P.batch_diffusion_problem(spec))
+
+
+def test_closed_form_counts_small_workload():
+    pr = P.workload_poisson_small()
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1)
+    info = B.gdsw_get_info(h)
+    B.gdsw_destroy(h)
+    assert (info["n_gamma_nodes"], info["n_components"], info["sum_overlap_dofs"]) == (1141, 19, 10400)
+
+
+@pytest.mark.slow
+def test_closed_form_counts_large_workload():
+    pr = P.workload_poisson_large()
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, options=B.gdsw_default_options(local=1))
+    info = B.gdsw_get_info(h)
+    B.gdsw_destroy(h)
+    assert (info["n_gamma_nodes"], info["n_components"], info["sum_overlap_dofs"]) == (325591, 2863, 2785280)
+
+
+def test_invalid_arguments_are_reported():
+    pr = P.poisson3d(6, 2)
+    bad = pr.part.copy()
+    bad[0] = 99
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(pr.A, bad, pr.n_parts, 1)
+    assert e.value.status == 1 and "part" in str(e.value)
+    A = pr.A.tolil()
+    A[0, 1] = -2.0          # breaks symmetry
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(A.tocsr(), pr.part, pr.n_parts, 1)
+    assert "symmetric" in str(e.value)
+    with pytest.raises(B.GdswError):
+        B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, options=B.gdsw_default_options(jacobi_sweeps=0))
+    A = pr.A.tolil()
+    A[3, 3] = np.nan
+    with pytest.raises(B.GdswError):
+        B.gdsw_analyze(A.tocsr(), pr.part, pr.n_parts, 1)
+
+
+def test_factor_without_analysis_state_error():
+    # a handle whose analysis failed cannot be factored
+    pr = P.poisson3d(6, 2)
+    h = B.ctypes.c_void_p()
+    rowptr, col, val = B._csr_arrays(pr.A)
+    csr = B.CSR(pr.n, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+    bad = np.full(pr.n, 7, dtype=np.int32)
+    st = B.lib().gdsw_analyze(B.ctypes.byref(csr), bad.ctypes.data, 2, 1, None, 0, None, B.ctypes.byref(h))
+    assert st == 1
+    assert "part" in B.gdsw_last_error(h.value)
+    assert B.lib().gdsw_factor(h.value, None) == 7
+    B.gdsw_destroy(h.value)
