@@ -116,6 +116,10 @@ struct Device {
     int64_t local_entries = 0;
     int KLp = 1, KUp = 1;   // slot counts of the sweep layout
     size_t max_lds = 64 * 1024;   // dynamic LDS a workgroup may use on this device
+    double *gm_V = nullptr, *gm_part = nullptr;   // GMRES basis and partial sums
+    int gm_m = 0;
+    GState *gm_st = nullptr;
+    void *sweep_buf = nullptr;    // iterates of subdomains too large for LDS
 };
 
 // ---------------------------------------------------------------------------
@@ -146,7 +150,7 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     D.kp = D.alloc<double>(n);
     D.kq = D.alloc<double>(n);
     D.kt = D.alloc<double>(n);
-    D.kpart = D.alloc<double>(nblocks(n, KNT));
+    D.kpart = D.alloc<double>(KRED);
     D.kst = D.alloc<KState>(1);
     // the sync below makes the host vectors above safe to release
     HIPCHK(hipStreamSynchronize(s));
@@ -217,6 +221,13 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
             case GDSW_FP32: pack_ilu<float>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
             case GDSW_BF16: pack_ilu<bf16>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
             default: pack_ilu<fp16>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
+        }
+        // subdomains whose three sweep vectors do not fit in LDS (and that the
+        // register-resident kernel does not cover) keep them in global memory
+        {
+            const size_t asz = prec == GDSW_FP64 ? 8 : 4;
+            if (3 * asz * size_t(S.max_ni) > D.max_lds)
+                D.sweep_buf = D.raw_alloc(3 * asz * size_t(S.ov_ptr[S.np]));
         }
         HIPCHK(hipStreamSynchronize(s));
         D.release(d_lval, sizeof(double) * ne);
@@ -518,12 +529,17 @@ static void launch_local(const Symbolic &S, Device &D, const double *r, const in
     using AT = typename AccOf<VT>::type;
     if (S.opt.local == GDSW_LOCAL_ILU0) {
         if (launch_ilu_regs<VT>(S, D, r, done, s)) return;
-        const size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
-        if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS sweeps"};
+        size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
+        void *gbuf = nullptr;
+        if (lds > D.max_lds) {
+            if (!D.sweep_buf) throw DevError{GDSW_ERR_INTERNAL, "sweep buffer missing"};
+            gbuf = D.sweep_buf;
+            lds = 0;
+        }
         hipLaunchKernelGGL((k_ilu_jacobi_generic<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
                            D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc,
                            (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc,
-                           S.max_ni, done);
+                           S.max_ni, gbuf, done);
     } else {
         const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
         if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS band solve"};
@@ -620,7 +636,8 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const int n = int(S.n);
-    const int g = nblocks(n, KNT);
+    const int gr = std::min(KRED, nblocks(n, KNT));
+    double *pt = D.kpart;
     KState hs{};
     hs.rtol2 = rtol * rtol;
     hs.fixed = fixed;
@@ -628,7 +645,8 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
     HIPCHK(hipMemcpyAsync(D.kst, &hs, sizeof(KState), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, int64_t(n));
     hipLaunchKernelGGL(k_copy, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, b, D.kr, int64_t(n));
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, b, b, n, D.kpart, D.kst, 0, 2);
+    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, b, b, n, pt, D.kst, 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_BB));
     HIPCHK(hipMemcpyAsync(&hs, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!(hs.bb > 0.0)) {
@@ -637,20 +655,24 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
     }
     int *done = &D.kst->done;
     launch_apply(h, D.kr, D.kz, 3, nullptr, s);
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kr, D.kz, n, D.kpart, D.kst, 1, 3);
-    hipLaunchKernelGGL(k_cg_update_p, dim3(g), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 1);
+    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kr, D.kz, n, pt, D.kst, 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RHO));
+    hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 1);
     const int limit = fixed > 0 ? fixed : maxit;
     int queued = 0;
     int chunk = 4;
     while (true) {
         const int c = std::min(chunk, limit - queued);
         for (int k = 0; k < c; ++k) {
-            hipLaunchKernelGGL(k_cg_spmv_dot, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, n,
-                               D.kpart, D.kst);
-            hipLaunchKernelGGL(k_cg_update_xr, dim3(g), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, n, D.kpart, D.kst);
+            hipLaunchKernelGGL(k_cg_spmv_dot, dim3(gr), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, n, pt,
+                               D.kst);
+            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_ALPHA));
+            hipLaunchKernelGGL(k_cg_update_xr, dim3(gr), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, n, pt, D.kst);
+            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RR));
             launch_apply(h, D.kr, D.kz, 3, done, s);
-            hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kr, D.kz, n, D.kpart, D.kst, 2, 4);
-            hipLaunchKernelGGL(k_cg_update_p, dim3(g), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 0);
+            hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kr, D.kz, n, pt, D.kst, 1);
+            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_BETA));
+            hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 0);
         }
         queued += c;
         HIPCHK(hipGetLastError());
@@ -660,9 +682,10 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
         chunk = std::min(chunk * 2, 32);
     }
     // true residual
-    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, n);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, n);
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(KNT), 0, s, D.kt, D.kt, n, D.kpart, D.kst, 3, 5);
+    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kt, D.kt, n, pt, D.kst, 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RED));
     KState fin{};
     HIPCHK(hipMemcpyAsync(&fin, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -712,10 +735,118 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
     return st;
 }
 
-gdsw_status solve_gmres(gdsw_handle_s *h, const double *, double *, int, double, int, int, gdsw_solve_info *,
-                        hipStream_t) {
-    h->err = "GMRES is not available in this build";
-    return GDSW_ERR_INVALID_ARG;
+// Restarted GMRES(m), right preconditioned, x0 = 0 (the oracle's order):
+// every cycle r = b - A x, V_0 = r / ||r||; step j: w = A M^{-1} V_j,
+// orthogonalised against V_0..V_j twice, Givens rotations on the new
+// Hessenberg column, stop when |g_{j+1}| <= rtol ||b||; at the end of the
+// cycle x += M^{-1} (V y) with y the small least-squares solution.
+gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restart, double rtol, int maxit,
+                        int fixed, gdsw_solve_info *info, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int64_t n = S.n;
+    const int m = std::max(1, std::min(restart, GM_MAX));
+    const int g = nblocks(n, KNT);
+    if (!D.gm_V || D.gm_m < m) {
+        if (D.gm_V) D.release(D.gm_V, sizeof(double) * size_t(D.gm_m + 1) * size_t(n));
+        D.gm_V = D.alloc<double>(int64_t(m + 1) * n);
+        D.gm_m = m;
+    }
+    if (!D.gm_st) D.gm_st = D.alloc<GState>(1);
+    const int gr = std::min(KRED, g);
+    if (!D.gm_part) D.gm_part = D.alloc<double>(int64_t(KRED) * (GM_MAX + 1));
+    // ||b||^2
+    KState ks{};
+    HIPCHK(hipMemcpyAsync(D.kst, &ks, sizeof(KState), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, b, b, int(n), D.kpart, D.kst, 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, gr, D.kst, int(KF_BB));
+    HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, n);
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(ks.bb > 0.0)) {
+        if (info) { info->iterations = 0; info->converged = 1; info->rel_res_recursive = 0; info->rel_res_true = 0; }
+        return std::isfinite(ks.bb) ? GDSW_OK : GDSW_ERR_INVALID_ARG;
+    }
+    GState* hs = new GState();
+    hs->bb = ks.bb;
+    hs->rtol2 = rtol * rtol;
+    hs->m = m;
+    hs->fixed = fixed;
+    hs->maxit = maxit;
+    HIPCHK(hipMemcpyAsync(D.gm_st, hs, sizeof(GState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    GState *st = D.gm_st;
+    double *V = D.gm_V;
+    double *v = D.kz, *t = D.kp, *w = D.kq, *r = D.kr, *u = D.kt;
+    const int *cdone = &st->cycle_done;
+    int guard = 0;
+    while (true) {
+        // r = b - A x
+        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, r, int(n));
+        hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
+        hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, r, n, D.gm_part, st, 1);
+        hipLaunchKernelGGL(k_gm_start_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st);
+        hipLaunchKernelGGL(k_gm_v0, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, r, n, st);
+        int queued = 0, chunk = 4;
+        while (true) {
+            const int c = std::min(chunk, m - queued);
+            for (int k = 0; k < c; ++k) {
+                hipLaunchKernelGGL(k_gm_get, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, v, n, st);
+                launch_apply(h, v, t, 3, cdone, s);
+                hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, t, w, int(n), st);
+                for (int pass = 0; pass < 2; ++pass) {
+                    hipLaunchKernelGGL(k_gm_dots, dim3(gr), dim3(KNT), 0, s, V, w, n, D.gm_part, st);
+                    hipLaunchKernelGGL(k_gm_dots_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st, pass);
+                    hipLaunchKernelGGL(k_gm_subtract, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, w, n, st);
+                }
+                hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, w, n, D.gm_part, st, 0);
+                hipLaunchKernelGGL(k_gm_step_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st);
+                hipLaunchKernelGGL(k_gm_scale, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, w, n, st);
+            }
+            queued += c;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hs->cycle_done || queued >= m) break;
+            chunk = std::min(chunk * 2, 16);
+        }
+        if (hs->j > 0 && hs->status != KS_BREAKDOWN) {
+            hipLaunchKernelGGL(k_gm_lsq, dim3(1), dim3(64), 0, s, st);
+            hipLaunchKernelGGL(k_gm_combine, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, u, n, st);
+            launch_apply(h, u, t, 3, nullptr, s);
+            hipLaunchKernelGGL(k_add, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, t, n);
+        }
+        HIPCHK(hipMemcpyAsync(hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hs->done) break;
+        if (++guard > maxit + 2) break;
+    }
+    const int status = hs->status, total = hs->total;
+    const double g_last = hs->j > 0 ? std::fabs(hs->g[hs->j]) : hs->beta;
+    delete hs;
+    // true residual
+    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, int(n));
+    hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, int(n));
+    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kt, D.kt, int(n), D.kpart, D.kst, 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, gr, D.kst, int(KF_RED));
+    HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = total;
+        info->rel_res_recursive = g_last / std::sqrt(ks.bb);
+        info->rel_res_true = std::sqrt(ks.red / ks.bb);
+        info->converged = fixed > 0 ? info->rel_res_true <= rtol : status == KS_CONVERGED;
+    }
+    if (status == KS_BREAKDOWN) {
+        h->err = "GMRES breakdown";
+        return GDSW_ERR_BREAKDOWN;
+    }
+    if (fixed > 0) return GDSW_OK;
+    if (status != KS_CONVERGED) {
+        h->err = "GMRES did not converge";
+        return GDSW_ERR_NOT_CONVERGED;
+    }
+    return GDSW_OK;
 }
 
 void destroy_device(gdsw_handle_s *h) {

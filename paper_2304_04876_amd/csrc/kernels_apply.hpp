@@ -123,22 +123,26 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
 }
 
 // Same sweeps for any slot counts and subdomain sizes: factors are read from
-// global memory on every sweep; r, the iterate pair live in LDS.
+// global memory on every sweep; r and the iterate pair live in LDS (or in
+// global memory when a subdomain does not fit).
 template <int NT, typename VT>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const int64_t *__restrict__ ell_off, int64_t ell_rows, int KL, int KU, const VT *__restrict__ Lv,
     const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
     const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
-    double *__restrict__ zloc, int maxrows, const int *__restrict__ done) {
+    double *__restrict__ zloc, int maxrows, void *__restrict__ gbuf, const int *__restrict__ done) {
     using AT = typename AccOf<VT>::type;
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smraw[];
-    AT *rb = reinterpret_cast<AT *>(smraw);
-    AT *cur = rb + maxrows, *nxt = cur + maxrows;
     const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
+    // the three vectors live in LDS, or (subdomains too large for it) in a
+    // per-subdomain slice of global memory, which stays in L2
+    AT *rb = gbuf ? reinterpret_cast<AT *>(gbuf) + 3 * o : reinterpret_cast<AT *>(smraw);
+    const int64_t stride = gbuf ? ni : maxrows;
+    AT *cur = rb + stride, *nxt = cur + stride;
     const int64_t eo = ell_off[i];
     for (int l = threadIdx.x; l < ni; l += NT) {
         const int d = ov_idx[o + l];

@@ -1,8 +1,10 @@
 // Device kernels of the Krylov iteration (FP64): CSR SpMV, fused vector
-// updates and dot products.  Every reduction is deterministic: each
-// workgroup writes a partial in a fixed order and the last workgroup to
-// finish (found with a counter) sums the partials in index order, then
-// updates the scalar state on the device, so the host only polls a flag.
+// updates and dot products.  Every reduction is deterministic: a fixed
+// number of workgroups each write one partial (grid-stride rows, fixed tree
+// within the workgroup), then a one-workgroup kernel sums the partials in
+// index order and updates the scalar state on the device, so the host only
+// polls a flag.  (The kernel boundary orders the partial writes before the
+// final sum; no device-wide fences are needed.)
 #pragma once
 
 #include "kernels_common.hpp"
@@ -12,28 +14,18 @@ namespace gdsw {
 struct KState {
     double rho, sigma, alpha, beta, rr, bb, rtol2, red;
     int iters, done, status, fixed, maxit, pad;
-    unsigned cnt[8];
 };
 
 enum { KS_RUNNING = 0, KS_CONVERGED = 1, KS_MAXIT = 2, KS_BREAKDOWN = 3 };
 
 constexpr int KNT = 256;
+constexpr int KRED = 1024;   // workgroups of every reducing kernel (fixed: fixed summation order)
 
-// sums gridDim.x partials in index order; called by the last workgroup only
-__device__ __forceinline__ double finish_partials(const double *partial, int np, double *sh) {
+// Sum of the per-workgroup partials in index order, by one workgroup.
+__device__ __forceinline__ double sum_partials(const double *partial, int np, double *sh) {
     double v = 0.0;
-    for (int q = threadIdx.x; q < np; q += KNT) v += __builtin_nontemporal_load(partial + q);
+    for (int q = threadIdx.x; q < np; q += KNT) v += partial[q];
     return block_sum<double, KNT>(v, sh);
-}
-
-// returns true in every thread of the last workgroup to arrive
-__device__ __forceinline__ bool arrive_last(unsigned *cnt, bool *flag) {
-    __threadfence();
-    if (threadIdx.x == 0) *flag = (atomicAdd(cnt, 1u) == gridDim.x - 1);
-    __syncthreads();
-    const bool last = *flag;
-    if (last) __threadfence();
-    return last;
 }
 
 __global__ __launch_bounds__(KNT) void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -46,100 +38,102 @@ __global__ __launch_bounds__(KNT) void k_spmv(const int32_t *__restrict__ rowptr
     y[i] = acc;
 }
 
-// q = A p; sigma = p.q; alpha = rho / sigma
+// q = A p and the partials of p.q (grid of KRED workgroups, grid-stride rows)
 __global__ __launch_bounds__(KNT) void k_cg_spmv_dot(const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col,
                                                      const double *__restrict__ val,
                                                      const double *__restrict__ p, double *__restrict__ q,
-                                                     int n, double *__restrict__ partial, KState *st) {
+                                                     int n, double *__restrict__ partial, const KState *st) {
     if (st->done) return;
     __shared__ double sh[KNT / 64];
-    __shared__ bool last;
-    const int i = blockIdx.x * KNT + threadIdx.x;
     double dot = 0.0;
-    if (i < n) {
+    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) {
         double acc = 0.0;
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += val[k] * p[col[k]];
         q[i] = acc;
-        dot = p[i] * acc;
+        dot += p[i] * acc;
     }
     dot = block_sum<double, KNT>(dot, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = dot;
-    if (!arrive_last(&st->cnt[0], &last)) return;
-    const double sigma = finish_partials(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-        st->cnt[0] = 0;
-        st->sigma = sigma;
-        if (!(sigma > 0.0) || !isfinite(sigma)) {
-            st->done = 1;
-            st->status = KS_BREAKDOWN;
-        } else {
-            st->alpha = st->rho / sigma;
-        }
-    }
 }
 
-// x += alpha p; r -= alpha q; rr = r.r; convergence test
+// x += alpha p; r -= alpha q; partials of r.r
 __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p,
                                                       const double *__restrict__ q, int n,
-                                                      double *__restrict__ partial, KState *st) {
+                                                      double *__restrict__ partial, const KState *st) {
     if (st->done) return;
     __shared__ double sh[KNT / 64];
-    __shared__ bool last;
     const double alpha = st->alpha;
-    const int i = blockIdx.x * KNT + threadIdx.x;
     double v = 0.0;
-    if (i < n) {
+    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) {
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
-        v = ri * ri;
+        v += ri * ri;
     }
     v = block_sum<double, KNT>(v, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
-    if (!arrive_last(&st->cnt[1], &last)) return;
-    const double rr = finish_partials(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-        st->cnt[1] = 0;
-        st->rr = rr;
-        st->iters += 1;
-        if (!isfinite(rr)) {
-            st->done = 1;
-            st->status = KS_BREAKDOWN;
-        } else if (st->fixed > 0) {
-            if (st->iters >= st->fixed) {
-                st->done = 1;
-                st->status = (rr <= st->rtol2 * st->bb) ? KS_CONVERGED : KS_MAXIT;
-            }
-        } else if (rr <= st->rtol2 * st->bb) {
-            st->done = 1;
-            st->status = KS_CONVERGED;
-        } else if (st->iters >= st->maxit) {
-            st->done = 1;
-            st->status = KS_MAXIT;
-        }
-    }
 }
 
-// mode 0: bb = a.b ; mode 1: rho = a.b ; mode 2: beta = a.b / rho, rho = a.b ;
-// mode 3: red = a.b (plain dot into st->red)
+// partials of a.b
 __global__ __launch_bounds__(KNT) void k_dot(const double *__restrict__ a, const double *__restrict__ b, int n,
-                                             double *__restrict__ partial, KState *st, int mode, int cidx) {
-    if (mode == 2 && st->done) return;
+                                             double *__restrict__ partial, const KState *st, int skip_if_done) {
+    if (skip_if_done && st->done) return;
     __shared__ double sh[KNT / 64];
-    __shared__ bool last;
-    const int i = blockIdx.x * KNT + threadIdx.x;
-    double v = (i < n) ? a[i] * b[i] : 0.0;
+    double v = 0.0;
+    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) v += a[i] * b[i];
     v = block_sum<double, KNT>(v, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
-    if (!arrive_last(&st->cnt[cidx], &last)) return;
-    const double t = finish_partials(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-        st->cnt[cidx] = 0;
-        if (mode == 0) st->bb = t;
-        else if (mode == 1) st->rho = t;
-        else if (mode == 2) {
+}
+
+// One workgroup: total of the partials and the scalar step it feeds.
+enum {
+    KF_BB = 0,      // bb = t
+    KF_RHO = 1,     // rho = t
+    KF_ALPHA = 2,   // sigma = t, alpha = rho / sigma
+    KF_RR = 3,      // rr = t, iteration count and stop tests
+    KF_BETA = 4,    // beta = t / rho, rho = t
+    KF_RED = 5      // red = t
+};
+
+__global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, int np, KState *st, int op) {
+    if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA) && st->done) return;
+    __shared__ double sh[KNT / 64];
+    const double t = sum_partials(partial, np, sh);
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case KF_BB: st->bb = t; break;
+        case KF_RHO: st->rho = t; break;
+        case KF_ALPHA:
+            st->sigma = t;
+            if (!(t > 0.0) || !isfinite(t)) {
+                st->done = 1;
+                st->status = KS_BREAKDOWN;
+            } else {
+                st->alpha = st->rho / t;
+            }
+            break;
+        case KF_RR:
+            st->rr = t;
+            st->iters += 1;
+            if (!isfinite(t)) {
+                st->done = 1;
+                st->status = KS_BREAKDOWN;
+            } else if (st->fixed > 0) {
+                if (st->iters >= st->fixed) {
+                    st->done = 1;
+                    st->status = (t <= st->rtol2 * st->bb) ? KS_CONVERGED : KS_MAXIT;
+                }
+            } else if (t <= st->rtol2 * st->bb) {
+                st->done = 1;
+                st->status = KS_CONVERGED;
+            } else if (st->iters >= st->maxit) {
+                st->done = 1;
+                st->status = KS_MAXIT;
+            }
+            break;
+        case KF_BETA:
             if (!isfinite(t) || st->rho == 0.0) {
                 st->done = 1;
                 st->status = KS_BREAKDOWN;
@@ -147,9 +141,8 @@ __global__ __launch_bounds__(KNT) void k_dot(const double *__restrict__ a, const
                 st->beta = t / st->rho;
                 st->rho = t;
             }
-        } else {
-            st->red = t;
-        }
+            break;
+        default: st->red = t; break;
     }
 }
 
@@ -171,6 +164,226 @@ __global__ void k_residual(const double *__restrict__ b, double *__restrict__ y,
 __global__ void k_copy(const double *__restrict__ a, double *__restrict__ b, int64_t n) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
         b[i] = a[i];
+}
+
+}  // namespace gdsw
+
+namespace gdsw {
+
+// ---------------------------------------------------------------------------
+// Restarted GMRES(m), right preconditioned, on the device.  The Arnoldi basis
+// V ((m+1) x n, one vector after another), the Hessenberg matrix, the Givens
+// rotations and the right-hand side g of the small least-squares problem live
+// in device memory; the step index and stop flags are in GState, so the host
+// only queues steps and polls once per chunk.  Orthogonalisation is classical
+// Gram-Schmidt applied twice (two reductions per step instead of j+1).
+constexpr int GM_MAX = 64;   // largest restart length
+
+struct GState {
+    double H[(GM_MAX + 1) * GM_MAX];   // column-major, leading dimension GM_MAX+1
+    double cs[GM_MAX], sn[GM_MAX], g[GM_MAX + 1], y[GM_MAX];
+    double h[GM_MAX + 1];              // coefficients of the current projection
+    double bb, rtol2, beta, wnorm;
+    int j;          // columns of the current cycle so far
+    int total;      // Arnoldi steps overall
+    int m, fixed, maxit;
+    int cycle_done, done, status;
+};
+
+// w = A t (skipped once the cycle has stopped)
+__global__ __launch_bounds__(KNT) void k_gm_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                 const double *__restrict__ val, const double *__restrict__ t,
+                                                 double *__restrict__ w, int n, const GState *st) {
+    if (st->cycle_done) return;
+    const int i = blockIdx.x * KNT + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) acc += val[p] * t[col[p]];
+    w[i] = acc;
+}
+
+// v = V_j (j from the state), the vector the preconditioner is applied to
+__global__ void k_gm_get(const double *__restrict__ V, double *__restrict__ v, int64_t n, const GState *st) {
+    if (st->cycle_done) return;
+    const double *src = V + int64_t(st->j) * n;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        v[i] = src[i];
+}
+
+// partials of h[i] = V_i . w for i <= j (one wavefront reduction per i)
+__global__ __launch_bounds__(KNT) void k_gm_dots(const double *__restrict__ V, const double *__restrict__ w, int64_t n,
+                                                 double *__restrict__ partial, const GState *st) {
+    if (st->cycle_done) return;
+    __shared__ double sh[(KNT / 64) * (GM_MAX + 1)];
+    const int j = st->j;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = 0; i <= j; ++i) {
+        const double *Vi = V + int64_t(i) * n;
+        double a = 0.0;
+        for (int64_t r = blockIdx.x * int64_t(KNT) + threadIdx.x; r < n; r += int64_t(gridDim.x) * KNT)
+            a += Vi[r] * w[r];
+        a = wave_sum(a);
+        if (lane == 0) sh[wave * (GM_MAX + 1) + i] = a;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += KNT) {
+        double t = 0.0;
+        for (int q = 0; q < KNT / 64; ++q) t += sh[q * (GM_MAX + 1) + i];
+        partial[int64_t(blockIdx.x) * (GM_MAX + 1) + i] = t;
+    }
+}
+
+// h[i] = sum of the partials (index order); add = 1 adds into H(:, j)
+__global__ __launch_bounds__(KNT) void k_gm_dots_finish(const double *__restrict__ partial, int np, GState *st,
+                                                        int add) {
+    if (st->cycle_done) return;
+    const int j = st->j;
+    for (int i = threadIdx.x; i <= j; i += KNT) {
+        double t = 0.0;
+        for (int b = 0; b < np; ++b) t += partial[int64_t(b) * (GM_MAX + 1) + i];
+        st->h[i] = t;
+        if (add) st->H[j * (GM_MAX + 1) + i] += t;
+        else st->H[j * (GM_MAX + 1) + i] = t;
+    }
+}
+
+// w -= sum_{i <= j} h[i] V_i
+__global__ void k_gm_subtract(const double *__restrict__ V, double *__restrict__ w, int64_t n, const GState *st) {
+    if (st->cycle_done) return;
+    const int j = st->j;
+    for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x) {
+        double acc = w[r];
+        for (int i = 0; i <= j; ++i) acc -= st->h[i] * V[int64_t(i) * n + r];
+        w[r] = acc;
+    }
+}
+
+// partials of ||w||^2 (skip: the cycle has stopped)
+__global__ __launch_bounds__(KNT) void k_gm_sqnorm(const double *__restrict__ w, int64_t n,
+                                                   double *__restrict__ partial, const GState *st, int at_start) {
+    if (at_start ? st->done : st->cycle_done) return;
+    __shared__ double sh[KNT / 64];
+    double v = 0.0;
+    for (int64_t r = blockIdx.x * int64_t(KNT) + threadIdx.x; r < n; r += int64_t(gridDim.x) * KNT) v += w[r] * w[r];
+    v = block_sum<double, KNT>(v, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// finishes one Arnoldi step: H(j+1, j) = ||w||, the Givens rotations, g,
+// the stop tests, and j += 1
+__global__ __launch_bounds__(KNT) void k_gm_step_finish(const double *__restrict__ partial, int np, GState *st) {
+    if (st->cycle_done) return;
+    __shared__ double sh[KNT / 64];
+    const double ss = sum_partials(partial, np, sh);
+    if (threadIdx.x != 0) return;
+    const int j = st->j;
+    double *Hj = st->H + j * (GM_MAX + 1);
+    const double hn = sqrt(ss);
+    Hj[j + 1] = hn;
+    st->wnorm = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = st->cs[i] * Hj[i] + st->sn[i] * Hj[i + 1];
+        Hj[i + 1] = -st->sn[i] * Hj[i] + st->cs[i] * Hj[i + 1];
+        Hj[i] = t;
+    }
+    const double den = sqrt(Hj[j] * Hj[j] + Hj[j + 1] * Hj[j + 1]);
+    if (!(den > 0.0) || !isfinite(den)) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_BREAKDOWN;
+        return;
+    }
+    st->cs[j] = Hj[j] / den;
+    st->sn[j] = Hj[j + 1] / den;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    st->j = j + 1;
+    st->total += 1;
+    const double res2 = st->g[j + 1] * st->g[j + 1];
+    if (st->fixed > 0) {
+        if (st->total >= st->fixed) { st->cycle_done = 1; st->done = 1; st->status = KS_CONVERGED; }
+    } else if (res2 <= st->rtol2 * st->bb) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_CONVERGED;
+    } else if (st->total >= st->maxit) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_MAXIT;
+    }
+    if (st->j >= st->m) st->cycle_done = 1;
+    // a vanishing new direction: the cycle's Krylov space holds the solution
+    if (hn == 0.0 && !st->cycle_done) st->cycle_done = 1;
+}
+
+// V_{j} = w / H(j, j-1)  (j already advanced)
+__global__ void k_gm_scale(double *__restrict__ V, const double *__restrict__ w, int64_t n, const GState *st) {
+    if (st->cycle_done || st->wnorm == 0.0) return;
+    const double s = 1.0 / st->wnorm;
+    double *dst = V + int64_t(st->j) * n;
+    for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x)
+        dst[r] = w[r] * s;
+}
+
+// start of a cycle: beta = ||r|| (from the partials), stop tests,
+// g = beta e_1, H = 0
+__global__ __launch_bounds__(KNT) void k_gm_start_finish(const double *__restrict__ partial, int np, GState *st) {
+    if (st->done) return;
+    __shared__ double sh[KNT / 64];
+    const double ss = sum_partials(partial, np, sh);
+    if (threadIdx.x != 0) return;
+    st->beta = sqrt(ss);
+    st->j = 0;
+    for (int i = 0; i <= GM_MAX; ++i) st->g[i] = 0.0;
+    for (int i = 0; i < (GM_MAX + 1) * GM_MAX; ++i) st->H[i] = 0.0;
+    st->g[0] = st->beta;
+    st->cycle_done = 0;
+    if (!isfinite(ss)) {
+        st->cycle_done = 1; st->done = 1; st->status = KS_BREAKDOWN;
+    } else if (st->fixed <= 0 && ss <= st->rtol2 * st->bb) {
+        st->cycle_done = 1; st->done = 1; st->status = KS_CONVERGED;
+    } else if (st->fixed > 0 && st->total >= st->fixed) {
+        st->cycle_done = 1; st->done = 1; st->status = KS_CONVERGED;
+    } else if (ss == 0.0) {
+        st->cycle_done = 1; st->done = 1; st->status = KS_CONVERGED;
+    }
+    st->wnorm = st->beta;
+}
+
+__global__ void k_gm_v0(double *__restrict__ V, const double *__restrict__ r, int64_t n, const GState *st) {
+    if (st->done || st->beta == 0.0) return;
+    const double s = 1.0 / st->beta;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        V[i] = r[i] * s;
+}
+
+// y = H(0:j, 0:j)^{-1} g(0:j) by back substitution (one thread)
+__global__ void k_gm_lsq(GState *st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int j = st->j;
+    for (int i = j - 1; i >= 0; --i) {
+        double t = st->g[i];
+        for (int k = i + 1; k < j; ++k) t -= st->H[k * (GM_MAX + 1) + i] * st->y[k];
+        st->y[i] = t / st->H[i * (GM_MAX + 1) + i];
+    }
+}
+
+// u = sum_{i < j} y_i V_i
+__global__ void k_gm_combine(const double *__restrict__ V, double *__restrict__ u, int64_t n, const GState *st) {
+    const int j = st->j;
+    for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < j; ++i) acc += st->y[i] * V[int64_t(i) * n + r];
+        u[r] = acc;
+    }
+}
+
+// x += t
+__global__ void k_add(double *__restrict__ x, const double *__restrict__ t, int64_t n) {
+    for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x)
+        x[r] += t[r];
 }
 
 }  // namespace gdsw

@@ -1,0 +1,76 @@
+"""Full-size parity on the 128^3 Poisson workload (2,097,152 dofs, 512
+subdomains, ILU(0) + 5+5 Jacobi sweeps, GDSW coarse space), in the launch
+configuration the benchmark times.  Expected values are oracle samples
+written by tests/golden/make_large_oracle_samples.py (oracle only); the rest
+are properties that hold at any size (symmetry of M, exact reproduction of
+the coarse term in the one-level/coarse split)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2304_04876_amd import binding as B
+from paper_2304_04876_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_poisson_oracle.npz")
+
+
+@pytest.fixture(scope="module")
+def large():
+    print("[large] setup 128^3 / 512 boxes ILU(0)", file=sys.stderr, flush=True)
+    pr = P.workload_poisson_large()
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0)
+    yield pr, g, np.load(GOLD)
+    g.close()
+
+
+def test_large_apply_samples(large):
+    pr, g, ref = large
+    r = torch.from_numpy(P.rhs_uniform(pr.n, 0)).cuda()
+    z = torch.zeros_like(r)
+    g.apply(r, z)
+    zs = z.cpu().numpy()[ref["idx"]]
+    assert np.abs(zs - ref["z_ilu0"]).max() <= 1e-12 * float(ref["z_norm"])
+    g.apply_part(r, z, 2)
+    zc = z.cpu().numpy()[ref["idx"]]
+    assert np.abs(zc - ref["zc"]).max() <= 1e-12 * float(ref["z_norm"])
+
+
+def test_large_coarse_matrix_samples(large):
+    pr, g, ref = large
+    n0 = g.info()["n0"]
+    assert n0 == 2863
+    A0 = g.map(B.MAP_A0).reshape(n0, n0)
+    scale = np.abs(ref["a0_diag"]).max()
+    assert np.abs(np.diag(A0) - ref["a0_diag"]).max() <= 1e-12 * scale
+    assert np.abs(A0[ref["a0_rows"], ref["a0_cols"]] - ref["a0_vals"]).max() <= 1e-12 * scale
+
+
+def test_large_preconditioner_symmetric(large):
+    pr, g, _ = large
+    r1 = torch.from_numpy(P.rhs_uniform(pr.n, 5)).cuda()
+    r2 = torch.from_numpy(P.rhs_uniform(pr.n, 6)).cuda()
+    z1, z2 = torch.zeros_like(r1), torch.zeros_like(r1)
+    g.apply(r1, z1)
+    g.apply(r2, z2)
+    a, b = float(torch.dot(r2, z1)), float(torch.dot(r1, z2))
+    assert abs(a - b) <= 1e-12 * abs(a)
+    assert float(torch.dot(r1, z1)) > 0
+
+
+def test_large_cg_iterations_and_iterate(large):
+    pr, g, ref = large
+    x = torch.zeros(pr.n, dtype=torch.float64, device="cuda")
+    for seed, it in zip((0, 1), ref["cg_iters"]):
+        b = torch.from_numpy(P.rhs_uniform(pr.n, seed)).cuda()
+        out = g.solve(b, x, rtol=1e-8)
+        assert abs(out["iterations"] - int(it)) <= 1, (out, it)
+        assert out["rel_res_true"] <= 1.5e-8
+    b = torch.from_numpy(P.rhs_uniform(pr.n, 0)).cuda()
+    g.solve(b, x, fixed_iters=int(ref["cg_iters"][0]))
+    xs = x.cpu().numpy()[ref["idx"]]
+    assert np.abs(xs - ref["x_fixed"]).max() <= 1e-10 * np.abs(ref["x_fixed"]).max()
