@@ -42,8 +42,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--local", choices=["ilu0", "exact"], default="ilu0")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default="fp64")
-    ap.add_argument("--N", type=int, default=128)
-    ap.add_argument("--P", type=int, default=8)
+    ap.add_argument("--workload", choices=["poisson", "elasticity"], default="poisson")
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     args = ap.parse_args()
@@ -59,15 +60,26 @@ def main():
     precs = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16, "fp16": B.FP16}
     pbytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[args.prec]
     local = B.LOCAL_ILU0 if args.local == "ilu0" else B.LOCAL_EXACT
-    log(f"[bench] building Poisson {args.N}^3 with {args.P}^3 boxes")
-    pr = P.poisson3d(args.N, args.P)
+    elastic = args.workload == "elasticity"
+    if elastic:
+        N, Pn = args.N or 48, args.P or 6
+        log(f"[bench] building Q1 elasticity {N}^3 with {Pn}^3 boxes")
+        pr = P.elasticity_q1(N, Pn)
+        Z = P.rigid_body_modes(pr)
+        krylov = B.KRYLOV_GMRES
+    else:
+        N, Pn = args.N or 128, args.P or 8
+        log(f"[bench] building Poisson {N}^3 with {Pn}^3 boxes")
+        pr = P.poisson3d(N, Pn)
+        Z = None
+        krylov = B.KRYLOV_CG
     n = pr.n
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
-    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, None,
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                        B.gdsw_default_options(local=local, local_prec=precs[args.prec],
                                               basis_prec=B.FP64 if args.prec == "fp64" else B.FP32))
     t_an = time.perf_counter() - t0
@@ -77,12 +89,17 @@ def main():
     log(f"[bench] setup {info['t_factor']:.3f}s  n0={info['n0']}  device bytes={info['device_bytes'] / 1e9:.2f} GB")
 
     nrhs = args.warmup + args.steps
-    rhs = torch.stack([torch.from_numpy(P.rhs_uniform(n, s)) for s in range(nrhs)]).to(dev)
+    if elastic:
+        # the assembled body-force load, scaled per step so that every solve
+        # starts from a different right-hand side
+        rhs = torch.stack([torch.from_numpy(pr.b * (1.0 + 0.1 * s)) for s in range(nrhs)]).to(dev)
+    else:
+        rhs = torch.stack([torch.from_numpy(P.rhs_uniform(n, s)) for s in range(nrhs)]).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
     for k in range(args.warmup):
-        B.gdsw_solve(h, rhs[k], x, rtol=1e-8, maxit=2000, stream=stream)
+        B.gdsw_solve(h, rhs[k], x, krylov=krylov, restart=30, rtol=1e-8, maxit=2000, stream=stream)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} solves")
     lat = []
@@ -93,7 +110,8 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         evs[k][0].record(stream)
-        out = B.gdsw_solve(h, rhs[args.warmup + k], x, rtol=1e-8, maxit=2000, stream=stream)
+        out = B.gdsw_solve(h, rhs[args.warmup + k], x, krylov=krylov, restart=30, rtol=1e-8, maxit=2000,
+                           stream=stream)
         evs[k][1].record(stream)
         iters.append(out["iterations"])
         res_true.append(out["rel_res_true"])
@@ -169,13 +187,16 @@ def main():
         from threadpoolctl import threadpool_limits
         from oracle import gdsw_oracle as O
         with threadpool_limits(limits=1):
-            M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local=args.local)
-            b0 = P.rhs_uniform(n, args.warmup)
+            M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local=args.local)
+            b0 = rhs[args.warmup].cpu().numpy()
             t0 = time.perf_counter()
-            res = O.pcg(pr.A, b0, M, rtol=1e-8)
+            if elastic:
+                res = O.gmres(pr.A, b0, M, rtol=1e-8, restart=30)
+            else:
+                res = O.pcg(pr.A, b0, M, rtol=1e-8)
             t_cpu = time.perf_counter() - t0
         cpu = {"value": round(1.0 / t_cpu, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full FP64 oracle PCG solve of the same problem (seed {args.warmup}, "
+               "sample": f"one full FP64 oracle solve of the same problem (right-hand side {args.warmup}, "
                          f"{res.iters} iterations, {t_cpu:.1f} s), preconditioner set up beforehand "
                          f"(untimed); BLAS limited to one thread"}
         if args.prec == "fp64":
@@ -197,7 +218,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
         "data": "synthetic",
-        "config": {"workload": f"poisson{args.N}^3_P{args.P}^3_{args.local}_gdsw_cg", "n": n,
+        "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30" if elastic
+                                else f"poisson{N}^3_P{Pn}^3_{args.local}_gdsw_cg"), "n": n,
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
                    "jacobi_sweeps": 5, "local_prec": args.prec, "rtol": 1e-8},
         "applies_per_sec": round(1e3 / apply_ms, 1),

@@ -113,6 +113,7 @@ typedef struct {
     int32_t max_bandwidth;    /* largest local bandwidth (exact solver)           */
     double t_analyze;         /* seconds: host symbolic analysis                  */
     double t_factor;          /* seconds: device numerical setup (synchronised)   */
+    int32_t n_problems;       /* independent problems packed in the handle        */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -126,7 +127,9 @@ enum {
     GDSW_MAP_PHI_ROWPTR = 5,   /* int64 [n+1]: CSR of Phi (after gdsw_factor)     */
     GDSW_MAP_PHI_COL = 6,      /* int32 [phi_entries]                             */
     GDSW_MAP_PHI_VAL = 7,      /* FP64  [phi_entries]  (after gdsw_factor)        */
-    GDSW_MAP_A0 = 8            /* FP64  [n0*n0] coarse matrix, row-major (after gdsw_factor) */
+    GDSW_MAP_A0 = 8            /* FP64  coarse matrix, row-major (after gdsw_factor): [n0*n0]
+                                  for one problem, the dense diagonal blocks one after
+                                  another for a batch */
 };
 
 /* Fills `opt` with the paper's defaults: overlap 1, GDSW coarse space,
@@ -191,6 +194,50 @@ gdsw_status gdsw_spmv(gdsw_handle h, const double *x_dev, double *y_dev, void *s
 gdsw_status gdsw_solve(gdsw_handle h, const double *b_dev, double *x_dev,
                        int32_t krylov, int32_t restart, double rtol, int32_t maxit,
                        int32_t fixed_iters, gdsw_solve_info *info, void *stream);
+
+/* ---- several independent problems in one handle ------------------------
+ * A batch handle packs `count` independent problems (matrices of any size
+ * and partition) as one block-diagonal system: their subdomains, interface
+ * components and coarse blocks never couple, the coarse matrix is one dense
+ * block per problem, and every kernel of the apply and the Krylov solve
+ * covers all problems in one launch (many subdomains per launch, the
+ * paper's reason for running several subdomains per GPU, Sec. VI).  Each
+ * problem keeps its own Krylov scalars and stopping test, and its
+ * reductions use row blocks of its own, so its results are the same alone
+ * and in a batch.  Vectors of a batch handle are the concatenation of the
+ * problems' vectors (length = sum of the n_k, problem k first at offset
+ * sum_{j<k} n_j).
+ *   A[count], part[count] ([n_k/dpn] each), n_parts[count]: per problem,
+ *   Z: NULL (constants) or Z[count] column-major [n_k x n_null] blocks. */
+gdsw_status gdsw_analyze_batch(int32_t count, const gdsw_csr *A, const int32_t *const *part,
+                               const int32_t *n_parts, int32_t dpn, const double *const *Z,
+                               int32_t n_null, const gdsw_options *opt, gdsw_handle *out);
+
+/* CG on every problem of a (batch) handle; infos[count] receives one record
+ * per problem (gdsw_solve on a batch handle reports the worst problem). */
+gdsw_status gdsw_solve_batch(gdsw_handle h, const double *b_dev, double *x_dev, double rtol,
+                             int32_t maxit, gdsw_solve_info *infos, void *stream);
+
+/* ---- continuous batching over the problems ("slots") of a handle --------
+ * gdsw_slots_begin binds caller-owned device vectors b_dev, x_dev (length
+ *   sum n_k) and marks every slot idle.
+ * gdsw_slot_start starts CG (x0 = 0) on slot k from the slot's rows of
+ *   b_dev, which the caller has filled; other slots are not disturbed.
+ * gdsw_slots_step advances every running slot by `iters` CG iterations in
+ *   shared kernel launches, synchronises `stream` and writes state[k]:
+ *   -1 idle, 0 running, 1 finished (result ready), 2 failed.
+ * gdsw_slot_finish reads slot k's record (true residual of its rows
+ *   recomputed), leaves its solution in its rows of x_dev and makes the
+ *   slot idle.
+ * Slots run concurrently; calls on one handle must not overlap. */
+gdsw_status gdsw_slots_begin(gdsw_handle h, const double *b_dev, double *x_dev, double rtol,
+                             int32_t maxit, void *stream);
+gdsw_status gdsw_slot_start(gdsw_handle h, int32_t slot, void *stream);
+gdsw_status gdsw_slots_step(gdsw_handle h, int32_t iters, int32_t *state, void *stream);
+gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info, void *stream);
+
+/* Dof offsets of the problems of a handle: offsets[count+1] (host). */
+gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);
 
 gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info);
 

@@ -33,7 +33,9 @@ _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
 
 EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
             "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
-            "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error")
+            "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
+            "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
+            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets")
 
 
 class Options(ctypes.Structure):
@@ -61,7 +63,8 @@ class Info(ctypes.Structure):
                 ("n0", ctypes.c_int32), ("local_factor_entries", ctypes.c_int64),
                 ("phi_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("max_local_rows", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
-                ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double)]
+                ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("n_problems", ctypes.c_int32)]
 
 
 def lib():
@@ -90,6 +93,15 @@ def lib():
         "gdsw_copy_map": (ctypes.c_int, [vp, i32, vp]),
         "gdsw_destroy": (ctypes.c_int, [vp]),
         "gdsw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "gdsw_analyze_batch": (ctypes.c_int, [i32, ctypes.POINTER(CSR), ctypes.POINTER(vp), vp, i32,
+                                              ctypes.POINTER(vp), i32, ctypes.POINTER(Options),
+                                              ctypes.POINTER(vp)]),
+        "gdsw_solve_batch": (ctypes.c_int, [vp, vp, vp, dbl, i32, ctypes.POINTER(SolveInfo), vp]),
+        "gdsw_slots_begin": (ctypes.c_int, [vp, vp, vp, dbl, i32, vp]),
+        "gdsw_slot_start": (ctypes.c_int, [vp, i32, vp]),
+        "gdsw_slots_step": (ctypes.c_int, [vp, i32, vp, vp]),
+        "gdsw_slot_finish": (ctypes.c_int, [vp, i32, ctypes.POINTER(SolveInfo), vp]),
+        "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -210,6 +222,90 @@ def gdsw_solve(h, b, x, krylov=KRYLOV_CG, restart=30, rtol=1e-8, maxit=1000, fix
            "seconds": info.seconds}
     if raise_on_error and st != GDSW_OK:
         raise GdswError(st, gdsw_last_error(h))
+    return out
+
+
+def gdsw_analyze_batch(problems, dpn=1, Z=None, options: Options | None = None):
+    """Symbolic phase of a batch of independent problems; ``problems`` is a
+    list of (A, part, n_parts).  ``Z``: None or a list of null-space blocks."""
+    count = len(problems)
+    keep = []
+    csrs = (CSR * count)()
+    parts = (ctypes.c_void_p * count)()
+    nparts = np.zeros(count, dtype=np.int32)
+    for k, (A, part, npk) in enumerate(problems):
+        rowptr, col, val = _csr_arrays(A)
+        p = np.ascontiguousarray(part, dtype=np.int32)
+        keep += [rowptr, col, val, p]
+        csrs[k] = CSR(A.shape[0], rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+        parts[k] = p.ctypes.data
+        nparts[k] = npk
+    zp = None
+    nz = 0
+    if Z is not None:
+        zarr = (ctypes.c_void_p * count)()
+        for k, zk in enumerate(Z):
+            zk = np.asfortranarray(np.asarray(zk, dtype=np.float64))
+            keep.append(zk)
+            zarr[k] = zk.ctypes.data
+            nz = zk.shape[1]
+        zp = zarr
+    opt = options if options is not None else gdsw_default_options()
+    h = ctypes.c_void_p()
+    st = lib().gdsw_analyze_batch(count, csrs, parts, nparts.ctypes.data, int(dpn), zp, nz,
+                                  ctypes.byref(opt), ctypes.byref(h))
+    if st != GDSW_OK:
+        msg = gdsw_last_error(h.value)
+        gdsw_destroy(h.value)
+        raise GdswError(st, msg)
+    return h.value
+
+
+def _info_dict(info, st=None):
+    d = {"iterations": info.iterations, "converged": bool(info.converged),
+         "rel_res_recursive": info.rel_res_recursive, "rel_res_true": info.rel_res_true,
+         "seconds": info.seconds}
+    if st is not None:
+        d["status"] = st
+    return d
+
+
+def gdsw_solve_batch(h, b, x, rtol=1e-8, maxit=1000, stream=None, raise_on_error=True):
+    count = gdsw_get_info(h)["n_problems"]
+    infos = (SolveInfo * count)()
+    st = lib().gdsw_solve_batch(h, _ptr(b), _ptr(x), float(rtol), int(maxit), infos, _stream(stream))
+    if raise_on_error and st != GDSW_OK:
+        raise GdswError(st, gdsw_last_error(h))
+    return [_info_dict(i) for i in infos]
+
+
+def gdsw_slots_begin(h, b, x, rtol=1e-8, maxit=1000, stream=None):
+    _check(h, lib().gdsw_slots_begin(h, _ptr(b), _ptr(x), float(rtol), int(maxit), _stream(stream)))
+
+
+def gdsw_slot_start(h, slot, stream=None):
+    _check(h, lib().gdsw_slot_start(h, int(slot), _stream(stream)))
+
+
+def gdsw_slots_step(h, iters, stream=None) -> np.ndarray:
+    count = gdsw_get_info(h)["n_problems"]
+    state = np.zeros(count, dtype=np.int32)
+    _check(h, lib().gdsw_slots_step(h, int(iters), state.ctypes.data, _stream(stream)))
+    return state
+
+
+def gdsw_slot_finish(h, slot, stream=None) -> dict:
+    info = SolveInfo()
+    st = lib().gdsw_slot_finish(h, int(slot), ctypes.byref(info), _stream(stream))
+    if st not in (GDSW_OK, 3, 4):
+        raise GdswError(st, gdsw_last_error(h))
+    return _info_dict(info, st)
+
+
+def gdsw_problem_offsets(h) -> np.ndarray:
+    count = gdsw_get_info(h)["n_problems"]
+    out = np.zeros(count + 1, dtype=np.int64)
+    _check(h, lib().gdsw_problem_offsets(h, out.ctypes.data))
     return out
 
 

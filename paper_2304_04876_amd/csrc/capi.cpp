@@ -32,6 +32,52 @@ gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts
     return st;
 }
 
+gdsw_status gdsw_analyze_batch(int32_t count, const gdsw_csr *A, const int32_t *const *part, const int32_t *n_parts,
+                               int32_t dpn, const double *const *Z, int32_t n_null, const gdsw_options *opt,
+                               gdsw_handle *out) {
+    if (!out) return GDSW_ERR_INVALID_ARG;
+    *out = nullptr;
+    gdsw_handle_s *h = new (std::nothrow) gdsw_handle_s();
+    if (!h) return GDSW_ERR_BUDGET;
+    gdsw_status st = gdsw::analyze_batch(h, count, A, part, n_parts, dpn, Z, n_null, opt);
+    *out = h;
+    return st;
+}
+
+gdsw_status gdsw_solve_batch(gdsw_handle h, const double *b_dev, double *x_dev, double rtol, int32_t maxit,
+                             gdsw_solve_info *infos, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::solve(h, b_dev, x_dev, GDSW_KRYLOV_CG, 0, rtol, maxit, 0, infos, h->sym.nprob, stream);
+}
+
+gdsw_status gdsw_slots_begin(gdsw_handle h, const double *b_dev, double *x_dev, double rtol, int32_t maxit,
+                             void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::slots_begin(h, b_dev, x_dev, rtol, maxit, stream);
+}
+
+gdsw_status gdsw_slot_start(gdsw_handle h, int32_t slot, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::slot_start(h, slot, stream);
+}
+
+gdsw_status gdsw_slots_step(gdsw_handle h, int32_t iters, int32_t *state, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::slots_step(h, iters, state, stream);
+}
+
+gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::slot_finish(h, slot, info, stream);
+}
+
+gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
+    if (!h || !offsets) return GDSW_ERR_INVALID_ARG;
+    if (!h->analyzed) return GDSW_ERR_STATE;
+    std::memcpy(offsets, h->sym.prob_ptr.data(), sizeof(int64_t) * h->sym.prob_ptr.size());
+    return GDSW_OK;
+}
+
 gdsw_status gdsw_factor(gdsw_handle h, void *stream) {
     if (!h) return GDSW_ERR_INVALID_ARG;
     if (!h->analyzed) {
@@ -72,7 +118,7 @@ gdsw_status gdsw_spmv(gdsw_handle h, const double *x_dev, double *y_dev, void *s
 gdsw_status gdsw_solve(gdsw_handle h, const double *b_dev, double *x_dev, int32_t krylov, int32_t restart,
                        double rtol, int32_t maxit, int32_t fixed_iters, gdsw_solve_info *info, void *stream) {
     if (!h) return GDSW_ERR_INVALID_ARG;
-    return gdsw::solve(h, b_dev, x_dev, krylov, restart, rtol, maxit, fixed_iters, info, stream);
+    return gdsw::solve(h, b_dev, x_dev, krylov, restart, rtol, maxit, fixed_iters, info, 1, stream);
 }
 
 gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
@@ -98,6 +144,7 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->max_bandwidth = S.max_bw;
     info->t_analyze = S.t_analyze;
     info->t_factor = h->t_factor;
+    info->n_problems = S.nprob;
     return GDSW_OK;
 }
 
@@ -112,7 +159,7 @@ static int64_t map_count(gdsw_handle h, int32_t map) {
         case GDSW_MAP_PHI_ROWPTR: return S.n + 1;
         case GDSW_MAP_PHI_COL:
         case GDSW_MAP_PHI_VAL: return S.blk.val_off.empty() ? 0 : S.blk.val_off.back();
-        case GDSW_MAP_A0: return int64_t(S.n0) * S.n0;
+        case GDSW_MAP_A0: return S.a0_off.empty() ? 0 : S.a0_off.back();
         default: return -1;
     }
 }

@@ -108,10 +108,23 @@ struct Device {
     int32_t *dof_blk = nullptr, *dof_lr = nullptr;
     double *partial = nullptr, *r0 = nullptr, *z0 = nullptr;
     double *A0 = nullptr;     // assembled coarse matrix
-    double *A0inv = nullptr;  // its inverse
+    double *A0inv = nullptr;  // its inverse (dense blocks, one per problem)
+    int32_t *cprob = nullptr, *prob_c0 = nullptr;
+    int64_t *a0_off = nullptr;
     // ---- Krylov ----
     double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kpart = nullptr;
-    KState *kst = nullptr;
+    KState *kst = nullptr;          // one per problem
+    int *kdone = nullptr;           // done flags mirrored per problem (skip mask of the apply)
+    int *kmask = nullptr;           // one-problem-active mask (slot start)
+    int32_t *kb_prob = nullptr, *kb_row0 = nullptr, *kb_row1 = nullptr, *pb_ptr = nullptr;
+    std::vector<int32_t> h_pb_ptr;  // host copy: first row block of every problem
+    int nkb = 0;
+    int32_t *sub_prob = nullptr, *blk_prob = nullptr;
+    int64_t *prob_ptr = nullptr;
+    // slots (continuous batching)
+    double *slot_x = nullptr;
+    const double *slot_b = nullptr;
+    std::vector<KState> h_state;
     int64_t phi_entries = 0;
     int64_t local_entries = 0;
     int KLp = 1, KUp = 1;   // slot counts of the sweep layout
@@ -150,8 +163,41 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     D.kp = D.alloc<double>(n);
     D.kq = D.alloc<double>(n);
     D.kt = D.alloc<double>(n);
-    D.kpart = D.alloc<double>(KRED);
-    D.kst = D.alloc<KState>(1);
+    // Krylov row blocks: KROWS rows each, never across problems
+    {
+        std::vector<int32_t> bp, b0, b1;
+        D.h_pb_ptr.assign(S.nprob + 1, 0);
+        for (int k = 0; k < S.nprob; ++k) {
+            for (int64_t r = S.prob_ptr[k]; r < S.prob_ptr[k + 1]; r += KROWS) {
+                bp.push_back(k);
+                b0.push_back(int32_t(r));
+                b1.push_back(int32_t(std::min<int64_t>(r + KROWS, S.prob_ptr[k + 1])));
+            }
+            D.h_pb_ptr[k + 1] = int32_t(bp.size());
+        }
+        D.nkb = int(bp.size());
+        D.kb_prob = D.upload(bp, s);
+        D.kb_row0 = D.upload(b0, s);
+        D.kb_row1 = D.upload(b1, s);
+        D.pb_ptr = D.upload(D.h_pb_ptr, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    D.kpart = D.alloc<double>(std::max(D.nkb, 1));
+    D.kst = D.alloc<KState>(S.nprob);
+    D.kdone = D.alloc<int>(S.nprob);
+    D.kmask = D.alloc<int>(S.nprob);
+    D.sub_prob = D.upload(S.sub_prob, s);
+    D.prob_ptr = D.upload(S.prob_ptr, s);
+    {
+        std::vector<int32_t> bprob(std::max<int32_t>(S.blk.nb, 1), 0);
+        for (int g = 0; g < S.blk.nb; ++g)
+            bprob[g] = S.blk.kind[g] == 0 ? S.sub_prob[S.blk.owner[g]]
+                                          : int32_t(std::upper_bound(S.prob_ptr.begin(), S.prob_ptr.end(),
+                                                                     int64_t(S.comp_nodes[S.comp_ptr[S.blk.owner[g]]]) * S.dpn) -
+                                                    S.prob_ptr.begin() - 1);
+        D.blk_prob = D.upload(bprob, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
     // the sync below makes the host vectors above safe to release
     HIPCHK(hipStreamSynchronize(s));
 }
@@ -370,8 +416,10 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         D.release(d_ibw, 4 * S.ibw.size());
     }
     // ---- A_0 = Phi_G^T A_GG Phi_G + sum_i E_i^T Phi_{I_i}
-    double *A0raw = D.alloc<double>(int64_t(n0) * n0);
-    HIPCHK(hipMemsetAsync(A0raw, 0, sizeof(double) * size_t(n0) * n0, s));
+    // A_0 is block diagonal over the independent problems: one dense block each
+    const int64_t na0 = S.a0_off[S.nprob];
+    double *A0raw = D.alloc<double>(na0);
+    HIPCHK(hipMemsetAsync(A0raw, 0, sizeof(double) * size_t(na0), s));
     {
         const int npairs = int(S.pair_c.size());
         if (npairs) {
@@ -414,31 +462,43 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
             D.release(ss, 8 * S.a0seg_src.size());
         }
     }
-    D.A0 = D.alloc<double>(int64_t(n0) * n0);
-    hipLaunchKernelGGL(k_symmetrize, dim3(nblocks(int64_t(n0) * n0, 256)), dim3(256), 0, s, A0raw, D.A0, n0);
-    // ---- A_0^{-1} by blocked Gauss-Jordan sweeps on a copy
-    D.A0inv = A0raw;
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(int64_t(n0) * n0, 256, 65536)), dim3(256), 0, s, D.A0, D.A0inv,
-                       int64_t(n0) * n0);
-    {
-        double *P = D.alloc<double>(GJ_NB * GJ_NB);
-        double *W = D.alloc<double>(int64_t(n0) * GJ_NB);
-        HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int), s));
-        const dim3 tiles((n0 + 63) / 64, (n0 + 63) / 64);
-        for (int k0 = 0; k0 < n0; k0 += GJ_NB) {
-            const int kb = std::min(GJ_NB, n0 - k0);
-            hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, D.A0inv, n0, k0, kb, P, d_status);
-            hipLaunchKernelGGL(k_gj_panel, dim3(nblocks(n0, 256)), dim3(256), 0, s, D.A0inv, n0, k0, kb, P, W);
-            hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, D.A0inv, n0, k0, kb, W);
-            hipLaunchKernelGGL(k_gj_fix, dim3(nblocks(n0, 256)), dim3(256), 0, s, D.A0inv, n0, k0, kb, W, P);
-        }
-        hipLaunchKernelGGL(k_negate, dim3(nblocks(int64_t(n0) * n0, 256, 65536)), dim3(256), 0, s, D.A0inv,
-                           int64_t(n0) * n0);
-        HIPCHK(hipGetLastError());
-        check_status(D, d_status, 1, s, "coarse matrix inverse");
-        D.release(P, 8 * GJ_NB * GJ_NB);
-        D.release(W, 8 * size_t(n0) * GJ_NB);
+    D.A0 = D.alloc<double>(na0);
+    for (int k = 0; k < S.nprob; ++k) {
+        const int nk = S.prob_c0[k + 1] - S.prob_c0[k];
+        if (nk == 0) continue;
+        hipLaunchKernelGGL(k_symmetrize, dim3(nblocks(int64_t(nk) * nk, 256)), dim3(256), 0, s, A0raw + S.a0_off[k],
+                           D.A0 + S.a0_off[k], nk);
     }
+    // ---- A_0^{-1} by blocked Gauss-Jordan sweeps, block by block, on a copy
+    D.A0inv = A0raw;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(na0, 256, 65536)), dim3(256), 0, s, D.A0, D.A0inv, na0);
+    {
+        int nmax = 0;
+        for (int k = 0; k < S.nprob; ++k) nmax = std::max(nmax, S.prob_c0[k + 1] - S.prob_c0[k]);
+        double *P = D.alloc<double>(GJ_NB * GJ_NB);
+        double *W = D.alloc<double>(int64_t(nmax) * GJ_NB);
+        HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
+        for (int k = 0; k < S.nprob; ++k) {
+            const int nk = S.prob_c0[k + 1] - S.prob_c0[k];
+            double *Ak = D.A0inv + S.a0_off[k];
+            const dim3 tiles((nk + 63) / 64, (nk + 63) / 64);
+            for (int k0 = 0; k0 < nk; k0 += GJ_NB) {
+                const int kb = std::min(GJ_NB, nk - k0);
+                hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Ak, nk, k0, kb, P, d_status + (k % S.np));
+                hipLaunchKernelGGL(k_gj_panel, dim3(nblocks(nk, 256)), dim3(256), 0, s, Ak, nk, k0, kb, P, W);
+                hipLaunchKernelGGL(k_gj_update, tiles, dim3(256), 0, s, Ak, nk, k0, kb, W);
+                hipLaunchKernelGGL(k_gj_fix, dim3(nblocks(nk, 256)), dim3(256), 0, s, Ak, nk, k0, kb, W, P);
+            }
+        }
+        hipLaunchKernelGGL(k_negate, dim3(nblocks(na0, 256, 65536)), dim3(256), 0, s, D.A0inv, na0);
+        HIPCHK(hipGetLastError());
+        check_status(D, d_status, std::min(S.np, S.nprob), s, "coarse matrix inverse");
+        D.release(P, 8 * GJ_NB * GJ_NB);
+        D.release(W, 8 * size_t(nmax) * GJ_NB);
+    }
+    D.cprob = D.upload(S.cprob, s);
+    D.prob_c0 = D.upload(S.prob_c0, s);
+    D.a0_off = D.upload(S.a0_off, s);
     if (S.opt.basis_prec == GDSW_FP32) {
         D.phi32 = D.alloc<float>(nphi);
         hipLaunchKernelGGL(k_cast<float>, dim3(nblocks(nphi, 256, 65536)), dim3(256), 0, s, D.phi, D.phi32, nphi);
@@ -499,7 +559,7 @@ gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
 
 // ---------------------------------------------------------------------------
 template <typename VT>
-static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const int *done, hipStream_t s) {
+static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
     if (D.KLp != 3 || D.KUp != 3) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
     constexpr int NT = f64 ? 512 : 1024;
@@ -511,7 +571,7 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
         if (lds > D.max_lds) return false;                                                                   \
         hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, 3, 3, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx,     \
                            D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc, \
-                           (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, done);                 \
+                           (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, sk);                   \
         return true;                                                                                         \
     }
     // largest row counts per thread that stay in registers without spilling
@@ -525,10 +585,10 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
 }
 
 template <typename VT>
-static void launch_local(const Symbolic &S, Device &D, const double *r, const int *done, hipStream_t s) {
+static void launch_local(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
     using AT = typename AccOf<VT>::type;
     if (S.opt.local == GDSW_LOCAL_ILU0) {
-        if (launch_ilu_regs<VT>(S, D, r, done, s)) return;
+        if (launch_ilu_regs<VT>(S, D, r, sk, s)) return;
         size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
         void *gbuf = nullptr;
         if (lds > D.max_lds) {
@@ -539,32 +599,32 @@ static void launch_local(const Symbolic &S, Device &D, const double *r, const in
         hipLaunchKernelGGL((k_ilu_jacobi_generic<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
                            D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc,
                            (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc,
-                           S.max_ni, gbuf, done);
+                           S.max_ni, gbuf, sk);
     } else {
         const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
         if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS band solve"};
         hipLaunchKernelGGL((k_band_apply<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
-                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, done);
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
     }
 }
 
-static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const int *done, hipStream_t s) {
+static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     if (which & 1) {
         switch (S.opt.local_prec) {
-            case GDSW_FP64: launch_local<double>(S, D, r, done, s); break;
-            case GDSW_FP32: launch_local<float>(S, D, r, done, s); break;
-            case GDSW_BF16: launch_local<bf16>(S, D, r, done, s); break;
-            default: launch_local<fp16>(S, D, r, done, s); break;
+            case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
+            case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
+            case GDSW_BF16: launch_local<bf16>(S, D, r, sk, s); break;
+            default: launch_local<fp16>(S, D, r, sk, s); break;
         }
     }
     if (which == 4) {   // the local solves alone (results stay in zloc)
         switch (S.opt.local_prec) {
-            case GDSW_FP64: launch_local<double>(S, D, r, done, s); break;
-            case GDSW_FP32: launch_local<float>(S, D, r, done, s); break;
-            case GDSW_BF16: launch_local<bf16>(S, D, r, done, s); break;
-            default: launch_local<fp16>(S, D, r, done, s); break;
+            case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
+            case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
+            case GDSW_BF16: launch_local<bf16>(S, D, r, sk, s); break;
+            default: launch_local<fp16>(S, D, r, sk, s); break;
         }
         HIPCHK(hipGetLastError());
         return;
@@ -574,23 +634,24 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         const PhiBlocks &B = S.blk;
         if (D.phi32)
             hipLaunchKernelGGL((k_coarse_restrict<256, float>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
-                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, done);
+                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, sk);
         else
             hipLaunchKernelGGL((k_coarse_restrict<256, double>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
-                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, done);
+                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, sk);
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
-                           D.partial, D.r0, S.n0, done);
-        hipLaunchKernelGGL(k_dense_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.r0, D.z0, S.n0, done);
+                           D.partial, D.r0, S.n0, sk);
+        hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0,
+                           D.cprob, D.r0, D.z0, S.n0, sk);
     }
     const int w = (which & 1) | (coarse ? 2 : 0);
     if (D.phi32)
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const float *)D.phi32, D.z0, z, S.n, done);
+                           (const float *)D.phi32, D.z0, z, S.n, sk);
     else
         hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
                            D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const double *)D.phi, D.z0, z, S.n, done);
+                           (const double *)D.phi, D.z0, z, S.n, sk);
     HIPCHK(hipGetLastError());
 }
 
@@ -604,7 +665,7 @@ gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void 
         return GDSW_ERR_INVALID_ARG;
     }
     try {
-        launch_apply(h, r, z, which, nullptr, static_cast<hipStream_t>(stream));
+        launch_apply(h, r, z, which, Skip(), static_cast<hipStream_t>(stream));
     } catch (const DevError &e) {
         h->err = e.msg;
         return e.st;
@@ -631,87 +692,144 @@ gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream) {
 //           ||r|| <= rtol ||b||; z = M r, beta = r.z / rho, p = z + beta p.
 // Iterations are queued in chunks; the host reads the device state once per
 // chunk, kernels after convergence return immediately.
-static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, int fixed,
-                            gdsw_solve_info *info, hipStream_t s) {
+static Skip make_skip(const Symbolic &S, const Device &D, const int *flag) {
+    Skip sk;
+    sk.flag = flag;
+    sk.sub_prob = D.sub_prob;
+    sk.blk_prob = D.blk_prob;
+    sk.cprob = D.cprob;
+    sk.prob_ptr = D.prob_ptr;
+    sk.nprob = S.nprob;
+    return sk;
+}
+
+// One CG iteration of every running problem (the oracle's order):
+//   q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q, stop if
+//   ||r|| <= rtol ||b||; z = M r, beta = r.z / rho, p = z + beta p.
+static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
+    const int nkb = D.nkb, np = S.nprob;
+    hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, D.kpart,
+                       D.kst, all);
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0);
+    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kpart, D.kst, all);
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR), 0);
+    launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s);
+    hipLaunchKernelGGL(k_dot, dim3(nkb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 1, all);
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BETA), 0);
+    hipLaunchKernelGGL(k_cg_update_p, dim3(nkb), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all);
+}
+
+// Starts CG (x0 = 0) for problem k alone, or for all problems (k < 0).
+static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int base = k < 0 ? 0 : D.h_pb_ptr[k];
+    const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
+    const int pbase = k < 0 ? 0 : k, pn = k < 0 ? S.nprob : 1;
+    const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(KNT), 0, s, x, D.kr, b, kb);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, kb);
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BB), pbase);
+    launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, k < 0 ? D.kdone : D.kmask), s);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 0, kb);
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase);
+    hipLaunchKernelGGL(k_cg_update_p, dim3(nb), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 1, kb);
+}
+
+// ||b - A x|| / ||b|| of problem k (all problems: k < 0) into state.red
+static void queue_true_residual(gdsw_handle_s *h, const double *b, const double *x, int k, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const int n = int(S.n);
-    const int gr = std::min(KRED, nblocks(n, KNT));
-    double *pt = D.kpart;
-    KState hs{};
-    hs.rtol2 = rtol * rtol;
-    hs.fixed = fixed;
-    hs.maxit = maxit;
-    HIPCHK(hipMemcpyAsync(D.kst, &hs, sizeof(KState), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, int64_t(n));
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, b, D.kr, int64_t(n));
-    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, b, b, n, pt, D.kst, 0);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_BB));
-    HIPCHK(hipMemcpyAsync(&hs, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (!(hs.bb > 0.0)) {
-        if (info) { info->iterations = 0; info->converged = 1; info->rel_res_recursive = 0; info->rel_res_true = 0; }
-        return std::isfinite(hs.bb) ? GDSW_OK : GDSW_ERR_INVALID_ARG;
-    }
-    int *done = &D.kst->done;
-    launch_apply(h, D.kr, D.kz, 3, nullptr, s);
-    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kr, D.kz, n, pt, D.kst, 0);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RHO));
-    hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 1);
-    const int limit = fixed > 0 ? fixed : maxit;
-    int queued = 0;
-    int chunk = 4;
-    while (true) {
-        const int c = std::min(chunk, limit - queued);
-        for (int k = 0; k < c; ++k) {
-            hipLaunchKernelGGL(k_cg_spmv_dot, dim3(gr), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, n, pt,
-                               D.kst);
-            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_ALPHA));
-            hipLaunchKernelGGL(k_cg_update_xr, dim3(gr), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, n, pt, D.kst);
-            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RR));
-            launch_apply(h, D.kr, D.kz, 3, done, s);
-            hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kr, D.kz, n, pt, D.kst, 1);
-            hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_BETA));
-            hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.kp, D.kz, n, D.kst, 0);
-        }
-        queued += c;
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&hs, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (hs.done || queued >= limit) break;
-        chunk = std::min(chunk * 2, 32);
-    }
-    // true residual
+    const int base = k < 0 ? 0 : D.h_pb_ptr[k];
+    const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
+    const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
     hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, n);
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
-    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kt, D.kt, n, pt, D.kst, 0);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, pt, gr, D.kst, int(KF_RED));
-    KState fin{};
-    HIPCHK(hipMemcpyAsync(&fin, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
+    hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst,
+                       (int *)nullptr, int(KF_RED), k < 0 ? 0 : k);
+}
+
+static void fill_info(const KState &f, gdsw_solve_info *info) {
+    info->iterations = f.iters;
+    info->converged = f.status == KS_CONVERGED;
+    info->rel_res_recursive = f.bb > 0 ? std::sqrt(f.rr / f.bb) : 0.0;
+    info->rel_res_true = f.bb > 0 ? std::sqrt(f.red / f.bb) : 0.0;
+}
+
+// Preconditioned CG from x0 = 0 for every problem of the handle.
+// Iterations are queued in chunks; the host reads the device states once
+// per chunk, kernels of finished problems return immediately.
+static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, int fixed,
+                            gdsw_solve_info *infos, int ninfo, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int np = S.nprob;
+    std::vector<KState> hs(np);
+    for (auto &k : hs) {
+        k = KState{};
+        k.rtol2 = rtol * rtol;
+        k.fixed = fixed;
+        k.maxit = maxit;
+    }
+    std::vector<int> zeros(np, 0);
+    HIPCHK(hipMemcpyAsync(D.kst, hs.data(), sizeof(KState) * np, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(D.kdone, zeros.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+    queue_cg_start(h, b, x, -1, s);
+    const int limit = fixed > 0 ? fixed : maxit;
+    int queued = 0, chunk = 4;
+    while (queued < limit) {
+        const int c = std::min(chunk, limit - queued);
+        for (int k = 0; k < c; ++k) queue_cg_iteration(h, x, s);
+        queued += c;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hs.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool all = true;
+        for (auto &k : hs) all = all && k.done;
+        if (all) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    queue_true_residual(h, b, x, -1, s);
+    HIPCHK(hipMemcpyAsync(hs.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (info) {
-        info->iterations = fin.iters;
-        info->converged = fin.status == KS_CONVERGED;
-        info->rel_res_recursive = std::sqrt(fin.rr / fin.bb);
-        info->rel_res_true = std::sqrt(fin.red / fin.bb);
+    gdsw_status st = GDSW_OK;
+    for (int k = 0; k < np; ++k) {
+        if (hs[k].status == KS_BREAKDOWN) st = GDSW_ERR_BREAKDOWN;
+        else if (fixed <= 0 && hs[k].status != KS_CONVERGED && st == GDSW_OK) st = GDSW_ERR_NOT_CONVERGED;
     }
-    if (fin.status == KS_BREAKDOWN) {
-        h->err = "CG breakdown";
-        return GDSW_ERR_BREAKDOWN;
+    if (infos) {
+        if (ninfo >= np) {
+            for (int k = 0; k < np; ++k) fill_info(hs[k], infos + k);
+        } else {
+            // one summary: the slowest / worst problem
+            gdsw_solve_info agg{};
+            agg.converged = 1;
+            for (int k = 0; k < np; ++k) {
+                gdsw_solve_info one{};
+                fill_info(hs[k], &one);
+                agg.iterations = std::max(agg.iterations, one.iterations);
+                agg.converged = agg.converged && one.converged;
+                agg.rel_res_recursive = std::max(agg.rel_res_recursive, one.rel_res_recursive);
+                agg.rel_res_true = std::max(agg.rel_res_true, one.rel_res_true);
+            }
+            *infos = agg;
+        }
     }
-    if (fixed > 0) return GDSW_OK;
-    if (fin.status != KS_CONVERGED) {
-        h->err = "CG did not converge";
-        return GDSW_ERR_NOT_CONVERGED;
-    }
-    return GDSW_OK;
+    if (st == GDSW_ERR_BREAKDOWN) h->err = "CG breakdown";
+    if (st == GDSW_ERR_NOT_CONVERGED) h->err = "CG did not converge";
+    return st;
 }
 
 gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restart, double rtol, int maxit,
                         int fixed, gdsw_solve_info *info, hipStream_t s);
 
 gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart, double rtol, int maxit,
-                  int fixed_iters, gdsw_solve_info *info, void *stream) {
+                  int fixed_iters, gdsw_solve_info *info, int ninfo, void *stream) {
     if (!h->factored || !h->dev) {
         h->err = "solve before factor";
         return GDSW_ERR_STATE;
@@ -725,13 +843,23 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
     auto t0 = std::chrono::steady_clock::now();
     gdsw_status st;
     try {
-        if (krylov == GDSW_KRYLOV_CG) st = solve_cg(h, b, x, rtol, maxit, fixed_iters, info, s);
-        else st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, info, s);
+        if (krylov == GDSW_KRYLOV_CG) {
+            st = solve_cg(h, b, x, rtol, maxit, fixed_iters, info, info ? ninfo : 0, s);
+        } else {
+            if (h->sym.nprob != 1) {
+                h->err = "GMRES needs a handle with one problem";
+                return GDSW_ERR_INVALID_ARG;
+            }
+            st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, info, s);
+        }
     } catch (const DevError &e) {
         h->err = e.msg;
         return e.st;
     }
-    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int k = 0; k < std::max(ninfo, 1); ++k) info[k].seconds = sec;
+    }
     return st;
 }
 
@@ -753,13 +881,14 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
         D.gm_m = m;
     }
     if (!D.gm_st) D.gm_st = D.alloc<GState>(1);
-    const int gr = std::min(KRED, g);
-    if (!D.gm_part) D.gm_part = D.alloc<double>(int64_t(KRED) * (GM_MAX + 1));
+    const int gr = std::min(GM_RED, g);
+    if (!D.gm_part) D.gm_part = D.alloc<double>(int64_t(GM_RED) * (GM_MAX + 1));
+    const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     // ||b||^2
     KState ks{};
     HIPCHK(hipMemcpyAsync(D.kst, &ks, sizeof(KState), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, b, b, int(n), D.kpart, D.kst, 0);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, gr, D.kst, int(KF_BB));
+    hipLaunchKernelGGL(k_dot, dim3(D.nkb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, all);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, (int *)nullptr, int(KF_BB), 0);
     HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, n);
     HIPCHK(hipStreamSynchronize(s));
@@ -778,7 +907,8 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     GState *st = D.gm_st;
     double *V = D.gm_V;
     double *v = D.kz, *t = D.kp, *w = D.kq, *r = D.kr, *u = D.kt;
-    const int *cdone = &st->cycle_done;
+    Skip gsk;
+    gsk.flag = &st->cycle_done;
     int guard = 0;
     while (true) {
         // r = b - A x
@@ -792,7 +922,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
             const int c = std::min(chunk, m - queued);
             for (int k = 0; k < c; ++k) {
                 hipLaunchKernelGGL(k_gm_get, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, v, n, st);
-                launch_apply(h, v, t, 3, cdone, s);
+                launch_apply(h, v, t, 3, gsk, s);
                 hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, t, w, int(n), st);
                 for (int pass = 0; pass < 2; ++pass) {
                     hipLaunchKernelGGL(k_gm_dots, dim3(gr), dim3(KNT), 0, s, V, w, n, D.gm_part, st);
@@ -813,7 +943,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
         if (hs->j > 0 && hs->status != KS_BREAKDOWN) {
             hipLaunchKernelGGL(k_gm_lsq, dim3(1), dim3(64), 0, s, st);
             hipLaunchKernelGGL(k_gm_combine, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, u, n, st);
-            launch_apply(h, u, t, 3, nullptr, s);
+            launch_apply(h, u, t, 3, Skip(), s);
             hipLaunchKernelGGL(k_add, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, t, n);
         }
         HIPCHK(hipMemcpyAsync(hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
@@ -825,10 +955,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     const double g_last = hs->j > 0 ? std::fabs(hs->g[hs->j]) : hs->beta;
     delete hs;
     // true residual
-    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, int(n));
-    hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, int(n));
-    hipLaunchKernelGGL(k_dot, dim3(gr), dim3(KNT), 0, s, D.kt, D.kt, int(n), D.kpart, D.kst, 0);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, gr, D.kst, int(KF_RED));
+    queue_true_residual(h, b, x, 0, s);
     HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (info) {
@@ -849,6 +976,146 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     return GDSW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Continuous batching over the problems of a handle: each problem is a slot
+// that runs its own CG; slots start and finish independently while every
+// running slot advances in the same kernel launches.
+gdsw_status slots_begin(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "slots before factor";
+        return GDSW_ERR_STATE;
+    }
+    if (!b || !x || b == x || !(rtol >= 0.0) || maxit <= 0) {
+        h->err = "slots_begin: bad arguments";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    Device &D = *h->dev;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int np = h->sym.nprob;
+    D.slot_b = b;
+    D.slot_x = x;
+    D.h_state.assign(np, KState{});
+    for (auto &k : D.h_state) {
+        k.rtol2 = rtol * rtol;
+        k.maxit = maxit;
+        k.done = 1;
+        k.status = KS_IDLE;
+    }
+    std::vector<int> ones(np, 1);
+    try {
+        HIPCHK(hipMemcpyAsync(D.kst, D.h_state.data(), sizeof(KState) * np, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(D.kdone, ones.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream) {
+    if (!h->dev || !h->dev->slot_x) {
+        h->err = "slot_start before slots_begin";
+        return GDSW_ERR_STATE;
+    }
+    Device &D = *h->dev;
+    const int np = h->sym.nprob;
+    if (slot < 0 || slot >= np) return GDSW_ERR_INVALID_ARG;
+    if (D.h_state[slot].status != KS_IDLE) {
+        h->err = "slot is busy";
+        return GDSW_ERR_STATE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        KState k = D.h_state[slot];
+        k.done = 0;
+        k.status = KS_RUNNING;
+        k.iters = 0;
+        D.h_state[slot] = k;
+        // this slot alone is active in the start-up apply
+        std::vector<int> mask(np, 1);
+        mask[slot] = 0;
+        const int zero = 0;
+        HIPCHK(hipMemcpyAsync(D.kst + slot, &k, sizeof(KState), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(D.kdone + slot, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(D.kmask, mask.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+        queue_cg_start(h, D.slot_b, D.slot_x, slot, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream) {
+    if (!h->dev || !h->dev->slot_x) {
+        h->err = "slots_step before slots_begin";
+        return GDSW_ERR_STATE;
+    }
+    Device &D = *h->dev;
+    const int np = h->sym.nprob;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        bool any = false;
+        for (auto &k : D.h_state) any = any || (k.status == KS_RUNNING && !k.done);
+        if (any)
+            for (int i = 0; i < iters; ++i) queue_cg_iteration(h, D.slot_x, s);
+        HIPCHK(hipGetLastError());
+        std::vector<KState> dev(np);
+        HIPCHK(hipMemcpyAsync(dev.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < np; ++k) {
+            if (D.h_state[k].status == KS_IDLE) {
+                if (state) state[k] = -1;
+                continue;
+            }
+            D.h_state[k] = dev[k];
+            if (state) state[k] = !dev[k].done ? 0 : (dev[k].status == KS_CONVERGED ? 1 : 2);
+        }
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream) {
+    if (!h->dev || !h->dev->slot_x) return GDSW_ERR_STATE;
+    Device &D = *h->dev;
+    if (slot < 0 || slot >= h->sym.nprob) return GDSW_ERR_INVALID_ARG;
+    if (D.h_state[slot].status == KS_IDLE || !D.h_state[slot].done) {
+        h->err = "slot has no finished result";
+        return GDSW_ERR_STATE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        queue_true_residual(h, D.slot_b, D.slot_x, slot, s);
+        KState k{};
+        HIPCHK(hipMemcpyAsync(&k, D.kst + slot, sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (info) {
+            fill_info(k, info);
+            info->seconds = 0.0;
+        }
+        const gdsw_status st = k.status == KS_CONVERGED ? GDSW_OK
+                               : k.status == KS_BREAKDOWN ? GDSW_ERR_BREAKDOWN : GDSW_ERR_NOT_CONVERGED;
+        KState idle = D.h_state[slot];
+        idle.done = 1;
+        idle.status = KS_IDLE;
+        D.h_state[slot] = idle;
+        const int one = 1;
+        HIPCHK(hipMemcpyAsync(D.kst + slot, &idle, sizeof(KState), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(D.kdone + slot, &one, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return st;
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+}
+
 void destroy_device(gdsw_handle_s *h) {
     delete h->dev;
     h->dev = nullptr;
@@ -864,7 +1131,7 @@ gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out) {
     try {
         if (map == GDSW_MAP_A0) {
             if (!D.A0) return GDSW_ERR_STATE;
-            HIPCHK(hipMemcpy(out, D.A0, sizeof(double) * size_t(S.n0) * S.n0, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(out, D.A0, sizeof(double) * size_t(S.a0_off[S.nprob]), hipMemcpyDeviceToHost));
             return GDSW_OK;
         }
         if (map == GDSW_MAP_PHI_VAL) {

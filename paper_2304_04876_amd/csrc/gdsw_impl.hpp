@@ -123,6 +123,15 @@ struct Symbolic {
     std::vector<int64_t> a0seg_src;           // index into the T1 buffer
     std::vector<int64_t> a0pair_tgt;          // target of every T2 value (same order as values)
 
+    // ---- independent problems packed in one handle (block-diagonal A) ----------
+    int32_t nprob = 1;
+    std::vector<int64_t> prob_ptr;  // [nprob+1] dof offsets
+    std::vector<int32_t> prob_sub;  // [nprob+1] subdomain offsets
+    std::vector<int32_t> prob_c0;   // [nprob+1] coarse column offsets
+    std::vector<int64_t> a0_off;    // [nprob+1] offsets of the dense A_0 blocks
+    std::vector<int32_t> cprob;     // [n0] problem of each coarse column
+    std::vector<int32_t> sub_prob;  // [np] problem of each subdomain
+
     double t_analyze = 0.0;
 };
 
@@ -143,13 +152,20 @@ namespace gdsw {
 // symbolic.cpp
 gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, int32_t n_parts,
                     int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt);
+gdsw_status analyze_batch(gdsw_handle_s *h, int32_t count, const gdsw_csr *A, const int32_t *const *part,
+                          const int32_t *n_parts, int32_t dpn, const double *const *Z, int32_t n_null,
+                          const gdsw_options *opt);
 // device.hip
 gdsw_status factor(gdsw_handle_s *h, void *stream);
 gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream);
 gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void *stream);
 gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream);
 gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart,
-                  double rtol, int maxit, int fixed_iters, gdsw_solve_info *info, void *stream);
+                  double rtol, int maxit, int fixed_iters, gdsw_solve_info *info, int ninfo, void *stream);
+gdsw_status slots_begin(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, void *stream);
+gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream);
+gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream);
+gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream);
 void destroy_device(gdsw_handle_s *h);
 int64_t device_bytes(const gdsw_handle_s *h);
 gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out);

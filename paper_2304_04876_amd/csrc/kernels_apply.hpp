@@ -26,9 +26,9 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
     const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
     const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
-    double *__restrict__ zloc, const int *__restrict__ done) {
+    double *__restrict__ zloc, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (done && *done) return;
+    if (sk.sub(blockIdx.x)) return;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *bufA = reinterpret_cast<AT *>(smraw);
     AT *bufB = bufA + NT * R;
@@ -131,9 +131,9 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     const int64_t *__restrict__ ell_off, int64_t ell_rows, int KL, int KU, const VT *__restrict__ Lv,
     const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
     const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
-    double *__restrict__ zloc, int maxrows, void *__restrict__ gbuf, const int *__restrict__ done) {
+    double *__restrict__ zloc, int maxrows, void *__restrict__ gbuf, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (done && *done) return;
+    if (sk.sub(blockIdx.x)) return;
     extern __shared__ __align__(16) unsigned char smraw[];
     const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
@@ -192,9 +192,9 @@ template <int NT, typename VT>
 __global__ __launch_bounds__(NT) void k_band_apply(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
-    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, const int *__restrict__ done) {
+    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (done && *done) return;
+    if (sk.sub(blockIdx.x)) return;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *sT = y + maxrows;
@@ -223,8 +223,8 @@ template <int NT, typename PT>
 __global__ __launch_bounds__(NT) void k_coarse_restrict(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    double *__restrict__ partial, const int *__restrict__ done) {
-    if (done && *done) return;
+    double *__restrict__ partial, Skip sk) {
+    if (sk.blk(blockIdx.x)) return;
     __shared__ double sh[NT / 64];
     const int g = blockIdx.x;
     const int64_t r0 = row_ptr[g];
@@ -253,26 +253,29 @@ __global__ __launch_bounds__(NT) void k_coarse_restrict(
 
 // r0[c] = sum of the partials of coarse column c (ascending block order)
 __global__ void k_coarse_reduce(const int64_t *__restrict__ red_ptr, const int32_t *__restrict__ red_idx,
-                                const double *__restrict__ partial, double *__restrict__ r0, int n0,
-                                const int *__restrict__ done) {
-    if (done && *done) return;
+                                const double *__restrict__ partial, double *__restrict__ r0, int n0, Skip sk) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n0) return;
+    if (c >= n0 || sk.col(c)) return;
     double acc = 0.0;
     for (int64_t q = red_ptr[c]; q < red_ptr[c + 1]; ++q) acc += partial[red_idx[q]];
     r0[c] = acc;
 }
 
-// y = A x for a dense row-major n x n matrix: one wavefront per row
-__global__ __launch_bounds__(256) void k_dense_gemv(const double *__restrict__ A, const double *__restrict__ x,
-                                                    double *__restrict__ y, int n, const int *__restrict__ done) {
-    if (done && *done) return;
+// z0 = A_0^{-1} r0 with A_0^{-1} block diagonal over the problems of the
+// handle (row-major dense blocks): one wavefront per row
+__global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ Ainv, const int64_t *__restrict__ a0_off,
+                                                    const int32_t *__restrict__ prob_c0,
+                                                    const int32_t *__restrict__ cprob, const double *__restrict__ x,
+                                                    double *__restrict__ y, int n0, Skip sk) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const double *a = A + int64_t(row) * n;
+    if (row >= n0 || sk.col(row)) return;
+    const int k = cprob[row];
+    const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
+    const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
+    const double *xk = x + c0;
     double acc = 0.0;
-    for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
+    for (int c = lane; c < nk; c += 64) acc += a[c] * xk[c];
     acc = wave_sum(acc);
     if (lane == 0) y[row] = acc;
 }
@@ -285,11 +288,9 @@ __global__ void k_prolong(int which, const int64_t *__restrict__ t_ptr, const in
                           const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
                           const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols,
                           const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-                          const double *__restrict__ z0, double *__restrict__ z, int64_t n,
-                          const int *__restrict__ done) {
-    if (done && *done) return;
+                          const double *__restrict__ z0, double *__restrict__ z, int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (d >= n) return;
+    if (d >= n || sk.dof(d)) return;
     double acc = 0.0;
     if (which & 1)
         for (int64_t p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];

@@ -50,4 +50,30 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     return t;
 }
 
+// Which parts of a launch to skip: a handle may pack several independent
+// problems (block-diagonal A); `flag[k]` != 0 means problem k is finished or
+// idle and its subdomains, coarse blocks, coarse columns and dofs are left
+// alone.  flag == nullptr: nothing is skipped.
+struct Skip {
+    const int *flag = nullptr;
+    const int32_t *sub_prob = nullptr;   // subdomain -> problem
+    const int32_t *blk_prob = nullptr;   // coarse block -> problem
+    const int32_t *cprob = nullptr;      // coarse column -> problem
+    const int64_t *prob_ptr = nullptr;   // dof offsets of the problems
+    int nprob = 1;
+    __device__ __forceinline__ bool sub(int i) const { return flag && flag[nprob > 1 ? sub_prob[i] : 0]; }
+    __device__ __forceinline__ bool blk(int g) const { return flag && flag[nprob > 1 ? blk_prob[g] : 0]; }
+    __device__ __forceinline__ bool col(int c) const { return flag && flag[nprob > 1 ? cprob[c] : 0]; }
+    __device__ __forceinline__ bool dof(int64_t d) const {
+        if (!flag) return false;
+        if (nprob == 1) return flag[0];
+        int lo = 0, hi = nprob;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (prob_ptr[mid] <= d) lo = mid; else hi = mid;
+        }
+        return flag[lo];
+    }
+};
+
 }  // namespace gdsw

@@ -1,10 +1,11 @@
 // Device kernels of the Krylov iteration (FP64): CSR SpMV, fused vector
-// updates and dot products.  Every reduction is deterministic: a fixed
-// number of workgroups each write one partial (grid-stride rows, fixed tree
-// within the workgroup), then a one-workgroup kernel sums the partials in
-// index order and updates the scalar state on the device, so the host only
-// polls a flag.  (The kernel boundary orders the partial writes before the
-// final sum; no device-wide fences are needed.)
+// updates and dot products, for one or several independent problems packed
+// in a handle, each with its own scalars and stopping test.  Every
+// reduction is deterministic: fixed row blocks each write one partial (fixed
+// tree within the workgroup), then one workgroup per problem sums its
+// partials in index order and updates the problem's scalar state on the
+// device, so the host only polls flags.  (The kernel boundary orders the
+// partial writes before the final sum; no device-wide fences are needed.)
 #pragma once
 
 #include "kernels_common.hpp"
@@ -16,15 +17,27 @@ struct KState {
     int iters, done, status, fixed, maxit, pad;
 };
 
-enum { KS_RUNNING = 0, KS_CONVERGED = 1, KS_MAXIT = 2, KS_BREAKDOWN = 3 };
+enum { KS_RUNNING = 0, KS_CONVERGED = 1, KS_MAXIT = 2, KS_BREAKDOWN = 3, KS_IDLE = 4 };
 
 constexpr int KNT = 256;
-constexpr int KRED = 1024;   // workgroups of every reducing kernel (fixed: fixed summation order)
+constexpr int KROWS = 2048;   // rows per workgroup of the reducing kernels
 
-// Sum of the per-workgroup partials in index order, by one workgroup.
-__device__ __forceinline__ double sum_partials(const double *partial, int np, double *sh) {
+// Row blocks of the Krylov kernels.  Block b covers rows [row0[b], row1[b])
+// of problem prob[b]; the blocks of a problem are consecutive, so the
+// partial sums of a problem, and the order they are added in, depend only on
+// that problem: results are the same whether it is solved alone or packed
+// with others.  A launch covers blocks base .. base + gridDim.x - 1.
+struct KBlk {
+    const int32_t *prob;
+    const int32_t *row0;
+    const int32_t *row1;
+    int base;
+};
+
+// Sum of partials [lo, hi) in index order, by one workgroup.
+__device__ __forceinline__ double sum_partials(const double *partial, int lo, int hi, double *sh) {
     double v = 0.0;
-    for (int q = threadIdx.x; q < np; q += KNT) v += partial[q];
+    for (int q = lo + int(threadIdx.x); q < hi; q += KNT) v += partial[q];
     return block_sum<double, KNT>(v, sh);
 }
 
@@ -38,56 +51,72 @@ __global__ __launch_bounds__(KNT) void k_spmv(const int32_t *__restrict__ rowptr
     y[i] = acc;
 }
 
-// q = A p and the partials of p.q (grid of KRED workgroups, grid-stride rows)
+// x = 0, r = b on the rows of the launched blocks
+__global__ __launch_bounds__(KNT) void k_cg_init(double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ b, KBlk kb) {
+    const int blk = kb.base + blockIdx.x;
+    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
+        x[i] = 0.0;
+        r[i] = b[i];
+    }
+}
+
+// q = A p and the partials of p.q
 __global__ __launch_bounds__(KNT) void k_cg_spmv_dot(const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col,
                                                      const double *__restrict__ val,
                                                      const double *__restrict__ p, double *__restrict__ q,
-                                                     int n, double *__restrict__ partial, const KState *st) {
-    if (st->done) return;
+                                                     double *__restrict__ partial, const KState *st, KBlk kb) {
+    const int blk = kb.base + blockIdx.x;
+    if (st[kb.prob[blk]].done) return;
     __shared__ double sh[KNT / 64];
     double dot = 0.0;
-    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) {
+    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
         double acc = 0.0;
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += val[k] * p[col[k]];
         q[i] = acc;
         dot += p[i] * acc;
     }
     dot = block_sum<double, KNT>(dot, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = dot;
+    if (threadIdx.x == 0) partial[blk] = dot;
 }
 
 // x += alpha p; r -= alpha q; partials of r.r
 __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p,
-                                                      const double *__restrict__ q, int n,
-                                                      double *__restrict__ partial, const KState *st) {
-    if (st->done) return;
+                                                      const double *__restrict__ q,
+                                                      double *__restrict__ partial, const KState *st, KBlk kb) {
+    const int blk = kb.base + blockIdx.x;
+    const KState &S = st[kb.prob[blk]];
+    if (S.done) return;
     __shared__ double sh[KNT / 64];
-    const double alpha = st->alpha;
+    const double alpha = S.alpha;
     double v = 0.0;
-    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) {
+    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
         v += ri * ri;
     }
     v = block_sum<double, KNT>(v, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+    if (threadIdx.x == 0) partial[blk] = v;
 }
 
 // partials of a.b
-__global__ __launch_bounds__(KNT) void k_dot(const double *__restrict__ a, const double *__restrict__ b, int n,
-                                             double *__restrict__ partial, const KState *st, int skip_if_done) {
-    if (skip_if_done && st->done) return;
+__global__ __launch_bounds__(KNT) void k_dot(const double *__restrict__ a, const double *__restrict__ b,
+                                             double *__restrict__ partial, const KState *st, int skip_if_done,
+                                             KBlk kb) {
+    const int blk = kb.base + blockIdx.x;
+    if (skip_if_done && st[kb.prob[blk]].done) return;
     __shared__ double sh[KNT / 64];
     double v = 0.0;
-    for (int i = blockIdx.x * KNT + threadIdx.x; i < n; i += gridDim.x * KNT) v += a[i] * b[i];
+    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) v += a[i] * b[i];
     v = block_sum<double, KNT>(v, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+    if (threadIdx.x == 0) partial[blk] = v;
 }
 
-// One workgroup: total of the partials and the scalar step it feeds.
+// One workgroup per problem (problems base .. base + gridDim.x - 1): total
+// of its partials and the scalar step it feeds; kdone mirrors `done`.
 enum {
     KF_BB = 0,      // bb = t
     KF_RHO = 1,     // rho = t
@@ -97,62 +126,76 @@ enum {
     KF_RED = 5      // red = t
 };
 
-__global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, int np, KState *st, int op) {
-    if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA) && st->done) return;
+__global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, const int32_t *__restrict__ pb_ptr,
+                                                   KState *st, int *__restrict__ kdone, int op, int base) {
+    const int k = base + blockIdx.x;
+    KState &S = st[k];
+    if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA) && S.done) return;
     __shared__ double sh[KNT / 64];
-    const double t = sum_partials(partial, np, sh);
+    const double t = sum_partials(partial, pb_ptr[k], pb_ptr[k + 1], sh);
     if (threadIdx.x != 0) return;
     switch (op) {
-        case KF_BB: st->bb = t; break;
-        case KF_RHO: st->rho = t; break;
+        case KF_BB:
+            S.bb = t;
+            if (t == 0.0) {   // zero right-hand side: x = 0 is the solution
+                S.done = 1;
+                S.status = KS_CONVERGED;
+            } else if (!isfinite(t)) {
+                S.done = 1;
+                S.status = KS_BREAKDOWN;
+            }
+            break;
+        case KF_RHO: S.rho = t; break;
         case KF_ALPHA:
-            st->sigma = t;
+            S.sigma = t;
             if (!(t > 0.0) || !isfinite(t)) {
-                st->done = 1;
-                st->status = KS_BREAKDOWN;
+                S.done = 1;
+                S.status = KS_BREAKDOWN;
             } else {
-                st->alpha = st->rho / t;
+                S.alpha = S.rho / t;
             }
             break;
         case KF_RR:
-            st->rr = t;
-            st->iters += 1;
+            S.rr = t;
+            S.iters += 1;
             if (!isfinite(t)) {
-                st->done = 1;
-                st->status = KS_BREAKDOWN;
-            } else if (st->fixed > 0) {
-                if (st->iters >= st->fixed) {
-                    st->done = 1;
-                    st->status = (t <= st->rtol2 * st->bb) ? KS_CONVERGED : KS_MAXIT;
+                S.done = 1;
+                S.status = KS_BREAKDOWN;
+            } else if (S.fixed > 0) {
+                if (S.iters >= S.fixed) {
+                    S.done = 1;
+                    S.status = (t <= S.rtol2 * S.bb) ? KS_CONVERGED : KS_MAXIT;
                 }
-            } else if (t <= st->rtol2 * st->bb) {
-                st->done = 1;
-                st->status = KS_CONVERGED;
-            } else if (st->iters >= st->maxit) {
-                st->done = 1;
-                st->status = KS_MAXIT;
+            } else if (t <= S.rtol2 * S.bb) {
+                S.done = 1;
+                S.status = KS_CONVERGED;
+            } else if (S.iters >= S.maxit) {
+                S.done = 1;
+                S.status = KS_MAXIT;
             }
             break;
         case KF_BETA:
-            if (!isfinite(t) || st->rho == 0.0) {
-                st->done = 1;
-                st->status = KS_BREAKDOWN;
+            if (!isfinite(t) || S.rho == 0.0) {
+                S.done = 1;
+                S.status = KS_BREAKDOWN;
             } else {
-                st->beta = t / st->rho;
-                st->rho = t;
+                S.beta = t / S.rho;
+                S.rho = t;
             }
             break;
-        default: st->red = t; break;
+        default: S.red = t; break;
     }
+    if (kdone) kdone[k] = S.done;
 }
 
 // p = z + beta p (init: p = z)
-__global__ __launch_bounds__(KNT) void k_cg_update_p(double *__restrict__ p, const double *__restrict__ z, int n,
-                                                     const KState *st, int init) {
-    if (!init && st->done) return;
-    const int i = blockIdx.x * KNT + threadIdx.x;
-    if (i >= n) return;
-    p[i] = init ? z[i] : z[i] + st->beta * p[i];
+__global__ __launch_bounds__(KNT) void k_cg_update_p(double *__restrict__ p, const double *__restrict__ z,
+                                                     const KState *st, int init, KBlk kb) {
+    const int blk = kb.base + blockIdx.x;
+    const KState &S = st[kb.prob[blk]];
+    if (!init && S.done) return;
+    const double beta = S.beta;
+    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) p[i] = init ? z[i] : z[i] + beta * p[i];
 }
 
 // y = b - y
@@ -178,6 +221,7 @@ namespace gdsw {
 // only queues steps and polls once per chunk.  Orthogonalisation is classical
 // Gram-Schmidt applied twice (two reductions per step instead of j+1).
 constexpr int GM_MAX = 64;   // largest restart length
+constexpr int GM_RED = 1024; // workgroups of the GMRES reductions (grid-stride rows)
 
 struct GState {
     double H[(GM_MAX + 1) * GM_MAX];   // column-major, leading dimension GM_MAX+1
@@ -274,7 +318,7 @@ __global__ __launch_bounds__(KNT) void k_gm_sqnorm(const double *__restrict__ w,
 __global__ __launch_bounds__(KNT) void k_gm_step_finish(const double *__restrict__ partial, int np, GState *st) {
     if (st->cycle_done) return;
     __shared__ double sh[KNT / 64];
-    const double ss = sum_partials(partial, np, sh);
+    const double ss = sum_partials(partial, 0, np, sh);
     if (threadIdx.x != 0) return;
     const int j = st->j;
     double *Hj = st->H + j * (GM_MAX + 1);
@@ -332,7 +376,7 @@ __global__ void k_gm_scale(double *__restrict__ V, const double *__restrict__ w,
 __global__ __launch_bounds__(KNT) void k_gm_start_finish(const double *__restrict__ partial, int np, GState *st) {
     if (st->done) return;
     __shared__ double sh[KNT / 64];
-    const double ss = sum_partials(partial, np, sh);
+    const double ss = sum_partials(partial, 0, np, sh);
     if (threadIdx.x != 0) return;
     st->beta = sqrt(ss);
     st->j = 0;

@@ -622,6 +622,35 @@ void build_coarse(Symbolic &s) {
     B.nb = int32_t(B.kind.size());
     // reduction lists (partials of each coarse column, ascending block order)
     const int32_t n0 = coarse ? s.n0 : 0;
+    // coarse columns and A_0 blocks of every problem (problems never couple,
+    // and components are ordered by their smallest node, so the columns of a
+    // problem are contiguous)
+    s.prob_c0.assign(s.nprob + 1, 0);
+    s.cprob.assign(n0, 0);
+    {
+        auto prob_of_dof = [&](int64_t d) {
+            return int32_t(std::upper_bound(s.prob_ptr.begin(), s.prob_ptr.end(), d) - s.prob_ptr.begin() - 1);
+        };
+        std::vector<int32_t> cnt(s.nprob, 0);
+        for (int32_t c = 0; c < s.nc && coarse; ++c) {
+            const int32_t k = prob_of_dof(int64_t(s.comp_nodes[s.comp_ptr[c]]) * dpn);
+            for (int32_t j = 0; j < s.comp_rank[c]; ++j) s.cprob[s.comp_col0[c] + j] = k;
+            cnt[k] += s.comp_rank[c];
+        }
+        for (int32_t c = 1; c < n0; ++c)
+            if (s.cprob[c] < s.cprob[c - 1]) fail(GDSW_ERR_INTERNAL, "coarse columns of a problem not contiguous");
+        for (int k = 0; k < s.nprob; ++k) s.prob_c0[k + 1] = s.prob_c0[k] + cnt[k];
+        s.a0_off.assign(s.nprob + 1, 0);
+        for (int k = 0; k < s.nprob; ++k) {
+            const int64_t nk = s.prob_c0[k + 1] - s.prob_c0[k];
+            s.a0_off[k + 1] = s.a0_off[k] + nk * nk;
+        }
+    }
+    auto a0_index = [&](int32_t a, int32_t b) {
+        const int32_t k = s.cprob[a];
+        const int64_t c0 = s.prob_c0[k], nk = s.prob_c0[k + 1] - c0;
+        return s.a0_off[k] + (a - c0) * nk + (b - c0);
+    };
     s.red_ptr.assign(n0 + 1, 0);
     for (int64_t q = 0; q < int64_t(B.cols.size()); ++q) s.red_ptr[B.cols[q] + 1]++;
     for (int32_t c = 0; c < n0; ++c) s.red_ptr[c + 1] += s.red_ptr[c];
@@ -673,7 +702,7 @@ void build_coarse(Symbolic &s) {
             s.pair_off.push_back(s.pair_off.back() + rc * rd);
             for (int64_t a = 0; a < rc; ++a)
                 for (int64_t b = 0; b < rd; ++b)
-                    s.a0pair_tgt.push_back(int64_t(s.comp_col0[c] + a) * n0 + (s.comp_col0[d] + b));
+                    s.a0pair_tgt.push_back(a0_index(int32_t(s.comp_col0[c] + a), int32_t(s.comp_col0[d] + b)));
         }
     }
     // subdomain terms E_i^T X_i: segments by target, ascending subdomain
@@ -691,7 +720,7 @@ void build_coarse(Symbolic &s) {
         const int32_t *cols = s.scol.data() + s.scol_ptr[i];
         for (int64_t a = 0; a < kk; ++a)
             for (int64_t b = 0; b < kk; ++b)
-                contrib.push_back({int64_t(cols[a]) * n0 + cols[b], s.t1_off[i] + a * kk + b});
+                contrib.push_back({a0_index(cols[a], cols[b]), s.t1_off[i] + a * kk + b});
     }
     std::stable_sort(contrib.begin(), contrib.end(),
                      [](const auto &x, const auto &y) { return x.first < y.first; });
@@ -713,6 +742,14 @@ gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, in
     try {
         Symbolic &s = h->sym;
         validate_and_copy(s, A, part, n_parts, dpn, Z, n_null, opt);
+        if (s.prob_ptr.empty()) {
+            s.nprob = 1;
+            s.prob_ptr = {0, s.n};
+            s.prob_sub = {0, s.np};
+        }
+        s.sub_prob.assign(s.np, 0);
+        for (int k = 0; k < s.nprob; ++k)
+            for (int32_t i = s.prob_sub[k]; i < s.prob_sub[k + 1]; ++i) s.sub_prob[i] = k;
         build_graph(s);
         build_overlap(s);
         build_interface(s);
@@ -730,6 +767,76 @@ gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, in
     h->sym.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->analyzed = true;
     return GDSW_OK;
+}
+
+gdsw_status analyze_batch(gdsw_handle_s *h, int32_t count, const gdsw_csr *A, const int32_t *const *part,
+                          const int32_t *n_parts, int32_t dpn, const double *const *Z, int32_t n_null,
+                          const gdsw_options *opt) {
+    try {
+        if (count <= 0 || !A || !part || !n_parts) fail(GDSW_ERR_INVALID_ARG, "batch: bad arguments");
+        if (dpn <= 0) fail(GDSW_ERR_INVALID_ARG, "batch: dpn");
+        if ((Z == nullptr) != (n_null <= 0) && !(Z == nullptr && n_null <= 1))
+            fail(GDSW_ERR_INVALID_ARG, "batch: null space arguments");
+        // block-diagonal concatenation; subdomain ids and dofs offset per problem
+        int64_t n = 0, nnz = 0, np = 0;
+        for (int k = 0; k < count; ++k) {
+            if (!A[k].rowptr || !A[k].col || !A[k].val || !part[k] || A[k].n <= 0 || A[k].n % dpn || n_parts[k] <= 0)
+                fail(GDSW_ERR_INVALID_ARG, "batch: problem " + std::to_string(k) + " malformed");
+            n += A[k].n;
+            nnz += A[k].rowptr[A[k].n];
+            np += n_parts[k];
+        }
+        if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31) || np >= (int64_t(1) << 31))
+            fail(GDSW_ERR_INVALID_ARG, "batch too large");
+        std::vector<int64_t> rowptr(n + 1, 0);
+        std::vector<int32_t> col(nnz);
+        std::vector<double> val(nnz);
+        std::vector<int32_t> prt(n / dpn);
+        std::vector<double> Zc;
+        const int nz = Z ? n_null : 1;
+        if (Z) Zc.assign(size_t(n) * nz, 0.0);
+        Symbolic &s = h->sym;
+        s.nprob = count;
+        s.prob_ptr.assign(count + 1, 0);
+        s.prob_sub.assign(count + 1, 0);
+        int64_t ro = 0, eo = 0;
+        int32_t so = 0;
+        for (int k = 0; k < count; ++k) {
+            const int64_t nk = A[k].n;
+            for (int64_t i = 0; i < nk; ++i) {
+                for (int64_t p = A[k].rowptr[i]; p < A[k].rowptr[i + 1]; ++p) {
+                    const int32_t c = A[k].col[p];
+                    if (c < 0 || c >= nk) fail(GDSW_ERR_INVALID_ARG, "batch: column out of range");
+                    col[eo] = int32_t(c + ro);
+                    val[eo] = A[k].val[p];
+                    ++eo;
+                }
+                rowptr[ro + i + 1] = eo;
+            }
+            for (int64_t v = 0; v < nk / dpn; ++v) {
+                const int32_t pv = part[k][v];
+                if (pv < 0 || pv >= n_parts[k]) fail(GDSW_ERR_INVALID_ARG, "batch: part out of range");
+                prt[ro / dpn + v] = so + pv;
+            }
+            if (Z) {
+                if (!Z[k]) fail(GDSW_ERR_INVALID_ARG, "batch: missing null space");
+                for (int j = 0; j < nz; ++j)
+                    for (int64_t i = 0; i < nk; ++i) Zc[size_t(j) * n + ro + i] = Z[k][size_t(j) * nk + i];
+            }
+            ro += nk;
+            so += n_parts[k];
+            s.prob_ptr[k + 1] = ro;
+            s.prob_sub[k + 1] = so;
+        }
+        gdsw_csr big{n, rowptr.data(), col.data(), val.data()};
+        return analyze(h, &big, prt.data(), int32_t(np), dpn, Z ? Zc.data() : nullptr, Z ? nz : 0, opt);
+    } catch (const Fail &f) {
+        h->err = f.msg;
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed in batch analysis";
+        return GDSW_ERR_BUDGET;
+    }
 }
 
 }  // namespace gdsw

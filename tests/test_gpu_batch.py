@@ -1,0 +1,132 @@
+"""Several independent problems packed in one handle (batching) and the
+continuous-batching slot interface: every problem's apply, iterations and
+solution must be bit-identical whether it runs alone or packed with others,
+and agree with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2304_04876_amd import binding as B
+from paper_2304_04876_amd import problems as P
+from oracle import gdsw_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _problems():
+    rng = np.random.default_rng(5)
+    d1 = P.diffusion3d(14, np.exp(rng.standard_normal(15 ** 3)), 2)
+    d2 = P.diffusion3d(11, np.exp(rng.standard_normal(12 ** 3)), 3)
+    p3 = P.poisson3d(9, 2)
+    return [d1, d2, p3]
+
+
+@pytest.mark.parametrize("local", [B.LOCAL_EXACT, B.LOCAL_ILU0])
+def test_batch_apply_and_solve_equal_alone(local):
+    probs = _problems()
+    say(f"[batch] apply/solve local={local}")
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
+                              options=B.gdsw_default_options(local=local))
+    B.gdsw_factor(hb)
+    offs = B.gdsw_problem_offsets(hb)
+    assert list(np.diff(offs)) == [p.n for p in probs]
+    n = int(offs[-1])
+    r = torch.from_numpy(np.concatenate([P.rhs_uniform(p.n, 10 + k) for k, p in enumerate(probs)])).cuda()
+    zb = torch.zeros_like(r)
+    B.gdsw_apply(hb, r, zb)
+    xb = torch.zeros_like(r)
+    infos = B.gdsw_solve_batch(hb, r, xb, rtol=1e-8)
+    for k, p in enumerate(probs):
+        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=local)
+        rk = r[offs[k]:offs[k + 1]].clone()
+        zk = torch.zeros_like(rk)
+        g.apply(rk, zk)
+        assert torch.equal(zk, zb[offs[k]:offs[k + 1]]), k
+        xk = torch.zeros_like(rk)
+        out = g.solve(rk, xk, rtol=1e-8)
+        assert out["iterations"] == infos[k]["iterations"]
+        assert torch.equal(xk, xb[offs[k]:offs[k + 1]]), k
+        # and the oracle agrees on the iteration count
+        M = O.GDSW(p.A, p.part, 1, p.n_parts, local="exact" if local == B.LOCAL_EXACT else "ilu0")
+        ref = O.pcg(p.A, rk.cpu().numpy(), M, rtol=1e-8)
+        assert abs(ref.iters - infos[k]["iterations"]) <= 1
+        g.close()
+    assert n == r.numel()
+    B.gdsw_destroy(hb)
+
+
+def test_batch_coarse_blocks_match_oracle():
+    probs = _problems()
+    say("[batch] coarse blocks")
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs])
+    B.gdsw_factor(hb)
+    A0 = B.gdsw_copy_map(hb, B.MAP_A0)
+    off = 0
+    for p in probs:
+        M = O.GDSW(p.A, p.part, 1, p.n_parts)
+        n0 = M.A0.shape[0]
+        blk = A0[off:off + n0 * n0].reshape(n0, n0)
+        assert np.abs(blk - M.A0).max() <= 1e-12 * np.abs(M.A0).max()
+        off += n0 * n0
+    assert off == A0.size
+    B.gdsw_destroy(hb)
+
+
+def test_slots_results_same_alone_and_in_the_mix():
+    probs = _problems()
+    say("[slots] staggered starts")
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
+                              options=B.gdsw_default_options(local=B.LOCAL_ILU0))
+    B.gdsw_factor(hb)
+    offs = B.gdsw_problem_offsets(hb)
+    b = torch.zeros(int(offs[-1]), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    B.gdsw_slots_begin(hb, b, x, rtol=1e-8, maxit=500)
+    rhs = [torch.from_numpy(P.rhs_uniform(p.n, 20 + k)).cuda() for k, p in enumerate(probs)]
+    results = {}
+    # slot 0 starts alone; slot 2 joins after 3 steps, slot 1 after 6
+    b[offs[0]:offs[1]] = rhs[0]
+    B.gdsw_slot_start(hb, 0)
+    steps = 0
+    started = {0}
+    while len(results) < 3:
+        st = B.gdsw_slots_step(hb, 1)
+        steps += 1
+        for k in range(3):
+            if st[k] == 1:
+                info = B.gdsw_slot_finish(hb, k)
+                results[k] = (info, x[offs[k]:offs[k + 1]].clone())
+        if steps == 3 and 2 not in started:
+            b[offs[2]:offs[3]] = rhs[2]
+            B.gdsw_slot_start(hb, 2)
+            started.add(2)
+        if steps == 6 and 1 not in started:
+            b[offs[1]:offs[2]] = rhs[1]
+            B.gdsw_slot_start(hb, 1)
+            started.add(1)
+        assert steps < 2000
+    for k, p in enumerate(probs):
+        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_ILU0)
+        xk = torch.zeros_like(rhs[k])
+        out = g.solve(rhs[k], xk, rtol=1e-8)
+        info, xs = results[k]
+        assert info["status"] == 0 and info["converged"]
+        assert info["iterations"] == out["iterations"]
+        assert torch.equal(xs, xk), k
+        assert info["rel_res_true"] <= 1.5e-8
+        g.close()
+    # a slot can be reused after it finished
+    b[offs[0]:offs[1]] = torch.from_numpy(P.rhs_uniform(probs[0].n, 99)).cuda()
+    B.gdsw_slot_start(hb, 0)
+    for _ in range(1000):
+        st = B.gdsw_slots_step(hb, 4)
+        if st[0] == 1:
+            break
+    assert B.gdsw_slot_finish(hb, 0)["converged"]
+    B.gdsw_destroy(hb)
