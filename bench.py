@@ -42,7 +42,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--local", choices=["ilu0", "exact"], default="ilu0")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default="fp64")
-    ap.add_argument("--workload", choices=["poisson", "elasticity"], default="poisson")
+    ap.add_argument("--workload", choices=["poisson", "elasticity", "batch", "serve"], default="poisson")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -56,6 +59,11 @@ def main():
     import torch
     from paper_2304_04876_amd import binding as B
     from paper_2304_04876_amd import problems as P
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     precs = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16, "fp16": B.FP16}
     pbytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[args.prec]
@@ -235,6 +243,149 @@ def main():
     }
     print(json.dumps(line), flush=True)
     B.gdsw_destroy(h)
+
+
+def bench_batch(args):
+    """256 independent diffusion problems (N in [16,48], P in [2,4], kappa =
+    exp(N(0,1)) per cell), exact local factors stored FP32, FP64 CG: all
+    problems packed in one handle and solved together, against the same
+    problems solved one after another with one FP64 handle each."""
+    import torch
+    from paper_2304_04876_amd import binding as B
+    from paper_2304_04876_amd import problems as P
+
+    log(f"[batch] generating {args.batch_count} diffusion problems")
+    specs = P.batch_diffusion_specs(args.batch_count)
+    probs = [P.batch_diffusion_problem(sp) for sp in specs]
+    t0 = time.perf_counter()
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
+                              options=B.gdsw_default_options(local=B.LOCAL_EXACT, local_prec=B.FP32,
+                                                             basis_prec=B.FP32))
+    t_an = time.perf_counter() - t0
+    B.gdsw_factor(hb)
+    info = B.gdsw_get_info(hb)
+    log(f"[batch] n={info['n']} subdomains={info['n_parts']} analysis {t_an:.1f}s setup {info['t_factor']:.2f}s "
+        f"device {info['device_bytes'] / 1e9:.1f} GB")
+    b = torch.from_numpy(np.concatenate([p.b for p in probs])).cuda()
+    x = torch.zeros_like(b)
+    B.gdsw_solve_batch(hb, b, x, rtol=1e-8, maxit=2000)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps)
+    for _ in range(reps):
+        infos = B.gdsw_solve_batch(hb, b, x, rtol=1e-8, maxit=2000)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    res = max(i["rel_res_true"] for i in infos)
+    its = [i["iterations"] for i in infos]
+    B.gdsw_destroy(hb)
+    # the same problems one at a time, FP64 local factors, one handle each
+    log("[batch] sequential FP64 reference")
+    seq = 0.0
+    seq_res = 0.0
+    for k, p in enumerate(probs):
+        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_EXACT)
+        bk = b[int(sum(q.n for q in probs[:k])):][:p.n].clone()
+        xk = torch.zeros_like(bk)
+        g.solve(bk, xk, rtol=1e-8, maxit=2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = g.solve(bk, xk, rtol=1e-8, maxit=2000)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        seq_res = max(seq_res, out["rel_res_true"])
+        g.close()
+    line = {
+        "metric": "GDSW-PCG solves/sec and M^-1 applies/sec at 1e-8 residual; p50/p99 solve latency",
+        "value": round(len(probs) / wall, 2), "unit": "solves/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(1e3 * wall, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+fp32", "data": "synthetic",
+        "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact_fp32_gdsw_cg",
+                   "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8},
+        "iterations_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
+        "rel_res_true_max": res,
+        "sequential_fp64_solves_per_s": round(len(probs) / seq, 2),
+        "sequential_fp64_rel_res_true_max": seq_res,
+        "setup_s": round(info["t_factor"], 3), "analysis_s": round(t_an, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Serving stream over 8 resident Poisson operators (N = 32..96,
+    P = round(N/16)), ILU(0) local factors in FP16 with FP32 arithmetic,
+    FP64 CG to 1e-8; Poisson arrivals at 0.5 and 0.8 of the measured
+    saturation rate; plus the same requests solved one at a time with FP64
+    handles (no batching) for comparison, and a run under a small HBM
+    budget."""
+    import torch
+    from paper_2304_04876_amd import binding as B
+    from paper_2304_04876_amd import problems as P
+    from paper_2304_04876_amd import serve as SV
+
+    ops = [P.serve_operator(N) for N in P.SERVE_SIZES]
+    log("[serve] operators " + ", ".join(f"{p.name} n={p.n}" for p in ops))
+    srv = SV.Server(ops, slots_per_op=4, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+
+    def make(nreq, rate, seed):
+        t, opi = SV.poisson_arrivals(nreq, rate, len(ops), seed)
+        return [SV.Request(rid=i, op=int(opi[i]), arrival=float(t[i]),
+                           b=P.rhs_uniform(ops[int(opi[i])].n, i)) for i in range(nreq)]
+
+    # saturation: everything arrives at once
+    sat_n = 8 * 4 * 3
+    reqs, _ = srv.run(make(sat_n, 1e9, 1))
+    mu = SV.summarize(reqs, srv).solves_per_s
+    log(f"[serve] saturation {mu:.1f} solves/s")
+    out = {}
+    for frac in (0.5, 0.8):
+        nreq = args.serve_requests + args.serve_warmup
+        reqs, _ = srv.run(make(nreq, frac * mu, 2))
+        st = SV.summarize(reqs, srv, skip=args.serve_warmup)
+        out[frac] = st
+        log(f"[serve] load {frac}: {st.solves_per_s:.1f} solves/s p50 {st.p50_ms:.1f} ms p99 {st.p99_ms:.1f} ms")
+    slots_bytes = srv.device_bytes
+    srv.close()
+    # forced-small HBM budget: one slot per operator
+    small = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+    reqs, _ = small.run(make(400, 0.5 * mu, 3))
+    st_small = SV.summarize(reqs, small, skip=50)
+    small.close()
+    # plain FP64 GPU path: the same kind of requests one at a time
+    log("[serve] sequential FP64 reference")
+    handles = [B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_ILU0) for p in ops]
+    reqs = make(160, 1e9, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    resmax = 0.0
+    for r in reqs:
+        bd = torch.from_numpy(r.b).cuda()
+        xd = torch.zeros_like(bd)
+        o = handles[r.op].solve(bd, xd, rtol=1e-8)
+        resmax = max(resmax, o["rel_res_true"])
+    torch.cuda.synchronize()
+    seq_rate = len(reqs) / (time.perf_counter() - t0)
+    for g in handles:
+        g.close()
+    s5 = out[0.5]
+    line = {
+        "metric": "GDSW-PCG solves/sec and M^-1 applies/sec at 1e-8 residual; p50/p99 solve latency",
+        "value": round(s5.solves_per_s, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.serve_requests,
+        "warmup": args.serve_warmup, "ms_per_step": round(1e3 / s5.solves_per_s, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+fp16", "data": "synthetic",
+        "config": {"workload": "serve8_poisson32-96_ilu0_fp16_gdsw_cg", "slots_per_op": 4, "rtol": 1e-8,
+                   "step_iters": srv.step_iters},
+        "saturation_solves_per_s": round(mu, 2),
+        "load": {str(f): {"solves_per_s": round(v.solves_per_s, 2), "p50_ms": round(v.p50_ms, 2),
+                          "p99_ms": round(v.p99_ms, 2), "mean_iters": round(v.mean_iters, 1),
+                          "max_rel_res_true": v.max_rel_res_true} for f, v in out.items()},
+        "small_budget_one_slot": {"solves_per_s": round(st_small.solves_per_s, 2),
+                                  "p50_ms": round(st_small.p50_ms, 2), "p99_ms": round(st_small.p99_ms, 2)},
+        "device_bytes_4_slots": int(slots_bytes),
+        "sequential_fp64_solves_per_s": round(seq_rate, 2),
+        "sequential_fp64_rel_res_true_max": resmax,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

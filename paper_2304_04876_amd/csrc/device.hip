@@ -88,7 +88,9 @@ struct Device {
     double *dscale = nullptr;   // diagonal scaling of reduced-precision factors (or null)
     // ---- restriction / prolongation ----
     int32_t *ov_idx = nullptr;
-    int64_t *ov_ptr = nullptr, *t_ptr = nullptr;
+    int64_t *ov_ptr = nullptr;
+    int32_t *t_ptr = nullptr;
+    Sell sell{};          // A for the SpMV
     int32_t *t_pos = nullptr;
     double *zloc = nullptr;
     // ---- local factors ----
@@ -128,6 +130,7 @@ struct Device {
     int64_t phi_entries = 0;
     int64_t local_entries = 0;
     int KLp = 1, KUp = 1;   // slot counts of the sweep layout
+    int max_n0 = 0;         // largest coarse block
     size_t max_lds = 64 * 1024;   // dynamic LDS a workgroup may use on this device
     double *gm_V = nullptr, *gm_part = nullptr;   // GMRES basis and partial sums
     int gm_m = 0;
@@ -154,7 +157,37 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     D.adiag = D.upload(adiag, s);
     D.ov_idx = D.upload(S.ov_idx, s);
     D.ov_ptr = D.upload(S.ov_ptr, s);
-    D.t_ptr = D.upload(S.t_ptr, s);
+    {
+        std::vector<int32_t> tp(S.t_ptr.begin(), S.t_ptr.end());
+        D.t_ptr = D.upload(tp, s);
+        // sliced ELL copy of A
+        const int64_t nsl = (S.n + SELL_C - 1) / SELL_C;
+        std::vector<int64_t> off(nsl + 1, 0);
+        std::vector<int32_t> wid(nsl, 0);
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            int32_t w = 0;
+            for (int64_t i = sl * SELL_C; i < std::min<int64_t>(S.n, (sl + 1) * SELL_C); ++i)
+                w = std::max<int32_t>(w, int32_t(S.rowptr[i + 1] - S.rowptr[i]));
+            wid[sl] = w;
+            off[sl + 1] = off[sl] + int64_t(w) * SELL_C;
+        }
+        std::vector<double> sv(off[nsl], 0.0);
+        std::vector<int32_t> sc(off[nsl], 0);
+        for (int64_t i = 0; i < S.n; ++i) {
+            const int64_t base = off[i / SELL_C] + i % SELL_C;
+            int j = 0;
+            for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p, ++j) {
+                sv[base + int64_t(j) * SELL_C] = S.val[p];
+                sc[base + int64_t(j) * SELL_C] = S.col[p];
+            }
+            for (; j < wid[i / SELL_C]; ++j) sc[base + int64_t(j) * SELL_C] = int32_t(i);
+        }
+        D.sell.off = D.upload(off, s);
+        D.sell.width = D.upload(wid, s);
+        D.sell.val = D.upload(sv, s);
+        D.sell.col = D.upload(sc, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
     D.t_pos = D.upload(S.t_pos, s);
     D.zloc = D.alloc<double>(S.ov_ptr[S.np]);
     const int64_t n = S.n;
@@ -498,6 +531,7 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     }
     D.cprob = D.upload(S.cprob, s);
     D.prob_c0 = D.upload(S.prob_c0, s);
+    for (int k = 0; k < S.nprob; ++k) D.max_n0 = std::max(D.max_n0, S.prob_c0[k + 1] - S.prob_c0[k]);
     D.a0_off = D.upload(S.a0_off, s);
     if (S.opt.basis_prec == GDSW_FP32) {
         D.phi32 = D.alloc<float>(nphi);
@@ -608,10 +642,13 @@ static void launch_local(const Symbolic &S, Device &D, const double *r, const Sk
     }
 }
 
-static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk, hipStream_t s) {
+// z = M^{-1} r (which = 3), or one part of it; with dot_r the prolongation
+// also writes the Krylov-block partials of dot_r . z into the partial buffer.
+static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk, hipStream_t s,
+                         const double *dot_r = nullptr) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
-    if (which & 1) {
+    if (which & 1 || which == 4) {
         switch (S.opt.local_prec) {
             case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
             case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
@@ -620,38 +657,47 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         }
     }
     if (which == 4) {   // the local solves alone (results stay in zloc)
-        switch (S.opt.local_prec) {
-            case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
-            case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
-            case GDSW_BF16: launch_local<bf16>(S, D, r, sk, s); break;
-            default: launch_local<fp16>(S, D, r, sk, s); break;
-        }
         HIPCHK(hipGetLastError());
         return;
     }
     const bool coarse = (which & 2) && D.A0inv != nullptr;
     if (coarse) {
         const PhiBlocks &B = S.blk;
+        const dim3 gr((B.nb + 3) / 4);
         if (D.phi32)
-            hipLaunchKernelGGL((k_coarse_restrict<256, float>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
-                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, sk);
+            hipLaunchKernelGGL(k_coarse_restrict<float>, gr, dim3(256), 0, s, r, D.blk_row_ptr, D.blk_rows,
+                               D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, B.nb, sk);
         else
-            hipLaunchKernelGGL((k_coarse_restrict<256, double>), dim3(B.nb), dim3(256), 0, s, r, D.blk_row_ptr,
-                               D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, sk);
+            hipLaunchKernelGGL(k_coarse_restrict<double>, gr, dim3(256), 0, s, r, D.blk_row_ptr, D.blk_rows,
+                               D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, B.nb, sk);
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
-        hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0,
-                           D.cprob, D.r0, D.z0, S.n0, sk);
+        if (D.max_n0 >= 1024)
+            hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
+                               D.r0, D.z0, S.n0, sk);
+        else
+            hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0,
+                               D.cprob, D.r0, D.z0, S.n0, sk);
     }
     const int w = (which & 1) | (coarse ? 2 : 0);
-    if (D.phi32)
+    if (dot_r) {
+        if (D.phi32)
+            hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
+                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
+                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+        else
+            hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
+                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
+                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+    } else if (D.phi32) {
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
                            (const float *)D.phi32, D.z0, z, S.n, sk);
-    else
+    } else {
         hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
                            D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
                            (const double *)D.phi, D.z0, z, S.n, sk);
+    }
     HIPCHK(hipGetLastError());
 }
 
@@ -680,8 +726,8 @@ gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream) {
     }
     if (!x || !y || x == y) return GDSW_ERR_INVALID_ARG;
     const int n = int(h->sym.n);
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->rowptr,
-                       h->dev->col, h->dev->val, x, y, n);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
+                       x, y, n);
     return hipGetLastError() == hipSuccess ? GDSW_OK : GDSW_ERR_HIP;
 }
 
@@ -711,13 +757,11 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     Device &D = *h->dev;
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     const int nkb = D.nkb, np = S.nprob;
-    hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.rowptr, D.col, D.val, D.kp, D.kq, D.kpart,
-                       D.kst, all);
+    hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.sell, D.kp, D.kq, D.kpart, D.kst, all);
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0);
     hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kpart, D.kst, all);
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR), 0);
-    launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s);
-    hipLaunchKernelGGL(k_dot, dim3(nkb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 1, all);
+    launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s, D.kr);   // also the partials of r.z
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BETA), 0);
     hipLaunchKernelGGL(k_cg_update_p, dim3(nkb), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all);
 }
@@ -747,7 +791,7 @@ static void queue_true_residual(gdsw_handle_s *h, const double *b, const double 
     const int base = k < 0 ? 0 : D.h_pb_ptr[k];
     const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, D.kt, n);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
     hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst,
@@ -912,7 +956,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     int guard = 0;
     while (true) {
         // r = b - A x
-        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, x, r, int(n));
+        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
         hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, r, n, D.gm_part, st, 1);
         hipLaunchKernelGGL(k_gm_start_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st);
@@ -923,7 +967,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
             for (int k = 0; k < c; ++k) {
                 hipLaunchKernelGGL(k_gm_get, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, v, n, st);
                 launch_apply(h, v, t, 3, gsk, s);
-                hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.rowptr, D.col, D.val, t, w, int(n), st);
+                hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
                 for (int pass = 0; pass < 2; ++pass) {
                     hipLaunchKernelGGL(k_gm_dots, dim3(gr), dim3(KNT), 0, s, V, w, n, D.gm_part, st);
                     hipLaunchKernelGGL(k_gm_dots_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st, pass);

@@ -218,35 +218,35 @@ __global__ __launch_bounds__(NT) void k_band_apply(
 
 // ---------------------------------------------------------------------------
 // Coarse restriction Phi^T r, block by block: partial[col_ptr[g] + s] =
-// sum_l B_g(l, s) r[rows_g(l)], fixed reduction order.
-template <int NT, typename PT>
-__global__ __launch_bounds__(NT) void k_coarse_restrict(
+// sum_l B_g(l, s) r[rows_g(l)], one wavefront per block (lane-strided rows,
+// up to 8 columns per pass, fixed butterfly reduction).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_coarse_restrict(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    double *__restrict__ partial, Skip sk) {
-    if (sk.blk(blockIdx.x)) return;
-    __shared__ double sh[NT / 64];
-    const int g = blockIdx.x;
+    double *__restrict__ partial, int nb, Skip sk) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= nb || sk.blk(g)) return;
     const int64_t r0 = row_ptr[g];
     const int nr = int(row_ptr[g + 1] - r0);
     const int k = int(col_ptr[g + 1] - col_ptr[g]);
-    const PT *B = phi + val_off[g];
+    const PT *Bg = phi + val_off[g];
     constexpr int KB = 8;
     for (int s0 = 0; s0 < k; s0 += KB) {
         double acc[KB];
 #pragma unroll
         for (int s = 0; s < KB; ++s) acc[s] = 0.0;
-        for (int l = threadIdx.x; l < nr; l += NT) {
+        for (int l = lane; l < nr; l += 64) {
             const double x = r[rows[r0 + l]];
 #pragma unroll
             for (int s = 0; s < KB; ++s)
-                if (s0 + s < k) acc[s] += double(to_acc(B[int64_t(s0 + s) * nr + l])) * x;
+                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x;
         }
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
-            if (s0 + s >= k) break;
-            const double t = block_sum<double, NT>(acc[s], sh);
-            if (threadIdx.x == 0) partial[col_ptr[g] + s0 + s] = t;
+            const double t = wave_sum(acc[s]);
+            if (lane == 0 && s0 + s < k) partial[col_ptr[g] + s0 + s] = t;
         }
     }
 }
@@ -280,10 +280,53 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
     if (lane == 0) y[row] = acc;
 }
 
+// Same with one workgroup (4 wavefronts) per row, for blocks of large order.
+__global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict__ Ainv, const int64_t *__restrict__ a0_off,
+                                                       const int32_t *__restrict__ prob_c0,
+                                                       const int32_t *__restrict__ cprob, const double *__restrict__ x,
+                                                       double *__restrict__ y, int n0, Skip sk) {
+    __shared__ double sh[4];
+    const int row = blockIdx.x;
+    if (sk.col(row)) return;
+    const int k = cprob[row];
+    const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
+    const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
+    const double *xk = x + c0;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < nk; c += 256) acc += a[c] * xk[c];
+    acc = block_sum<double, 256>(acc, sh);
+    if (threadIdx.x == 0) y[row] = acc;
+}
+
 // z[d] = sum over the local rows holding d (ascending subdomain) of zloc
 //        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part)
 template <typename PT>
-__global__ void k_prolong(int which, const int64_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
+__device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_t *__restrict__ t_ptr,
+                                              const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
+                                              const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr,
+                                              const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ col_ptr,
+                                              const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
+                                              const PT *__restrict__ phi, const double *__restrict__ z0) {
+    double acc = 0.0;
+    if (which & 1)
+        for (int p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
+    if (which & 2) {
+        const int g = dof_blk[d];
+        if (g >= 0) {
+            const int64_t nr = row_ptr[g + 1] - row_ptr[g];
+            const int64_t c0 = col_ptr[g];
+            const int k = int(col_ptr[g + 1] - c0);
+            const PT *Bg = phi + val_off[g] + dof_lr[d];
+            double s = 0.0;
+            for (int q = 0; q < k; ++q) s += double(to_acc(Bg[q * nr])) * z0[cols[c0 + q]];
+            acc += s;
+        }
+    }
+    return acc;
+}
+
+template <typename PT>
+__global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
                           const double *__restrict__ zloc, const int32_t *__restrict__ dof_blk,
                           const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
                           const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols,
@@ -291,22 +334,33 @@ __global__ void k_prolong(int which, const int64_t *__restrict__ t_ptr, const in
                           const double *__restrict__ z0, double *__restrict__ z, int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (d >= n || sk.dof(d)) return;
-    double acc = 0.0;
-    if (which & 1)
-        for (int64_t p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
-    if (which & 2) {
-        const int g = dof_blk[d];
-        if (g >= 0) {
-            const int64_t nr = row_ptr[g + 1] - row_ptr[g];
-            const int64_t c0 = col_ptr[g];
-            const int k = int(col_ptr[g + 1] - c0);
-            const PT *B = phi + val_off[g] + dof_lr[d];
-            double s = 0.0;
-            for (int q = 0; q < k; ++q) s += double(to_acc(B[q * nr])) * z0[cols[c0 + q]];
-            acc += s;
-        }
+    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
+}
+
+// The same over the row blocks of the Krylov iteration (256 threads, rows
+// [row0[b], row1[b]) of one problem), also writing the block's partial of
+// r . z for the next CG step.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_prolong_dot(
+    int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
+    const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
+    const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
+    const PT *__restrict__ phi, const double *__restrict__ z0, double *__restrict__ z, Skip sk,
+    const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
+    double *__restrict__ partial) {
+    __shared__ double sh[4];
+    const int blk = blockIdx.x;
+    const int row0 = kb_row0[blk], row1 = kb_row1[blk];
+    if (sk.dof(row0)) return;
+    double dot = 0.0;
+    for (int d = row0 + threadIdx.x; d < row1; d += 256) {
+        const double v =
+            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
+        z[d] = v;
+        dot += rvec[d] * v;
     }
-    z[d] = acc;
+    dot = block_sum<double, 256>(dot, sh);
+    if (threadIdx.x == 0) partial[blk] = dot;
 }
 
 }  // namespace gdsw

@@ -41,14 +41,30 @@ __device__ __forceinline__ double sum_partials(const double *partial, int lo, in
     return block_sum<double, KNT>(v, sh);
 }
 
-__global__ __launch_bounds__(KNT) void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                              const double *__restrict__ val, const double *__restrict__ x,
-                                              double *__restrict__ y, int n) {
+// A in sliced ELL form for the SpMV: slices of SELL_C consecutive rows, each
+// slice padded to its longest row and stored slot-major, so that
+// consecutive threads (rows) read consecutive addresses.
+constexpr int SELL_C = 256;
+struct Sell {
+    const int64_t *off;    // [nslices+1] value offsets of the slices
+    const int32_t *width;  // [nslices] slots of each slice
+    const double *val;
+    const int32_t *col;
+};
+
+__device__ __forceinline__ double sell_row(const Sell &A, int i, const double *__restrict__ x) {
+    const int sl = i / SELL_C, lane = i % SELL_C;
+    const int64_t base = A.off[sl] + lane;
+    const int w = A.width[sl];
+    double acc = 0.0;
+    for (int j = 0; j < w; ++j) acc += A.val[base + int64_t(j) * SELL_C] * x[A.col[base + int64_t(j) * SELL_C]];
+    return acc;
+}
+
+__global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y, int n) {
     const int i = blockIdx.x * KNT + threadIdx.x;
     if (i >= n) return;
-    double acc = 0.0;
-    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) acc += val[p] * x[col[p]];
-    y[i] = acc;
+    y[i] = sell_row(A, i, x);
 }
 
 // x = 0, r = b on the rows of the launched blocks
@@ -62,18 +78,14 @@ __global__ __launch_bounds__(KNT) void k_cg_init(double *__restrict__ x, double 
 }
 
 // q = A p and the partials of p.q
-__global__ __launch_bounds__(KNT) void k_cg_spmv_dot(const int32_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col,
-                                                     const double *__restrict__ val,
-                                                     const double *__restrict__ p, double *__restrict__ q,
+__global__ __launch_bounds__(KNT) void k_cg_spmv_dot(Sell A, const double *__restrict__ p, double *__restrict__ q,
                                                      double *__restrict__ partial, const KState *st, KBlk kb) {
     const int blk = kb.base + blockIdx.x;
     if (st[kb.prob[blk]].done) return;
     __shared__ double sh[KNT / 64];
     double dot = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
-        double acc = 0.0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += val[k] * p[col[k]];
+        const double acc = sell_row(A, i, p);
         q[i] = acc;
         dot += p[i] * acc;
     }
@@ -235,15 +247,12 @@ struct GState {
 };
 
 // w = A t (skipped once the cycle has stopped)
-__global__ __launch_bounds__(KNT) void k_gm_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                                 const double *__restrict__ val, const double *__restrict__ t,
-                                                 double *__restrict__ w, int n, const GState *st) {
+__global__ __launch_bounds__(KNT) void k_gm_spmv(Sell A, const double *__restrict__ t, double *__restrict__ w, int n,
+                                                 const GState *st) {
     if (st->cycle_done) return;
     const int i = blockIdx.x * KNT + threadIdx.x;
     if (i >= n) return;
-    double acc = 0.0;
-    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) acc += val[p] * t[col[p]];
-    w[i] = acc;
+    w[i] = sell_row(A, i, t);
 }
 
 // v = V_j (j from the state), the vector the preconditioner is applied to
