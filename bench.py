@@ -30,6 +30,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel measured with rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (calibrated by a device copy of known size; see
+# profiles/hbm_traffic_*.md).  A figure only applies to the kernel source it
+# was measured on: `src` is a hash of that kernel's text, checked below.
+MEASURED_TRAFFIC = {
+    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 270.9e6, "src": "5175fa6096dad374"},
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2304_04876_amd", "csrc", "kernels_apply.hpp")
+    text = open(path).read()
+    marks = {"k_ilu_jacobi": ("template <int NT, int R, int KL, int KU, typename VT>",
+                              "// Same sweeps for any slot counts and subdomain sizes")}
+    if kernel not in marks:
+        return None
+    a, b = text.index(marks[kernel][0]), text.index(marks[kernel][1])
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -184,8 +204,12 @@ def main():
         alg_bytes = 2 * info["local_factor_entries"] * pbytes + info["sum_overlap_dofs"] * (4 + 8 + 8)
         kname = "k_band_apply"
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = None
+    meas = MEASURED_TRAFFIC.get((kname, f"poisson{N}^3_P{Pn}^3" if not elastic else f"elasticity{N}^3", args.prec))
+    if meas and kernel_source_hash(kname) == meas["src"]:
+        traffic = int(meas["bytes"])
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": int(alg_bytes), "avg_launch_ms": round(k_ms, 5)}
 
     # ---- CPU baseline: the oracle on a bounded sample ------------------------------

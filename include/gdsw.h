@@ -114,6 +114,8 @@ typedef struct {
     double t_analyze;         /* seconds: host symbolic analysis                  */
     double t_factor;          /* seconds: device numerical setup (synchronised)   */
     int32_t n_problems;       /* independent problems packed in the handle        */
+    int32_t local_variant;    /* launch configuration of the local solves (-1 = fixed rule) */
+    int32_t gemv_variant;     /* coarse GEMV: -1 fixed rule, 0 wavefront, 1 workgroup per row */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -235,6 +237,16 @@ gdsw_status gdsw_slots_begin(gdsw_handle h, const double *b_dev, double *x_dev, 
 gdsw_status gdsw_slot_start(gdsw_handle h, int32_t slot, void *stream);
 gdsw_status gdsw_slots_step(gdsw_handle h, int32_t iters, int32_t *state, void *stream);
 gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info, void *stream);
+
+/* Autotuner: times every launch configuration of the local-solve kernel
+ * (ILU(0): register-resident sweeps with 512 or 1024 threads, streaming
+ * sweeps with 256 or 512 threads; exact: band solves with 256, 512 or 1024
+ * threads) and both coarse GEMV variants on the handle's own factors, `reps`
+ * launches each, and keeps the fastest for all later applies.  times_ms
+ * (optional, host, 6 floats) receives the average milliseconds per launch
+ * (-1 for configurations that do not fit): [0..3] local variants, [4..5]
+ * GEMV variants.  Synchronises `stream`. */
+gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
 /* Dof offsets of the problems of a handle: offsets[count+1] (host). */
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);

@@ -35,7 +35,7 @@ EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refacto
             "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
-            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets")
+            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune")
 
 
 class Options(ctypes.Structure):
@@ -64,7 +64,8 @@ class Info(ctypes.Structure):
                 ("phi_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("max_local_rows", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
                 ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
-                ("n_problems", ctypes.c_int32)]
+                ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
+                ("gemv_variant", ctypes.c_int32)]
 
 
 def lib():
@@ -102,6 +103,7 @@ def lib():
         "gdsw_slots_step": (ctypes.c_int, [vp, i32, vp, vp]),
         "gdsw_slot_finish": (ctypes.c_int, [vp, i32, ctypes.POINTER(SolveInfo), vp]),
         "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
+        "gdsw_autotune": (ctypes.c_int, [vp, i32, vp, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -300,6 +302,12 @@ def gdsw_slot_finish(h, slot, stream=None) -> dict:
     if st not in (GDSW_OK, 3, 4):
         raise GdswError(st, gdsw_last_error(h))
     return _info_dict(info, st)
+
+
+def gdsw_autotune(h, reps=10, stream=None) -> list:
+    times = np.full(6, -1.0, dtype=np.float32)
+    _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
+    return times.tolist()
 
 
 def gdsw_problem_offsets(h) -> np.ndarray:

@@ -71,6 +71,11 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
     return gdsw::slot_finish(h, slot, info, stream);
 }
 
+gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream) {
+    if (!h || reps <= 0) return GDSW_ERR_INVALID_ARG;
+    return gdsw::autotune(h, reps, times_ms, stream);
+}
+
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
     if (!h || !offsets) return GDSW_ERR_INVALID_ARG;
     if (!h->analyzed) return GDSW_ERR_STATE;
@@ -145,6 +150,8 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->t_analyze = S.t_analyze;
     info->t_factor = h->t_factor;
     info->n_problems = S.nprob;
+    info->local_variant = gdsw::tuned_variant(h, 0);
+    info->gemv_variant = gdsw::tuned_variant(h, 1);
     return GDSW_OK;
 }
 

@@ -131,11 +131,14 @@ struct Device {
     int64_t local_entries = 0;
     int KLp = 1, KUp = 1;   // slot counts of the sweep layout
     int max_n0 = 0;         // largest coarse block
+    int nb_big = 0;         // leading coarse-basis blocks restricted by a workgroup each
     size_t max_lds = 64 * 1024;   // dynamic LDS a workgroup may use on this device
     double *gm_V = nullptr, *gm_part = nullptr;   // GMRES basis and partial sums
     int gm_m = 0;
     GState *gm_st = nullptr;
     void *sweep_buf = nullptr;    // iterates of subdomains too large for LDS
+    int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
+    int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
 
 // ---------------------------------------------------------------------------
@@ -362,6 +365,11 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     if (S.opt.coarse != GDSW_COARSE_GDSW || S.n0 == 0 || B.nb == 0) return;
     const int n0 = S.n0;
     D.blk_row_ptr = D.upload(B.row_ptr, s);
+    // interior blocks come first; they (and any block of many rows) take a
+    // workgroup each in the restriction
+    D.nb_big = 0;
+    while (D.nb_big < B.nb && (B.kind[D.nb_big] == 0 || B.row_ptr[D.nb_big + 1] - B.row_ptr[D.nb_big] >= 512))
+        ++D.nb_big;
     D.blk_col_ptr = D.upload(B.col_ptr, s);
     D.blk_val_off = D.upload(B.val_off, s);
     D.blk_rows = D.upload(B.rows, s);
@@ -438,7 +446,7 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         check_status(D, d_status, S.np, s, "interior Cholesky");
         const size_t lds2 = sizeof(double) * (size_t(std::max(S.max_nii, 1)) + BS_NB * BS_LD);
         if (lds2 > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "interior block too large for LDS"};
-        hipLaunchKernelGGL(k_ext_solve<256>, dim3(S.np), dim3(256), lds2, s, iband, d_ioff, d_ibw, d_int_ptr,
+        hipLaunchKernelGGL(k_ext_solve<512>, dim3(S.np), dim3(512), lds2, s, iband, d_ioff, d_ibw, d_int_ptr,
                            d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
@@ -592,11 +600,16 @@ gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename VT>
+// Launch configurations of the local-solve kernels.  ILU(0): 0 = registers,
+// 512 threads; 1 = registers, 1024 threads; 2 = streaming, 256 threads;
+// 3 = streaming, 512 threads.  Exact: 0 = 256 threads, 1 = 512, 2 = 1024.
+// -1 picks by a fixed rule; gdsw_autotune times the candidates.
+constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 3;
+
+template <typename VT, int NT>
 static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
     if (D.KLp != 3 || D.KUp != 3) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
-    constexpr int NT = f64 ? 512 : 1024;
     const int need = (S.max_ni + NT - 1) / NT;
     using AT = typename AccOf<VT>::type;
 #define GDSW_ILU_CASE(RR)                                                                                    \
@@ -608,38 +621,76 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
                            (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, sk);                   \
         return true;                                                                                         \
     }
-    // largest row counts per thread that stay in registers without spilling
+    // the row counts per thread whose factor entries stay in registers
+    // without spilling at this workgroup size
     GDSW_ILU_CASE(2)
     GDSW_ILU_CASE(4)
-    GDSW_ILU_CASE(6)
-    GDSW_ILU_CASE(8)
-    if constexpr (f64) { GDSW_ILU_CASE(11) }
+    if constexpr (!(f64 && NT == 1024)) {
+        GDSW_ILU_CASE(6)
+        GDSW_ILU_CASE(8)
+    }
+    if constexpr (NT == 512) { GDSW_ILU_CASE(11) }
 #undef GDSW_ILU_CASE
     return false;
 }
 
+template <typename VT, int NT>
+static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+    using AT = typename AccOf<VT>::type;
+    size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
+    void *gbuf = nullptr;
+    if (lds > D.max_lds) {
+        if (!D.sweep_buf) return false;
+        gbuf = D.sweep_buf;
+        lds = 0;
+    }
+    hipLaunchKernelGGL((k_ilu_jacobi_generic<NT, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                       D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc,
+                       (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, S.max_ni, gbuf, sk);
+    return true;
+}
+
+template <typename VT, int NT>
+static bool launch_band(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+    using AT = typename AccOf<VT>::type;
+    if (std::is_same<VT, double>::value && NT > 512) return false;   // would spill registers
+    const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
+    if (lds > D.max_lds) return false;
+    hipLaunchKernelGGL((k_band_apply<NT, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                       (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
+    return true;
+}
+
+template <typename VT>
+static bool launch_local_variant(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
+                                 hipStream_t s) {
+    if (S.opt.local == GDSW_LOCAL_ILU0) {
+        switch (v) {
+            case 0: return launch_ilu_regs<VT, 512>(S, D, r, sk, s);
+            case 1: return launch_ilu_regs<VT, 1024>(S, D, r, sk, s);
+            case 2: return launch_ilu_stream<VT, 256>(S, D, r, sk, s);
+            default: return launch_ilu_stream<VT, 512>(S, D, r, sk, s);
+        }
+    }
+    switch (v) {
+        case 0: return launch_band<VT, 256>(S, D, r, sk, s);
+        case 1: return launch_band<VT, 512>(S, D, r, sk, s);
+        default: return launch_band<VT, 1024>(S, D, r, sk, s);
+    }
+}
+
 template <typename VT>
 static void launch_local(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
-    using AT = typename AccOf<VT>::type;
-    if (S.opt.local == GDSW_LOCAL_ILU0) {
-        if (launch_ilu_regs<VT>(S, D, r, sk, s)) return;
-        size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
-        void *gbuf = nullptr;
-        if (lds > D.max_lds) {
-            if (!D.sweep_buf) throw DevError{GDSW_ERR_INTERNAL, "sweep buffer missing"};
-            gbuf = D.sweep_buf;
-            lds = 0;
-        }
-        hipLaunchKernelGGL((k_ilu_jacobi_generic<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
-                           D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc,
-                           (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc,
-                           S.max_ni, gbuf, sk);
-    } else {
-        const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
-        if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "subdomain too large for the LDS band solve"};
-        hipLaunchKernelGGL((k_band_apply<256, VT>), dim3(S.np), dim3(256), lds, s, r, D.ov_idx, D.ov_ptr,
-                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
-    }
+    if (D.local_variant >= 0 && launch_local_variant<VT>(S, D, D.local_variant, r, sk, s)) return;
+    // fixed rule: register-resident sweeps when they fit (FP64: 512 threads,
+    // reduced precision: 1024), else streaming; band solves with 512 threads
+    static const int ilu_order_f64[] = {0, 1, 2, 3}, ilu_order_lo[] = {1, 0, 2, 3}, band_order[] = {1, 0, 2};
+    const bool ilu = S.opt.local == GDSW_LOCAL_ILU0;
+    const int *order = ilu ? (std::is_same<VT, double>::value ? ilu_order_f64 : ilu_order_lo) : band_order;
+    const int nv = ilu ? N_ILU_VARIANTS : N_BAND_VARIANTS;
+    for (int q = 0; q < nv; ++q)
+        if (launch_local_variant<VT>(S, D, order[q], r, sk, s)) return;
+    throw DevError{GDSW_ERR_INVALID_ARG, "no local-solve kernel fits this subdomain size"};
 }
 
 // z = M^{-1} r (which = 3), or one part of it; with dot_r the prolongation
@@ -663,16 +714,28 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
     const bool coarse = (which & 2) && D.A0inv != nullptr;
     if (coarse) {
         const PhiBlocks &B = S.blk;
-        const dim3 gr((B.nb + 3) / 4);
-        if (D.phi32)
-            hipLaunchKernelGGL(k_coarse_restrict<float>, gr, dim3(256), 0, s, r, D.blk_row_ptr, D.blk_rows,
-                               D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, B.nb, sk);
-        else
-            hipLaunchKernelGGL(k_coarse_restrict<double>, gr, dim3(256), 0, s, r, D.blk_row_ptr, D.blk_rows,
-                               D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, B.nb, sk);
+        // blocks with many rows (subdomain interiors) first, then the small ones
+        const int nbig = D.nb_big, nsmall = B.nb - nbig;
+        if (D.phi32) {
+            if (nbig)
+                hipLaunchKernelGGL((k_coarse_restrict_wg<256, float>), dim3(nbig), dim3(256), 0, s, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, 0, sk);
+            if (nsmall)
+                hipLaunchKernelGGL(k_coarse_restrict_wave<float>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
+                                   D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32,
+                                   D.partial, nbig, B.nb, sk);
+        } else {
+            if (nbig)
+                hipLaunchKernelGGL((k_coarse_restrict_wg<256, double>), dim3(nbig), dim3(256), 0, s, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, 0, sk);
+            if (nsmall)
+                hipLaunchKernelGGL(k_coarse_restrict_wave<double>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
+                                   D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi,
+                                   D.partial, nbig, B.nb, sk);
+        }
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
-        if (D.max_n0 >= 1024)
+        if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
             hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
                                D.r0, D.z0, S.n0, sk);
         else
@@ -1158,6 +1221,85 @@ gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void 
         h->err = e.msg;
         return e.st;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times every launch configuration of the local-solve kernel and
+// both coarse GEMV variants on the handle's own data and keeps the fastest.
+template <typename VT>
+static float time_local(gdsw_handle_s *h, int v, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const Skip none;
+    if (!launch_local_variant<VT>(S, D, v, D.kr, none, s)) return -1.0f;
+    HIPCHK(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) launch_local_variant<VT>(S, D, v, D.kr, none, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return ms / reps;
+}
+
+gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "autotune before factor";
+        return GDSW_ERR_STATE;
+    }
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(S.n, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, S.n);
+        const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
+        float best = -1.0f;
+        int bv = -1;
+        for (int v = 0; v < nv; ++v) {
+            float t;
+            switch (S.opt.local_prec) {
+                case GDSW_FP64: t = time_local<double>(h, v, reps, s, e0, e1); break;
+                case GDSW_FP32: t = time_local<float>(h, v, reps, s, e0, e1); break;
+                case GDSW_BF16: t = time_local<bf16>(h, v, reps, s, e0, e1); break;
+                default: t = time_local<fp16>(h, v, reps, s, e0, e1); break;
+            }
+            if (times) times[v] = t;
+            if (t > 0.0f && (best < 0.0f || t < best)) {
+                best = t;
+                bv = v;
+            }
+        }
+        D.local_variant = bv;
+        if (D.A0inv) {
+            float tg[2];
+            for (int v = 0; v < 2; ++v) {
+                D.gemv_variant = v;
+                launch_apply(h, D.kr, D.kz, 2, Skip(), s);
+                HIPCHK(hipEventRecord(e0, s));
+                for (int k = 0; k < reps; ++k) launch_apply(h, D.kr, D.kz, 2, Skip(), s);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&tg[v], e0, e1));
+                if (times) times[4 + v] = tg[v] / reps;
+            }
+            D.gemv_variant = tg[1] < tg[0] ? 1 : 0;
+        }
+        HIPCHK(hipEventDestroy(e0));
+        HIPCHK(hipEventDestroy(e1));
+    } catch (const DevError &e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+int tuned_variant(const gdsw_handle_s *h, int which) {
+    if (!h->dev) return -1;
+    return which == 0 ? h->dev->local_variant : h->dev->gemv_variant;
 }
 
 void destroy_device(gdsw_handle_s *h) {

@@ -166,6 +166,8 @@ gdsw_status slots_begin(gdsw_handle_s *h, const double *b, double *x, double rto
 gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream);
 gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream);
 gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream);
+gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream);
+int tuned_variant(const gdsw_handle_s *h, int which);
 void destroy_device(gdsw_handle_s *h);
 int64_t device_bytes(const gdsw_handle_s *h);
 gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out);

@@ -218,14 +218,47 @@ __global__ __launch_bounds__(NT) void k_band_apply(
 
 // ---------------------------------------------------------------------------
 // Coarse restriction Phi^T r, block by block: partial[col_ptr[g] + s] =
-// sum_l B_g(l, s) r[rows_g(l)], one wavefront per block (lane-strided rows,
-// up to 8 columns per pass, fixed butterfly reduction).
-template <typename PT>
-__global__ __launch_bounds__(256) void k_coarse_restrict(
+// sum_l B_g(l, s) r[rows_g(l)], fixed reduction order.  Large blocks (the
+// interiors of subdomains) get a workgroup each, small ones (interface
+// components) a wavefront each; up to 8 columns per pass.
+template <int NT, typename PT>
+__global__ __launch_bounds__(NT) void k_coarse_restrict_wg(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    double *__restrict__ partial, int nb, Skip sk) {
-    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    double *__restrict__ partial, int g0, Skip sk) {
+    const int g = g0 + blockIdx.x;
+    if (sk.blk(g)) return;
+    __shared__ double sh[NT / 64];
+    const int64_t r0 = row_ptr[g];
+    const int nr = int(row_ptr[g + 1] - r0);
+    const int k = int(col_ptr[g + 1] - col_ptr[g]);
+    const PT *Bg = phi + val_off[g];
+    constexpr int KB = 8;
+    for (int s0 = 0; s0 < k; s0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int s = 0; s < KB; ++s) acc[s] = 0.0;
+        for (int l = threadIdx.x; l < nr; l += NT) {
+            const double x = r[rows[r0 + l]];
+#pragma unroll
+            for (int s = 0; s < KB; ++s)
+                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x;
+        }
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            if (s0 + s >= k) break;
+            const double t = block_sum<double, NT>(acc[s], sh);
+            if (threadIdx.x == 0) partial[col_ptr[g] + s0 + s] = t;
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_coarse_restrict_wave(
+    const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
+    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+    double *__restrict__ partial, int g0, int nb, Skip sk) {
+    const int g = g0 + blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= nb || sk.blk(g)) return;
     const int64_t r0 = row_ptr[g];

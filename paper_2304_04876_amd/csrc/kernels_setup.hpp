@@ -244,18 +244,19 @@ __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int
 
 // ---------------------------------------------------------------------------
 // Band triangular solves with one LDS vector: y <- (L L^T)^{-1} y.
-// Forward: blocks of BS rows; the diagonal triangle is solved by wavefront 0
+// Forward: blocks of BS_NB rows; the diagonal triangle is solved by wavefront 0
 // (lanes = rows, the solved value broadcast with a shuffle), then the rows
 // that couple to the block (at most b below it) are updated, one thread per
 // row reading its contiguous band segment.  Backward: the same blocks in
 // reverse; the transposed triangle by wavefront 0, then the entries above the
 // block are updated one thread per column, reading band rows of the block
 // (consecutive threads, consecutive addresses).
-constexpr int BS_NB = 32;
+constexpr int BS_NB = 64;   // rows per block = lanes of the wavefront that solves the triangle
 constexpr int BS_LD = BS_NB + 1;
 
 template <typename VT, typename AT, int NT>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
+    constexpr int BS_G = sizeof(AT) == 8 ? 16 : 32;   // loads in flight per thread and group
     const int64_t w = b + 1;
     const int tid = threadIdx.x;
     for (int k0 = 0; k0 < n; k0 += BS_NB) {
@@ -281,8 +282,17 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         for (int r = k0 + kb + tid; r < rend; r += NT) {
             const int s0 = max(0, r - b - k0);
             const VT *row = L + int64_t(r) * w + (k0 - r + b);
+            // the loads of a group of the row segment are issued before its sums
             AT acc = 0;
-            for (int s = s0; s < kb; ++s) acc += to_acc(row[s]) * y[k0 + s];
+#pragma unroll 1
+            for (int g = 0; g < BS_NB; g += BS_G) {
+                AT v[BS_G];
+#pragma unroll
+                for (int q = 0; q < BS_G; ++q)
+                    v[q] = (g + q >= s0 && g + q < kb) ? to_acc(row[g + q]) : AT(0);
+#pragma unroll
+                for (int q = 0; q < BS_G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
+            }
             y[r] -= acc;
         }
         __syncthreads();
@@ -312,7 +322,15 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         for (int j = jbeg + tid; j < k0; j += NT) {
             const int smax = min(kb, j + b - k0 + 1);
             AT acc = 0;
-            for (int s = 0; s < smax; ++s) acc += to_acc(L[int64_t(k0 + s) * w + (j - k0 - s + b)]) * y[k0 + s];
+#pragma unroll 1
+            for (int g = 0; g < BS_NB; g += BS_G) {
+                AT v[BS_G];
+#pragma unroll
+                for (int q = 0; q < BS_G; ++q)
+                    v[q] = (g + q < smax) ? to_acc(L[int64_t(k0 + g + q) * w + (j - k0 - g - q + b)]) : AT(0);
+#pragma unroll
+                for (int q = 0; q < BS_G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
+            }
             y[j] -= acc;
         }
         __syncthreads();

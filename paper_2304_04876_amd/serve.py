@@ -17,7 +17,6 @@ runs in the library's kernels.
 """
 from __future__ import annotations
 
-import heapq
 import time
 from dataclasses import dataclass, field
 
@@ -86,15 +85,17 @@ class Server:
         self.device_bytes = B.gdsw_get_info(self.h)["device_bytes"] + 2 * 8 * n
 
     def _slots_for_budget(self, budget):
-        """Slots per operator that fit `budget` device bytes (0: four)."""
+        """Slots per operator that fit `budget` device bytes (0: four): the
+        footprint of one slot per operator is measured on a probe handle."""
         if not budget:
             return 4
-        per_slot = 0
-        for op in self.ops:
-            h = B.gdsw_analyze(op.A, op.part, op.n_parts, 1, None, B.gdsw_default_options(**self.opts))
-            B.gdsw_factor(h, self.stream)
-            per_slot += B.gdsw_get_info(h)["device_bytes"] + 2 * 8 * op.n
-            B.gdsw_destroy(h)
+        probe = B.gdsw_analyze_batch([(op.A, op.part, op.n_parts) for op in self.ops],
+                                     options=B.gdsw_default_options(**self.opts))
+        try:
+            B.gdsw_factor(probe, self.stream)
+            per_slot = B.gdsw_get_info(probe)["device_bytes"] + 2 * 8 * sum(op.n for op in self.ops)
+        finally:
+            B.gdsw_destroy(probe)
         return int(budget // per_slot)
 
     def close(self):

@@ -269,3 +269,41 @@ def test_gmres_poisson_ilu0_matches_cg_solution():
     x = spla.spsolve(pr.A.tocsc(), b)
     assert np.linalg.norm(host(xd) - x) <= 1e-6 * np.linalg.norm(x)
     g.close()
+
+
+@pytest.mark.parametrize("local,prec", [(B.LOCAL_ILU0, B.FP64), (B.LOCAL_ILU0, B.FP16), (B.LOCAL_EXACT, B.FP32)])
+def test_autotune_keeps_results(local, prec):
+    pr = P.poisson3d(24, 2)
+    say(f"[autotune] local={local} prec={prec}")
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=local, local_prec=prec,
+               basis_prec=B.FP64 if prec == B.FP64 else B.FP32)
+    r = dev(P.rhs_uniform(pr.n, 8))
+    z0 = torch.zeros_like(r)
+    g.apply(r, z0)
+    times = B.gdsw_autotune(g.h, reps=3)
+    info = g.info()
+    nv = 4 if local == B.LOCAL_ILU0 else 3
+    valid = [t for t in times[:nv] if t > 0]
+    assert valid and info["local_variant"] >= 0
+    assert times[info["local_variant"]] == min(valid)
+    assert info["gemv_variant"] in (0, 1)
+    z1 = torch.zeros_like(r)
+    g.apply(r, z1)
+    # every launch configuration computes each row in the same order
+    assert torch.equal(z0, z1)
+    g.close()
+
+
+def test_refactor_with_new_values():
+    pr = P.poisson3d(12, 3)
+    say("[refactor]")
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0)
+    r = dev(P.rhs_uniform(pr.n, 1))
+    z1 = torch.zeros_like(r)
+    g.apply(r, z1)
+    B.gdsw_refactor(g.h, 2.0 * pr.A.tocsr().data)
+    z2 = torch.zeros_like(r)
+    g.apply(r, z2)
+    # M^{-1} of 2A is half of M^{-1} of A (every step is linear in A's scale)
+    assert float((z2 - 0.5 * z1).abs().max()) <= 1e-13 * float(z1.abs().max())
+    g.close()

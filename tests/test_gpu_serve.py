@@ -1,0 +1,57 @@
+"""The serving loop: resident operators, continuous batching of requests that
+arrive while others run, and each result identical alone and in the mix."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from paper_2304_04876_amd import binding as B
+from paper_2304_04876_amd import problems as P
+from paper_2304_04876_amd import serve as SV
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_served_results_equal_alone():
+    print("[serve] 3 operators, 2 slots each, 24 requests", file=sys.stderr, flush=True)
+    ops = [P.poisson3d(12, 2), P.poisson3d(16, 2), P.poisson3d(10, 1)]
+    srv = SV.Server(ops, slots_per_op=2, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32,
+                    step_iters=2)
+    t, opi = SV.poisson_arrivals(24, 400.0, len(ops), seed=3)
+    reqs = [SV.Request(rid=i, op=int(opi[i]), arrival=float(t[i]), b=P.rhs_uniform(ops[int(opi[i])].n, 100 + i))
+            for i in range(24)]
+    reqs, sols = srv.run(reqs, keep_solutions=True)
+    srv.close()
+    # requests overlapped on the device: some started while others ran
+    overlap = sum(1 for a in reqs for b in reqs if a.rid < b.rid and b.start < a.finish and a.start < b.finish)
+    assert overlap > 0
+    alone = [B.Gdsw(op.A, op.part, op.n_parts, 1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+             for op in ops]
+    for r in reqs:
+        assert r.status == 0 and r.rel_res_true <= 1.5e-8
+        bd = torch.from_numpy(r.b).cuda()
+        xd = torch.zeros_like(bd)
+        out = alone[r.op].solve(bd, xd, rtol=1e-8)
+        assert out["iterations"] == r.iterations
+        assert torch.equal(xd, sols[r.rid]), r.rid
+        # and the solution is the FP64 one to the accuracy the tolerance allows
+        x = spla.spsolve(ops[r.op].A.tocsc(), r.b)
+        assert np.linalg.norm(sols[r.rid].cpu().numpy() - x) <= 1e-6 * np.linalg.norm(x)
+    for g in alone:
+        g.close()
+
+
+def test_budget_admission():
+    ops = [P.poisson3d(10, 2), P.poisson3d(12, 2)]
+    # a budget that holds exactly one slot per operator
+    probe = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+    one = probe.device_bytes
+    probe.close()
+    srv = SV.Server(ops, hbm_budget_bytes=int(1.5 * one), local=B.LOCAL_ILU0, local_prec=B.FP16,
+                    basis_prec=B.FP32)
+    assert srv.slots_per_op == 1
+    srv.close()
+    with pytest.raises(B.GdswError):
+        SV.Server(ops, hbm_budget_bytes=1000, local=B.LOCAL_ILU0)
