@@ -115,6 +115,10 @@ def main():
     B.gdsw_factor(h, stream)
     info = B.gdsw_get_info(h)
     log(f"[bench] setup {info['t_factor']:.3f}s  n0={info['n0']}  device bytes={info['device_bytes'] / 1e9:.2f} GB")
+    tune_ms = B.gdsw_autotune(h, reps=5, stream=stream)
+    info = B.gdsw_get_info(h)
+    log(f"[bench] autotune (ms per launch) {[round(t, 4) for t in tune_ms]} -> local variant "
+        f"{info['local_variant']}, gemv variant {info['gemv_variant']}")
 
     nrhs = args.warmup + args.steps
     if elastic:
@@ -253,7 +257,8 @@ def main():
         "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30" if elastic
                                 else f"poisson{N}^3_P{Pn}^3_{args.local}_gdsw_cg"), "n": n,
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
-                   "jacobi_sweeps": 5, "local_prec": args.prec, "rtol": 1e-8},
+                   "jacobi_sweeps": 5, "local_prec": args.prec, "rtol": 1e-8,
+                   "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"]},
         "applies_per_sec": round(1e3 / apply_ms, 1),
         "apply_ms": round(apply_ms, 4),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),

@@ -718,7 +718,7 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         const int nbig = D.nb_big, nsmall = B.nb - nbig;
         if (D.phi32) {
             if (nbig)
-                hipLaunchKernelGGL((k_coarse_restrict_wg<256, float>), dim3(nbig), dim3(256), 0, s, r, D.blk_row_ptr,
+                hipLaunchKernelGGL((k_coarse_restrict_wg<512, float>), dim3(nbig), dim3(512), 0, s, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, 0, sk);
             if (nsmall)
                 hipLaunchKernelGGL(k_coarse_restrict_wave<float>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
@@ -726,7 +726,7 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
                                    D.partial, nbig, B.nb, sk);
         } else {
             if (nbig)
-                hipLaunchKernelGGL((k_coarse_restrict_wg<256, double>), dim3(nbig), dim3(256), 0, s, r, D.blk_row_ptr,
+                hipLaunchKernelGGL((k_coarse_restrict_wg<512, double>), dim3(nbig), dim3(512), 0, s, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, 0, sk);
             if (nsmall)
                 hipLaunchKernelGGL(k_coarse_restrict_wave<double>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,

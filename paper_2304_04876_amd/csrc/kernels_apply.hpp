@@ -188,8 +188,10 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
 // ---------------------------------------------------------------------------
 // Exact local solve A_i^{-1} r_i with the banded Cholesky factor, one
 // workgroup per subdomain, vector in LDS, gather and scatter fused.
+// (compiled for up to 1024 threads whatever NT is: that register budget
+// keeps the unrolled triangle solve from spilling)
 template <int NT, typename VT>
-__global__ __launch_bounds__(NT) void k_band_apply(
+__global__ __launch_bounds__(1024) void k_band_apply(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
     const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
@@ -238,11 +240,21 @@ __global__ __launch_bounds__(NT) void k_coarse_restrict_wg(
         double acc[KB];
 #pragma unroll
         for (int s = 0; s < KB; ++s) acc[s] = 0.0;
-        for (int l = threadIdx.x; l < nr; l += NT) {
-            const double x = r[rows[r0 + l]];
+        // rows in pairs so that the loads of two rows are in flight together
+        int l = threadIdx.x;
+        for (; l + NT < nr; l += 2 * NT) {
+            const double x0 = r[rows[r0 + l]], x1 = r[rows[r0 + l + NT]];
 #pragma unroll
             for (int s = 0; s < KB; ++s)
-                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x;
+                if (s0 + s < k)
+                    acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x0 +
+                              double(to_acc(Bg[int64_t(s0 + s) * nr + l + NT])) * x1;
+        }
+        if (l < nr) {
+            const double x0 = r[rows[r0 + l]];
+#pragma unroll
+            for (int s = 0; s < KB; ++s)
+                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x0;
         }
 #pragma unroll
         for (int s = 0; s < KB; ++s) {

@@ -20,7 +20,7 @@ struct KState {
 enum { KS_RUNNING = 0, KS_CONVERGED = 1, KS_MAXIT = 2, KS_BREAKDOWN = 3, KS_IDLE = 4 };
 
 constexpr int KNT = 256;
-constexpr int KROWS = 2048;   // rows per workgroup of the reducing kernels
+constexpr int KROWS = 256;    // rows per workgroup of the Krylov kernels (one row per thread)
 
 // Row blocks of the Krylov kernels.  Block b covers rows [row0[b], row1[b])
 // of problem prob[b]; the blocks of a problem are consecutive, so the

@@ -139,7 +139,7 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
 // ---------------------------------------------------------------------------
 // Banded Cholesky A = L L^T of one symmetric positive definite matrix per
 // workgroup, in place in FP64.  Row-major band storage: row r holds columns
-// r-b .. r at band[r*(b+1) + (c - r + b)].  Blocked right-looking algorithm
+// r-b .. r at band[r*(b+1) + (c - r + b)]; the diagonal slot holds 1/L_rr.  Blocked right-looking algorithm
 // with panels of NB columns: factor the diagonal block in LDS, solve the
 // rows below it (at most b of them), then update the (at most b x b) window
 // below the panel.  The fill of a banded Cholesky factor stays inside the
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_band_chol(double *__restrict__ band, con
         for (int e = tid; e < kb * kb; e += NT) {
             const int t = e / kb, s = e % kb;
             if (s <= t && t - s <= b)
-                L[int64_t(k0 + t) * w + (s - t + b)] = (s == t) ? sdg[t] : sD[t * CH_LD + s];
+                L[int64_t(k0 + t) * w + (s - t + b)] = (s == t) ? 1.0 / sdg[t] : sD[t * CH_LD + s];
         }
         // (b) rows below the diagonal block: P <- P L_D^{-T}
         const int rbeg = k0 + kb;
@@ -243,96 +243,139 @@ __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int
 }
 
 // ---------------------------------------------------------------------------
-// Band triangular solves with one LDS vector: y <- (L L^T)^{-1} y.
-// Forward: blocks of BS_NB rows; the diagonal triangle is solved by wavefront 0
-// (lanes = rows, the solved value broadcast with a shuffle), then the rows
-// that couple to the block (at most b below it) are updated, one thread per
-// row reading its contiguous band segment.  Backward: the same blocks in
-// reverse; the transposed triangle by wavefront 0, then the entries above the
-// block are updated one thread per column, reading band rows of the block
-// (consecutive threads, consecutive addresses).
-constexpr int BS_NB = 64;   // rows per block = lanes of the wavefront that solves the triangle
+// Band triangular solves with one LDS vector: y <- (L L^T)^{-1} y, L in the
+// band layout above (reciprocal diagonal).  Blocks of 64 rows, two barriers
+// per block:
+//   forward, step of block k: every thread subtracts block k's contribution
+//   from one row below it (its 64-value band segment, loads issued in
+//   groups), and the workgroup stages block k+1's triangle in LDS; then
+//   wavefront 0 solves block k+1 (lane t = row t), broadcasting each solved
+//   value with a lane read;
+//   backward (L^T z = y) is the mirror image by columns: the entries above
+//   block k get its contribution (column j of the block's rows: consecutive
+//   threads, consecutive addresses), and wavefront 0 solves block k-1's
+//   transposed triangle (lane t = column t).
+constexpr int BS_NB = 64;
 constexpr int BS_LD = BS_NB + 1;
+
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// sT(t, s) = L(k0+t, k0+s) for s < t, 1/L(k0+t, k0+t) for s = t (all threads)
+template <typename VT, typename AT, int NT>
+__device__ __forceinline__ void band_stage_triangle(const VT *__restrict__ L, int64_t w, int b, int k0, int kb,
+                                                    AT *sT) {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < BS_NB * BS_NB; e += NT) {
+        const int t = e / BS_NB, s = e % BS_NB;
+        AT v = 0;
+        if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
+        sT[t * BS_LD + s] = v;
+    }
+}
+
+template <typename AT>
+__device__ __forceinline__ void band_block_fwd(const AT *sT, AT *y, int k0, int kb, int lane) {
+    AT yt = lane < kb ? y[k0 + lane] : AT(0);
+    const AT *row = sT + lane * BS_LD;
+#pragma unroll 8
+    for (int s = 0; s < BS_NB; ++s) {
+        if (s < kb) {
+            const AT l = row[s];
+            if (lane == s) yt *= l;
+            const AT ys = lane_read(yt, s);
+            if (lane > s) yt -= l * ys;
+        }
+    }
+    if (lane < kb) y[k0 + lane] = yt;
+}
+
+template <typename AT>
+__device__ __forceinline__ void band_block_bwd(const AT *sT, AT *y, int k0, int kb, int lane) {
+    AT yt = lane < kb ? y[k0 + lane] : AT(0);
+#pragma unroll 8
+    for (int s = BS_NB - 1; s >= 0; --s) {
+        if (s < kb) {
+            const AT l = sT[s * BS_LD + lane];   // L(k0+s, k0+lane), or the reciprocal pivot at s = lane
+            if (lane == s) yt *= l;
+            const AT zs = lane_read(yt, s);
+            if (lane < s) yt -= l * zs;
+        }
+    }
+    if (lane < kb) y[k0 + lane] = yt;
+}
 
 template <typename VT, typename AT, int NT>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
-    constexpr int BS_G = sizeof(AT) == 8 ? 16 : 32;   // loads in flight per thread and group
+    constexpr int G = sizeof(AT) == 8 ? 8 : 32;   // loads in flight per thread and group
     const int64_t w = b + 1;
-    const int tid = threadIdx.x;
-    for (int k0 = 0; k0 < n; k0 += BS_NB) {
-        const int kb = min(BS_NB, n - k0);
-        for (int e = tid; e < BS_NB * BS_NB; e += NT) {
-            const int t = e / BS_NB, s = e % BS_NB;
-            AT v = 0;
-            if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
-            sT[t * BS_LD + s] = v;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            AT yt = (tid < kb) ? y[k0 + tid] : AT(0);
-            for (int s = 0; s < kb; ++s) {
-                if (tid == s) yt = yt / sT[s * BS_LD + s];
-                const AT ys = __shfl(yt, s, 64);
-                if (tid > s && tid < kb) yt -= sT[tid * BS_LD + s] * ys;
-            }
-            if (tid < kb) y[k0 + tid] = yt;
-        }
-        __syncthreads();
-        const int rend = min(n, k0 + kb + b);
-        for (int r = k0 + kb + tid; r < rend; r += NT) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nblk = (n + BS_NB - 1) / BS_NB;
+    // ---- forward
+    band_stage_triangle<VT, AT, NT>(L, w, b, 0, min(BS_NB, n), sT);
+    __syncthreads();
+    if (tid < 64) band_block_fwd(sT, y, 0, min(BS_NB, n), lane);
+    __syncthreads();
+    for (int blk = 0; blk + 1 < nblk; ++blk) {
+        const int k0 = blk * BS_NB, kb = BS_NB;       // every block but the last is full
+        const int k1 = k0 + BS_NB, kb1 = min(BS_NB, n - k1);
+        const int rend = min(n, k1 + b);
+        for (int r = k1 + tid; r < rend; r += NT) {
             const int s0 = max(0, r - b - k0);
             const VT *row = L + int64_t(r) * w + (k0 - r + b);
-            // the loads of a group of the row segment are issued before its sums
             AT acc = 0;
 #pragma unroll 1
-            for (int g = 0; g < BS_NB; g += BS_G) {
-                AT v[BS_G];
+            for (int g = 0; g < BS_NB; g += G) {
+                AT v[G];
 #pragma unroll
-                for (int q = 0; q < BS_G; ++q)
-                    v[q] = (g + q >= s0 && g + q < kb) ? to_acc(row[g + q]) : AT(0);
+                for (int q = 0; q < G; ++q) v[q] = (g + q >= s0) ? to_acc(row[g + q]) : AT(0);
 #pragma unroll
-                for (int q = 0; q < BS_G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
+                for (int q = 0; q < G; ++q) acc += v[q] * y[k0 + g + q];
             }
             y[r] -= acc;
         }
+        band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
+        __syncthreads();
+        if (tid < 64) band_block_fwd(sT, y, k1, kb1, lane);
+        __syncthreads();
+        (void)kb;
+    }
+    // ---- backward
+    {
+        const int k0 = (nblk - 1) * BS_NB, kb = n - k0;
+        band_stage_triangle<VT, AT, NT>(L, w, b, k0, kb, sT);
+        __syncthreads();
+        if (tid < 64) band_block_bwd(sT, y, k0, kb, lane);
         __syncthreads();
     }
-    const int nblk = (n + BS_NB - 1) / BS_NB;
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int k0 = bi * BS_NB;
-        const int kb = min(BS_NB, n - k0);
-        for (int e = tid; e < BS_NB * BS_NB; e += NT) {
-            const int t = e / BS_NB, s = e % BS_NB;
-            AT v = 0;
-            if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
-            sT[t * BS_LD + s] = v;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            AT yt = (tid < kb) ? y[k0 + tid] : AT(0);
-            for (int s = kb - 1; s >= 0; --s) {
-                if (tid == s) yt = yt / sT[s * BS_LD + s];
-                const AT zs = __shfl(yt, s, 64);
-                if (tid < s) yt -= sT[s * BS_LD + tid] * zs;
-            }
-            if (tid < kb) y[k0 + tid] = yt;
-        }
-        __syncthreads();
+    for (int blk = nblk - 1; blk > 0; --blk) {
+        const int k0 = blk * BS_NB, kb = min(BS_NB, n - k0);
+        const int p0 = k0 - BS_NB;
         const int jbeg = max(0, k0 - b);
         for (int j = jbeg + tid; j < k0; j += NT) {
             const int smax = min(kb, j + b - k0 + 1);
+            const VT *col = L + int64_t(k0) * w + (j - k0 + b);   // entry s at col[s * (w - 1)]
             AT acc = 0;
 #pragma unroll 1
-            for (int g = 0; g < BS_NB; g += BS_G) {
-                AT v[BS_G];
+            for (int g = 0; g < BS_NB; g += G) {
+                AT v[G];
 #pragma unroll
-                for (int q = 0; q < BS_G; ++q)
-                    v[q] = (g + q < smax) ? to_acc(L[int64_t(k0 + g + q) * w + (j - k0 - g - q + b)]) : AT(0);
+                for (int q = 0; q < G; ++q) v[q] = (g + q < smax) ? to_acc(col[int64_t(g + q) * (w - 1)]) : AT(0);
 #pragma unroll
-                for (int q = 0; q < BS_G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
+                for (int q = 0; q < G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
             }
             y[j] -= acc;
         }
+        band_stage_triangle<VT, AT, NT>(L, w, b, p0, BS_NB, sT);
+        __syncthreads();
+        if (tid < 64) band_block_bwd(sT, y, p0, BS_NB, lane);
         __syncthreads();
     }
 }
@@ -370,7 +413,7 @@ __global__ void k_ext_rhs(const double *__restrict__ Aval, const int64_t *__rest
 // hand side at a time through LDS, written into the subdomain's interior
 // block of Phi.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_ext_solve(const double *__restrict__ iband,
+__global__ __launch_bounds__(1024) void k_ext_solve(const double *__restrict__ iband,
                                                   const int64_t *__restrict__ iband_off,
                                                   const int32_t *__restrict__ ibw,
                                                   const int64_t *__restrict__ int_ptr,
