@@ -27,8 +27,10 @@ Steps, in the order of the paper's construction:
   O9  energy-minimising extension, eq. (2), with A_II block diagonal
   O10 coarse matrix A_0 = Phi^T A Phi (the paper prints Phi A Phi^T; only
       Phi^T A Phi has the right shape for eq. (1))
-  O11 local factors: exact (sparse LU, a library primitive) or ILU(0)
-      (Sec. V-B, "Incomplete Local Solver")
+  O11 local factors: exact (sparse LU, a library primitive) or level-based
+      ILU(k) (Sec. V-B, "Incomplete Local Solver"; k = 0 by default, Sec.
+      VII-C varies it), computed exactly (row by row) or by the iterative
+      FastILU variant (Jacobi sweeps on the factor entries, Sec. V-B)
   O12 coarse factor: dense Cholesky
   O13 apply, eq. (1); with ILU(0) the two triangular solves are done by
       Jacobi sweeps from a zero start (Sec. V-B: five iterations by default)
@@ -54,9 +56,9 @@ _LIB = None
 
 
 def build_c(force: bool = False) -> str:
-    """Compile the oracle's plain C helpers (ILU(0)) with gcc."""
+    """Compile the oracle's plain C helpers (incomplete LU) with gcc."""
     so = os.path.join(_HERE, "liboracle.so")
-    src = os.path.join(_HERE, "ilu0.c")
+    src = os.path.join(_HERE, "ilu.c")
     if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
         tmp = so + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src])
@@ -71,6 +73,9 @@ def _lib():
         _LIB.oracle_ilu0.restype = ctypes.c_int
         _LIB.oracle_ilu0.argtypes = [ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]
+        _LIB.oracle_iluk_pattern.restype = ctypes.c_int64
+        _LIB.oracle_iluk_pattern.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
     return _LIB
 
 
@@ -212,13 +217,17 @@ class GDSW:
     coarse space of eq. (2), built plainly in FP64.
 
     local = "exact" uses a sparse direct solve of every A_i; local = "ilu0"
-    uses ILU(0) of A_i in its natural (ascending global dof) order with the
-    two triangular solves replaced by ``sweeps`` undamped Jacobi sweeps each,
-    from a zero start.  coarse = False drops the coarse term (one level).
+    uses ILU(k) (k = ``ilu_level``, 0 by default) of A_i in its natural
+    (ascending global dof) order with the two triangular solves replaced by
+    ``sweeps`` undamped Jacobi sweeps each, from a zero start; the factors
+    are exact ILU(k) factors, or with ``factor_sweeps`` > 0 the FastILU
+    approximation after that many sweeps.  coarse = False drops the coarse
+    term (one level).
     """
 
     def __init__(self, A, part, dpn: int, n_parts: int, Z=None, overlap: int = 1,
-                 coarse: bool = True, local: str = "exact", sweeps: int = 5):
+                 coarse: bool = True, local: str = "exact", sweeps: int = 5,
+                 ilu_level: int = 0, factor_sweeps: int = 0):
         self.A = sp.csr_matrix(A, dtype=np.float64)
         self.A.sort_indices()
         self.n = self.A.shape[0]
@@ -228,6 +237,8 @@ class GDSW:
         self.overlap = int(overlap)
         self.local = local
         self.sweeps = int(sweeps)
+        self.ilu_level = int(ilu_level)
+        self.factor_sweeps = int(factor_sweeps)
         self.use_coarse = bool(coarse)
         if Z is None:
             Z = np.ones((self.n, 1))
@@ -256,7 +267,10 @@ class GDSW:
             if self.local == "exact":
                 self.local_solvers.append(spla.splu(Ai.tocsc()))
             elif self.local == "ilu0":
-                self.local_solvers.append(ilu0_factors(Ai))
+                if self.ilu_level == 0 and self.factor_sweeps == 0:
+                    self.local_solvers.append(ilu0_factors(Ai))
+                else:
+                    self.local_solvers.append(ilu_factors(Ai, self.ilu_level, self.factor_sweeps))
             else:
                 raise ValueError(self.local)
 
@@ -385,6 +399,97 @@ def ilu0_factors(Ai: sp.csr_matrix) -> ILU0:
     if rc != 0:
         raise np.linalg.LinAlgError(f"ILU(0) breakdown (code {rc})")
     F = sp.csr_matrix((val, col, rowptr), shape=M.shape)
+    NL = sp.tril(F, k=-1, format="csr")
+    NU = sp.triu(F, k=1, format="csr")
+    return ILU0(NL, NU, F.diagonal().copy())
+
+
+def iluk_pattern(Ai: sp.csr_matrix, level: int):
+    """The ILU(level) pattern of A_i (level-of-fill rule, plain C): returns
+    the CSR matrix holding A_i's values on that pattern (0 at fill entries)
+    and the level of every entry."""
+    M = sp.csr_matrix(Ai, dtype=np.float64, copy=True)
+    M.sort_indices()
+    n = M.shape[0]
+    rowptr = np.ascontiguousarray(M.indptr, dtype=np.int64)
+    col = np.ascontiguousarray(M.indices, dtype=np.int32)
+    cap = max(4 * col.size, 16)
+    while True:
+        orp = np.zeros(n + 1, dtype=np.int64)
+        oc = np.zeros(cap, dtype=np.int32)
+        ol = np.zeros(cap, dtype=np.int32)
+        nnz = _lib().oracle_iluk_pattern(n, rowptr.ctypes.data, col.ctypes.data, int(level),
+                                         orp.ctypes.data, oc.ctypes.data, ol.ctypes.data, cap)
+        if nnz == -2:
+            raise MemoryError("ILU(k) pattern")
+        if nnz >= 0:
+            break
+        cap = -nnz
+    oc, ol = oc[:nnz], ol[:nnz]
+    P = sp.csr_matrix((np.ones(nnz), oc, orp), shape=M.shape)
+    # A's values on the pattern: positions of A's entries inside it
+    vals = np.zeros(nnz)
+    for i in range(n):
+        cols = oc[orp[i]:orp[i + 1]]
+        k = np.searchsorted(cols, col[rowptr[i]:rowptr[i + 1]])
+        vals[orp[i] + k] = M.data[rowptr[i]:rowptr[i + 1]]
+    P.data = vals
+    return P, ol
+
+
+def fastilu_sweeps(P: sp.csr_matrix, sweeps: int) -> sp.csr_matrix:
+    """FastILU: the incomplete factors on the pattern of P (which holds the
+    values a_ij of A there, 0 at fill) approximated by Jacobi sweeps over
+    the factor entries (Sec. V-B, iterative variants).  Every sweep computes
+    each entry from the previous sweep's values:
+        i > j:  l_ij = (a_ij - sum_{m<j} l_im u_mj) / u_jj
+        i <= j: u_ij =  a_ij - sum_{m<i} l_im u_mj
+    (sums over the m with (i, m) and (m, j) in the pattern, ascending m).
+    Start (a reading; the paper names no initial guess): l_ij = a_ij / a_jj,
+    u_ij = a_ij, i.e. the lower and upper parts of A.  The result holds the
+    strictly lower entries of the unit-lower L and the entries of U."""
+    n = P.shape[0]
+    ip, ix, a = P.indptr, P.indices, P.data
+    where = [dict(zip(ix[ip[i]:ip[i + 1]].tolist(), range(ip[i], ip[i + 1]))) for i in range(n)]
+    dpos = np.array([where[i][i] for i in range(n)])
+    v = a.copy()
+    for i in range(n):
+        for e in range(ip[i], ip[i + 1]):
+            if ix[e] < i:
+                v[e] = a[e] / a[dpos[ix[e]]]
+    for _ in range(sweeps):
+        new = np.empty_like(v)
+        for i in range(n):
+            for e in range(ip[i], ip[i + 1]):
+                j = int(ix[e])
+                lim = min(i, j)
+                acc = a[e]
+                for f in range(ip[i], ip[i + 1]):
+                    m = int(ix[f])
+                    if m >= lim:
+                        break
+                    g = where[m].get(j)
+                    if g is not None:
+                        acc -= v[f] * v[g]
+                new[e] = acc / v[dpos[j]] if i > j else acc
+        v = new
+    return sp.csr_matrix((v, ix.copy(), ip.copy()), shape=P.shape)
+
+
+def ilu_factors(Ai: sp.csr_matrix, level: int = 0, factor_sweeps: int = 0) -> ILU0:
+    """ILU(level) of A_i, rows in the given order: exact (row by row, plain
+    C) when factor_sweeps == 0, else FastILU after factor_sweeps sweeps."""
+    P, _ = iluk_pattern(Ai, level)
+    if factor_sweeps > 0:
+        F = fastilu_sweeps(P, factor_sweeps)
+    else:
+        rowptr = np.ascontiguousarray(P.indptr, dtype=np.int64)
+        col = np.ascontiguousarray(P.indices, dtype=np.int32)
+        val = np.ascontiguousarray(P.data, dtype=np.float64)
+        rc = _lib().oracle_ilu0(P.shape[0], rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+        if rc != 0:
+            raise np.linalg.LinAlgError(f"ILU({level}) breakdown (code {rc})")
+        F = sp.csr_matrix((val, col, rowptr), shape=P.shape)
     NL = sp.tril(F, k=-1, format="csr")
     NU = sp.triu(F, k=1, format="csr")
     return ILU0(NL, NU, F.diagonal().copy())

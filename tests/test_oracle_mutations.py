@@ -95,3 +95,68 @@ def test_mutant_cg_beta(monkeypatch):
             return M.apply(r) * (1.0 if self.k % 2 else 3.0) + 0.1 * r
     bad = O.pcg(pr.A, b, Bad(), 1e-12, maxit=60)
     assert np.linalg.norm(bad.x - x) > 1e-9 * np.linalg.norm(x) or bad.iters > good.iters
+
+
+# ---- FastILU and ILU(k) mutants: each must trip an ILU pin ---------------------
+
+def _mutant_fastilu(mode):
+    import scipy.sparse as sp
+
+    def sweeps_fn(Pm, sweeps):
+        n = Pm.shape[0]
+        ip, ix, a = Pm.indptr, Pm.indices, Pm.data
+        where = [dict(zip(ix[ip[i]:ip[i + 1]].tolist(), range(ip[i], ip[i + 1]))) for i in range(n)]
+        dpos = np.array([where[i][i] for i in range(n)])
+        v = a.copy()
+        for i in range(n):
+            for e in range(ip[i], ip[i + 1]):
+                if ix[e] < i:
+                    v[e] = 0.0 if mode == "zero_start" else a[e] / a[dpos[ix[e]]]
+        for _ in range(sweeps):
+            new = v if mode == "in_place" else np.empty_like(v)
+            for i in range(n):
+                for e in range(ip[i], ip[i + 1]):
+                    j = int(ix[e])
+                    acc = a[e]
+                    for f in range(ip[i], ip[i + 1]):
+                        m = int(ix[f])
+                        if m >= min(i, j):
+                            break
+                        g = where[m].get(j)
+                        if g is not None:
+                            acc -= v[f] * v[g]
+                    divide = i > j and mode != "no_division"
+                    new[e] = acc / v[dpos[j]] if divide else acc
+            v = new
+        return sp.csr_matrix((v, ix.copy(), ip.copy()), shape=Pm.shape)
+    return sweeps_fn
+
+
+def _ilu_pins_fail():
+    from tests import test_oracle_ilu_pins as T
+    failures = 0
+    for fn in (T.test_fastilu_tridiagonal_propagation, T.test_fastilu_first_sweep_by_hand,
+               lambda: T.test_fastilu_fixed_point_is_ilu(1)):
+        try:
+            fn()
+        except AssertionError:
+            failures += 1
+    return failures
+
+
+def test_fastilu_pins_pass_unmutated():
+    assert _ilu_pins_fail() == 0
+
+
+@pytest.mark.parametrize("mode", ["in_place", "no_division", "zero_start"])
+def test_mutant_fastilu(monkeypatch, mode):
+    monkeypatch.setattr(O, "fastilu_sweeps", _mutant_fastilu(mode))
+    assert _ilu_pins_fail() > 0
+
+
+def test_mutant_iluk_without_fill(monkeypatch):
+    from tests import test_oracle_ilu_pins as T
+    real = O.iluk_pattern
+    monkeypatch.setattr(O, "iluk_pattern", lambda A, level: real(A, 0))
+    with pytest.raises(AssertionError):
+        T.test_ilu1_fill_of_the_7point_stencil()
