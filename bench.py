@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--ilu-level", type=int, default=0)
+    ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,7 +111,8 @@ def main():
     t0 = time.perf_counter()
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                        B.gdsw_default_options(local=local, local_prec=precs[args.prec],
-                                              basis_prec=B.FP64 if args.prec == "fp64" else B.FP32))
+                                              basis_prec=B.FP64 if args.prec == "fp64" else B.FP32,
+                                              ilu_level=args.ilu_level, ilu_factor_sweeps=args.factor_sweeps))
     t_an = time.perf_counter() - t0
     log(f"[bench] analysis {t_an:.2f}s; numerical setup on the GPU")
     B.gdsw_factor(h, stream)
@@ -185,6 +188,21 @@ def main():
         times.append(e0.elapsed_time(e1) / (reps // 5))
     apply_ms = float(np.median(times))
 
+    # ---- elasticity: error against the FP64 oracle (sampled) -------------------------
+    err = None
+    if elastic and (N, Pn) == (48, 6):
+        gold = np.load(os.path.join(ROOT, "tests", "golden", "elasticity_oracle.npz"))
+        idx = torch.from_numpy(gold["idx"]).to(dev)
+        xe = torch.zeros_like(r)
+        oe = B.gdsw_solve(h, rhs[0], xe, krylov=krylov, restart=30, rtol=1e-8, maxit=2000, stream=stream)
+        torch.cuda.synchronize()
+        err = {"apply_rel": float(np.abs(z_eager[idx].cpu().numpy() - gold["z"]).max() / float(gold["z_norm"])),
+               "solution_rel": float(np.abs(xe[idx].cpu().numpy() - gold["x_gm"]).max() / float(gold["x_norm"])),
+               "iterations": int(oe["iterations"]), "oracle_iterations": int(gold["gm_iters"]),
+               "sample": "4096 seeded dofs; max-norm error relative to the oracle's max-norm; the oracle's "
+                         "FP64 GMRES(30) solution to 1e-8 with the assembled load"}
+        log(f"[bench] error vs oracle {err}")
+
     # ---- dominant kernel: the batched local solves, timed alone ---------------------
     kreps = args.kernel_reps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -223,7 +241,8 @@ def main():
         from threadpoolctl import threadpool_limits
         from oracle import gdsw_oracle as O
         with threadpool_limits(limits=1):
-            M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local=args.local)
+            M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local=args.local, ilu_level=args.ilu_level,
+                       factor_sweeps=args.factor_sweeps)
             b0 = rhs[args.warmup].cpu().numpy()
             t0 = time.perf_counter()
             if elastic:
@@ -241,6 +260,9 @@ def main():
                 log(f"[bench] WARNING: GPU iterations {gpu_it} vs oracle {res.iters}")
 
     ms_per_step = 1e3 * wall / args.steps
+    local_name = args.local
+    if args.local == "ilu0" and (args.ilu_level or args.factor_sweeps):
+        local_name = f"ilu{args.ilu_level}" + (f"_fast{args.factor_sweeps}" if args.factor_sweeps else "")
     line = {
         "metric": "GDSW-PCG solves/sec and M^-1 applies/sec at 1e-8 residual; p50/p99 solve latency",
         "value": round(solves_per_s, 3),
@@ -255,9 +277,10 @@ def main():
         "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
         "data": "synthetic",
         "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30" if elastic
-                                else f"poisson{N}^3_P{Pn}^3_{args.local}_gdsw_cg"), "n": n,
+                                else f"poisson{N}^3_P{Pn}^3_{local_name}_gdsw_cg"), "n": n,
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
-                   "jacobi_sweeps": 5, "local_prec": args.prec, "rtol": 1e-8,
+                   "jacobi_sweeps": 5, "ilu_level": args.ilu_level, "ilu_factor_sweeps": args.factor_sweeps,
+                   "local_prec": args.prec, "rtol": 1e-8,
                    "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"]},
         "applies_per_sec": round(1e3 / apply_ms, 1),
         "apply_ms": round(apply_ms, 4),
@@ -270,6 +293,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if err is not None:
+        line["error_vs_oracle"] = err
     print(json.dumps(line), flush=True)
     B.gdsw_destroy(h)
 

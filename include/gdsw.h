@@ -78,6 +78,14 @@ typedef struct {
     int32_t basis_prec;       /* GDSW_FP64 / FP32 (storage of Phi)                */
     int64_t hbm_budget_bytes; /* device bytes the handle may allocate; 0 = no cap */
     uint64_t flags;           /* reserved, must be 0                              */
+    int32_t ilu_level;        /* GDSW_LOCAL_ILU0 only: level of fill k of ILU(k)
+                                 (Sec. V-B, levels varied in Sec. VII-C); 0..8,
+                                 default 0                                         */
+    int32_t ilu_factor_sweeps;/* GDSW_LOCAL_ILU0 only: 0 = exact incomplete
+                                 factors (level-scheduled, row by row); s > 0 =
+                                 the iterative FastILU variant, s Jacobi sweeps
+                                 over the factor entries (Sec. V-B; the paper's
+                                 experiments use 3); default 0                    */
 } gdsw_options;
 
 /* Square sparse matrix in CSR form, HOST pointers: rowptr[n+1] (int64),
@@ -129,9 +137,13 @@ enum {
     GDSW_MAP_PHI_ROWPTR = 5,   /* int64 [n+1]: CSR of Phi (after gdsw_factor)     */
     GDSW_MAP_PHI_COL = 6,      /* int32 [phi_entries]                             */
     GDSW_MAP_PHI_VAL = 7,      /* FP64  [phi_entries]  (after gdsw_factor)        */
-    GDSW_MAP_A0 = 8            /* FP64  coarse matrix, row-major (after gdsw_factor): [n0*n0]
+    GDSW_MAP_A0 = 8,           /* FP64  coarse matrix, row-major (after gdsw_factor): [n0*n0]
                                   for one problem, the dense diagonal blocks one after
                                   another for a batch */
+    GDSW_MAP_LOCAL_ROWPTR = 9, /* int64 [sum_overlap_dofs+1]: CSR row pointers of the
+                                  local matrices' patterns (ILU(k) patterns with fill
+                                  for GDSW_LOCAL_ILU0), subdomains one after another */
+    GDSW_MAP_LOCAL_COL = 10    /* int32 [local entries]: local column indices        */
 };
 
 /* Fills `opt` with the paper's defaults: overlap 1, GDSW coarse space,

@@ -28,8 +28,9 @@ FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 KRYLOV_CG, KRYLOV_GMRES = 0, 1
 MAP_OV_PTR, MAP_OV_IDX, MAP_IS_GAMMA, MAP_COMP_OF_NODE, MAP_COMP_RANK = 0, 1, 2, 3, 4
 MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8
+MAP_LOCAL_ROWPTR, MAP_LOCAL_COL = 9, 10
 _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
-              5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64}
+              5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64, 9: np.int64, 10: np.int32}
 
 EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
             "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
@@ -42,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int32), ("coarse", ctypes.c_int32), ("local", ctypes.c_int32),
                 ("jacobi_sweeps", ctypes.c_int32), ("local_prec", ctypes.c_int32),
                 ("basis_prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
-                ("flags", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint64), ("ilu_level", ctypes.c_int32),
+                ("ilu_factor_sweeps", ctypes.c_int32)]
 
 
 class CSR(ctypes.Structure):

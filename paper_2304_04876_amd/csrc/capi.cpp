@@ -167,6 +167,8 @@ static int64_t map_count(gdsw_handle h, int32_t map) {
         case GDSW_MAP_PHI_COL:
         case GDSW_MAP_PHI_VAL: return S.blk.val_off.empty() ? 0 : S.blk.val_off.back();
         case GDSW_MAP_A0: return S.a0_off.empty() ? 0 : S.a0_off.back();
+        case GDSW_MAP_LOCAL_ROWPTR: return int64_t(S.lrowptr.size());
+        case GDSW_MAP_LOCAL_COL: return int64_t(S.lcol.size());
         default: return -1;
     }
 }
@@ -222,6 +224,12 @@ gdsw_status gdsw_copy_map(gdsw_handle h, int32_t map, void *out) {
         case GDSW_MAP_PHI_VAL:
         case GDSW_MAP_A0:
             return gdsw::copy_device_map(h, map, out);
+        case GDSW_MAP_LOCAL_ROWPTR:
+            std::memcpy(out, S.lrowptr.data(), 8 * S.lrowptr.size());
+            return GDSW_OK;
+        case GDSW_MAP_LOCAL_COL:
+            std::memcpy(out, S.lcol.data(), 4 * S.lcol.size());
+            return GDSW_OK;
         default:
             return GDSW_ERR_INVALID_ARG;
     }

@@ -107,6 +107,10 @@ struct Device {
     float *phi32 = nullptr;   // FP32 copy when basis_prec == FP32
     int64_t *red_ptr = nullptr;
     int32_t *red_idx = nullptr;
+    int64_t *blk_poff = nullptr;   // first restriction partial of every block
+    int32_t *tile_blk = nullptr, *tile_l0 = nullptr, *tile_l1 = nullptr;   // restriction tiles of the big blocks
+    int64_t *tile_poff = nullptr;
+    int ntiles = 0;
     int32_t *dof_blk = nullptr, *dof_lr = nullptr;
     double *partial = nullptr, *r0 = nullptr, *z0 = nullptr;
     double *A0 = nullptr;     // assembled coarse matrix
@@ -294,10 +298,37 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
         double *d_lval = D.alloc<double>(ne);
         hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_lgpos,
                            (const int64_t *)nullptr, d_lval, ne, D.dscale, D.arow, D.col);
-        hipLaunchKernelGGL(k_ilu0_factor, dim3(S.np), dim3(256), 0, s, D.ov_ptr, d_lrowptr, d_lcol, d_ldiag,
-                           d_lvl_base, d_lvl_ptr, d_lvl_rows, d_lval, d_status);
-        HIPCHK(hipGetLastError());
-        check_status(D, d_status, S.np, s, "ILU(0)");
+        if (S.opt.ilu_factor_sweeps > 0) {
+            // FastILU: sweeps over the factor entries from the start l = a/a_jj, u = a
+            double *d_a = D.alloc<double>(ne), *d_v = D.alloc<double>(ne);
+            int64_t *d_fptr = D.upload(S.fi_ptr, s);
+            int32_t *d_pairs = D.upload(S.fi_pairs, s);
+            int32_t *d_dpos = D.upload(S.fi_dpos, s);
+            HIPCHK(hipMemcpyAsync(d_a, d_lval, sizeof(double) * size_t(ne), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_fastilu_start, dim3(nblocks(ne, 256)), dim3(256), 0, s, d_a, d_dpos, d_lval, ne);
+            double *cur = d_lval, *nxt = d_v;
+            for (int k = 0; k < S.opt.ilu_factor_sweeps; ++k) {
+                hipLaunchKernelGGL(k_fastilu_sweep, dim3(nblocks(ne, 256)), dim3(256), 0, s, d_a, d_fptr, d_pairs,
+                                   d_dpos, cur, nxt, ne);
+                std::swap(cur, nxt);
+            }
+            if (cur != d_lval)
+                HIPCHK(hipMemcpyAsync(d_lval, cur, sizeof(double) * size_t(ne), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_ilu_pivot_check, dim3(S.np), dim3(256), 0, s, D.ov_ptr, d_lrowptr, d_ldiag, d_lval,
+                               d_status);
+            HIPCHK(hipGetLastError());
+            check_status(D, d_status, S.np, s, "FastILU");
+            D.release(d_a, sizeof(double) * ne);
+            D.release(d_v, sizeof(double) * ne);
+            D.release(d_fptr, sizeof(int64_t) * S.fi_ptr.size());
+            D.release(d_pairs, sizeof(int32_t) * S.fi_pairs.size());
+            D.release(d_dpos, sizeof(int32_t) * S.fi_dpos.size());
+        } else {
+            hipLaunchKernelGGL(k_ilu0_factor, dim3(S.np), dim3(256), 0, s, D.ov_ptr, d_lrowptr, d_lcol, d_ldiag,
+                               d_lvl_base, d_lvl_ptr, d_lvl_rows, d_lval, d_status);
+            HIPCHK(hipGetLastError());
+            check_status(D, d_status, S.np, s, "ILU");
+        }
         switch (prec) {
             case GDSW_FP64: pack_ilu<double>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
             case GDSW_FP32: pack_ilu<float>(h, d_lrowptr, d_lcol, d_ldiag, d_lval, s); break;
@@ -374,11 +405,58 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     D.blk_val_off = D.upload(B.val_off, s);
     D.blk_rows = D.upload(B.rows, s);
     D.blk_cols = D.upload(B.cols, s);
-    D.red_ptr = D.upload(S.red_ptr, s);
-    D.red_idx = D.upload(S.red_idx, s);
+    // restriction partials: block g has ntile(g) tiles of k(g) partials each
+    // (one tile unless it is a big block of more than RT_ROWS rows); the
+    // reduction of column c adds them by ascending block, then tile
+    {
+        std::vector<int64_t> poff(size_t(B.nb) + 1, 0);
+        std::vector<int32_t> ntile(size_t(B.nb), 1), tb, tl0, tl1;
+        std::vector<int64_t> tpo;
+        for (int g = 0; g < B.nb; ++g) {
+            const int64_t nr = B.row_ptr[g + 1] - B.row_ptr[g];
+            const int64_t k = B.col_ptr[g + 1] - B.col_ptr[g];
+            if (g < D.nb_big) {
+                const int64_t nt = std::max<int64_t>(1, (nr + RT_ROWS - 1) / RT_ROWS);
+                const int64_t per = (nr + nt - 1) / nt;
+                ntile[g] = int32_t(nt);
+                for (int64_t t = 0; t < nt; ++t) {
+                    tb.push_back(g);
+                    tl0.push_back(int32_t(std::min(nr, t * per)));
+                    tl1.push_back(int32_t(std::min(nr, (t + 1) * per)));
+                    tpo.push_back(poff[g] + t * k);
+                }
+            }
+            poff[g + 1] = poff[g] + int64_t(ntile[g]) * k;
+        }
+        if (poff[B.nb] >= (int64_t(1) << 31)) throw DevError{GDSW_ERR_INTERNAL, "too many restriction partials"};
+        std::vector<int32_t> qblk(B.cols.size());
+        for (int g = 0; g < B.nb; ++g)
+            for (int64_t q = B.col_ptr[g]; q < B.col_ptr[g + 1]; ++q) qblk[size_t(q)] = g;
+        std::vector<int64_t> rptr(size_t(n0) + 1, 0);
+        std::vector<int32_t> ridx;
+        ridx.reserve(size_t(poff[B.nb]));
+        for (int c = 0; c < n0; ++c) {
+            for (int64_t e = S.red_ptr[c]; e < S.red_ptr[c + 1]; ++e) {
+                const int64_t q = S.red_idx[size_t(e)];
+                const int g = qblk[size_t(q)];
+                const int64_t k = B.col_ptr[g + 1] - B.col_ptr[g], sidx = q - B.col_ptr[g];
+                for (int t = 0; t < ntile[g]; ++t) ridx.push_back(int32_t(poff[g] + t * k + sidx));
+            }
+            rptr[c + 1] = int64_t(ridx.size());
+        }
+        D.red_ptr = D.upload(rptr, s);
+        D.red_idx = D.upload(ridx, s);
+        D.blk_poff = D.upload(poff, s);
+        D.ntiles = int(tb.size());
+        D.tile_blk = D.upload(tb, s);
+        D.tile_l0 = D.upload(tl0, s);
+        D.tile_l1 = D.upload(tl1, s);
+        D.tile_poff = D.upload(tpo, s);
+        D.partial = D.alloc<double>(poff[B.nb]);
+        HIPCHK(hipStreamSynchronize(s));   // the host vectors above go out of scope
+    }
     D.dof_blk = D.upload(S.dof_blk, s);
     D.dof_lr = D.upload(S.dof_lr, s);
-    D.partial = D.alloc<double>(int64_t(B.cols.size()));
     D.r0 = D.alloc<double>(n0);
     D.z0 = D.alloc<double>(n0);
     const int64_t nphi = B.val_off[B.nb];
@@ -717,21 +795,23 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         // blocks with many rows (subdomain interiors) first, then the small ones
         const int nbig = D.nb_big, nsmall = B.nb - nbig;
         if (D.phi32) {
-            if (nbig)
-                hipLaunchKernelGGL((k_coarse_restrict_wg<512, float>), dim3(nbig), dim3(512), 0, s, r, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.partial, 0, sk);
+            if (D.ntiles)
+                hipLaunchKernelGGL(k_coarse_restrict_tile<float>, dim3(D.ntiles), dim3(RT_NT), 0, s, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.tile_blk,
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.partial, sk);
             if (nsmall)
                 hipLaunchKernelGGL(k_coarse_restrict_wave<float>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
                                    D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32,
-                                   D.partial, nbig, B.nb, sk);
+                                   D.blk_poff, D.partial, nbig, B.nb, sk);
         } else {
-            if (nbig)
-                hipLaunchKernelGGL((k_coarse_restrict_wg<512, double>), dim3(nbig), dim3(512), 0, s, r, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.partial, 0, sk);
+            if (D.ntiles)
+                hipLaunchKernelGGL(k_coarse_restrict_tile<double>, dim3(D.ntiles), dim3(RT_NT), 0, s, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.tile_blk,
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.partial, sk);
             if (nsmall)
                 hipLaunchKernelGGL(k_coarse_restrict_wave<double>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
                                    D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi,
-                                   D.partial, nbig, B.nb, sk);
+                                   D.blk_poff, D.partial, nbig, B.nb, sk);
         }
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);

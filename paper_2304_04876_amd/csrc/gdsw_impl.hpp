@@ -103,6 +103,11 @@ struct Symbolic {
     int32_t KL = 0, KU = 0;         // max strictly lower / upper entries per row
     std::vector<int64_t> ell_off;   // [np+1] padded row offsets
     int64_t ell_rows = 0;
+    // FastILU: per local entry its product pairs (positions into the local
+    // values, two int32 each) and the pivot position of a lower entry (-1)
+    std::vector<int64_t> fi_ptr;
+    std::vector<int32_t> fi_pairs;
+    std::vector<int32_t> fi_dpos;
 
     // ---- coarse space ---------------------------------------------------------------
     PhiBlocks blk;

@@ -219,49 +219,65 @@ __global__ __launch_bounds__(1024) void k_band_apply(
 }
 
 // ---------------------------------------------------------------------------
-// Coarse restriction Phi^T r, block by block: partial[col_ptr[g] + s] =
-// sum_l B_g(l, s) r[rows_g(l)], fixed reduction order.  Large blocks (the
-// interiors of subdomains) get a workgroup each, small ones (interface
-// components) a wavefront each; up to 8 columns per pass.
-template <int NT, typename PT>
-__global__ __launch_bounds__(NT) void k_coarse_restrict_wg(
+// Coarse restriction Phi^T r.  Each block B_g (rows_g x k_g, column-major)
+// contributes partial sums of its columns; a column's partials are added in
+// a fixed order by k_coarse_reduce.  Blocks of many rows (subdomain
+// interiors) are cut into tiles of at most 1024 rows, one 256-thread
+// workgroup per tile (4 rows per thread, every load of a pass issued before
+// the sums); small blocks (interface components) take a wavefront each.
+// Up to 8 columns per pass.
+constexpr int RT_NT = 256, RT_RPT = 4, RT_ROWS = RT_NT * RT_RPT;
+template <typename PT>
+__global__ __launch_bounds__(RT_NT) void k_coarse_restrict_tile(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    double *__restrict__ partial, int g0, Skip sk) {
-    const int g = g0 + blockIdx.x;
+    const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
+    const int64_t *__restrict__ tile_poff, double *__restrict__ partial, Skip sk) {
+    constexpr int KB = 8, NW = RT_NT / 64;
+    __shared__ double sh[KB][NW];
+    const int t = blockIdx.x;
+    const int g = tile_blk[t];
     if (sk.blk(g)) return;
-    __shared__ double sh[NT / 64];
     const int64_t r0 = row_ptr[g];
     const int nr = int(row_ptr[g + 1] - r0);
     const int k = int(col_ptr[g + 1] - col_ptr[g]);
+    const int l0 = tile_l0[t], l1 = tile_l1[t];
     const PT *Bg = phi + val_off[g];
-    constexpr int KB = 8;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double x[RT_RPT];
+#pragma unroll
+    for (int j = 0; j < RT_RPT; ++j) {
+        const int l = l0 + tid + j * RT_NT;
+        x[j] = l < l1 ? r[rows[r0 + l]] : 0.0;
+    }
     for (int s0 = 0; s0 < k; s0 += KB) {
+        double bv[KB][RT_RPT];
+#pragma unroll
+        for (int s = 0; s < KB; ++s)
+#pragma unroll
+            for (int j = 0; j < RT_RPT; ++j) {
+                const int l = l0 + tid + j * RT_NT;
+                bv[s][j] = (s0 + s < k && l < l1) ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
+            }
         double acc[KB];
 #pragma unroll
-        for (int s = 0; s < KB; ++s) acc[s] = 0.0;
-        // rows in pairs so that the loads of two rows are in flight together
-        int l = threadIdx.x;
-        for (; l + NT < nr; l += 2 * NT) {
-            const double x0 = r[rows[r0 + l]], x1 = r[rows[r0 + l + NT]];
-#pragma unroll
-            for (int s = 0; s < KB; ++s)
-                if (s0 + s < k)
-                    acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x0 +
-                              double(to_acc(Bg[int64_t(s0 + s) * nr + l + NT])) * x1;
-        }
-        if (l < nr) {
-            const double x0 = r[rows[r0 + l]];
-#pragma unroll
-            for (int s = 0; s < KB; ++s)
-                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x0;
-        }
-#pragma unroll
         for (int s = 0; s < KB; ++s) {
-            if (s0 + s >= k) break;
-            const double t = block_sum<double, NT>(acc[s], sh);
-            if (threadIdx.x == 0) partial[col_ptr[g] + s0 + s] = t;
+            acc[s] = 0.0;
+#pragma unroll
+            for (int j = 0; j < RT_RPT; ++j) acc[s] += bv[s][j] * x[j];
+            acc[s] = wave_sum(acc[s]);
         }
+        if (lane == 0)
+#pragma unroll
+            for (int s = 0; s < KB; ++s) sh[s][wv] = acc[s];
+        __syncthreads();
+        if (tid < KB && s0 + tid < k) {
+            double v = sh[tid][0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) v += sh[tid][w];
+            partial[tile_poff[t] + s0 + tid] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -269,7 +285,7 @@ template <typename PT>
 __global__ __launch_bounds__(256) void k_coarse_restrict_wave(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    double *__restrict__ partial, int g0, int nb, Skip sk) {
+    const int64_t *__restrict__ poff, double *__restrict__ partial, int g0, int nb, Skip sk) {
     const int g = g0 + blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= nb || sk.blk(g)) return;
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(256) void k_coarse_restrict_wave(
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
             const double t = wave_sum(acc[s]);
-            if (lane == 0 && s0 + s < k) partial[col_ptr[g] + s0 + s] = t;
+            if (lane == 0 && s0 + s < k) partial[poff[g] + s0 + s] = t;
         }
     }
 }
@@ -301,8 +317,17 @@ __global__ void k_coarse_reduce(const int64_t *__restrict__ red_ptr, const int32
                                 const double *__restrict__ partial, double *__restrict__ r0, int n0, Skip sk) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n0 || sk.col(c)) return;
+    constexpr int U = 8;
     double acc = 0.0;
-    for (int64_t q = red_ptr[c]; q < red_ptr[c + 1]; ++q) acc += partial[red_idx[q]];
+    const int64_t q1 = red_ptr[c + 1];
+    for (int64_t q0 = red_ptr[c]; q0 < q1; q0 += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = q0 + u < q1 ? partial[red_idx[q0 + u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (q0 + u < q1) acc += v[u];
+    }
     r0[c] = acc;
 }
 
@@ -319,8 +344,20 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
     const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
     const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
     const double *xk = x + c0;
+    constexpr int U = 8;
     double acc = 0.0;
-    for (int c = lane; c < nk; c += 64) acc += a[c] * xk[c];
+    for (int c0 = lane; c0 < nk; c0 += U * 64) {
+        double av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u * 64;
+            av[u] = c < nk ? a[c] : 0.0;
+            xv[u] = c < nk ? xk[c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c0 + u * 64 < nk) acc += av[u] * xv[u];
+    }
     acc = wave_sum(acc);
     if (lane == 0) y[row] = acc;
 }
@@ -337,8 +374,20 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
     const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
     const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
     const double *xk = x + c0;
+    constexpr int U = 4;
     double acc = 0.0;
-    for (int c = threadIdx.x; c < nk; c += 256) acc += a[c] * xk[c];
+    for (int c0 = threadIdx.x; c0 < nk; c0 += U * 256) {
+        double av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u * 256;
+            av[u] = c < nk ? a[c] : 0.0;
+            xv[u] = c < nk ? xk[c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c0 + u * 256 < nk) acc += av[u] * xv[u];
+    }
     acc = block_sum<double, 256>(acc, sh);
     if (threadIdx.x == 0) y[row] = acc;
 }
@@ -362,8 +411,20 @@ __device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_
             const int64_t c0 = col_ptr[g];
             const int k = int(col_ptr[g + 1] - c0);
             const PT *Bg = phi + val_off[g] + dof_lr[d];
+            // columns in chunks of 8, loads first, products added in order
+            constexpr int U = 8;
             double s = 0.0;
-            for (int q = 0; q < k; ++q) s += double(to_acc(Bg[q * nr])) * z0[cols[c0 + q]];
+            for (int q0 = 0; q0 < k; q0 += U) {
+                double bv[U], zv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    bv[u] = q0 + u < k ? double(to_acc(Bg[(q0 + u) * nr])) : 0.0;
+                    zv[u] = q0 + u < k ? z0[cols[c0 + q0 + u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (q0 + u < k) s += bv[u] * zv[u];
+            }
             acc += s;
         }
     }

@@ -36,9 +36,23 @@ struct KBlk {
 
 // Sum of partials [lo, hi) in index order, by one workgroup.
 __device__ __forceinline__ double sum_partials(const double *partial, int lo, int hi, double *sh) {
-    double v = 0.0;
-    for (int q = lo + int(threadIdx.x); q < hi; q += KNT) v += partial[q];
-    return block_sum<double, KNT>(v, sh);
+    // eight independent chains keep eight loads in flight per thread; the
+    // order depends only on hi - lo
+    constexpr int C = 8;
+    double v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = 0.0;
+    int q = lo + int(threadIdx.x);
+    for (; q + (C - 1) * KNT < hi; q += C * KNT) {
+        double a[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = partial[q + c * KNT];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] += a[c];
+    }
+    for (; q < hi; q += KNT) v[0] += partial[q];
+    const double t = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    return block_sum<double, KNT>(t, sh);
 }
 
 // A in sliced ELL form for the SpMV: slices of SELL_C consecutive rows, each
@@ -56,8 +70,26 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
     const int sl = i / SELL_C, lane = i % SELL_C;
     const int64_t base = A.off[sl] + lane;
     const int w = A.width[sl];
+    // slots in chunks of 8: all loads of a chunk are issued before the
+    // products are added (in slot order)
+    constexpr int U = 8;
     double acc = 0.0;
-    for (int j = 0; j < w; ++j) acc += A.val[base + int64_t(j) * SELL_C] * x[A.col[base + int64_t(j) * SELL_C]];
+    for (int j0 = 0; j0 < w; j0 += U) {
+        int c[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + int64_t(j0 + u) * SELL_C;
+            c[u] = j0 + u < w ? A.col[e] : 0;
+            v[u] = j0 + u < w ? A.val[e] : 0.0;
+        }
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = j0 + u < w ? x[c[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < w) acc += v[u] * xv[u];
+    }
     return acc;
 }
 

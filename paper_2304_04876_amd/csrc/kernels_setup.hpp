@@ -9,18 +9,63 @@
 namespace gdsw {
 
 // out[dst[p]] = val[src[p]] * (scale ? scale[row[src[p]]] * scale[col[src[p]]] : 1)
-// (dst == nullptr: out[p]).  Used to gather the local matrices A_i and
-// A_{I_i I_i} from A, optionally symmetrically diagonally scaled.
+// (dst == nullptr: out[p]; src[p] < 0: a fill entry, 0).  Used to gather the
+// local matrices A_i and A_{I_i I_i} from A, optionally symmetrically
+// diagonally scaled.
 __global__ void k_gather_vals(const double *__restrict__ val, const int64_t *__restrict__ src,
                               const int64_t *__restrict__ dst, double *__restrict__ out, int64_t cnt,
                               const double *__restrict__ scale, const int32_t *__restrict__ arow,
                               const int32_t *__restrict__ acol) {
     for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < cnt;
          p += int64_t(gridDim.x) * blockDim.x) {
-        int64_t s = src[p];
-        double v = val[s];
-        if (scale) v *= scale[arow[s]] * scale[acol[s]];
+        const int64_t s = src[p];
+        double v = 0.0;
+        if (s >= 0) {
+            v = val[s];
+            if (scale) v *= scale[arow[s]] * scale[acol[s]];
+        }
         out[dst ? dst[p] : p] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FastILU (Sec. V-B, iterative variant of the incomplete factorisation):
+// the entries of L (unit lower, strictly lower part stored) and U on the
+// local patterns are fixed points of
+//     l_ij = (a_ij - sum_{m<j} l_im u_mj) / u_jj   (i > j)
+//     u_ij =  a_ij - sum_{m<i} l_im u_mj           (i <= j)
+// and a sweep evaluates every entry from the previous sweep's values (one
+// thread per entry, product pairs precomputed in ascending m).  Start:
+// l_ij = a_ij / a_jj, u_ij = a_ij.
+__global__ void k_fastilu_start(const double *__restrict__ a, const int32_t *__restrict__ dpos,
+                                double *__restrict__ v, int64_t ne) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= ne) return;
+    const int32_t d = dpos[e];
+    v[e] = d >= 0 ? a[e] / a[d] : a[e];
+}
+
+__global__ void k_fastilu_sweep(const double *__restrict__ a, const int64_t *__restrict__ fptr,
+                                const int32_t *__restrict__ pairs, const int32_t *__restrict__ dpos,
+                                const double *__restrict__ vold, double *__restrict__ vnew, int64_t ne) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= ne) return;
+    double acc = a[e];
+    for (int64_t q = fptr[e]; q < fptr[e + 1]; ++q) acc -= vold[pairs[2 * q]] * vold[pairs[2 * q + 1]];
+    const int32_t d = dpos[e];
+    vnew[e] = d >= 0 ? acc / vold[d] : acc;
+}
+
+// status[i] = 1 + a local row of subdomain i whose pivot is zero or not
+// finite (after FastILU sweeps); 0 if there is none
+__global__ void k_ilu_pivot_check(const int64_t *__restrict__ ov_ptr, const int64_t *__restrict__ lrowptr,
+                                  const int32_t *__restrict__ ldiag, const double *__restrict__ v,
+                                  int *__restrict__ status) {
+    const int i = blockIdx.x;
+    const int64_t o = ov_ptr[i], ni = ov_ptr[i + 1] - o;
+    for (int64_t l = threadIdx.x; l < ni; l += blockDim.x) {
+        const double u = v[lrowptr[o + l] + ldiag[o + l]];
+        if (u == 0.0 || !isfinite(u)) atomicCAS(status + i, 0, int(1 + l));
     }
 }
 
@@ -246,9 +291,9 @@ __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int
 // Band triangular solves with one LDS vector: y <- (L L^T)^{-1} y, L in the
 // band layout above (reciprocal diagonal).  Blocks of 64 rows, two barriers
 // per block:
-//   forward, step of block k: every thread subtracts block k's contribution
-//   from one row below it (its 64-value band segment, loads issued in
-//   groups), and the workgroup stages block k+1's triangle in LDS; then
+//   forward, step of block k: block k's contribution is subtracted from the
+//   rows below it, 16 lanes per row reading the row's 64-value band segment
+//   side by side, and the workgroup stages block k+1's triangle in LDS; then
 //   wavefront 0 solves block k+1 (lane t = row t), broadcasting each solved
 //   value with a lane read;
 //   backward (L^T z = y) is the mirror image by columns: the entries above
@@ -314,7 +359,7 @@ __device__ __forceinline__ void band_block_bwd(const AT *sT, AT *y, int k0, int 
 
 template <typename VT, typename AT, int NT>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
-    constexpr int G = sizeof(AT) == 8 ? 8 : 32;   // loads in flight per thread and group
+    constexpr int G = sizeof(AT) == 8 ? 8 : 32;   // loads in flight per thread and group (backward)
     const int64_t w = b + 1;
     const int tid = threadIdx.x, lane = tid & 63;
     const int nblk = (n + BS_NB - 1) / BS_NB;
@@ -323,29 +368,41 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
     __syncthreads();
     if (tid < 64) band_block_fwd(sT, y, 0, min(BS_NB, n), lane);
     __syncthreads();
+    // rows below a solved block: 16 lanes per row, lane q takes the block's
+    // columns q, q+16, q+32, q+48 (consecutive lanes, consecutive addresses)
+    // and the 16 partial products are summed across the lanes
+    constexpr int LPR = 16, RPI = NT / LPR;
+    const int sub = tid & (LPR - 1), rg = tid / LPR;
     for (int blk = 0; blk + 1 < nblk; ++blk) {
-        const int k0 = blk * BS_NB, kb = BS_NB;       // every block but the last is full
+        const int k0 = blk * BS_NB;
         const int k1 = k0 + BS_NB, kb1 = min(BS_NB, n - k1);
         const int rend = min(n, k1 + b);
-        for (int r = k1 + tid; r < rend; r += NT) {
-            const int s0 = max(0, r - b - k0);
-            const VT *row = L + int64_t(r) * w + (k0 - r + b);
+        AT yq[BS_NB / LPR];
+#pragma unroll
+        for (int q = 0; q < BS_NB / LPR; ++q) yq[q] = y[k0 + sub + q * LPR];
+        for (int r0 = k1; r0 < rend; r0 += RPI) {
+            const int r = r0 + rg;
             AT acc = 0;
-#pragma unroll 1
-            for (int g = 0; g < BS_NB; g += G) {
-                AT v[G];
+            if (r < rend) {
+                const int s0 = max(0, r - b - k0);
+                const VT *row = L + int64_t(r) * w + (k0 - r + b);
+                AT v[BS_NB / LPR];
 #pragma unroll
-                for (int q = 0; q < G; ++q) v[q] = (g + q >= s0) ? to_acc(row[g + q]) : AT(0);
+                for (int q = 0; q < BS_NB / LPR; ++q) {
+                    const int s = sub + q * LPR;
+                    v[q] = s >= s0 ? to_acc(row[s]) : AT(0);
+                }
 #pragma unroll
-                for (int q = 0; q < G; ++q) acc += v[q] * y[k0 + g + q];
+                for (int q = 0; q < BS_NB / LPR; ++q) acc += v[q] * yq[q];
             }
-            y[r] -= acc;
+#pragma unroll
+            for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, LPR);
+            if (r < rend && sub == 0) y[r] -= acc;
         }
         band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
         __syncthreads();
         if (tid < 64) band_block_fwd(sT, y, k1, kb1, lane);
         __syncthreads();
-        (void)kb;
     }
     // ---- backward
     {

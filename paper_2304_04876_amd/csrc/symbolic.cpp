@@ -27,6 +27,7 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,8 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
     if (o.local_prec < GDSW_FP64 || o.local_prec > GDSW_FP16) fail(GDSW_ERR_INVALID_ARG, "local_prec");
     if (o.basis_prec != GDSW_FP64 && o.basis_prec != GDSW_FP32) fail(GDSW_ERR_INVALID_ARG, "basis_prec");
     if (o.flags != 0) fail(GDSW_ERR_INVALID_ARG, "flags must be 0");
+    if (o.ilu_level < 0 || o.ilu_level > 8) fail(GDSW_ERR_INVALID_ARG, "ilu_level out of range");
+    if (o.ilu_factor_sweeps < 0 || o.ilu_factor_sweeps > 100) fail(GDSW_ERR_INVALID_ARG, "ilu_factor_sweeps");
     if (Z == nullptr && n_null > 1) fail(GDSW_ERR_INVALID_ARG, "Z == NULL needs n_null <= 1");
     if (Z != nullptr && (n_null <= 0 || n_null > 64)) fail(GDSW_ERR_INVALID_ARG, "n_null out of range");
     s.opt = o;
@@ -348,7 +351,123 @@ void build_interface(Symbolic &s) {
 }
 
 // ---------------------------------------------------------------------------
-// local matrices of the overlapping subdomains (CSR + band profile + ILU(0)
+// Level-of-fill pattern of ILU(p) of one local matrix (Sec. V-B, level-based
+// incomplete LU): entries of A_i have level 0; eliminating pivot row k < l
+// from row l reaches (l, j), j > k in row k, at level lev(l,k) + lev(k,j) + 1;
+// the smallest such level counts and entries above p are dropped.  Row l is
+// assembled with a min-heap of the pivots still to eliminate (ascending), so
+// fill entries that become pivots themselves are eliminated in turn.
+// On entry C/G/RL hold A_i's pattern row by row (columns ascending, G the
+// position in A); on return the ILU(p) pattern, G = -1 on fill entries.
+static void iluk_fill(int64_t ni, std::vector<int32_t> &C, std::vector<int64_t> &G, std::vector<int64_t> &RL,
+                      int p) {
+    std::vector<int32_t> nc, nlev;
+    std::vector<int64_t> ng, nrl(ni, 0), start(ni + 1, 0);
+    nc.reserve(C.size() * 2);
+    nlev.reserve(C.size() * 2);
+    ng.reserve(C.size() * 2);
+    std::vector<int32_t> lev(ni, -1);      // -1: not in the current row
+    std::vector<int64_t> gp(ni, -1);
+    std::vector<int32_t> cols;
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> pivots;
+    int64_t pos = 0;
+    for (int64_t l = 0; l < ni; ++l) {
+        cols.clear();
+        for (int64_t q = 0; q < RL[l]; ++q, ++pos) {
+            const int32_t c = C[pos];
+            lev[c] = 0;
+            gp[c] = G[pos];
+            cols.push_back(c);
+            if (c < l) pivots.push(c);
+        }
+        while (!pivots.empty()) {
+            const int32_t k = pivots.top();
+            pivots.pop();
+            const int32_t lk = lev[k];
+            for (int64_t e = start[k]; e < start[k + 1]; ++e) {
+                const int32_t j = nc[e];
+                if (j <= k) continue;
+                const int32_t nl = lk + nlev[e] + 1;
+                if (nl > p) continue;
+                if (lev[j] < 0) {
+                    lev[j] = nl;
+                    gp[j] = -1;
+                    cols.push_back(j);
+                    if (j < l) pivots.push(j);
+                } else if (nl < lev[j]) {
+                    lev[j] = nl;
+                }
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int32_t c : cols) {
+            nc.push_back(c);
+            nlev.push_back(lev[c]);
+            ng.push_back(gp[c]);
+            lev[c] = -1;
+        }
+        nrl[l] = int64_t(cols.size());
+        start[l + 1] = start[l] + nrl[l];
+    }
+    C.swap(nc);
+    G.swap(ng);
+    RL.swap(nrl);
+}
+
+// ---------------------------------------------------------------------------
+// FastILU product lists (Sec. V-B, iterative variant of the incomplete
+// factorisation): for every entry (l, j) of a local pattern, the pairs of
+// positions (l, m), (m, j) with m < min(l, j) in ascending m, and for l > j
+// the position of the pivot u_jj.  Positions index the concatenated local
+// CSR values of all subdomains.
+static void build_fastilu(Symbolic &s) {
+    const int np = s.np;
+    const int64_t ne = int64_t(s.lcol.size());
+    if (ne >= (int64_t(1) << 31)) fail(GDSW_ERR_INVALID_ARG, "too many local entries for FastILU");
+    s.fi_ptr.assign(ne + 1, 0);
+    s.fi_dpos.assign(ne, -1);
+    // position of (m, j) in local row m of subdomain i, or -1
+    auto find = [&](int64_t o, int32_t m, int32_t j) -> int64_t {
+        const int32_t *b = s.lcol.data() + s.lrowptr[o + m], *e = s.lcol.data() + s.lrowptr[o + m + 1];
+        const int32_t *it = std::lower_bound(b, e, j);
+        return (it != e && *it == j) ? int64_t(it - s.lcol.data()) : -1;
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(dynamic)
+        for (int i = 0; i < np; ++i) {
+            const int64_t o = s.ov_ptr[i], ni = s.ov_ptr[i + 1] - o;
+            for (int64_t l = 0; l < ni; ++l) {
+                const int64_t rs = s.lrowptr[o + l], re = s.lrowptr[o + l + 1];
+                for (int64_t e = rs; e < re; ++e) {
+                    const int32_t j = s.lcol[e];
+                    const int32_t lim = std::min<int32_t>(int32_t(l), j);
+                    int64_t cnt = 0;
+                    for (int64_t f = rs; f < re && s.lcol[f] < lim; ++f) {
+                        const int64_t g = find(o, s.lcol[f], j);
+                        if (g < 0) continue;
+                        if (pass == 1) {
+                            const int64_t q = s.fi_ptr[e] + cnt;
+                            s.fi_pairs[2 * q] = int32_t(f);
+                            s.fi_pairs[2 * q + 1] = int32_t(g);
+                        }
+                        ++cnt;
+                    }
+                    if (pass == 0) {
+                        s.fi_ptr[e + 1] = cnt;
+                        if (j < l) s.fi_dpos[e] = int32_t(s.lrowptr[o + j] + s.ldiag[o + j]);
+                    }
+                }
+            }
+        }
+        if (pass == 0) {
+            for (int64_t e = 0; e < ne; ++e) s.fi_ptr[e + 1] += s.fi_ptr[e];
+            s.fi_pairs.resize(2 * s.fi_ptr[ne]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// local matrices of the overlapping subdomains (CSR + band profile + ILU(k)
 // level schedule) and of the interior blocks (band profile)
 void build_local(Symbolic &s) {
     const int np = s.np;
@@ -377,15 +496,21 @@ void build_local(Symbolic &s) {
             int32_t b = 0;
             for (int64_t l = 0; l < ni; ++l) {
                 int32_t d = s.ov_idx[o + l];
-                int32_t nl = 0, nu = 0;
                 for (int64_t p = s.rowptr[d]; p < s.rowptr[d + 1]; ++p) {
                     int32_t q = g2l[s.col[p]];
                     if (q < 0) continue;
                     C.push_back(q);
                     G.push_back(p);
                     RL[l]++;
-                    if (q < l) { ++nl; b = std::max<int32_t>(b, int32_t(l - q)); }
-                    if (q > l) ++nu;
+                    if (q < l) b = std::max<int32_t>(b, int32_t(l - q));
+                }
+            }
+            if (s.opt.local == GDSW_LOCAL_ILU0 && s.opt.ilu_level > 0) iluk_fill(ni, C, G, RL, s.opt.ilu_level);
+            for (int64_t l = 0, pos = 0; l < ni; ++l) {
+                int32_t nl = 0, nu = 0;
+                for (int64_t q = 0; q < RL[l]; ++q, ++pos) {
+                    if (C[pos] < l) ++nl;
+                    if (C[pos] > l) ++nu;
                 }
                 kl = std::max(kl, nl);
                 ku = std::max(ku, nu);
@@ -472,6 +597,7 @@ void build_local(Symbolic &s) {
         s.ell_off[i + 1] = s.ell_off[i] + ((ni + 63) / 64) * 64;
     }
     s.ell_rows = s.ell_off[np];
+    if (s.opt.local == GDSW_LOCAL_ILU0 && s.opt.ilu_factor_sweeps > 0) build_fastilu(s);
 }
 
 // ---------------------------------------------------------------------------

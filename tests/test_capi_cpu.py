@@ -142,3 +142,39 @@ def test_factor_without_analysis_state_error():
     assert "part" in B.gdsw_last_error(h.value)
     assert B.lib().gdsw_factor(h.value, None) == 7
     B.gdsw_destroy(h.value)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("case", ["poisson", "diffusion", "elasticity"])
+def test_iluk_patterns_match_oracle(level, case):
+    """The library's ILU(k) patterns of every local matrix equal the oracle's
+    level-of-fill patterns (an independent implementation of the same rule)."""
+    if case == "poisson":
+        pr = P.poisson3d(9, 2)
+    elif case == "diffusion":
+        rng = np.random.default_rng(1)
+        pr = P.diffusion3d(8, np.exp(rng.standard_normal(9 ** 3)), 2)
+    else:
+        pr = P.elasticity_q1(4, 2)
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, None,
+                       B.gdsw_default_options(local=B.LOCAL_ILU0, ilu_level=level))
+    rp = B.gdsw_copy_map(h, B.MAP_LOCAL_ROWPTR)
+    cols = B.gdsw_copy_map(h, B.MAP_LOCAL_COL)
+    ovp = B.gdsw_copy_map(h, B.MAP_OV_PTR)
+    ovi = B.gdsw_copy_map(h, B.MAP_OV_IDX)
+    B.gdsw_destroy(h)
+    for i in range(pr.n_parts):
+        d = ovi[ovp[i]:ovp[i + 1]]
+        Ai = pr.A[d][:, d].tocsr()
+        Pm, _ = O.iluk_pattern(Ai, level)
+        r = rp[ovp[i]:ovp[i + 1] + 1]
+        assert np.array_equal(r - r[0], Pm.indptr), i
+        assert np.array_equal(cols[r[0]:r[-1]], Pm.indices), i
+
+
+def test_ilu_options_validated():
+    pr = P.poisson3d(6, 2)
+    for bad in (dict(ilu_level=-1), dict(ilu_level=9), dict(ilu_factor_sweeps=-2)):
+        with pytest.raises(B.GdswError):
+            B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, None,
+                           B.gdsw_default_options(local=B.LOCAL_ILU0, **bad))
