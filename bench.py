@@ -35,20 +35,32 @@ HBM_PEAK_GBS = 8000.0
 # profiles/hbm_traffic_*.md).  A figure only applies to the kernel source it
 # was measured on: `src` is a hash of that kernel's text, checked below.
 MEASURED_TRAFFIC = {
-    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 270.9e6, "src": "5175fa6096dad374"},
+    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 270859455, "src": "34321762b8a672e1"},
+    ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14252765139, "src": "bac8ad1f0edc4531"},
+    ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1602182413, "src": "bac8ad1f0edc4531"},
 }
 
 
 def kernel_source_hash(kernel):
+    """Hash of the source text a kernel is built from (its own text and the
+    device functions it calls), to tie a counter measurement to a kernel."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2304_04876_amd", "csrc", "kernels_apply.hpp")
-    text = open(path).read()
-    marks = {"k_ilu_jacobi": ("template <int NT, int R, int KL, int KU, typename VT>",
-                              "// Same sweeps for any slot counts and subdomain sizes")}
-    if kernel not in marks:
+    csrc = os.path.join(ROOT, "paper_2304_04876_amd", "csrc")
+    segments = {
+        "k_ilu_jacobi": [("kernels_apply.hpp", "template <int NT, int R, int KL, int KU, typename VT>",
+                          "// Same sweeps for any slot counts and subdomain sizes")],
+        "k_band_apply": [("kernels_setup.hpp", "constexpr int BS_NB = 64;", "// Extension, eq. (2)."),
+                         ("kernels_apply.hpp", "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor",
+                          "// Coarse restriction Phi^T r.")],
+    }
+    if kernel not in segments:
         return None
-    a, b = text.index(marks[kernel][0]), text.index(marks[kernel][1])
-    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for fname, start, end in segments[kernel]:
+        text = open(os.path.join(csrc, fname)).read()
+        a, b = text.index(start), text.index(end)
+        h.update(text[a:b].encode())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -66,6 +78,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--graphs", action="store_true", help="queue CG iterations as captured HIP graphs")
     ap.add_argument("--ilu-level", type=int, default=0)
     ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--N", type=int, default=None)
@@ -112,7 +125,8 @@ def main():
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                        B.gdsw_default_options(local=local, local_prec=precs[args.prec],
                                               basis_prec=B.FP64 if args.prec == "fp64" else B.FP32,
-                                              ilu_level=args.ilu_level, ilu_factor_sweeps=args.factor_sweeps))
+                                              ilu_level=args.ilu_level, ilu_factor_sweeps=args.factor_sweeps,
+                                              flags=B.FLAG_GRAPHS if args.graphs else 0))
     t_an = time.perf_counter() - t0
     log(f"[bench] analysis {t_an:.2f}s; numerical setup on the GPU")
     B.gdsw_factor(h, stream)
@@ -220,14 +234,17 @@ def main():
         nloc = info["sum_overlap_dofs"]
         offdiag = info["local_factor_entries"] - nloc
         alg_bytes = offdiag * (pbytes + 2) + nloc * pbytes + nloc * (4 + 8 + 8)
-        kname = "k_ilu_jacobi"
+        kname = "k_ilu_jacobi" if info["local_variant"] in (0, 1) else "k_ilu_jacobi_generic"
     else:
         # band factor read twice (forward and backward) + vectors
         alg_bytes = 2 * info["local_factor_entries"] * pbytes + info["sum_overlap_dofs"] * (4 + 8 + 8)
         kname = "k_band_apply"
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = None
-    meas = MEASURED_TRAFFIC.get((kname, f"poisson{N}^3_P{Pn}^3" if not elastic else f"elasticity{N}^3", args.prec))
+    meas = None
+    if args.ilu_level == 0:
+        meas = MEASURED_TRAFFIC.get((kname, f"poisson{N}^3_P{Pn}^3" if not elastic else f"elasticity{N}^3",
+                                     args.prec))
     if meas and kernel_source_hash(kname) == meas["src"]:
         traffic = int(meas["bytes"])
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -281,7 +298,8 @@ def main():
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
                    "jacobi_sweeps": 5, "ilu_level": args.ilu_level, "ilu_factor_sweeps": args.factor_sweeps,
                    "local_prec": args.prec, "rtol": 1e-8,
-                   "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"]},
+                   "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"],
+                   "tuned_apply_streams": info["apply_streams"], "graphs": bool(args.graphs)},
         "applies_per_sec": round(1e3 / apply_ms, 1),
         "apply_ms": round(apply_ms, 4),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
@@ -314,7 +332,8 @@ def bench_batch(args):
     t0 = time.perf_counter()
     hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
                               options=B.gdsw_default_options(local=B.LOCAL_EXACT, local_prec=B.FP32,
-                                                             basis_prec=B.FP32))
+                                                             basis_prec=B.FP32,
+                                                             flags=B.FLAG_GRAPHS if args.graphs else 0))
     t_an = time.perf_counter() - t0
     B.gdsw_factor(hb)
     info = B.gdsw_get_info(hb)

@@ -66,6 +66,12 @@ enum { GDSW_LOCAL_EXACT = 0, GDSW_LOCAL_ILU0 = 1 };
  * applied to the local parts only). */
 enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2, GDSW_FP16 = 3 };
 
+/* Option flags.  GDSW_FLAG_GRAPHS: CG iterations (gdsw_solve, gdsw_solve_batch,
+ * gdsw_slots_step) are queued as captured HIP graphs of k iterations, one
+ * graph per (x pointer, k) kept by the handle and replayed on the caller's
+ * stream, instead of kernel by kernel; results are bit-identical. */
+enum { GDSW_FLAG_GRAPHS = 1 };
+
 /* Krylov method of gdsw_solve. */
 enum { GDSW_KRYLOV_CG = 0, GDSW_KRYLOV_GMRES = 1 };
 
@@ -77,7 +83,7 @@ typedef struct {
     int32_t local_prec;       /* GDSW_FP64 / FP32 / BF16 / FP16                   */
     int32_t basis_prec;       /* GDSW_FP64 / FP32 (storage of Phi)                */
     int64_t hbm_budget_bytes; /* device bytes the handle may allocate; 0 = no cap */
-    uint64_t flags;           /* reserved, must be 0                              */
+    uint64_t flags;           /* GDSW_FLAG_* bits, 0 by default                   */
     int32_t ilu_level;        /* GDSW_LOCAL_ILU0 only: level of fill k of ILU(k)
                                  (Sec. V-B, levels varied in Sec. VII-C); 0..8,
                                  default 0                                         */
@@ -124,6 +130,9 @@ typedef struct {
     int32_t n_problems;       /* independent problems packed in the handle        */
     int32_t local_variant;    /* launch configuration of the local solves (-1 = fixed rule) */
     int32_t gemv_variant;     /* coarse GEMV: -1 fixed rule, 0 wavefront, 1 workgroup per row */
+    int32_t apply_streams;    /* coarse part of the apply: -1 fixed rule (second stream when
+                                 the subdomains do not fill the compute units), 1 same stream
+                                 as the local solves, 2 second stream                */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -253,11 +262,13 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
 /* Autotuner: times every launch configuration of the local-solve kernel
  * (ILU(0): register-resident sweeps with 512 or 1024 threads, streaming
  * sweeps with 256 or 512 threads; exact: band solves with 256, 512 or 1024
- * threads) and both coarse GEMV variants on the handle's own factors, `reps`
- * launches each, and keeps the fastest for all later applies.  times_ms
- * (optional, host, 6 floats) receives the average milliseconds per launch
- * (-1 for configurations that do not fit): [0..3] local variants, [4..5]
- * GEMV variants.  Synchronises `stream`. */
+ * threads), both coarse GEMV variants, and the whole apply with the coarse
+ * part on the caller's stream after the local solves or on a second stream
+ * beside them, on the handle's own factors, `reps` launches each, and keeps
+ * the fastest for all later applies.  times_ms (optional, host, 8 floats)
+ * receives the average milliseconds per launch (-1 for configurations that
+ * do not fit): [0..3] local variants, [4..5] GEMV variants, [6..7] apply in
+ * one stream / two streams.  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
 /* Dof offsets of the problems of a handle: offsets[count+1] (host). */

@@ -26,6 +26,7 @@ COARSE_NONE, COARSE_GDSW = 0, 1
 LOCAL_EXACT, LOCAL_ILU0 = 0, 1
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 KRYLOV_CG, KRYLOV_GMRES = 0, 1
+FLAG_GRAPHS = 1
 MAP_OV_PTR, MAP_OV_IDX, MAP_IS_GAMMA, MAP_COMP_OF_NODE, MAP_COMP_RANK = 0, 1, 2, 3, 4
 MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8
 MAP_LOCAL_ROWPTR, MAP_LOCAL_COL = 9, 10
@@ -67,7 +68,7 @@ class Info(ctypes.Structure):
                 ("max_local_rows", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
                 ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
-                ("gemv_variant", ctypes.c_int32)]
+                ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32)]
 
 
 def lib():
@@ -307,7 +308,7 @@ def gdsw_slot_finish(h, slot, stream=None) -> dict:
 
 
 def gdsw_autotune(h, reps=10, stream=None) -> list:
-    times = np.full(6, -1.0, dtype=np.float32)
+    times = np.full(8, -1.0, dtype=np.float32)
     _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
     return times.tolist()
 

@@ -152,6 +152,7 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->n_problems = S.nprob;
     info->local_variant = gdsw::tuned_variant(h, 0);
     info->gemv_variant = gdsw::tuned_variant(h, 1);
+    info->apply_streams = gdsw::tuned_variant(h, 2);
     return GDSW_OK;
 }
 

@@ -77,7 +77,27 @@ struct Device {
         if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
         return p;
     }
+    // the coarse part of an apply runs on `side` beside the local solves
+    // (fork/join with two events); created with the default priority
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int apply_streams = -1;   // -1: rule (two streams when np < compute units), 1 or 2: tuned
+    int n_cu = 256;
+    // captured CG chunks (GDSW_FLAG_GRAPHS): key (x, iterations)
+    hipStream_t cap = nullptr;
+    struct CgGraph {
+        const double *x;
+        int iters;
+        hipGraphExec_t exec;
+    };
+    std::vector<CgGraph> cg_graphs;
+
     ~Device() {
+        for (auto &g : cg_graphs) (void)hipGraphExecDestroy(g.exec);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         for (void *p : allocs) (void)hipFree(p);
     }
 
@@ -119,6 +139,7 @@ struct Device {
     int64_t *a0_off = nullptr;
     // ---- Krylov ----
     double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kpart = nullptr;
+    double *kpart2 = nullptr;   // second partial sums (r.r beside r.z)
     KState *kst = nullptr;          // one per problem
     int *kdone = nullptr;           // done flags mirrored per problem (skip mask of the apply)
     int *kmask = nullptr;           // one-problem-active mask (slot start)
@@ -223,6 +244,7 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         HIPCHK(hipStreamSynchronize(s));
     }
     D.kpart = D.alloc<double>(std::max(D.nkb, 1));
+    D.kpart2 = D.alloc<double>(std::max(D.nkb, 1));
     D.kst = D.alloc<KState>(S.nprob);
     D.kdone = D.alloc<int>(S.nprob);
     D.kmask = D.alloc<int>(S.nprob);
@@ -647,6 +669,12 @@ gdsw_status factor(gdsw_handle_s *h, void *stream) {
             HIPCHK(hipGetDevice(&dev));
             HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             h->dev->max_lds = size_t(lds);
+            int cus = 0;
+            HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            h->dev->n_cu = cus;
+            HIPCHK(hipStreamCreateWithFlags(&h->dev->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->dev->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->dev->ev_join, hipEventDisableTiming));
         }
         upload_all(h, s);
         factor_local(h, s);
@@ -692,7 +720,7 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
     using AT = typename AccOf<VT>::type;
 #define GDSW_ILU_CASE(RR)                                                                                    \
     if (need <= RR) {                                                                                        \
-        const size_t lds = 2 * sizeof(AT) * NT * RR;                                                         \
+        const size_t lds = (3 * sizeof(AT) + (f64 ? 0 : sizeof(double))) * NT * RR;                          \
         if (lds > D.max_lds) return false;                                                                   \
         hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, 3, 3, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx,     \
                            D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc, \
@@ -777,7 +805,46 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
                          const double *dot_r = nullptr) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
-    if (which & 1 || which == 4) {
+    const bool local = (which & 1) || which == 4;
+    const bool coarse = (which & 2) && D.A0inv != nullptr;
+    // the coarse chain (restriction, reduction, GEMV) and the local solves
+    // are independent: the chain may run on the side stream beside them,
+    // which pays when the local solves leave compute units idle
+    const bool two = D.apply_streams == 2 || (D.apply_streams < 0 && S.np < D.n_cu);
+    const bool fork = local && coarse && two && D.side != nullptr;
+    hipStream_t sc = s;
+    if (fork) {
+        HIPCHK(hipEventRecord(D.ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(D.side, D.ev_fork, 0));
+        sc = D.side;
+    }
+    if (coarse) {
+        const PhiBlocks &B = S.blk;
+        // blocks with many rows (subdomain interiors) first, then the small ones
+        const int nbig = D.nb_big, nsmall = B.nb - nbig;
+        const int nwg = D.ntiles + (nsmall + RT_NT / 64 - 1) / (RT_NT / 64);
+        if (nwg > 0) {
+            if (D.phi32)
+                hipLaunchKernelGGL(k_coarse_restrict<float>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.tile_blk,
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.blk_poff, D.partial, D.ntiles, nbig, B.nb,
+                                   sk);
+            else
+                hipLaunchKernelGGL(k_coarse_restrict<double>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.tile_blk,
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.blk_poff, D.partial, D.ntiles, nbig, B.nb,
+                                   sk);
+        }
+        hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, sc, D.red_ptr, D.red_idx,
+                           D.partial, D.r0, S.n0, sk);
+        if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
+            hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
+                               D.r0, D.z0, S.n0, sk);
+        else
+            hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
+                               D.cprob, D.r0, D.z0, S.n0, sk);
+    }
+    if (local) {
         switch (S.opt.local_prec) {
             case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
             case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
@@ -785,53 +852,24 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
             default: launch_local<fp16>(S, D, r, sk, s); break;
         }
     }
+    if (fork) {
+        HIPCHK(hipEventRecord(D.ev_join, D.side));
+        HIPCHK(hipStreamWaitEvent(s, D.ev_join, 0));
+    }
     if (which == 4) {   // the local solves alone (results stay in zloc)
         HIPCHK(hipGetLastError());
         return;
-    }
-    const bool coarse = (which & 2) && D.A0inv != nullptr;
-    if (coarse) {
-        const PhiBlocks &B = S.blk;
-        // blocks with many rows (subdomain interiors) first, then the small ones
-        const int nbig = D.nb_big, nsmall = B.nb - nbig;
-        if (D.phi32) {
-            if (D.ntiles)
-                hipLaunchKernelGGL(k_coarse_restrict_tile<float>, dim3(D.ntiles), dim3(RT_NT), 0, s, r, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.tile_blk,
-                                   D.tile_l0, D.tile_l1, D.tile_poff, D.partial, sk);
-            if (nsmall)
-                hipLaunchKernelGGL(k_coarse_restrict_wave<float>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
-                                   D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32,
-                                   D.blk_poff, D.partial, nbig, B.nb, sk);
-        } else {
-            if (D.ntiles)
-                hipLaunchKernelGGL(k_coarse_restrict_tile<double>, dim3(D.ntiles), dim3(RT_NT), 0, s, r, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.tile_blk,
-                                   D.tile_l0, D.tile_l1, D.tile_poff, D.partial, sk);
-            if (nsmall)
-                hipLaunchKernelGGL(k_coarse_restrict_wave<double>, dim3((nsmall + 3) / 4), dim3(256), 0, s, r,
-                                   D.blk_row_ptr, D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi,
-                                   D.blk_poff, D.partial, nbig, B.nb, sk);
-        }
-        hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, s, D.red_ptr, D.red_idx,
-                           D.partial, D.r0, S.n0, sk);
-        if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
-            hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
-                               D.r0, D.z0, S.n0, sk);
-        else
-            hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, s, D.A0inv, D.a0_off, D.prob_c0,
-                               D.cprob, D.r0, D.z0, S.n0, sk);
     }
     const int w = (which & 1) | (coarse ? 2 : 0);
     if (dot_r) {
         if (D.phi32)
             hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart, D.kpart2);
         else
             hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart, D.kpart2);
     } else if (D.phi32) {
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
@@ -901,12 +939,51 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     const int nkb = D.nkb, np = S.nprob;
     hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.sell, D.kp, D.kq, D.kpart, D.kst, all);
-    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0);
-    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kpart, D.kst, all);
-    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR), 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
+                       (const double *)nullptr);
+    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kst, all);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s, D.kr);   // also the partials of r.z
-    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BETA), 0);
-    hipLaunchKernelGGL(k_cg_update_p, dim3(nkb), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all);
+    // stop test on ||r||^2, then beta from r.z (both summed by the prolongation)
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR_BETA), 0,
+                       D.kpart2);
+    hipLaunchKernelGGL(k_cg_update_p, dim3((nkb + UPB - 1) / UPB), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all, nkb);
+}
+
+// `iters` CG iterations: queued kernel by kernel, or with GDSW_FLAG_GRAPHS as
+// one captured graph per (x, iters), captured on a private stream on first
+// use and replayed on s.
+static void queue_cg_chunk(gdsw_handle_s *h, double *x, int iters, hipStream_t s) {
+    Device &D = *h->dev;
+    if (!(h->sym.opt.flags & GDSW_FLAG_GRAPHS)) {
+        for (int k = 0; k < iters; ++k) queue_cg_iteration(h, x, s);
+        return;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : D.cg_graphs)
+        if (g.x == x && g.iters == iters) exec = g.exec;
+    if (!exec) {
+        if (!D.cap) HIPCHK(hipStreamCreateWithFlags(&D.cap, hipStreamNonBlocking));
+        if (D.cg_graphs.size() >= 16) {
+            HIPCHK(hipStreamSynchronize(s));
+            for (auto &g : D.cg_graphs) (void)hipGraphExecDestroy(g.exec);
+            D.cg_graphs.clear();
+        }
+        HIPCHK(hipStreamBeginCapture(D.cap, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            for (int k = 0; k < iters; ++k) queue_cg_iteration(h, x, D.cap);
+        } catch (...) {
+            (void)hipStreamEndCapture(D.cap, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(D.cap, &graph));
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+        D.cg_graphs.push_back({x, iters, exec});
+    }
+    HIPCHK(hipGraphLaunch(exec, s));
 }
 
 // Starts CG (x0 = 0) for problem k alone, or for all problems (k < 0).
@@ -919,11 +996,13 @@ static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, 
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(KNT), 0, s, x, D.kr, b, kb);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BB), pbase);
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BB), pbase,
+                       (const double *)nullptr);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, k < 0 ? D.kdone : D.kmask), s);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase);
-    hipLaunchKernelGGL(k_cg_update_p, dim3(nb), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 1, kb);
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase,
+                       (const double *)nullptr);
+    hipLaunchKernelGGL(k_cg_update_p, dim3((nb + UPB - 1) / UPB), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 1, kb, nb);
 }
 
 // ||b - A x|| / ||b|| of problem k (all problems: k < 0) into state.red
@@ -938,7 +1017,7 @@ static void queue_true_residual(gdsw_handle_s *h, const double *b, const double 
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
     hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst,
-                       (int *)nullptr, int(KF_RED), k < 0 ? 0 : k);
+                       (int *)nullptr, int(KF_RED), k < 0 ? 0 : k, (const double *)nullptr);
 }
 
 static void fill_info(const KState &f, gdsw_solve_info *info) {
@@ -971,7 +1050,7 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
     int queued = 0, chunk = 4;
     while (queued < limit) {
         const int c = std::min(chunk, limit - queued);
-        for (int k = 0; k < c; ++k) queue_cg_iteration(h, x, s);
+        queue_cg_chunk(h, x, c, s);
         queued += c;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hs.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
@@ -1075,7 +1154,8 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     KState ks{};
     HIPCHK(hipMemcpyAsync(D.kst, &ks, sizeof(KState), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_dot, dim3(D.nkb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, all);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, (int *)nullptr, int(KF_BB), 0);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, (int *)nullptr, int(KF_BB), 0,
+                       (const double *)nullptr);
     HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, n);
     HIPCHK(hipStreamSynchronize(s));
@@ -1247,8 +1327,7 @@ gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream
     try {
         bool any = false;
         for (auto &k : D.h_state) any = any || (k.status == KS_RUNNING && !k.done);
-        if (any)
-            for (int i = 0; i < iters; ++i) queue_cg_iteration(h, D.slot_x, s);
+        if (any && iters > 0) queue_cg_chunk(h, D.slot_x, iters, s);
         HIPCHK(hipGetLastError());
         std::vector<KState> dev(np);
         HIPCHK(hipMemcpyAsync(dev.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
@@ -1365,6 +1444,18 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                 if (times) times[4 + v] = tg[v] / reps;
             }
             D.gemv_variant = tg[1] < tg[0] ? 1 : 0;
+            float ta[2];
+            for (int v = 0; v < 2; ++v) {
+                D.apply_streams = v + 1;
+                launch_apply(h, D.kr, D.kz, 3, Skip(), s);
+                HIPCHK(hipEventRecord(e0, s));
+                for (int k = 0; k < reps; ++k) launch_apply(h, D.kr, D.kz, 3, Skip(), s);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&ta[v], e0, e1));
+                if (times) times[6 + v] = ta[v] / reps;
+            }
+            D.apply_streams = ta[1] < ta[0] ? 2 : 1;
         }
         HIPCHK(hipEventDestroy(e0));
         HIPCHK(hipEventDestroy(e1));
@@ -1379,7 +1470,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
 
 int tuned_variant(const gdsw_handle_s *h, int which) {
     if (!h->dev) return -1;
-    return which == 0 ? h->dev->local_variant : h->dev->gemv_variant;
+    return which == 0 ? h->dev->local_variant : which == 1 ? h->dev->gemv_variant : h->dev->apply_streams;
 }
 
 void destroy_device(gdsw_handle_s *h) {

@@ -17,9 +17,12 @@ namespace gdsw {
 // One workgroup per subdomain.  Thread t owns rows t, t+NT, ... (R of them);
 // its rows' factor entries (KL lower, KU upper slots) stay in registers for
 // all sweeps, so the factors are read from HBM once per apply; the two
-// iterates live in LDS and alternate.  The restriction gather (with the
-// optional diagonal scaling of the reduced-precision factors) and the write
-// of the local result are fused in.
+// iterates live in LDS and alternate.  The inverse pivots (and, for reduced
+// precision, the rows' diagonal scale) are staged in LDS with the first
+// loads, so that no global load waits in the middle or at the end.  The
+// restriction gather (with the optional diagonal scaling of the
+// reduced-precision factors) and the write of the local result are fused
+// in.  LDS: 3 NT R accumulator values (+ NT R doubles with scaling).
 template <int NT, int R, int KL, int KU, typename VT>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
@@ -32,6 +35,8 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *bufA = reinterpret_cast<AT *>(smraw);
     AT *bufB = bufA + NT * R;
+    AT *sdinv = bufB + NT * R;
+    double *sscale = reinterpret_cast<double *>(sdinv + NT * R);   // used with dscale only
     const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
@@ -49,8 +54,13 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
         if (l < ni) {
             const int d = ov_idx[o + l];
             double x = r[d];
-            if (dscale) x *= dscale[d];
+            if (dscale) {
+                const double sc = dscale[d];
+                sscale[l] = sc;
+                x *= sc;
+            }
             rr[m] = AT(x);
+            sdinv[l] = to_acc(dinv[eo + l]);
         }
         const bool ok = l < npad;
 #pragma unroll
@@ -91,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     for (int m = 0; m < R; ++m) {
         const int l = tid + m * NT;
         if (l < ni) {
-            rr[m] = to_acc(dinv[eo + l]) * cur[l];
+            rr[m] = sdinv[l] * cur[l];
             nxt[l] = rr[m];
         }
     }
@@ -116,7 +126,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
         const int l = tid + m * NT;
         if (l < ni) {
             double v = double(cur[l]);
-            if (dscale) v *= dscale[ov_idx[o + l]];
+            if (dscale) v *= sscale[l];
             zloc[o + l] = v;
         }
     }
@@ -226,22 +236,18 @@ __global__ __launch_bounds__(1024) void k_band_apply(
 // workgroup per tile (4 rows per thread, every load of a pass issued before
 // the sums); small blocks (interface components) take a wavefront each.
 // Up to 8 columns per pass.
-constexpr int RT_NT = 256, RT_RPT = 4, RT_ROWS = RT_NT * RT_RPT;
+constexpr int RT_NT = 256, RT_RPT = 4, RT_ROWS = RT_NT * RT_RPT, RT_KB = 8;
+
 template <typename PT>
-__global__ __launch_bounds__(RT_NT) void k_coarse_restrict_tile(
-    const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
-    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
-    const int64_t *__restrict__ tile_poff, double *__restrict__ partial, Skip sk) {
-    constexpr int KB = 8, NW = RT_NT / 64;
-    __shared__ double sh[KB][NW];
-    const int t = blockIdx.x;
-    const int g = tile_blk[t];
-    if (sk.blk(g)) return;
+__device__ __forceinline__ void restrict_tile(const double *__restrict__ r, const int64_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ rows, const int64_t *__restrict__ col_ptr,
+                                              const int64_t *__restrict__ val_off, const PT *__restrict__ phi, int g,
+                                              int l0, int l1, int64_t po, double *__restrict__ partial,
+                                              double (*sh)[RT_NT / 64]) {
+    constexpr int KB = RT_KB, NW = RT_NT / 64;
     const int64_t r0 = row_ptr[g];
     const int nr = int(row_ptr[g + 1] - r0);
     const int k = int(col_ptr[g + 1] - col_ptr[g]);
-    const int l0 = tile_l0[t], l1 = tile_l1[t];
     const PT *Bg = phi + val_off[g];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double x[RT_RPT];
@@ -275,25 +281,23 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_restrict_tile(
             double v = sh[tid][0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) v += sh[tid][w];
-            partial[tile_poff[t] + s0 + tid] = v;
+            partial[po + s0 + tid] = v;
         }
         __syncthreads();
     }
 }
 
 template <typename PT>
-__global__ __launch_bounds__(256) void k_coarse_restrict_wave(
-    const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
-    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    const int64_t *__restrict__ poff, double *__restrict__ partial, int g0, int nb, Skip sk) {
-    const int g = g0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void restrict_wave(const double *__restrict__ r, const int64_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ rows, const int64_t *__restrict__ col_ptr,
+                                              const int64_t *__restrict__ val_off, const PT *__restrict__ phi, int g,
+                                              int64_t po, double *__restrict__ partial) {
     const int lane = threadIdx.x & 63;
-    if (g >= nb || sk.blk(g)) return;
     const int64_t r0 = row_ptr[g];
     const int nr = int(row_ptr[g + 1] - r0);
     const int k = int(col_ptr[g + 1] - col_ptr[g]);
     const PT *Bg = phi + val_off[g];
-    constexpr int KB = 8;
+    constexpr int KB = RT_KB;
     for (int s0 = 0; s0 < k; s0 += KB) {
         double acc[KB];
 #pragma unroll
@@ -307,8 +311,32 @@ __global__ __launch_bounds__(256) void k_coarse_restrict_wave(
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
             const double t = wave_sum(acc[s]);
-            if (lane == 0 && s0 + s < k) partial[poff[g] + s0 + s] = t;
+            if (lane == 0 && s0 + s < k) partial[po + s0 + s] = t;
         }
+    }
+}
+
+// One launch for both kinds: workgroups [0, ntiles) take the tiles of the
+// big blocks, the rest four small blocks each (blocks g_small, g_small+1, ...
+// below nb), so the short component blocks run beside the tiles.
+template <typename PT>
+__global__ __launch_bounds__(RT_NT) void k_coarse_restrict(
+    const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
+    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+    const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
+    const int64_t *__restrict__ tile_poff, const int64_t *__restrict__ poff, double *__restrict__ partial,
+    int ntiles, int g_small, int nb, Skip sk) {
+    __shared__ double sh[RT_KB][RT_NT / 64];
+    const int b = blockIdx.x;
+    if (b < ntiles) {
+        const int g = tile_blk[b];
+        if (sk.blk(g)) return;
+        restrict_tile<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, tile_l0[b], tile_l1[b], tile_poff[b], partial,
+                          sh);
+    } else {
+        const int g = g_small + (b - ntiles) * (RT_NT / 64) + int(threadIdx.x >> 6);
+        if (g >= nb || sk.blk(g)) return;
+        restrict_wave<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, poff[g], partial);
     }
 }
 
@@ -374,7 +402,7 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
     const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
     const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
     const double *xk = x + c0;
-    constexpr int U = 4;
+    constexpr int U = 16;
     double acc = 0.0;
     for (int c0 = threadIdx.x; c0 < nk; c0 += U * 256) {
         double av[U], xv[U];
@@ -444,8 +472,8 @@ __global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const in
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
-// [row0[b], row1[b]) of one problem), also writing the block's partial of
-// r . z for the next CG step.
+// [row0[b], row1[b]) of one problem), also writing the block's partials of
+// r . z and (partial2 != null) r . r for the next CG step.
 template <typename PT>
 __global__ __launch_bounds__(256) void k_prolong_dot(
     int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
@@ -453,20 +481,30 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
     const PT *__restrict__ phi, const double *__restrict__ z0, double *__restrict__ z, Skip sk,
     const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
-    double *__restrict__ partial) {
-    __shared__ double sh[4];
+    double *__restrict__ partial, double *__restrict__ partial2) {
+    __shared__ double sh[8];
     const int blk = blockIdx.x;
     const int row0 = kb_row0[blk], row1 = kb_row1[blk];
     if (sk.dof(row0)) return;
-    double dot = 0.0;
+    double dot = 0.0, rr = 0.0;
     for (int d = row0 + threadIdx.x; d < row1; d += 256) {
         const double v =
             prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
         z[d] = v;
-        dot += rvec[d] * v;
+        const double rd = rvec[d];
+        dot += rd * v;
+        rr += rd * rd;
     }
-    dot = block_sum<double, 256>(dot, sh);
-    if (threadIdx.x == 0) partial[blk] = dot;
+    if (partial2) {
+        block_sum2<double, 256>(dot, rr, sh);
+        if (threadIdx.x == 0) {
+            partial[blk] = dot;
+            partial2[blk] = rr;
+        }
+    } else {
+        dot = block_sum<double, 256>(dot, sh);
+        if (threadIdx.x == 0) partial[blk] = dot;
+    }
 }
 
 }  // namespace gdsw

@@ -125,25 +125,18 @@ __global__ __launch_bounds__(KNT) void k_cg_spmv_dot(Sell A, const double *__res
     if (threadIdx.x == 0) partial[blk] = dot;
 }
 
-// x += alpha p; r -= alpha q; partials of r.r
+// x += alpha p; r -= alpha q (r.r is summed with r.z after the apply)
 __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p,
-                                                      const double *__restrict__ q,
-                                                      double *__restrict__ partial, const KState *st, KBlk kb) {
+                                                      const double *__restrict__ q, const KState *st, KBlk kb) {
     const int blk = kb.base + blockIdx.x;
     const KState &S = st[kb.prob[blk]];
     if (S.done) return;
-    __shared__ double sh[KNT / 64];
     const double alpha = S.alpha;
-    double v = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
         x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        v += ri * ri;
+        r[i] -= alpha * q[i];
     }
-    v = block_sum<double, KNT>(v, sh);
-    if (threadIdx.x == 0) partial[blk] = v;
 }
 
 // partials of a.b
@@ -159,6 +152,39 @@ __global__ __launch_bounds__(KNT) void k_dot(const double *__restrict__ a, const
     if (threadIdx.x == 0) partial[blk] = v;
 }
 
+// rr = ||r||^2: iteration count and stop tests; returns whether CG stopped
+__device__ __forceinline__ bool cg_rr_step(KState &S, double t) {
+    S.rr = t;
+    S.iters += 1;
+    if (!isfinite(t)) {
+        S.done = 1;
+        S.status = KS_BREAKDOWN;
+    } else if (S.fixed > 0) {
+        if (S.iters >= S.fixed) {
+            S.done = 1;
+            S.status = (t <= S.rtol2 * S.bb) ? KS_CONVERGED : KS_MAXIT;
+        }
+    } else if (t <= S.rtol2 * S.bb) {
+        S.done = 1;
+        S.status = KS_CONVERGED;
+    } else if (S.iters >= S.maxit) {
+        S.done = 1;
+        S.status = KS_MAXIT;
+    }
+    return S.done != 0;
+}
+
+// t = r.z of the new residual: beta = t / rho, rho = t
+__device__ __forceinline__ void cg_beta_step(KState &S, double t) {
+    if (!isfinite(t) || S.rho == 0.0) {
+        S.done = 1;
+        S.status = KS_BREAKDOWN;
+    } else {
+        S.beta = t / S.rho;
+        S.rho = t;
+    }
+}
+
 // One workgroup per problem (problems base .. base + gridDim.x - 1): total
 // of its partials and the scalar step it feeds; kdone mirrors `done`.
 enum {
@@ -167,16 +193,26 @@ enum {
     KF_ALPHA = 2,   // sigma = t, alpha = rho / sigma
     KF_RR = 3,      // rr = t, iteration count and stop tests
     KF_BETA = 4,    // beta = t / rho, rho = t
-    KF_RED = 5      // red = t
+    KF_RED = 5,     // red = t
+    KF_RR_BETA = 6  // KF_RR with the totals of partial2 (r.r), then KF_BETA with t (r.z)
 };
 
 __global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, const int32_t *__restrict__ pb_ptr,
-                                                   KState *st, int *__restrict__ kdone, int op, int base) {
+                                                   KState *st, int *__restrict__ kdone, int op, int base,
+                                                   const double *__restrict__ partial2) {
     const int k = base + blockIdx.x;
     KState &S = st[k];
-    if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA) && S.done) return;
+    if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA || op == KF_RR_BETA) && S.done) return;
     __shared__ double sh[KNT / 64];
-    const double t = sum_partials(partial, pb_ptr[k], pb_ptr[k + 1], sh);
+    double t = sum_partials(partial, pb_ptr[k], pb_ptr[k + 1], sh);
+    if (op == KF_RR_BETA) {
+        __syncthreads();   // sh is reused
+        const double t2 = sum_partials(partial2, pb_ptr[k], pb_ptr[k + 1], sh);
+        if (threadIdx.x != 0) return;
+        if (!cg_rr_step(S, t2)) cg_beta_step(S, t);
+        if (kdone) kdone[k] = S.done;
+        return;
+    }
     if (threadIdx.x != 0) return;
     switch (op) {
         case KF_BB:
@@ -199,47 +235,38 @@ __global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ pa
                 S.alpha = S.rho / t;
             }
             break;
-        case KF_RR:
-            S.rr = t;
-            S.iters += 1;
-            if (!isfinite(t)) {
-                S.done = 1;
-                S.status = KS_BREAKDOWN;
-            } else if (S.fixed > 0) {
-                if (S.iters >= S.fixed) {
-                    S.done = 1;
-                    S.status = (t <= S.rtol2 * S.bb) ? KS_CONVERGED : KS_MAXIT;
-                }
-            } else if (t <= S.rtol2 * S.bb) {
-                S.done = 1;
-                S.status = KS_CONVERGED;
-            } else if (S.iters >= S.maxit) {
-                S.done = 1;
-                S.status = KS_MAXIT;
-            }
-            break;
-        case KF_BETA:
-            if (!isfinite(t) || S.rho == 0.0) {
-                S.done = 1;
-                S.status = KS_BREAKDOWN;
-            } else {
-                S.beta = t / S.rho;
-                S.rho = t;
-            }
-            break;
+        case KF_RR: cg_rr_step(S, t); break;
+        case KF_BETA: cg_beta_step(S, t); break;
         default: S.red = t; break;
     }
     if (kdone) kdone[k] = S.done;
 }
 
-// p = z + beta p (init: p = z)
+// p = z + beta p (init: p = z), UPB row blocks per workgroup (the loads of
+// all of them in flight together); row blocks kb.base .. kb.base + nb - 1
+constexpr int UPB = 4;
+static_assert(KROWS <= KNT, "one row per thread in a row block");
 __global__ __launch_bounds__(KNT) void k_cg_update_p(double *__restrict__ p, const double *__restrict__ z,
-                                                     const KState *st, int init, KBlk kb) {
-    const int blk = kb.base + blockIdx.x;
-    const KState &S = st[kb.prob[blk]];
-    if (!init && S.done) return;
-    const double beta = S.beta;
-    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) p[i] = init ? z[i] : z[i] + beta * p[i];
+                                                     const KState *st, int init, KBlk kb, int nb) {
+    double zv[UPB], pv[UPB], beta[UPB];
+    int idx[UPB];
+#pragma unroll
+    for (int u = 0; u < UPB; ++u) {
+        const int b = blockIdx.x * UPB + u;
+        idx[u] = -1;
+        if (b >= nb) continue;
+        const int blk = kb.base + b;
+        const KState &S = st[kb.prob[blk]];
+        const int i = kb.row0[blk] + int(threadIdx.x);
+        if ((!init && S.done) || i >= kb.row1[blk]) continue;
+        idx[u] = i;
+        beta[u] = S.beta;
+        zv[u] = z[i];
+        pv[u] = init ? 0.0 : p[i];
+    }
+#pragma unroll
+    for (int u = 0; u < UPB; ++u)
+        if (idx[u] >= 0) p[idx[u]] = init ? zv[u] : zv[u] + beta[u] * pv[u];
 }
 
 // y = b - y

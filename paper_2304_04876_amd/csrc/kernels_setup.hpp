@@ -380,24 +380,31 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         AT yq[BS_NB / LPR];
 #pragma unroll
         for (int q = 0; q < BS_NB / LPR; ++q) yq[q] = y[k0 + sub + q * LPR];
-        for (int r0 = k1; r0 < rend; r0 += RPI) {
-            const int r = r0 + rg;
-            AT acc = 0;
-            if (r < rend) {
+        // RB row groups per pass: all their loads are issued before the sums
+        constexpr int RB = sizeof(AT) == 8 ? 2 : 4;
+        for (int r0 = k1; r0 < rend; r0 += RB * RPI) {
+            AT v[RB][BS_NB / LPR];
+#pragma unroll
+            for (int it = 0; it < RB; ++it) {
+                const int r = r0 + it * RPI + rg;
                 const int s0 = max(0, r - b - k0);
                 const VT *row = L + int64_t(r) * w + (k0 - r + b);
-                AT v[BS_NB / LPR];
 #pragma unroll
                 for (int q = 0; q < BS_NB / LPR; ++q) {
                     const int s = sub + q * LPR;
-                    v[q] = s >= s0 ? to_acc(row[s]) : AT(0);
+                    v[it][q] = (r < rend && s >= s0) ? to_acc(row[s]) : AT(0);
                 }
-#pragma unroll
-                for (int q = 0; q < BS_NB / LPR; ++q) acc += v[q] * yq[q];
             }
 #pragma unroll
-            for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, LPR);
-            if (r < rend && sub == 0) y[r] -= acc;
+            for (int it = 0; it < RB; ++it) {
+                const int r = r0 + it * RPI + rg;
+                AT acc = 0;
+#pragma unroll
+                for (int q = 0; q < BS_NB / LPR; ++q) acc += v[it][q] * yq[q];
+#pragma unroll
+                for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, LPR);
+                if (r < rend && sub == 0) y[r] -= acc;
+            }
         }
         band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
         __syncthreads();

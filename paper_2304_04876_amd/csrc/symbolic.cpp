@@ -68,7 +68,7 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
     if (o.jacobi_sweeps < 1 || o.jacobi_sweeps > 1000) fail(GDSW_ERR_INVALID_ARG, "jacobi_sweeps");
     if (o.local_prec < GDSW_FP64 || o.local_prec > GDSW_FP16) fail(GDSW_ERR_INVALID_ARG, "local_prec");
     if (o.basis_prec != GDSW_FP64 && o.basis_prec != GDSW_FP32) fail(GDSW_ERR_INVALID_ARG, "basis_prec");
-    if (o.flags != 0) fail(GDSW_ERR_INVALID_ARG, "flags must be 0");
+    if (o.flags & ~uint64_t(GDSW_FLAG_GRAPHS)) fail(GDSW_ERR_INVALID_ARG, "unknown flags");
     if (o.ilu_level < 0 || o.ilu_level > 8) fail(GDSW_ERR_INVALID_ARG, "ilu_level out of range");
     if (o.ilu_factor_sweeps < 0 || o.ilu_factor_sweeps > 100) fail(GDSW_ERR_INVALID_ARG, "ilu_factor_sweeps");
     if (Z == nullptr && n_null > 1) fail(GDSW_ERR_INVALID_ARG, "Z == NULL needs n_null <= 1");

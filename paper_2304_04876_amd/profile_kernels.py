@@ -2,7 +2,9 @@
 rocprofv3 (kernel trace, FETCH_SIZE / WRITE_SIZE passes):
 
 * the batched local-solve kernel of the 128^3 Poisson workload (512
-  subdomains, ILU(0) + 5+5 Jacobi sweeps or banded Cholesky), ``--reps`` times;
+  subdomains, ILU(0) + 5+5 Jacobi sweeps or banded Cholesky), or with
+  ``--elasticity`` of the Q1 elasticity workload (48^3 elements, 6^3
+  boxes, banded Cholesky), ``--reps`` times;
 * the full preconditioner apply once;
 * a plain device copy of a known size (``--copy-mib`` MiB read and written),
   ``--reps`` times, to calibrate the byte counters.
@@ -23,6 +25,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--P", type=int, default=8)
+    ap.add_argument("--elasticity", action="store_true")
     a = ap.parse_args()
 
     import torch
@@ -30,9 +33,14 @@ def main():
     from paper_2304_04876_amd import problems as P
 
     precs = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16, "fp16": B.FP16}
-    pr = P.poisson3d(a.N, a.P)
+    if a.elasticity:
+        pr = P.workload_elasticity()
+        Z = P.rigid_body_modes(pr)
+    else:
+        pr = P.poisson3d(a.N, a.P)
+        Z = None
     print(f"[profile] setup {pr.name} local={a.local} prec={a.prec}", file=sys.stderr, flush=True)
-    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1,
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                local=B.LOCAL_ILU0 if a.local == "ilu0" else B.LOCAL_EXACT, local_prec=precs[a.prec],
                basis_prec=B.FP64 if a.prec == "fp64" else B.FP32)
     r = torch.from_numpy(P.rhs_uniform(pr.n, 0)).cuda()

@@ -307,3 +307,55 @@ def test_refactor_with_new_values():
     # M^{-1} of 2A is half of M^{-1} of A (every step is linear in A's scale)
     assert float((z2 - 0.5 * z1).abs().max()) <= 1e-13 * float(z1.abs().max())
     g.close()
+
+
+def test_graph_captured_cg_matches_eager():
+    """GDSW_FLAG_GRAPHS: CG chunks replayed from captured graphs give the same
+    iterates bit for bit as kernel-by-kernel queuing, over several solves in a
+    row (graphs replayed many times, eager work in between), for one problem
+    and for the slots of a batch."""
+    pr = P.poisson3d(16, 2)
+    say("[graphs] CG eager vs captured")
+    ge = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0)
+    gg = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0, flags=B.FLAG_GRAPHS)
+    for seed in range(4):
+        b = dev(P.rhs_uniform(pr.n, 40 + seed))
+        xe, xg = torch.zeros_like(b), torch.zeros_like(b)
+        oe = ge.solve(b, xe, rtol=1e-8)
+        og = gg.solve(b, xg, rtol=1e-8)
+        assert oe["iterations"] == og["iterations"] and oe["converged"]
+        assert torch.equal(xe, xg), seed
+        ze = torch.zeros_like(b)
+        ge.apply(b, ze)   # eager work between the replays
+    ge.close()
+    gg.close()
+    probs = [P.poisson3d(9, 2), P.poisson3d(11, 2)]
+    res = {}
+    for flags in (0, B.FLAG_GRAPHS):
+        hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
+                                  options=B.gdsw_default_options(local=B.LOCAL_ILU0, flags=flags))
+        B.gdsw_factor(hb)
+        offs = B.gdsw_problem_offsets(hb)
+        bb = torch.zeros(int(offs[-1]), dtype=torch.float64, device="cuda")
+        xx = torch.zeros_like(bb)
+        B.gdsw_slots_begin(hb, bb, xx, rtol=1e-8, maxit=500)
+        out = []
+        for rnd in range(2):
+            for k, p in enumerate(probs):
+                bb[offs[k]:offs[k + 1]] = dev(P.rhs_uniform(p.n, 60 + 2 * rnd + k))
+                B.gdsw_slot_start(hb, k)
+            done = set()
+            for _ in range(500):
+                st = B.gdsw_slots_step(hb, 3)
+                for k in range(len(probs)):
+                    if st[k] == 1 and k not in done:
+                        info = B.gdsw_slot_finish(hb, k)
+                        out.append((info["iterations"], xx[offs[k]:offs[k + 1]].clone()))
+                        done.add(k)
+                if len(done) == len(probs):
+                    break
+        res[flags] = out
+        B.gdsw_destroy(hb)
+    assert len(res[0]) == len(res[B.FLAG_GRAPHS]) == 4
+    for (ia, xa), (ib, xb) in zip(res[0], res[B.FLAG_GRAPHS]):
+        assert ia == ib and torch.equal(xa, xb)
