@@ -865,11 +865,11 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         if (D.phi32)
             hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart, D.kpart2);
+                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
         else
             hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart, D.kpart2);
+                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
     } else if (D.phi32) {
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
@@ -941,9 +941,9 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.sell, D.kp, D.kq, D.kpart, D.kst, all);
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
-    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kst, all);
+    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kpart2, D.kst, all);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s, D.kr);   // also the partials of r.z
-    // stop test on ||r||^2, then beta from r.z (both summed by the prolongation)
+    // stop test on ||r||^2 (partials from the update), then beta from r.z
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR_BETA), 0,
                        D.kpart2);
     hipLaunchKernelGGL(k_cg_update_p, dim3((nkb + UPB - 1) / UPB), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all, nkb);

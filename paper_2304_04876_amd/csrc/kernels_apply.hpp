@@ -472,8 +472,8 @@ __global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const in
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
-// [row0[b], row1[b]) of one problem), also writing the block's partials of
-// r . z and (partial2 != null) r . r for the next CG step.
+// [row0[b], row1[b]) of one problem), also writing the block's partial of
+// r . z for the next CG step.
 template <typename PT>
 __global__ __launch_bounds__(256) void k_prolong_dot(
     int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
@@ -481,30 +481,20 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
     const PT *__restrict__ phi, const double *__restrict__ z0, double *__restrict__ z, Skip sk,
     const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
-    double *__restrict__ partial, double *__restrict__ partial2) {
-    __shared__ double sh[8];
+    double *__restrict__ partial) {
+    __shared__ double sh[4];
     const int blk = blockIdx.x;
     const int row0 = kb_row0[blk], row1 = kb_row1[blk];
     if (sk.dof(row0)) return;
-    double dot = 0.0, rr = 0.0;
+    double dot = 0.0;
     for (int d = row0 + threadIdx.x; d < row1; d += 256) {
         const double v =
             prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
         z[d] = v;
-        const double rd = rvec[d];
-        dot += rd * v;
-        rr += rd * rd;
+        dot += rvec[d] * v;
     }
-    if (partial2) {
-        block_sum2<double, 256>(dot, rr, sh);
-        if (threadIdx.x == 0) {
-            partial[blk] = dot;
-            partial2[blk] = rr;
-        }
-    } else {
-        dot = block_sum<double, 256>(dot, sh);
-        if (threadIdx.x == 0) partial[blk] = dot;
-    }
+    dot = block_sum<double, 256>(dot, sh);
+    if (threadIdx.x == 0) partial[blk] = dot;
 }
 
 }  // namespace gdsw

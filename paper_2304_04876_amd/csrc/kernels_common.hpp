@@ -50,28 +50,6 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     return t;
 }
 
-// Two block sums with one pair of barriers (same order as block_sum for each).
-template <typename T, int NT>
-__device__ __forceinline__ void block_sum2(T &a, T &b, T *sh) {   // sh: 2 NT/64 values
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        sh[w] = a;
-        sh[NT / 64 + w] = b;
-    }
-    __syncthreads();
-    T ta = 0, tb = 0;
-#pragma unroll
-    for (int k = 0; k < NT / 64; ++k) {
-        ta += sh[k];
-        tb += sh[NT / 64 + k];
-    }
-    __syncthreads();
-    a = ta;
-    b = tb;
-}
-
 // Which parts of a launch to skip: a handle may pack several independent
 // problems (block-diagonal A); `flag[k]` != 0 means problem k is finished or
 // idle and its subdomains, coarse blocks, coarse columns and dofs are left

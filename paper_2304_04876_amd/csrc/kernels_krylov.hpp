@@ -125,18 +125,26 @@ __global__ __launch_bounds__(KNT) void k_cg_spmv_dot(Sell A, const double *__res
     if (threadIdx.x == 0) partial[blk] = dot;
 }
 
-// x += alpha p; r -= alpha q (r.r is summed with r.z after the apply)
+// x += alpha p; r -= alpha q; partials of r.r (the stop test is taken
+// together with beta after the apply)
 __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p,
-                                                      const double *__restrict__ q, const KState *st, KBlk kb) {
+                                                      const double *__restrict__ q,
+                                                      double *__restrict__ partial, const KState *st, KBlk kb) {
     const int blk = kb.base + blockIdx.x;
     const KState &S = st[kb.prob[blk]];
     if (S.done) return;
+    __shared__ double sh[KNT / 64];
     const double alpha = S.alpha;
+    double v = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
         x[i] += alpha * p[i];
-        r[i] -= alpha * q[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v += ri * ri;
     }
+    v = block_sum<double, KNT>(v, sh);
+    if (threadIdx.x == 0) partial[blk] = v;
 }
 
 // partials of a.b
@@ -194,7 +202,7 @@ enum {
     KF_RR = 3,      // rr = t, iteration count and stop tests
     KF_BETA = 4,    // beta = t / rho, rho = t
     KF_RED = 5,     // red = t
-    KF_RR_BETA = 6  // KF_RR with the totals of partial2 (r.r), then KF_BETA with t (r.z)
+    KF_RR_BETA = 6  // KF_RR with the total of partial2 (r.r), then KF_BETA with t (r.z)
 };
 
 __global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, const int32_t *__restrict__ pb_ptr,
