@@ -240,6 +240,14 @@ def main():
         alg_bytes = 2 * info["local_factor_entries"] * pbytes + info["sum_overlap_dofs"] * (4 + 8 + 8)
         kname = "k_band_apply"
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    # the whole apply (graph-replayed): local solves, coarse restriction
+    # (Phi once + row index and r per row), A_0^{-1} GEMV, prolongation
+    # (local results and their positions, dof maps, Phi again, z)
+    s_phi = 8 if args.prec == "fp64" else 4
+    nloc = info["sum_overlap_dofs"]
+    apply_bytes = (alg_bytes + 2 * info["phi_entries"] * s_phi + n * 12 + 8 * info["n0"] ** 2
+                   + nloc * 12 + n * 20)
+    apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
     traffic = None
     meas = None
     if args.ilu_level == 0:
@@ -309,6 +317,9 @@ def main():
         "setup_s": round(info["t_factor"], 3),
         "analysis_s": round(t_an, 3),
         "roofline": roofline,
+        "apply_roofline": {"bound": "hbm", "alg_bytes_per_apply": int(apply_bytes),
+                           "achieved": round(apply_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(apply_gbs / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
     }
     if err is not None:

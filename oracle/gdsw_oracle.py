@@ -262,6 +262,10 @@ class GDSW:
     def _local_factors(self):
         self.local_solvers = []
         for Ri in self.R:
+            if Ri.size == 0:
+                # a subdomain id that owns no node: its term of eq. (1) is empty
+                self.local_solvers.append(None)
+                continue
             Ai = self.A[Ri][:, Ri].tocsr()
             Ai.sort_indices()
             if self.local == "exact":
@@ -345,7 +349,8 @@ class GDSW:
         r = np.asarray(r, dtype=np.float64)
         z = np.zeros(self.n)
         for i, Ri in enumerate(self.R):
-            z[Ri] += self.local_solve(i, r[Ri])
+            if Ri.size:
+                z[Ri] += self.local_solve(i, r[Ri])
         if self.cs is not None:
             r0 = self.cs.phi.T @ r
             z0 = sla.cho_solve(self.A0_chol, r0)

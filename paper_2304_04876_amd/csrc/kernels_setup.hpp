@@ -359,6 +359,7 @@ __device__ __forceinline__ void band_block_bwd(const AT *sT, AT *y, int k0, int 
 
 template <typename VT, typename AT, int NT>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
+    if (n <= 0) return;   // an empty subdomain or interior (uniform over the workgroup)
     constexpr int G = sizeof(AT) == 8 ? 8 : 32;   // loads in flight per thread and group (backward)
     const int64_t w = b + 1;
     const int tid = threadIdx.x, lane = tid & 63;

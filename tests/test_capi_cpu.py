@@ -178,3 +178,30 @@ def test_ilu_options_validated():
         with pytest.raises(B.GdswError):
             B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, None,
                            B.gdsw_default_options(local=B.LOCAL_ILU0, **bad))
+
+
+def test_size_limits_and_degenerate_inputs():
+    """Limits and degenerate inputs are refused with INVALID_ARG, not run:
+    an empty matrix; an ILU subdomain beyond the 16-bit local column range
+    (41^3 = 68,921 dofs in one subdomain); a partition with an empty
+    subdomain is accepted (the empty subdomain has no rows)."""
+    import scipy.sparse as sp
+    empty = sp.csr_matrix((0, 0))
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(empty, np.zeros(0, dtype=np.int32), 1, 1)
+    assert e.value.status == 1
+    pr = P.poisson3d(41, 1)
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1, options=B.gdsw_default_options(local=B.LOCAL_ILU0))
+    assert e.value.status == 1 and "65535" in str(e.value)
+    # the same subdomain is fine for the exact (band) local solver
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1)
+    assert B.gdsw_get_info(h)["max_local_rows"] == 41 ** 3
+    B.gdsw_destroy(h)
+    # three parts named, the last one empty
+    pr = P.poisson3d(8, 2)
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts + 1, 1)
+    info = B.gdsw_get_info(h)
+    ovp = B.gdsw_copy_map(h, B.MAP_OV_PTR)
+    assert info["n_parts"] == pr.n_parts + 1 and ovp[-1] == ovp[-2]
+    B.gdsw_destroy(h)

@@ -359,3 +359,25 @@ def test_graph_captured_cg_matches_eager():
     assert len(res[0]) == len(res[B.FLAG_GRAPHS]) == 4
     for (ia, xa), (ib, xb) in zip(res[0], res[B.FLAG_GRAPHS]):
         assert ia == ib and torch.equal(xa, xb)
+
+
+@pytest.mark.parametrize("local", ["exact", "ilu0"])
+def test_empty_subdomain(local):
+    """A partition naming a subdomain that owns no node (id 3 of 0..8 unused):
+    the apply matches the oracle and CG converges as the oracle's does."""
+    pr = P.poisson3d(12, 2)
+    part = pr.part.copy()
+    part[part >= 3] += 1
+    n_parts = pr.n_parts + 1
+    say(f"[apply] empty subdomain local={local}")
+    M = O.GDSW(pr.A, part, 1, n_parts, local=local)
+    g = B.Gdsw(pr.A, part, n_parts, 1, local=0 if local == "exact" else 1)
+    r = P.rhs_uniform(pr.n, 13)
+    rd, zd = dev(r), torch.zeros(pr.n, dtype=torch.float64, device="cuda")
+    g.apply(rd, zd)
+    assert rel_max(host(zd), M.apply(r)) <= 1e-12
+    xd = torch.zeros_like(rd)
+    out = g.solve(rd, xd, rtol=1e-8)
+    ref = O.pcg(pr.A, r, M, rtol=1e-8)
+    assert abs(out["iterations"] - ref.iters) <= 1 and out["rel_res_true"] <= 1.5e-8
+    g.close()
