@@ -87,7 +87,7 @@ struct Device {
     hipStream_t cap = nullptr;
     struct CgGraph {
         const double *x;
-        int iters;
+        int iters, par;
         hipGraphExec_t exec;
     };
     std::vector<CgGraph> cg_graphs;
@@ -140,6 +140,8 @@ struct Device {
     // ---- Krylov ----
     double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kpart = nullptr;
     double *kpart2 = nullptr;   // second partial sums (r.r beside r.z)
+    double *kp2 = nullptr;      // the other CG direction buffer (p alternates between kp and kp2)
+    int cg_par = 0;             // which of the two holds the current direction
     KState *kst = nullptr;          // one per problem
     int *kdone = nullptr;           // done flags mirrored per problem (skip mask of the apply)
     int *kmask = nullptr;           // one-problem-active mask (slot start)
@@ -222,6 +224,7 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     D.kr = D.alloc<double>(n);
     D.kz = D.alloc<double>(n);
     D.kp = D.alloc<double>(n);
+    D.kp2 = D.alloc<double>(n);
     D.kq = D.alloc<double>(n);
     D.kt = D.alloc<double>(n);
     // Krylov row blocks: KROWS rows each, never across problems
@@ -938,15 +941,18 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     Device &D = *h->dev;
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     const int nkb = D.nkb, np = S.nprob;
-    hipLaunchKernelGGL(k_cg_spmv_dot, dim3(nkb), dim3(KNT), 0, s, D.sell, D.kp, D.kq, D.kpart, D.kst, all);
+    double *pold = D.cg_par ? D.kp2 : D.kp, *pnew = D.cg_par ? D.kp : D.kp2;
+    // p = z + beta p fused into the product with A
+    hipLaunchKernelGGL(k_cg_spmv_dot_p, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
+                       (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
-    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, D.kp, D.kq, D.kpart2, D.kst, all);
+    hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, pnew, D.kq, D.kpart2, D.kst, all);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s, D.kr);   // also the partials of r.z
     // stop test on ||r||^2 (partials from the update), then beta from r.z
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR_BETA), 0,
                        D.kpart2);
-    hipLaunchKernelGGL(k_cg_update_p, dim3((nkb + UPB - 1) / UPB), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 0, all, nkb);
+    D.cg_par ^= 1;
 }
 
 // `iters` CG iterations: queued kernel by kernel, or with GDSW_FLAG_GRAPHS as
@@ -959,8 +965,9 @@ static void queue_cg_chunk(gdsw_handle_s *h, double *x, int iters, hipStream_t s
         return;
     }
     hipGraphExec_t exec = nullptr;
+    const int par = D.cg_par;   // the direction buffers alternate: a graph is tied to its start parity
     for (auto &g : D.cg_graphs)
-        if (g.x == x && g.iters == iters) exec = g.exec;
+        if (g.x == x && g.iters == iters && g.par == par) exec = g.exec;
     if (!exec) {
         if (!D.cap) HIPCHK(hipStreamCreateWithFlags(&D.cap, hipStreamNonBlocking));
         if (D.cg_graphs.size() >= 16) {
@@ -973,6 +980,7 @@ static void queue_cg_chunk(gdsw_handle_s *h, double *x, int iters, hipStream_t s
         try {
             for (int k = 0; k < iters; ++k) queue_cg_iteration(h, x, D.cap);
         } catch (...) {
+            D.cg_par = par;
             (void)hipStreamEndCapture(D.cap, &graph);
             if (graph) (void)hipGraphDestroy(graph);
             throw;
@@ -981,8 +989,9 @@ static void queue_cg_chunk(gdsw_handle_s *h, double *x, int iters, hipStream_t s
         const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(e);
-        D.cg_graphs.push_back({x, iters, exec});
+        D.cg_graphs.push_back({x, iters, par, exec});
     }
+    D.cg_par = par ^ (iters & 1);
     HIPCHK(hipGraphLaunch(exec, s));
 }
 
@@ -1002,7 +1011,9 @@ static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, 
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 0, kb);
     hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase,
                        (const double *)nullptr);
-    hipLaunchKernelGGL(k_cg_update_p, dim3((nb + UPB - 1) / UPB), dim3(KNT), 0, s, D.kp, D.kz, D.kst, 1, kb, nb);
+    // p_old = z with beta = 0: the first product takes p = z
+    hipLaunchKernelGGL(k_cg_start_p, dim3((nb + UPB - 1) / UPB), dim3(KNT), 0, s, D.cg_par ? D.kp2 : D.kp, D.kz,
+                       kb, nb);
 }
 
 // ||b - A x|| / ||b|| of problem k (all problems: k < 0) into state.red
@@ -1298,6 +1309,7 @@ gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream) {
         k.done = 0;
         k.status = KS_RUNNING;
         k.iters = 0;
+        k.beta = 0.0;   // the first product takes p = z
         D.h_state[slot] = k;
         // this slot alone is active in the start-up apply
         std::vector<int> mask(np, 1);

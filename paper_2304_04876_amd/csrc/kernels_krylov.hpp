@@ -99,6 +99,41 @@ __global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__
     y[i] = sell_row(A, i, x);
 }
 
+// One row of A (z + beta p_old): the vector is formed on the fly from z and
+// the previous direction, the same fma for every occurrence of an entry, so
+// the value a row uses for its neighbour equals the one that neighbour
+// writes as its own p_new.
+__device__ __forceinline__ double p_next(double beta, double pold, double z) { return __builtin_fma(beta, pold, z); }
+
+__device__ __forceinline__ double sell_row_p(const Sell &A, int i, const double *__restrict__ z,
+                                             const double *__restrict__ pold, double beta) {
+    const int sl = i / SELL_C, lane = i % SELL_C;
+    const int64_t base = A.off[sl] + lane;
+    const int w = A.width[sl];
+    constexpr int U = 8;
+    double acc = 0.0;
+    for (int j0 = 0; j0 < w; j0 += U) {
+        int c[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + int64_t(j0 + u) * SELL_C;
+            c[u] = j0 + u < w ? A.col[e] : 0;
+            v[u] = j0 + u < w ? A.val[e] : 0.0;
+        }
+        double zv[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            zv[u] = j0 + u < w ? z[c[u]] : 0.0;
+            pv[u] = j0 + u < w ? pold[c[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < w) acc += v[u] * p_next(beta, pv[u], zv[u]);
+    }
+    return acc;
+}
+
 // x = 0, r = b on the rows of the launched blocks
 __global__ __launch_bounds__(KNT) void k_cg_init(double *__restrict__ x, double *__restrict__ r,
                                                  const double *__restrict__ b, KBlk kb) {
@@ -109,17 +144,25 @@ __global__ __launch_bounds__(KNT) void k_cg_init(double *__restrict__ x, double 
     }
 }
 
-// q = A p and the partials of p.q
-__global__ __launch_bounds__(KNT) void k_cg_spmv_dot(Sell A, const double *__restrict__ p, double *__restrict__ q,
-                                                     double *__restrict__ partial, const KState *st, KBlk kb) {
+// The update p = z + beta p fused into the next product: p_new = z + beta
+// p_old (written by each row for itself), q = A p_new and the partials of
+// p_new . q.  At the start of CG p_old = z and beta = 0, so p_new = z.
+__global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__restrict__ z,
+                                                       const double *__restrict__ pold, double *__restrict__ pnew,
+                                                       double *__restrict__ q, double *__restrict__ partial,
+                                                       const KState *st, KBlk kb) {
     const int blk = kb.base + blockIdx.x;
-    if (st[kb.prob[blk]].done) return;
+    const KState &S = st[kb.prob[blk]];
+    if (S.done) return;
     __shared__ double sh[KNT / 64];
+    const double beta = S.beta;
     double dot = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
-        const double acc = sell_row(A, i, p);
+        const double acc = sell_row_p(A, i, z, pold, beta);
+        const double pi = p_next(beta, pold[i], z[i]);
+        pnew[i] = pi;
         q[i] = acc;
-        dot += p[i] * acc;
+        dot += pi * acc;
     }
     dot = block_sum<double, KNT>(dot, sh);
     if (threadIdx.x == 0) partial[blk] = dot;
@@ -250,31 +293,20 @@ __global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ pa
     if (kdone) kdone[k] = S.done;
 }
 
-// p = z + beta p (init: p = z), UPB row blocks per workgroup (the loads of
-// all of them in flight together); row blocks kb.base .. kb.base + nb - 1
+// p = z on the row blocks kb.base .. kb.base + nb - 1 (start of CG), UPB
+// row blocks per workgroup
 constexpr int UPB = 4;
 static_assert(KROWS <= KNT, "one row per thread in a row block");
-__global__ __launch_bounds__(KNT) void k_cg_update_p(double *__restrict__ p, const double *__restrict__ z,
-                                                     const KState *st, int init, KBlk kb, int nb) {
-    double zv[UPB], pv[UPB], beta[UPB];
-    int idx[UPB];
+__global__ __launch_bounds__(KNT) void k_cg_start_p(double *__restrict__ p, const double *__restrict__ z, KBlk kb,
+                                                    int nb) {
 #pragma unroll
     for (int u = 0; u < UPB; ++u) {
         const int b = blockIdx.x * UPB + u;
-        idx[u] = -1;
-        if (b >= nb) continue;
+        if (b >= nb) break;
         const int blk = kb.base + b;
-        const KState &S = st[kb.prob[blk]];
         const int i = kb.row0[blk] + int(threadIdx.x);
-        if ((!init && S.done) || i >= kb.row1[blk]) continue;
-        idx[u] = i;
-        beta[u] = S.beta;
-        zv[u] = z[i];
-        pv[u] = init ? 0.0 : p[i];
+        if (i < kb.row1[blk]) p[i] = z[i];
     }
-#pragma unroll
-    for (int u = 0; u < UPB; ++u)
-        if (idx[u] >= 0) p[idx[u]] = init ? zv[u] : zv[u] + beta[u] * pv[u];
 }
 
 // y = b - y
