@@ -385,7 +385,8 @@ def bench_batch(args):
         "ms_per_step": round(1e3 * wall, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+fp32", "data": "synthetic",
         "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact_fp32_gdsw_cg",
-                   "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8},
+                   "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8,
+                   "graphs": bool(args.graphs)},
         "iterations_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
         "rel_res_true_max": res,
         "sequential_fp64_solves_per_s": round(len(probs) / seq, 2),
@@ -409,7 +410,8 @@ def bench_serve(args):
 
     ops = [P.serve_operator(N) for N in P.SERVE_SIZES]
     log("[serve] operators " + ", ".join(f"{p.name} n={p.n}" for p in ops))
-    srv = SV.Server(ops, slots_per_op=4, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+    srv = SV.Server(ops, slots_per_op=4, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32,
+                    graphs=args.graphs)
 
     def make(nreq, rate, seed):
         t, opi = SV.poisson_arrivals(nreq, rate, len(ops), seed)
@@ -431,7 +433,8 @@ def bench_serve(args):
     slots_bytes = srv.device_bytes
     srv.close()
     # forced-small HBM budget: one slot per operator
-    small = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+    small = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32,
+                      graphs=args.graphs)
     reqs, _ = small.run(make(400, 0.5 * mu, 3))
     st_small = SV.summarize(reqs, small, skip=50)
     small.close()
@@ -458,6 +461,7 @@ def bench_serve(args):
         "warmup": args.serve_warmup, "ms_per_step": round(1e3 / s5.solves_per_s, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+fp16", "data": "synthetic",
         "config": {"workload": "serve8_poisson32-96_ilu0_fp16_gdsw_cg", "slots_per_op": 4, "rtol": 1e-8,
+                   "graphs": bool(args.graphs),
                    "step_iters": srv.step_iters},
         "saturation_solves_per_s": round(mu, 2),
         "load": {str(f): {"solves_per_s": round(v.solves_per_s, 2), "p50_ms": round(v.p50_ms, 2),

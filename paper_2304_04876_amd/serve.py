@@ -55,14 +55,15 @@ class ServeStats:
 class Server:
     def __init__(self, operators, slots_per_op=None, hbm_budget_bytes=0, local=B.LOCAL_ILU0,
                  local_prec=B.FP16, basis_prec=B.FP32, rtol=1e-8, maxit=1000, step_iters=4,
-                 stream=None):
+                 stream=None, graphs=False):
         import torch
         self.torch = torch
         self.ops = operators
         self.rtol = rtol
         self.maxit = maxit
         self.step_iters = step_iters
-        self.opts = dict(local=local, local_prec=local_prec, basis_prec=basis_prec)
+        self.opts = dict(local=local, local_prec=local_prec, basis_prec=basis_prec,
+                         flags=B.FLAG_GRAPHS if graphs else 0)
         self.stream = stream
         if slots_per_op is None:
             slots_per_op = self._slots_for_budget(hbm_budget_bytes)
