@@ -34,7 +34,8 @@ Steps, in the order of the paper's construction:
   O12 coarse factor: dense Cholesky
   O13 apply, eq. (1); with ILU(0) the two triangular solves are done by
       Jacobi sweeps from a zero start (Sec. V-B: five iterations by default)
-  O14 preconditioned CG and right-preconditioned GMRES(m)
+  O14 preconditioned CG and right-preconditioned GMRES(m); O14b the
+      single-reduce GMRES(m) of the experiments (Sec. VII)
 
 Readings where the paper is silent or inconsistent are stated at each step.
 """
@@ -640,3 +641,148 @@ def gmres(A, b, M=None, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000
     if fixed_iters is not None:
         converged = true <= rtol
     return SolveResult(x, total, converged, hist[-1], true, hist)
+
+
+# ---------------------------------------------------------------------------
+# O14b single-reduce GMRES (Sec. VII: the experiments use a single-reduce
+# variant of GMRES(30), one global reduction per iteration, cited there
+# without its steps; reading: the classical Gram-Schmidt process applied
+# twice, with the second pass and the normalisation of a basis vector
+# delayed to the next step so that both share that step's one reduction.)
+#
+# Step j of a cycle holds Q = [q_0 .. q_{j-1}] (orthonormal), the columns
+# 0 .. j-2 of the unrotated Hessenberg matrix H, the candidate u for q_j
+# (already projected once against Q) with its first-pass coefficients a,
+# and z = A M^{-1} u.  One reduction gives
+#     c = Q^T u,  d = Q^T z,  e = u.u,  f = u.z.
+# Then (Pythagoras, Q orthonormal) beta = sqrt(e - c.c) is the norm of the
+# twice-projected candidate u - Q c, q_j = (u - Q c) / beta, and column j-1
+# of H is (a + c; beta).  By linearity and the Arnoldi relation
+# A M^{-1} Q = [Q q_j] H(0:j+1, 0:j),
+#     A M^{-1} q_j = (z - [Q q_j] H c) / beta,
+# whose projections onto Q and q_j follow from d, f and H c without touching
+# the vectors again; subtracting them gives the next candidate.  Step 0 has
+# Q empty and u = r, so its reduction also yields ||r||.
+# ---------------------------------------------------------------------------
+
+def sr_coefficients(H: np.ndarray, a_prev: np.ndarray, j: int, c: np.ndarray, d: np.ndarray,
+                    e: float, f: float):
+    """The small arithmetic of single-reduce step j: beta, the completed
+    column j-1 of H (written into H when j >= 1), H c and the first-pass
+    coefficients a of A M^{-1} q_j against q_0 .. q_j.  beta = 0 marks an
+    invariant Krylov space (u already lies in the span of Q)."""
+    beta2 = e - c @ c
+    beta = float(np.sqrt(beta2)) if beta2 > 0.0 else 0.0
+    if j >= 1:
+        H[:j, j - 1] = a_prev + c
+        H[j, j - 1] = beta
+    if beta == 0.0:
+        return beta, None, None
+    Hc = H[:j + 1, :j] @ c
+    a = np.empty(j + 1)
+    a[:j] = (d - Hc[:j]) / beta
+    a[j] = ((f - c @ d) / beta - Hc[j]) / beta
+    return beta, Hc, a
+
+
+def sr_basis_vector(Q: np.ndarray, j: int, u: np.ndarray, c: np.ndarray, beta: float) -> np.ndarray:
+    """q_j = (u - Q c) / beta: the candidate's second projection and its
+    normalisation."""
+    return (u - Q[:, :j] @ c) / beta
+
+
+def sr_next_candidate(Q: np.ndarray, j: int, z: np.ndarray, beta: float, Hc: np.ndarray,
+                      a: np.ndarray) -> np.ndarray:
+    """A M^{-1} q_j = (z - [Q q_j] H c) / beta, projected once against
+    q_0 .. q_j with the coefficients a."""
+    w = (z - Q[:, :j + 1] @ Hc) / beta
+    return w - Q[:, :j + 1] @ a
+
+
+def gmres_single_reduce(A, b, M=None, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000,
+                        fixed_iters: int | None = None, return_basis: bool = False):
+    """Right-preconditioned restarted GMRES(m) from x0 = 0 with one global
+    reduction per Arnoldi step (steps above).  In exact arithmetic it yields
+    the iterates of ``gmres``.  Column j-1 of H is complete one step after
+    A M^{-1} is applied to its candidate, so the residual estimate, the
+    Givens rotations and the stopping test lag by one step; the last step of
+    a cycle needs no operator application.  ``return_basis`` also returns
+    (Q, H) of the last cycle (for checks of the Arnoldi relation)."""
+    A = sp.csr_matrix(A)
+    b = np.asarray(b, dtype=np.float64)
+    apply = (lambda v: v.copy()) if M is None else M.apply
+    n = b.size
+    x = np.zeros(n)
+    bnorm = np.linalg.norm(b)
+    hist = [1.0 if bnorm > 0 else 0.0]
+    basis = None
+    if bnorm == 0.0:
+        res = SolveResult(x, 0, True, 0.0, 0.0, hist)
+        return (res, basis) if return_basis else res
+    total = 0
+    limit = fixed_iters if fixed_iters is not None else maxit
+    converged = False
+    while total < limit and not converged:
+        m = restart
+        Q = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        R = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        u = b - A @ x
+        a = np.zeros(0)
+        k = 0              # completed columns of this cycle
+        stop = False
+        for j in range(m + 1):
+            z = A @ apply(u) if j < m else None
+            c = Q[:, :j].T @ u
+            e = u @ u
+            d = Q[:, :j].T @ z if z is not None else np.zeros(j)
+            f = u @ z if z is not None else 0.0
+            beta, Hc, a_new = sr_coefficients(H, a, j, c, d, e, f)
+            if j == 0:
+                g[0] = beta
+                if beta == 0.0 or (fixed_iters is None and beta <= rtol * bnorm):
+                    converged = True
+                    break
+            else:
+                # Givens rotations on the completed column j-1
+                R[:j + 1, j - 1] = H[:j + 1, j - 1]
+                for i in range(j - 1):
+                    t = cs[i] * R[i, j - 1] + sn[i] * R[i + 1, j - 1]
+                    R[i + 1, j - 1] = -sn[i] * R[i, j - 1] + cs[i] * R[i + 1, j - 1]
+                    R[i, j - 1] = t
+                den = np.hypot(R[j - 1, j - 1], R[j, j - 1])
+                cs[j - 1] = R[j - 1, j - 1] / den
+                sn[j - 1] = R[j, j - 1] / den
+                R[j - 1, j - 1] = den
+                R[j, j - 1] = 0.0
+                g[j] = -sn[j - 1] * g[j - 1]
+                g[j - 1] = cs[j - 1] * g[j - 1]
+                total += 1
+                k = j
+                hist.append(abs(g[j]) / bnorm)
+                if fixed_iters is None and abs(g[j]) <= rtol * bnorm:
+                    converged = True
+                    stop = True
+                elif total >= limit:
+                    stop = True
+            if beta == 0.0:
+                break
+            Q[:, j] = sr_basis_vector(Q, j, u, c, beta)
+            if stop or j == m:
+                break
+            u = sr_next_candidate(Q, j, z, beta, Hc, a_new)
+            a = a_new
+        if k > 0:
+            y = sla.solve_triangular(R[:k, :k], g[:k])
+            x += apply(Q[:, :k] @ y)
+        basis = (Q[:, :k + 1].copy(), H[:k + 1, :k].copy())
+        if k == 0:
+            break
+    true = np.linalg.norm(b - A @ x) / bnorm
+    if fixed_iters is not None:
+        converged = true <= rtol
+    res = SolveResult(x, total, converged, hist[-1], true, hist)
+    return (res, basis) if return_basis else res

@@ -160,3 +160,63 @@ def test_mutant_iluk_without_fill(monkeypatch):
     monkeypatch.setattr(O, "iluk_pattern", lambda A, level: real(A, 0))
     with pytest.raises(AssertionError):
         T.test_ilu1_fill_of_the_7point_stencil()
+
+
+# single-reduce GMRES: planted mistakes in the per-step arithmetic.  (Errors
+# in the first-pass coefficients alone are not planted: the next step's
+# second pass measures and removes them, so they change results only at
+# rounding level.)
+def _mutant_sr_coefficients(mode):
+    def coeffs(H, a_prev, j, c, d, e, f):
+        beta2 = e if mode == "no_pythagoras" else e - c @ c
+        beta = float(np.sqrt(beta2)) if beta2 > 0.0 else 0.0
+        if j >= 1:
+            H[:j, j - 1] = a_prev + c
+            H[j, j - 1] = beta
+        if beta == 0.0:
+            return beta, None, None
+        Hc = H[:j + 1, :j] @ c
+        if mode == "no_relation":
+            Hc = 0.0 * Hc
+        a = np.empty(j + 1)
+        a[:j] = (d - Hc[:j]) / beta
+        a[j] = ((f - c @ d) / beta - Hc[j]) / beta
+        return beta, Hc, a
+    return coeffs
+
+
+def _sr_pins_fail():
+    from tests import test_oracle_gmres_sr_pins as T
+    failures = 0
+    for fn in (lambda: T.test_arnoldi_relation_and_orthonormal_basis(17),
+               lambda: T.test_nearly_invariant_krylov_space(1e-12),
+               lambda: T.test_same_iterates_as_mgs_gmres(30),
+               lambda: T.test_minimal_residual_over_krylov_space(6)):
+        try:
+            fn()
+        except AssertionError:
+            failures += 1
+    return failures
+
+
+def test_sr_pins_pass_unmutated():
+    assert _sr_pins_fail() == 0
+
+
+@pytest.mark.parametrize("mode", ["no_pythagoras", "no_relation"])
+def test_mutant_single_reduce_coefficients(monkeypatch, mode):
+    monkeypatch.setattr(O, "sr_coefficients", _mutant_sr_coefficients(mode))
+    assert _sr_pins_fail() > 0
+
+
+def test_mutant_single_reduce_one_pass(monkeypatch):
+    monkeypatch.setattr(O, "sr_basis_vector", lambda Q, j, u, c, beta: u / beta)
+    assert _sr_pins_fail() > 0
+
+
+def test_mutant_single_reduce_unscaled_direction(monkeypatch):
+    def bad(Q, j, z, beta, Hc, a):
+        w = z - Q[:, :j + 1] @ Hc
+        return w - Q[:, :j + 1] @ a
+    monkeypatch.setattr(O, "sr_next_candidate", bad)
+    assert _sr_pins_fail() > 0
