@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--graphs", action="store_true", help="queue CG iterations as captured HIP graphs")
+    ap.add_argument("--gmres", choices=["single_reduce", "classical"], default="single_reduce",
+                    help="GMRES variant of the elasticity workload: one reduction per iteration (the "
+                         "paper's experiments) or classical Gram-Schmidt applied twice")
     ap.add_argument("--ilu-level", type=int, default=0)
     ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--N", type=int, default=None)
@@ -109,7 +112,7 @@ def main():
         log(f"[bench] building Q1 elasticity {N}^3 with {Pn}^3 boxes")
         pr = P.elasticity_q1(N, Pn)
         Z = P.rigid_body_modes(pr)
-        krylov = B.KRYLOV_GMRES
+        krylov = B.KRYLOV_GMRES_SR if args.gmres == "single_reduce" else B.KRYLOV_GMRES
     else:
         N, Pn = args.N or 128, args.P or 8
         log(f"[bench] building Poisson {N}^3 with {Pn}^3 boxes")
@@ -271,7 +274,8 @@ def main():
             b0 = rhs[args.warmup].cpu().numpy()
             t0 = time.perf_counter()
             if elastic:
-                res = O.gmres(pr.A, b0, M, rtol=1e-8, restart=30)
+                res = (O.gmres_single_reduce if args.gmres == "single_reduce" else O.gmres)(
+                    pr.A, b0, M, rtol=1e-8, restart=30)
             else:
                 res = O.pcg(pr.A, b0, M, rtol=1e-8)
             t_cpu = time.perf_counter() - t0
@@ -301,7 +305,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
         "data": "synthetic",
-        "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30" if elastic
+        "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30"
+                                f"{'_single_reduce' if args.gmres == 'single_reduce' else ''}" if elastic
                                 else f"poisson{N}^3_P{Pn}^3_{local_name}_gdsw_cg"), "n": n,
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
                    "jacobi_sweeps": 5, "ilu_level": args.ilu_level, "ilu_factor_sweeps": args.factor_sweeps,

@@ -73,7 +73,7 @@ enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2, GDSW_FP16 = 3 };
 enum { GDSW_FLAG_GRAPHS = 1 };
 
 /* Krylov method of gdsw_solve. */
-enum { GDSW_KRYLOV_CG = 0, GDSW_KRYLOV_GMRES = 1 };
+enum { GDSW_KRYLOV_CG = 0, GDSW_KRYLOV_GMRES = 1, GDSW_KRYLOV_GMRES_SR = 2 };
 
 typedef struct {
     int32_t overlap;          /* layers of graph overlap (>= 0); paper: 1        */
@@ -205,8 +205,16 @@ gdsw_status gdsw_apply_part(gdsw_handle h, const double *r_dev, double *z_dev,
 gdsw_status gdsw_spmv(gdsw_handle h, const double *x_dev, double *y_dev, void *stream);
 
 /* Preconditioned Krylov solve of A x = b (Sec. VII), x0 = 0.
- *   krylov : GDSW_KRYLOV_CG or GDSW_KRYLOV_GMRES (right preconditioned).
- *   restart: GMRES restart length (paper: 30); ignored by CG.
+ *   krylov : GDSW_KRYLOV_CG, GDSW_KRYLOV_GMRES (right preconditioned,
+ *            classical Gram-Schmidt applied twice: three reductions per
+ *            iteration) or GDSW_KRYLOV_GMRES_SR (the single-reduce GMRES of
+ *            the paper's experiments, Sec. VII: the same iterates in exact
+ *            arithmetic, one reduction per iteration; the second projection
+ *            pass and the normalisation of each basis vector are delayed to
+ *            the next iteration, so convergence is seen one iteration later
+ *            and one extra preconditioned product is formed).
+ *            The GMRES variants need a handle with one problem.
+ *   restart: GMRES restart length (paper: 30, at most 64); ignored by CG.
  *   rtol   : stop when ||r_k||_2 <= rtol ||b||_2.
  *   maxit  : iteration cap.  If fixed_iters > 0 exactly that many iterations
  *            are run whatever the residual (used to compare iterates).

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "SINGULAR", 3: "BREAKDOWN", 4: "NO
 COARSE_NONE, COARSE_GDSW = 0, 1
 LOCAL_EXACT, LOCAL_ILU0 = 0, 1
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
-KRYLOV_CG, KRYLOV_GMRES = 0, 1
+KRYLOV_CG, KRYLOV_GMRES, KRYLOV_GMRES_SR = 0, 1, 2
 FLAG_GRAPHS = 1
 MAP_OV_PTR, MAP_OV_IDX, MAP_IS_GAMMA, MAP_COMP_OF_NODE, MAP_COMP_RANK = 0, 1, 2, 3, 4
 MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8

@@ -1103,7 +1103,7 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
 }
 
 gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restart, double rtol, int maxit,
-                        int fixed, gdsw_solve_info *info, hipStream_t s);
+                        int fixed, bool single_reduce, gdsw_solve_info *info, hipStream_t s);
 
 gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart, double rtol, int maxit,
                   int fixed_iters, gdsw_solve_info *info, int ninfo, void *stream) {
@@ -1112,7 +1112,7 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
         return GDSW_ERR_STATE;
     }
     if (!b || !x || b == x || !(rtol >= 0.0) || maxit < 0 || fixed_iters < 0 ||
-        (krylov != GDSW_KRYLOV_CG && krylov != GDSW_KRYLOV_GMRES)) {
+        (krylov != GDSW_KRYLOV_CG && krylov != GDSW_KRYLOV_GMRES && krylov != GDSW_KRYLOV_GMRES_SR)) {
         h->err = "solve: bad arguments";
         return GDSW_ERR_INVALID_ARG;
     }
@@ -1127,7 +1127,7 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
                 h->err = "GMRES needs a handle with one problem";
                 return GDSW_ERR_INVALID_ARG;
             }
-            st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, info, s);
+            st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, krylov == GDSW_KRYLOV_GMRES_SR, info, s);
         }
     } catch (const DevError &e) {
         h->err = e.msg;
@@ -1145,8 +1145,12 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
 // orthogonalised against V_0..V_j twice, Givens rotations on the new
 // Hessenberg column, stop when |g_{j+1}| <= rtol ||b||; at the end of the
 // cycle x += M^{-1} (V y) with y the small least-squares solution.
+// single_reduce: the same iteration with one reduction per step (the
+// second projection pass and the normalisation delayed one step; the
+// kernels k_sr_*); a cycle of m columns takes m + 1 steps, the last one
+// without an operator application.
 gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restart, double rtol, int maxit,
-                        int fixed, gdsw_solve_info *info, hipStream_t s) {
+                        int fixed, bool single_reduce, gdsw_solve_info *info, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const int64_t n = S.n;
@@ -1159,7 +1163,8 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     }
     if (!D.gm_st) D.gm_st = D.alloc<GState>(1);
     const int gr = std::min(GM_RED, g);
-    if (!D.gm_part) D.gm_part = D.alloc<double>(int64_t(GM_RED) * (GM_MAX + 1));
+    if (!D.gm_part) D.gm_part = D.alloc<double>(std::max<int64_t>(int64_t(GM_RED) * (GM_MAX + 1),
+                                                                 int64_t(SR_MAXB) * SR_NV));
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     // ||b||^2
     KState ks{};
@@ -1188,7 +1193,48 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     Skip gsk;
     gsk.flag = &st->cycle_done;
     int guard = 0;
-    while (true) {
+    const int64_t sr_chunks = (n + int64_t(KNT) * SR_R - 1) / (int64_t(KNT) * SR_R);
+    const int sr_nb = int(std::min<int64_t>(sr_chunks, SR_MAXB));
+    while (single_reduce) {
+        // u = r = b - A x; step 0 forms ||r|| in its reduction
+        hipLaunchKernelGGL(k_sr_cycle_start, dim3(1), dim3(1024), 0, s, st);
+        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+        hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
+        int queued = 0, chunk = 4;
+        while (true) {
+            const int c = std::min(chunk, m + 1 - queued);
+            for (int k = 0; k < c; ++k) {
+                const int j = queued + k;
+                const bool last = j == m;   // completes column m-1 only
+                if (!last) {
+                    launch_apply(h, r, t, 3, gsk, s);
+                    hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
+                }
+                hipLaunchKernelGGL(k_sr_reduce, dim3(sr_nb), dim3(KNT), 0, s, V, r, last ? nullptr : w, n, j,
+                                   D.gm_part, st);
+                hipLaunchKernelGGL(k_sr_finish, dim3(1), dim3(SR_FIN_NT), 0, s, D.gm_part, sr_nb, st, j);
+                if (!last)
+                    hipLaunchKernelGGL(k_sr_update, dim3(nblocks(n, 256)), dim3(256), 0, s, V, r, w, n, j, st);
+            }
+            queued += c;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hs, st, GSTATE_POLL, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hs->cycle_done || queued > m) break;
+            chunk = std::min(chunk * 2, 16);
+        }
+        if (hs->j > 0 && hs->status != KS_BREAKDOWN) {
+            hipLaunchKernelGGL(k_gm_lsq, dim3(1), dim3(64), 0, s, st);
+            hipLaunchKernelGGL(k_gm_combine, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, u, n, st);
+            launch_apply(h, u, t, 3, Skip(), s);
+            hipLaunchKernelGGL(k_add, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, t, n);
+        }
+        HIPCHK(hipMemcpyAsync(hs, st, GSTATE_POLL, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hs->done || hs->j == 0) break;
+        if (++guard > maxit + 2) break;
+    }
+    while (!single_reduce) {
         // r = b - A x
         hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
@@ -1204,7 +1250,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
                 hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
                 for (int pass = 0; pass < 2; ++pass) {
                     hipLaunchKernelGGL(k_gm_dots, dim3(gr), dim3(KNT), 0, s, V, w, n, D.gm_part, st);
-                    hipLaunchKernelGGL(k_gm_dots_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st, pass);
+                    hipLaunchKernelGGL(k_gm_dots_finish, dim3(1), dim3(GM_FIN_NT), 0, s, D.gm_part, gr, st, pass);
                     hipLaunchKernelGGL(k_gm_subtract, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, w, n, st);
                 }
                 hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, w, n, D.gm_part, st, 0);
@@ -1213,7 +1259,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
             }
             queued += c;
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hs, st, GSTATE_POLL, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (hs->cycle_done || queued >= m) break;
             chunk = std::min(chunk * 2, 16);
@@ -1224,7 +1270,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
             launch_apply(h, u, t, 3, Skip(), s);
             hipLaunchKernelGGL(k_add, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, t, n);
         }
-        HIPCHK(hipMemcpyAsync(hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hs, st, GSTATE_POLL, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hs->done) break;
         if (++guard > maxit + 2) break;

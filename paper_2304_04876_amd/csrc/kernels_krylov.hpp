@@ -8,6 +8,8 @@
 // partial writes before the final sum; no device-wide fences are needed.)
 #pragma once
 
+#include <cstddef>
+
 #include "kernels_common.hpp"
 
 namespace gdsw {
@@ -335,15 +337,52 @@ constexpr int GM_MAX = 64;   // largest restart length
 constexpr int GM_RED = 1024; // workgroups of the GMRES reductions (grid-stride rows)
 
 struct GState {
-    double H[(GM_MAX + 1) * GM_MAX];   // column-major, leading dimension GM_MAX+1
-    double cs[GM_MAX], sn[GM_MAX], g[GM_MAX + 1], y[GM_MAX];
-    double h[GM_MAX + 1];              // coefficients of the current projection
+    // the part the host polls (copied back up to `cs`)
     double bb, rtol2, beta, wnorm;
-    int j;          // columns of the current cycle so far
+    int j;          // completed columns of the current cycle
     int total;      // Arnoldi steps overall
     int m, fixed, maxit;
     int cycle_done, done, status;
+    double g[GM_MAX + 1];
+    // device only
+    double cs[GM_MAX], sn[GM_MAX], y[GM_MAX];
+    double h[GM_MAX + 1];              // coefficients of the current projection
+    double H[(GM_MAX + 1) * GM_MAX];   // column-major, leading dimension GM_MAX+1 (rotated columns)
+    // single-reduce variant
+    double Hu[(GM_MAX + 1) * GM_MAX];  // the same columns before the rotations
+    double a[GM_MAX + 1];              // first-pass coefficients of the pending column
+    double cc[GM_MAX], cg[GM_MAX + 1]; // coefficients of the vector update
+    double inv_beta;
 };
+constexpr size_t GSTATE_POLL = offsetof(GState, cs);
+constexpr int GM_LD = GM_MAX + 1;
+
+// out[v] = sum over b < np of p[v * sv + b * sb], v < nv, by one workgroup:
+// a wavefront takes VU values at a time, its lanes stride over b, then the
+// wavefront's fixed tree; the order depends only on np.
+template <int NT>
+__device__ void sum_partial_values(const double *__restrict__ p, int64_t sv, int64_t sb, int np, int nv,
+                                   double *out) {
+    constexpr int NW = NT / 64, VU = 4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int v0 = wave * VU; v0 < nv; v0 += NW * VU) {
+        double acc[VU];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) acc[u] = 0.0;
+        for (int b = lane; b < np; b += 64) {
+            double t[VU];
+#pragma unroll
+            for (int u = 0; u < VU; ++u) t[u] = v0 + u < nv ? p[(v0 + u) * sv + b * sb] : 0.0;
+#pragma unroll
+            for (int u = 0; u < VU; ++u) acc[u] += t[u];
+        }
+#pragma unroll
+        for (int u = 0; u < VU; ++u) {
+            const double t = wave_sum(acc[u]);
+            if (lane == 0 && v0 + u < nv) out[v0 + u] = t;
+        }
+    }
+}
 
 // w = A t (skipped once the cycle has stopped)
 __global__ __launch_bounds__(KNT) void k_gm_spmv(Sell A, const double *__restrict__ t, double *__restrict__ w, int n,
@@ -386,13 +425,16 @@ __global__ __launch_bounds__(KNT) void k_gm_dots(const double *__restrict__ V, c
 }
 
 // h[i] = sum of the partials (index order); add = 1 adds into H(:, j)
-__global__ __launch_bounds__(KNT) void k_gm_dots_finish(const double *__restrict__ partial, int np, GState *st,
-                                                        int add) {
+constexpr int GM_FIN_NT = 1024;
+__global__ __launch_bounds__(GM_FIN_NT) void k_gm_dots_finish(const double *__restrict__ partial, int np, GState *st,
+                                                              int add) {
     if (st->cycle_done) return;
+    __shared__ double sv[GM_MAX + 1];
     const int j = st->j;
-    for (int i = threadIdx.x; i <= j; i += KNT) {
-        double t = 0.0;
-        for (int b = 0; b < np; ++b) t += partial[int64_t(b) * (GM_MAX + 1) + i];
+    sum_partial_values<GM_FIN_NT>(partial, 1, GM_MAX + 1, np, j + 1, sv);
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += GM_FIN_NT) {
+        const double t = sv[i];
         st->h[i] = t;
         if (add) st->H[j * (GM_MAX + 1) + i] += t;
         else st->H[j * (GM_MAX + 1) + i] = t;
@@ -536,6 +578,281 @@ __global__ void k_gm_combine(const double *__restrict__ V, double *__restrict__ 
 __global__ void k_add(double *__restrict__ x, const double *__restrict__ t, int64_t n) {
     for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n; r += int64_t(gridDim.x) * blockDim.x)
         x[r] += t[r];
+}
+
+// ---------------------------------------------------------------------------
+// Single-reduce GMRES(m) (Sec. VII: the experiments' Krylov solver performs
+// one global reduction per iteration).  Classical Gram-Schmidt applied
+// twice, with the second pass and the normalisation of each basis vector
+// delayed to the next step so that both share its one reduction.  Step j
+// holds Q = [q_0 .. q_{j-1}], the candidate u for q_j (projected once) and
+// z = A M^{-1} u.  One reduction gives c = Q^T u, d = Q^T z, e = u.u,
+// f = u.z; then beta = sqrt(e - c.c), q_j = (u - Q c) / beta, column j-1 of
+// H = (a + c; beta), and, by the Arnoldi relation,
+// A M^{-1} q_j = (z - [Q q_j] H c) / beta, whose projections a onto
+// q_0 .. q_j follow from d, f and H c; the next candidate is
+// A M^{-1} q_j - [Q q_j] a.  Step 0 has Q empty and u = r.
+
+constexpr int SR_R = 4;          // rows per thread and chunk of the reduction
+constexpr int SR_MAXB = 1024;    // workgroups of the reduction (chunks are strided over them)
+constexpr int SR_NV = 2 * GM_MAX + 2;
+
+// Partials of c_i (value i), d_i (j + i), e (2j), f (2j + 1), value-major:
+// partial[v * SR_MAXB + block].  z == nullptr (the last step of a cycle):
+// d and f are zero.
+__global__ __launch_bounds__(KNT) void k_sr_reduce(const double *__restrict__ Q, const double *__restrict__ u,
+                                                   const double *__restrict__ z, int64_t n, int j,
+                                                   double *__restrict__ partial, const GState *st) {
+    if (st->cycle_done) return;
+    __shared__ double sh[KNT / 64][SR_NV];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nv = 2 * j + 2;
+    for (int v = lane; v < nv; v += 64) sh[wave][v] = 0.0;
+    const int64_t nchunk = (n + int64_t(KNT) * SR_R - 1) / (int64_t(KNT) * SR_R);
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int64_t r0 = ch * KNT * SR_R + threadIdx.x;
+        double uu[SR_R], zz[SR_R];
+#pragma unroll
+        for (int k = 0; k < SR_R; ++k) {
+            const int64_t r = r0 + int64_t(k) * KNT;
+            uu[k] = r < n ? u[r] : 0.0;
+            zz[k] = (z != nullptr && r < n) ? z[r] : 0.0;
+        }
+        double e = 0.0, f = 0.0;
+#pragma unroll
+        for (int k = 0; k < SR_R; ++k) {
+            e += uu[k] * uu[k];
+            f += uu[k] * zz[k];
+        }
+        e = wave_sum(e);
+        f = wave_sum(f);
+        if (lane == 0) {
+            sh[wave][2 * j] += e;
+            sh[wave][2 * j + 1] += f;
+        }
+        // four basis vectors at a time: all their loads are issued first
+        constexpr int U = 4;
+        int i = 0;
+        for (; i + U <= j; i += U) {
+            double q[U][SR_R];
+#pragma unroll
+            for (int t = 0; t < U; ++t)
+#pragma unroll
+                for (int k = 0; k < SR_R; ++k) {
+                    const int64_t r = r0 + int64_t(k) * KNT;
+                    q[t][k] = r < n ? Q[int64_t(i + t) * n + r] : 0.0;
+                }
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                double c = 0.0, d = 0.0;
+#pragma unroll
+                for (int k = 0; k < SR_R; ++k) {
+                    c += q[t][k] * uu[k];
+                    d += q[t][k] * zz[k];
+                }
+                c = wave_sum(c);
+                d = wave_sum(d);
+                if (lane == 0) {
+                    sh[wave][i + t] += c;
+                    sh[wave][j + i + t] += d;
+                }
+            }
+        }
+        for (; i < j; ++i) {
+            double c = 0.0, d = 0.0;
+#pragma unroll
+            for (int k = 0; k < SR_R; ++k) {
+                const int64_t r = r0 + int64_t(k) * KNT;
+                const double q = r < n ? Q[int64_t(i) * n + r] : 0.0;
+                c += q * uu[k];
+                d += q * zz[k];
+            }
+            c = wave_sum(c);
+            d = wave_sum(d);
+            if (lane == 0) {
+                sh[wave][i] += c;
+                sh[wave][j + i] += d;
+            }
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += KNT) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < KNT / 64; ++w) t += sh[w][v];
+        partial[int64_t(v) * SR_MAXB + blockIdx.x] = t;
+    }
+}
+
+// The small arithmetic of step j (one workgroup): sums the partials,
+// completes column j-1 of H, forms H c, the first-pass coefficients of the
+// next column and the vector-update coefficients, then (one thread) the
+// Givens rotation of column j-1, g and the stopping tests.
+constexpr int SR_FIN_NT = 1024;
+__global__ __launch_bounds__(SR_FIN_NT) void k_sr_finish(const double *__restrict__ partial, int np, GState *st,
+                                                         int j) {
+    if (st->cycle_done) return;
+    __shared__ double sv[SR_NV];
+    __shared__ double sH[GM_LD * GM_MAX];
+    __shared__ double sHc[GM_MAX + 1], scs[GM_MAX], ssn[GM_MAX], sdot[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    sum_partial_values<SR_FIN_NT>(partial, SR_MAXB, 1, np, 2 * j + 2, sv);
+    // columns 0 .. j-2 (rows 0 .. j), the rotations so far
+    for (int i = 0; i + 1 < j; ++i)
+        for (int k = tid; k <= j; k += SR_FIN_NT) sH[k + i * GM_LD] = st->Hu[k + i * GM_LD];
+    for (int i = tid; i + 1 < j; i += SR_FIN_NT) {
+        scs[i] = st->cs[i];
+        ssn[i] = st->sn[i];
+    }
+    __syncthreads();
+    const double *c = sv, *d = sv + j;
+    const double e = sv[2 * j], f = sv[2 * j + 1];
+    if (wave == 0) {
+        double cc = 0.0, cd = 0.0;
+        for (int i = lane; i < j; i += 64) {
+            cc += c[i] * c[i];
+            cd += c[i] * d[i];
+        }
+        cc = wave_sum(cc);
+        cd = wave_sum(cd);
+        if (lane == 0) {
+            sdot[0] = cc;
+            sdot[1] = cd;
+        }
+    }
+    for (int i = tid; i < j; i += SR_FIN_NT) sH[i + (j - 1) * GM_LD] = st->a[i] + c[i];
+    __syncthreads();
+    const double beta2 = e - sdot[0];
+    const bool finite = isfinite(beta2) && isfinite(f);
+    const double beta = beta2 > 0.0 && finite ? sqrt(beta2) : 0.0;
+    if (j >= 1 && tid == 0) sH[j + (j - 1) * GM_LD] = beta;
+    __syncthreads();
+    if (j >= 1)
+        for (int k = tid; k <= j; k += SR_FIN_NT) st->Hu[k + (j - 1) * GM_LD] = sH[k + (j - 1) * GM_LD];
+    for (int k = tid; k <= j; k += SR_FIN_NT) {
+        double t = 0.0;   // (H c)_k: column i has rows 0 .. i+1
+        for (int i = k > 0 ? k - 1 : 0; i < j; ++i) t += sH[k + i * GM_LD] * c[i];
+        sHc[k] = t;
+    }
+    __syncthreads();
+    if (beta > 0.0) {
+        const double ib = 1.0 / beta;
+        for (int k = tid; k <= j; k += SR_FIN_NT) {
+            const double a = k < j ? (d[k] - sHc[k]) * ib : ((f - sdot[1]) * ib - sHc[j]) * ib;
+            st->a[k] = a;
+            st->cg[k] = sHc[k] * ib + a;
+            if (k < j) st->cc[k] = c[k];
+        }
+        if (tid == 0) st->inv_beta = ib;
+    }
+    if (tid != 0) return;
+    if (!finite) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_BREAKDOWN;
+        return;
+    }
+    if (j == 0) {
+        // ||r|| of the cycle's start
+        st->beta = beta;
+        st->wnorm = beta;
+        st->g[0] = beta;
+        if (beta == 0.0 || (st->fixed <= 0 && beta2 <= st->rtol2 * st->bb) ||
+            (st->fixed > 0 && st->total >= st->fixed)) {
+            st->cycle_done = 1;
+            st->done = 1;
+            st->status = KS_CONVERGED;
+        }
+        return;
+    }
+    // Givens rotations on the completed column j-1
+    double *x = sH + (j - 1) * GM_LD;
+    for (int i = 0; i + 1 < j; ++i) {
+        const double t = scs[i] * x[i] + ssn[i] * x[i + 1];
+        x[i + 1] = -ssn[i] * x[i] + scs[i] * x[i + 1];
+        x[i] = t;
+    }
+    const double den = sqrt(x[j - 1] * x[j - 1] + x[j] * x[j]);
+    if (!(den > 0.0) || !isfinite(den)) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_BREAKDOWN;
+        return;
+    }
+    const double cj = x[j - 1] / den, sj = x[j] / den;
+    st->cs[j - 1] = cj;
+    st->sn[j - 1] = sj;
+    x[j - 1] = den;
+    x[j] = 0.0;
+    double *Rj = st->H + (j - 1) * GM_LD;
+    for (int k = 0; k <= j; ++k) Rj[k] = x[k];
+    const double gp = st->g[j - 1];
+    st->g[j] = -sj * gp;
+    st->g[j - 1] = cj * gp;
+    st->j = j;
+    st->total += 1;
+    st->wnorm = beta;
+    const double res2 = st->g[j] * st->g[j];
+    if (st->fixed > 0) {
+        if (st->total >= st->fixed) { st->cycle_done = 1; st->done = 1; st->status = KS_CONVERGED; }
+    } else if (res2 <= st->rtol2 * st->bb) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_CONVERGED;
+    } else if (st->total >= st->maxit) {
+        st->cycle_done = 1;
+        st->done = 1;
+        st->status = KS_MAXIT;
+    }
+    if (j >= st->m) st->cycle_done = 1;
+    // an invariant Krylov space: the cycle holds the solution
+    if (beta == 0.0) st->cycle_done = 1;
+}
+
+// q_j = (u - Q c) / beta into column j of Q, and the next candidate
+// u = z / beta - sum_{k <= j} cg_k q_k (the same pass over Q).
+__global__ __launch_bounds__(256) void k_sr_update(double *__restrict__ Q, double *__restrict__ u,
+                                                   const double *__restrict__ z, int64_t n, int j,
+                                                   const GState *st) {
+    if (st->cycle_done) return;
+    const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= n) return;
+    double ac = 0.0, ag = 0.0;
+    constexpr int U = 8;
+    int i = 0;
+    for (; i + U <= j; i += U) {
+        double q[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) q[t] = Q[int64_t(i + t) * n + r];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            ac += st->cc[i + t] * q[t];
+            ag += st->cg[i + t] * q[t];
+        }
+    }
+    for (; i < j; ++i) {
+        const double q = Q[int64_t(i) * n + r];
+        ac += st->cc[i] * q;
+        ag += st->cg[i] * q;
+    }
+    const double ib = st->inv_beta;
+    const double qj = (u[r] - ac) * ib;
+    Q[int64_t(j) * n + r] = qj;
+    u[r] = (z[r] * ib - ag) - st->cg[j] * qj;
+}
+
+// start of a single-reduce cycle: H, g and the step count cleared
+__global__ void k_sr_cycle_start(GState *st) {
+    if (st->done) return;
+    for (int i = threadIdx.x; i < GM_LD * GM_MAX; i += blockDim.x) {
+        st->H[i] = 0.0;
+        st->Hu[i] = 0.0;
+    }
+    for (int i = threadIdx.x; i <= GM_MAX; i += blockDim.x) st->g[i] = 0.0;
+    if (threadIdx.x == 0) {
+        st->j = 0;
+        st->cycle_done = 0;
+    }
 }
 
 }  // namespace gdsw
