@@ -279,6 +279,22 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
  * one stream / two streams.  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
+/* Pins the launch configurations gdsw_autotune chooses from, for callers
+ * that fix them themselves (and for tests of each configuration):
+ *   local_variant: -1 = fixed rule, else an index of times_ms[0..3] above;
+ *   gemv_variant : -1 = rule (workgroup per row from n0 >= 1024), 0 = one
+ *                  wavefront per row, 1 = one workgroup per row;
+ *   apply_streams: -1 = rule (two streams when there are fewer subdomains
+ *                  than compute units), 1 or 2.
+ * The local variant is launched once on `stream` (on internal buffers) to
+ * check that it fits the handle; one that does not (LDS, registers) gives
+ * GDSW_ERR_INVALID_ARG and nothing changes.  The local-solve and stream
+ * configurations compute each value in the same order (results do not
+ * depend on them); the two GEMV variants sum a row of A_0^{-1} in different
+ * orders and agree to rounding. */
+gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant,
+                            int32_t apply_streams, void *stream);
+
 /* Dof offsets of the problems of a handle: offsets[count+1] (host). */
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);
 

@@ -37,7 +37,7 @@ EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refacto
             "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
-            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune")
+            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch")
 
 
 class Options(ctypes.Structure):
@@ -107,6 +107,7 @@ def lib():
         "gdsw_slot_finish": (ctypes.c_int, [vp, i32, ctypes.POINTER(SolveInfo), vp]),
         "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
         "gdsw_autotune": (ctypes.c_int, [vp, i32, vp, vp]),
+        "gdsw_set_launch": (ctypes.c_int, [vp, i32, i32, i32, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -311,6 +312,11 @@ def gdsw_autotune(h, reps=10, stream=None) -> list:
     times = np.full(8, -1.0, dtype=np.float32)
     _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
     return times.tolist()
+
+
+def gdsw_set_launch(h, local_variant=-1, gemv_variant=-1, apply_streams=-1, stream=None):
+    _check(h, lib().gdsw_set_launch(h, int(local_variant), int(gemv_variant), int(apply_streams),
+                                    _stream(stream)))
 
 
 def gdsw_problem_offsets(h) -> np.ndarray:

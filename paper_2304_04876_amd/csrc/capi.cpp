@@ -76,6 +76,12 @@ gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *st
     return gdsw::autotune(h, reps, times_ms, stream);
 }
 
+gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant, int32_t apply_streams,
+                            void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::set_launch(h, local_variant, gemv_variant, apply_streams, stream);
+}
+
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
     if (!h || !offsets) return GDSW_ERR_INVALID_ARG;
     if (!h->analyzed) return GDSW_ERR_STATE;

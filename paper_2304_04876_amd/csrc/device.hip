@@ -762,7 +762,6 @@ static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, con
 template <typename VT, int NT>
 static bool launch_band(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
     using AT = typename AccOf<VT>::type;
-    if (std::is_same<VT, double>::value && NT > 512) return false;   // would spill registers
     const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
     if (lds > D.max_lds) return false;
     hipLaunchKernelGGL((k_band_apply<NT, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
@@ -1523,6 +1522,48 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
         h->err = e.msg;
         return e.st;
     }
+    return GDSW_OK;
+}
+
+gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "set_launch before factor";
+        return GDSW_ERR_STATE;
+    }
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
+    if (local_variant < -1 || local_variant >= nv || gemv_variant < -1 || gemv_variant > 1 || apply_streams < -1 ||
+        apply_streams == 0 || apply_streams > 2) {
+        h->err = "set_launch: configuration out of range";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    if (local_variant >= 0) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        bool fits = false;
+        try {
+            hipLaunchKernelGGL(k_fill, dim3(nblocks(S.n, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, S.n);
+            const Skip none;
+            switch (S.opt.local_prec) {
+                case GDSW_FP64: fits = launch_local_variant<double>(S, D, local_variant, D.kr, none, s); break;
+                case GDSW_FP32: fits = launch_local_variant<float>(S, D, local_variant, D.kr, none, s); break;
+                case GDSW_BF16: fits = launch_local_variant<bf16>(S, D, local_variant, D.kr, none, s); break;
+                default: fits = launch_local_variant<fp16>(S, D, local_variant, D.kr, none, s); break;
+            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));
+        } catch (const DevError &e) {
+            h->err = e.msg;
+            return e.st;
+        }
+        if (!fits) {
+            h->err = "set_launch: the local-solve configuration does not fit this handle";
+            return GDSW_ERR_INVALID_ARG;
+        }
+    }
+    D.local_variant = local_variant;
+    D.gemv_variant = gemv_variant;
+    D.apply_streams = apply_streams;
     return GDSW_OK;
 }
 

@@ -357,10 +357,42 @@ __device__ __forceinline__ void band_block_bwd(const AT *sT, AT *y, int k0, int 
     if (lane < kb) y[k0 + lane] = yt;
 }
 
+// The staging split in two, for the register budgets that allow it: the
+// triangle's loads into registers, issued with the row or column updates of
+// the same step so that both are in flight together, and the store into
+// LDS after the updates.
+template <int NT>
+constexpr int tri_per_thread() { return (BS_NB * BS_NB + NT - 1) / NT; }
+
+template <typename VT, typename AT, int NT>
+__device__ __forceinline__ void band_load_triangle(const VT *__restrict__ L, int64_t w, int b, int k0, int kb,
+                                                   AT (&tv)[tri_per_thread<NT>()]) {
+#pragma unroll
+    for (int c = 0; c < tri_per_thread<NT>(); ++c) {
+        const int e = int(threadIdx.x) + c * NT;
+        const int t = e / BS_NB, s = e % BS_NB;
+        tv[c] = (e < BS_NB * BS_NB && t < kb && s <= t && t - s <= b) ? to_acc(L[int64_t(k0 + t) * w + (s - t + b)])
+                                                                      : AT(0);
+    }
+}
+
+template <typename AT, int NT>
+__device__ __forceinline__ void band_store_triangle(const AT (&tv)[tri_per_thread<NT>()], AT *sT) {
+#pragma unroll
+    for (int c = 0; c < tri_per_thread<NT>(); ++c) {
+        const int e = int(threadIdx.x) + c * NT;
+        if (e < BS_NB * BS_NB) sT[(e / BS_NB) * BS_LD + e % BS_NB] = tv[c];
+    }
+}
+
 template <typename VT, typename AT, int NT>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
     if (n <= 0) return;   // an empty subdomain or interior (uniform over the workgroup)
-    constexpr int G = sizeof(AT) == 8 ? 8 : 32;   // loads in flight per thread and group (backward)
+    constexpr bool F64 = sizeof(AT) == 8;
+    constexpr int G = F64 ? 8 : 32;   // loads in flight per thread and group (backward)
+    // triangle loads overlapped with the updates where the register budget
+    // holds the extra values (FP32 accumulation from 512 threads, FP64 at 1024)
+    constexpr bool PREF = F64 ? NT >= 1024 : NT >= 512;
     const int64_t w = b + 1;
     const int tid = threadIdx.x, lane = tid & 63;
     const int nblk = (n + BS_NB - 1) / BS_NB;
@@ -378,6 +410,8 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         const int k0 = blk * BS_NB;
         const int k1 = k0 + BS_NB, kb1 = min(BS_NB, n - k1);
         const int rend = min(n, k1 + b);
+        AT tv[tri_per_thread<NT>()];
+        if constexpr (PREF) band_load_triangle<VT, AT, NT>(L, w, b, k1, kb1, tv);   // block k+1's triangle
         AT yq[BS_NB / LPR];
 #pragma unroll
         for (int q = 0; q < BS_NB / LPR; ++q) yq[q] = y[k0 + sub + q * LPR];
@@ -407,7 +441,8 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
                 if (r < rend && sub == 0) y[r] -= acc;
             }
         }
-        band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
+        if constexpr (PREF) band_store_triangle<AT, NT>(tv, sT);
+        else band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
         __syncthreads();
         if (tid < 64) band_block_fwd(sT, y, k1, kb1, lane);
         __syncthreads();
@@ -424,6 +459,8 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         const int k0 = blk * BS_NB, kb = min(BS_NB, n - k0);
         const int p0 = k0 - BS_NB;
         const int jbeg = max(0, k0 - b);
+        AT tv[tri_per_thread<NT>()];
+        if constexpr (PREF) band_load_triangle<VT, AT, NT>(L, w, b, p0, BS_NB, tv);   // block k-1's triangle
         for (int j = jbeg + tid; j < k0; j += NT) {
             const int smax = min(kb, j + b - k0 + 1);
             const VT *col = L + int64_t(k0) * w + (j - k0 + b);   // entry s at col[s * (w - 1)]
@@ -438,7 +475,8 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
             }
             y[j] -= acc;
         }
-        band_stage_triangle<VT, AT, NT>(L, w, b, p0, BS_NB, sT);
+        if constexpr (PREF) band_store_triangle<AT, NT>(tv, sT);
+        else band_stage_triangle<VT, AT, NT>(L, w, b, p0, BS_NB, sT);
         __syncthreads();
         if (tid < 64) band_block_bwd(sT, y, p0, BS_NB, lane);
         __syncthreads();

@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--P", type=int, default=8)
     ap.add_argument("--elasticity", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch configurations first "
+                    "(as the benchmark does), so the counters see the configuration it times")
     a = ap.parse_args()
 
     import torch
@@ -46,6 +48,10 @@ def main():
     r = torch.from_numpy(P.rhs_uniform(pr.n, 0)).cuda()
     z = torch.zeros_like(r)
     torch.cuda.synchronize()
+    if a.tune:
+        times = B.gdsw_autotune(g.h, reps=3)
+        print(f"[profile] autotune {times} -> local variant {g.info()['local_variant']}", file=sys.stderr,
+              flush=True)
     print(f"[profile] local solves x{a.reps}", file=sys.stderr, flush=True)
     for _ in range(a.reps):
         g.apply_part(r, None, 4)

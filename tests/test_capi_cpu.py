@@ -144,6 +144,15 @@ def test_factor_without_analysis_state_error():
     B.gdsw_destroy(h.value)
 
 
+def test_set_launch_before_factor_state_error():
+    pr = P.poisson3d(6, 2)
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1)
+    assert B.lib().gdsw_set_launch(h, 0, 0, 1, None) == 7
+    assert "factor" in B.gdsw_last_error(h)
+    assert B.lib().gdsw_set_launch(None, 0, 0, 1, None) == 1
+    B.gdsw_destroy(h)
+
+
 @pytest.mark.parametrize("level", [0, 1, 2])
 @pytest.mark.parametrize("case", ["poisson", "diffusion", "elasticity"])
 def test_iluk_patterns_match_oracle(level, case):

@@ -381,3 +381,61 @@ def test_empty_subdomain(local):
     ref = O.pcg(pr.A, r, M, rtol=1e-8)
     assert abs(out["iterations"] - ref.iters) <= 1 and out["rel_res_true"] <= 1.5e-8
     g.close()
+
+
+@pytest.mark.parametrize("local,prec", [(B.LOCAL_ILU0, B.FP64), (B.LOCAL_EXACT, B.FP64), (B.LOCAL_EXACT, B.FP32),
+                                        (B.LOCAL_ILU0, B.BF16)])
+def test_every_launch_configuration(local, prec):
+    """Each launch configuration of the local solves, the coarse GEMV and the
+    stream split, pinned with gdsw_set_launch.  For one GEMV variant the
+    apply is bitwise the same whatever the local-solve variant and stream
+    split (each value is computed in the same order); the two GEMV variants
+    sum a row in different orders and agree to rounding; FP64 applies are
+    within the apply tolerance of the oracle."""
+    pr = P.poisson3d(20, 2)
+    say(f"[launch] local={local} prec={prec}")
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=local, local_prec=prec,
+               basis_prec=B.FP64 if prec == B.FP64 else B.FP32)
+    r_h = P.rhs_uniform(pr.n, 5)
+    r = dev(r_h)
+    nv = 4 if local == B.LOCAL_ILU0 else 3
+    per_gemv = []
+    ran = 0
+    for gv in (0, 1):
+        z_first = None
+        for v in range(nv):
+            for ns in (1, 2):
+                try:
+                    B.gdsw_set_launch(g.h, v, gv, ns)
+                except B.GdswError as e:
+                    assert e.status == 1 and "fit" in str(e)
+                    break
+                z = torch.zeros_like(r)
+                g.apply(r, z)
+                if z_first is None:
+                    z_first = z
+                assert torch.equal(z, z_first), (v, gv, ns)
+                ran += 1
+        per_gemv.append(host(z_first))
+    assert ran >= 8
+    a, b = per_gemv
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    if prec == B.FP64:
+        M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local="exact" if local == B.LOCAL_EXACT else "ilu0")
+        zo = M.apply(r_h)
+        for z in per_gemv:
+            assert np.abs(z - zo).max() <= 1e-12 * np.abs(zo).max()
+    # out of range: rejected
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_set_launch(g.h, nv, 0, 1)
+    assert e.value.status == 1
+    with pytest.raises(B.GdswError):
+        B.gdsw_set_launch(g.h, -1, 2, 1)
+    with pytest.raises(B.GdswError):
+        B.gdsw_set_launch(g.h, -1, 0, 0)
+    # back to the rules
+    B.gdsw_set_launch(g.h)
+    z = torch.zeros_like(r)
+    g.apply(r, z)
+    assert np.abs(host(z) - a).max() <= 1e-13 * np.abs(a).max()
+    g.close()
