@@ -138,7 +138,7 @@ def main():
     tune_ms = B.gdsw_autotune(h, reps=5, stream=stream)
     info = B.gdsw_get_info(h)
     log(f"[bench] autotune (ms per launch) {[round(t, 4) for t in tune_ms]} -> local variant "
-        f"{info['local_variant']}, gemv variant {info['gemv_variant']}")
+        f"{info['local_variant']}, gemv variant {info['gemv_variant']}, prolongation variant {info['prolong_variant']}")
 
     nrhs = args.warmup + args.steps
     if elastic:
@@ -312,7 +312,8 @@ def main():
                    "jacobi_sweeps": 5, "ilu_level": args.ilu_level, "ilu_factor_sweeps": args.factor_sweeps,
                    "local_prec": args.prec, "rtol": 1e-8,
                    "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"],
-                   "tuned_apply_streams": info["apply_streams"], "graphs": bool(args.graphs)},
+                   "tuned_apply_streams": info["apply_streams"], "tuned_prolong_variant": info["prolong_variant"],
+                   "graphs": bool(args.graphs)},
         "applies_per_sec": round(1e3 / apply_ms, 1),
         "apply_ms": round(apply_ms, 4),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),

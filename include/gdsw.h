@@ -133,6 +133,9 @@ typedef struct {
     int32_t apply_streams;    /* coarse part of the apply: -1 fixed rule (second stream when
                                  the subdomains do not fill the compute units), 1 same stream
                                  as the local solves, 2 second stream                */
+    int32_t prolong_variant;  /* coarse part of the prolongation: -1 fixed rule (by blocks
+                                 when Phi holds >= 16 values per dof), 0 per dof,
+                                 1 by blocks                                         */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -273,10 +276,14 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
  * threads), both coarse GEMV variants, and the whole apply with the coarse
  * part on the caller's stream after the local solves or on a second stream
  * beside them, on the handle's own factors, `reps` launches each, and keeps
- * the fastest for all later applies.  times_ms (optional, host, 8 floats)
+ * the fastest for all later applies; also the coarse part of the
+ * prolongation z += Phi z0 per dof (each dof reads its row of Phi) or by
+ * blocks (each block of Phi times z0 streamed once on the coarse chain, the
+ * per-dof pass then adds one value).  times_ms (optional, host, 10 floats)
  * receives the average milliseconds per launch (-1 for configurations that
  * do not fit): [0..3] local variants, [4..5] GEMV variants, [6..7] apply in
- * one stream / two streams.  Synchronises `stream`. */
+ * one stream / two streams, [8..9] apply with the prolongation per dof / by
+ * blocks.  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
 /* Pins the launch configurations gdsw_autotune chooses from, for callers
@@ -285,15 +292,19 @@ gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *st
  *   gemv_variant : -1 = rule (workgroup per row from n0 >= 1024), 0 = one
  *                  wavefront per row, 1 = one workgroup per row;
  *   apply_streams: -1 = rule (two streams when there are fewer subdomains
- *                  than compute units), 1 or 2.
+ *                  than compute units), 1 or 2;
+ *   prolong_variant: -1 = rule (by blocks when Phi holds at least 16
+ *                  values per dof), 0 = per dof, 1 = by blocks (allocates
+ *                  one vector of n doubles on first use).
  * The local variant is launched once on `stream` (on internal buffers) to
  * check that it fits the handle; one that does not (LDS, registers) gives
  * GDSW_ERR_INVALID_ARG and nothing changes.  The local-solve and stream
  * configurations compute each value in the same order (results do not
- * depend on them); the two GEMV variants sum a row of A_0^{-1} in different
- * orders and agree to rounding. */
+ * depend on them, and the two prolongation forms add each dof's products
+ * in the same order); the two GEMV variants sum a row of A_0^{-1} in
+ * different orders and agree to rounding. */
 gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant,
-                            int32_t apply_streams, void *stream);
+                            int32_t apply_streams, int32_t prolong_variant, void *stream);
 
 /* Dof offsets of the problems of a handle: offsets[count+1] (host). */
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);

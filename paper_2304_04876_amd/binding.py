@@ -68,7 +68,8 @@ class Info(ctypes.Structure):
                 ("max_local_rows", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
                 ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
-                ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32)]
+                ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32),
+                ("prolong_variant", ctypes.c_int32)]
 
 
 def lib():
@@ -107,7 +108,7 @@ def lib():
         "gdsw_slot_finish": (ctypes.c_int, [vp, i32, ctypes.POINTER(SolveInfo), vp]),
         "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
         "gdsw_autotune": (ctypes.c_int, [vp, i32, vp, vp]),
-        "gdsw_set_launch": (ctypes.c_int, [vp, i32, i32, i32, vp]),
+        "gdsw_set_launch": (ctypes.c_int, [vp, i32, i32, i32, i32, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -309,14 +310,14 @@ def gdsw_slot_finish(h, slot, stream=None) -> dict:
 
 
 def gdsw_autotune(h, reps=10, stream=None) -> list:
-    times = np.full(8, -1.0, dtype=np.float32)
+    times = np.full(10, -1.0, dtype=np.float32)
     _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
     return times.tolist()
 
 
-def gdsw_set_launch(h, local_variant=-1, gemv_variant=-1, apply_streams=-1, stream=None):
+def gdsw_set_launch(h, local_variant=-1, gemv_variant=-1, apply_streams=-1, prolong_variant=-1, stream=None):
     _check(h, lib().gdsw_set_launch(h, int(local_variant), int(gemv_variant), int(apply_streams),
-                                    _stream(stream)))
+                                    int(prolong_variant), _stream(stream)))
 
 
 def gdsw_problem_offsets(h) -> np.ndarray:

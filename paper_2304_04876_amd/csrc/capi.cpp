@@ -77,9 +77,9 @@ gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *st
 }
 
 gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant, int32_t apply_streams,
-                            void *stream) {
+                            int32_t prolong_variant, void *stream) {
     if (!h) return GDSW_ERR_INVALID_ARG;
-    return gdsw::set_launch(h, local_variant, gemv_variant, apply_streams, stream);
+    return gdsw::set_launch(h, local_variant, gemv_variant, apply_streams, prolong_variant, stream);
 }
 
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
@@ -159,6 +159,7 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->local_variant = gdsw::tuned_variant(h, 0);
     info->gemv_variant = gdsw::tuned_variant(h, 1);
     info->apply_streams = gdsw::tuned_variant(h, 2);
+    info->prolong_variant = gdsw::tuned_variant(h, 3);
     return GDSW_OK;
 }
 

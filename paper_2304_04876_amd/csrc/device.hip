@@ -159,6 +159,10 @@ struct Device {
     int KLp = 1, KUp = 1;   // slot counts of the sweep layout
     int max_n0 = 0;         // largest coarse block
     int nb_big = 0;         // leading coarse-basis blocks restricted by a workgroup each
+    int max_k_big = 0;      // most columns of a big block
+    bool split_rule = false;   // prolongation's coarse part by blocks under the fixed rule
+    int prolong_split = -1;    // -1: rule, 0: per dof, 1: by blocks (k_coarse_prolong into zc)
+    double *zc = nullptr;      // coarse part of the prolongation, by blocks
     size_t max_lds = 64 * 1024;   // dynamic LDS a workgroup may use on this device
     double *gm_V = nullptr, *gm_part = nullptr;   // GMRES basis and partial sums
     int gm_m = 0;
@@ -426,6 +430,12 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     D.nb_big = 0;
     while (D.nb_big < B.nb && (B.kind[D.nb_big] == 0 || B.row_ptr[D.nb_big + 1] - B.row_ptr[D.nb_big] >= 512))
         ++D.nb_big;
+    for (int g = 0; g < D.nb_big; ++g)
+        D.max_k_big = std::max(D.max_k_big, int(B.col_ptr[g + 1] - B.col_ptr[g]));
+    // many columns per row of Phi (elasticity: ~90): the per-dof form reads
+    // them with scattered loads, the block form streams each block once
+    D.split_rule = B.val_off[size_t(B.nb)] >= 16 * S.n && sizeof(double) * size_t(D.max_k_big) <= D.max_lds;
+    if (D.split_rule) D.zc = D.alloc<double>(S.n);
     D.blk_col_ptr = D.upload(B.col_ptr, s);
     D.blk_val_off = D.upload(B.val_off, s);
     D.blk_rows = D.upload(B.rows, s);
@@ -814,6 +824,8 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
     // which pays when the local solves leave compute units idle
     const bool two = D.apply_streams == 2 || (D.apply_streams < 0 && S.np < D.n_cu);
     const bool fork = local && coarse && two && D.side != nullptr;
+    const bool split = coarse && D.zc != nullptr && (D.prolong_split == 1 || (D.prolong_split < 0 && D.split_rule));
+    const double *zc = split ? D.zc : nullptr;
     hipStream_t sc = s;
     if (fork) {
         HIPCHK(hipEventRecord(D.ev_fork, s));
@@ -845,6 +857,17 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         else
             hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
                                D.cprob, D.r0, D.z0, S.n0, sk);
+        if (split && nwg > 0) {
+            const size_t lds = sizeof(double) * size_t(std::max(1, D.max_k_big));
+            if (D.phi32)
+                hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwg), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const float *)D.phi32,
+                                   D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
+            else
+                hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwg), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                                   D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const double *)D.phi,
+                                   D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
+        }
     }
     if (local) {
         switch (S.opt.local_prec) {
@@ -867,19 +890,19 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         if (D.phi32)
             hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const float *)D.phi32, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               (const float *)D.phi32, D.z0, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
         else
             hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                                D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const double *)D.phi, D.z0, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               (const double *)D.phi, D.z0, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
     } else if (D.phi32) {
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const float *)D.phi32, D.z0, z, S.n, sk);
+                           (const float *)D.phi32, D.z0, zc, z, S.n, sk);
     } else {
         hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
                            D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const double *)D.phi, D.z0, z, S.n, sk);
+                           (const double *)D.phi, D.z0, zc, z, S.n, sk);
     }
     HIPCHK(hipGetLastError());
 }
@@ -1513,6 +1536,23 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                 if (times) times[6 + v] = ta[v] / reps;
             }
             D.apply_streams = ta[1] < ta[0] ? 2 : 1;
+            // coarse part of the prolongation per dof or by blocks
+            const size_t lds = sizeof(double) * size_t(D.max_k_big);
+            if (lds <= D.max_lds) {
+                if (!D.zc) D.zc = D.alloc<double>(S.n);
+                float tp[2];
+                for (int v = 0; v < 2; ++v) {
+                    D.prolong_split = v;
+                    launch_apply(h, D.kr, D.kz, 3, Skip(), s);
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int k = 0; k < reps; ++k) launch_apply(h, D.kr, D.kz, 3, Skip(), s);
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    HIPCHK(hipEventElapsedTime(&tp[v], e0, e1));
+                    if (times) times[8 + v] = tp[v] / reps;
+                }
+                D.prolong_split = tp[1] < tp[0] ? 1 : 0;
+            }
         }
         HIPCHK(hipEventDestroy(e0));
         HIPCHK(hipEventDestroy(e1));
@@ -1525,7 +1565,8 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
     return GDSW_OK;
 }
 
-gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, void *stream) {
+gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams,
+                       int prolong_variant, void *stream) {
     if (!h->factored || !h->dev) {
         h->err = "set_launch before factor";
         return GDSW_ERR_STATE;
@@ -1534,8 +1575,12 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
     Device &D = *h->dev;
     const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
     if (local_variant < -1 || local_variant >= nv || gemv_variant < -1 || gemv_variant > 1 || apply_streams < -1 ||
-        apply_streams == 0 || apply_streams > 2) {
+        apply_streams == 0 || apply_streams > 2 || prolong_variant < -1 || prolong_variant > 1) {
         h->err = "set_launch: configuration out of range";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    if (prolong_variant == 1 && sizeof(double) * size_t(D.max_k_big) > D.max_lds) {
+        h->err = "set_launch: the block prolongation does not fit this handle";
         return GDSW_ERR_INVALID_ARG;
     }
     if (local_variant >= 0) {
@@ -1561,15 +1606,27 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
             return GDSW_ERR_INVALID_ARG;
         }
     }
+    if (prolong_variant == 1 && !D.zc && D.A0inv) {
+        try {
+            D.zc = D.alloc<double>(S.n);
+        } catch (const DevError &e) {
+            h->err = e.msg;
+            return e.st;
+        }
+    }
     D.local_variant = local_variant;
     D.gemv_variant = gemv_variant;
     D.apply_streams = apply_streams;
+    D.prolong_split = prolong_variant;
     return GDSW_OK;
 }
 
 int tuned_variant(const gdsw_handle_s *h, int which) {
     if (!h->dev) return -1;
-    return which == 0 ? h->dev->local_variant : which == 1 ? h->dev->gemv_variant : h->dev->apply_streams;
+    return which == 0 ? h->dev->local_variant
+         : which == 1 ? h->dev->gemv_variant
+         : which == 2 ? h->dev->apply_streams
+                      : h->dev->prolong_split;
 }
 
 void destroy_device(gdsw_handle_s *h) {

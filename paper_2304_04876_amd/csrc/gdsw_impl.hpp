@@ -172,7 +172,8 @@ gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream);
 gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream);
 gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream);
 gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream);
-gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, void *stream);
+gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, int prolong_variant,
+                       void *stream);
 int tuned_variant(const gdsw_handle_s *h, int which);
 void destroy_device(gdsw_handle_s *h);
 int64_t device_bytes(const gdsw_handle_s *h);

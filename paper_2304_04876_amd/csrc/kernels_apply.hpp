@@ -420,21 +420,94 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
     if (threadIdx.x == 0) y[row] = acc;
 }
 
+// Coarse part of the prolongation by blocks, for coarse bases with many
+// columns per block: zc[rows of B_g] = B_g z0(cols_g).  A tile of a big
+// block per workgroup (RT_RPT rows per thread, the block's z0 entries staged
+// in LDS, columns in passes of RT_KB with every load of a pass issued first)
+// and a wavefront per small block.  Each row adds its products in column
+// order from zero, the order of the per-dof form below, so both forms give
+// the same bits.
+template <typename PT>
+__global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows, const int64_t *__restrict__ col_ptr,
+    const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+    const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
+    const double *__restrict__ z0, double *__restrict__ zc, int ntiles, int g_small, int nb, Skip sk) {
+    extern __shared__ double sz[];   // z0 entries of the tile's block (max columns of a big block)
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (b < ntiles) {
+        const int g = tile_blk[b];
+        if (sk.blk(g)) return;
+        const int64_t r0 = row_ptr[g];
+        const int nr = int(row_ptr[g + 1] - r0);
+        const int64_t c0 = col_ptr[g];
+        const int k = int(col_ptr[g + 1] - c0);
+        const int l0 = tile_l0[b], l1 = tile_l1[b];
+        const PT *Bg = phi + val_off[g];
+        for (int q = tid; q < k; q += RT_NT) sz[q] = z0[cols[c0 + q]];
+        __syncthreads();
+        double acc[RT_RPT];
+#pragma unroll
+        for (int j = 0; j < RT_RPT; ++j) acc[j] = 0.0;
+        constexpr int KB = RT_KB;
+        for (int s0 = 0; s0 < k; s0 += KB) {
+            double bv[KB][RT_RPT];
+#pragma unroll
+            for (int s = 0; s < KB; ++s)
+#pragma unroll
+                for (int j = 0; j < RT_RPT; ++j) {
+                    const int l = l0 + tid + j * RT_NT;
+                    bv[s][j] = (s0 + s < k && l < l1) ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
+                }
+#pragma unroll
+            for (int s = 0; s < KB; ++s) {
+                if (s0 + s < k) {
+                    const double zz = sz[s0 + s];
+#pragma unroll
+                    for (int j = 0; j < RT_RPT; ++j) acc[j] += bv[s][j] * zz;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RT_RPT; ++j) {
+            const int l = l0 + tid + j * RT_NT;
+            if (l < l1) zc[rows[r0 + l]] = acc[j];
+        }
+    } else {
+        const int g = g_small + (b - ntiles) * (RT_NT / 64) + (tid >> 6);
+        if (g >= nb || sk.blk(g)) return;
+        const int64_t r0 = row_ptr[g];
+        const int nr = int(row_ptr[g + 1] - r0);
+        const int64_t c0 = col_ptr[g];
+        const int k = int(col_ptr[g + 1] - c0);
+        const PT *Bg = phi + val_off[g];
+        for (int l = tid & 63; l < nr; l += 64) {
+            double acc = 0.0;
+            for (int s = 0; s < k; ++s) acc += double(to_acc(Bg[int64_t(s) * nr + l])) * z0[cols[c0 + s]];
+            zc[rows[r0 + l]] = acc;
+        }
+    }
+}
+
 // z[d] = sum over the local rows holding d (ascending subdomain) of zloc
 //        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part)
+// zc != nullptr: the coarse part was formed by blocks (k_coarse_prolong).
 template <typename PT>
 __device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_t *__restrict__ t_ptr,
                                               const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
                                               const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr,
                                               const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ col_ptr,
                                               const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
-                                              const PT *__restrict__ phi, const double *__restrict__ z0) {
+                                              const PT *__restrict__ phi, const double *__restrict__ z0,
+                                              const double *__restrict__ zc) {
     double acc = 0.0;
     if (which & 1)
         for (int p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
     if (which & 2) {
         const int g = dof_blk[d];
-        if (g >= 0) {
+        if (g >= 0 && zc) {
+            acc += zc[d];
+        } else if (g >= 0) {
             const int64_t nr = row_ptr[g + 1] - row_ptr[g];
             const int64_t c0 = col_ptr[g];
             const int k = int(col_ptr[g + 1] - c0);
@@ -465,10 +538,12 @@ __global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const in
                           const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
                           const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols,
                           const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-                          const double *__restrict__ z0, double *__restrict__ z, int64_t n, Skip sk) {
+                          const double *__restrict__ z0, const double *__restrict__ zc, double *__restrict__ z,
+                          int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (d >= n || sk.dof(d)) return;
-    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
+    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0,
+                           zc);
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
@@ -479,8 +554,8 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
     const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
     const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
-    const PT *__restrict__ phi, const double *__restrict__ z0, double *__restrict__ z, Skip sk,
-    const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
+    const PT *__restrict__ phi, const double *__restrict__ z0, const double *__restrict__ zc, double *__restrict__ z,
+    Skip sk, const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
     double *__restrict__ partial) {
     __shared__ double sh[4];
     const int blk = blockIdx.x;
@@ -489,7 +564,8 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     double dot = 0.0;
     for (int d = row0 + threadIdx.x; d < row1; d += 256) {
         const double v =
-            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0);
+            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0,
+                            zc);
         z[d] = v;
         dot += rvec[d] * v;
     }

@@ -147,9 +147,9 @@ def test_factor_without_analysis_state_error():
 def test_set_launch_before_factor_state_error():
     pr = P.poisson3d(6, 2)
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1)
-    assert B.lib().gdsw_set_launch(h, 0, 0, 1, None) == 7
+    assert B.lib().gdsw_set_launch(h, 0, 0, 1, 0, None) == 7
     assert "factor" in B.gdsw_last_error(h)
-    assert B.lib().gdsw_set_launch(None, 0, 0, 1, None) == 1
+    assert B.lib().gdsw_set_launch(None, 0, 0, 1, 0, None) == 1
     B.gdsw_destroy(h)
 
 

@@ -405,19 +405,20 @@ def test_every_launch_configuration(local, prec):
         z_first = None
         for v in range(nv):
             for ns in (1, 2):
-                try:
-                    B.gdsw_set_launch(g.h, v, gv, ns)
-                except B.GdswError as e:
-                    assert e.status == 1 and "fit" in str(e)
-                    break
-                z = torch.zeros_like(r)
-                g.apply(r, z)
-                if z_first is None:
-                    z_first = z
-                assert torch.equal(z, z_first), (v, gv, ns)
-                ran += 1
+                for pv in (0, 1):
+                    try:
+                        B.gdsw_set_launch(g.h, v, gv, ns, pv)
+                    except B.GdswError as e:
+                        assert e.status == 1 and "fit" in str(e)
+                        break
+                    z = torch.zeros_like(r)
+                    g.apply(r, z)
+                    if z_first is None:
+                        z_first = z
+                    assert torch.equal(z, z_first), (v, gv, ns, pv)
+                    ran += 1
         per_gemv.append(host(z_first))
-    assert ran >= 8
+    assert ran >= 16
     a, b = per_gemv
     assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
     if prec == B.FP64:
@@ -433,9 +434,42 @@ def test_every_launch_configuration(local, prec):
         B.gdsw_set_launch(g.h, -1, 2, 1)
     with pytest.raises(B.GdswError):
         B.gdsw_set_launch(g.h, -1, 0, 0)
+    with pytest.raises(B.GdswError):
+        B.gdsw_set_launch(g.h, -1, 0, 1, 2)
     # back to the rules
     B.gdsw_set_launch(g.h)
     z = torch.zeros_like(r)
     g.apply(r, z)
     assert np.abs(host(z) - a).max() <= 1e-13 * np.abs(a).max()
+    g.close()
+
+
+def test_prolongation_forms_agree_elasticity():
+    """The coarse part of the prolongation per dof and by blocks (elasticity:
+    up to 180 coarse columns per block) gives the same bits, within the
+    apply tolerance of the oracle, also inside GMRES."""
+    pr = P.elasticity_q1(6, 2)
+    Z = P.rigid_body_modes(pr)
+    say("[prolong forms] elasticity6")
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 3, Z)
+    M = O.GDSW(pr.A, pr.part, 3, pr.n_parts, Z=Z, local="exact")
+    r_h = P.rhs_uniform(pr.n, 2)
+    r = dev(r_h)
+    zs = []
+    for pv in (0, 1):
+        B.gdsw_set_launch(g.h, -1, -1, -1, pv)
+        assert g.info()["prolong_variant"] == pv
+        z = torch.zeros_like(r)
+        g.apply(r, z)
+        zs.append(z)
+    assert torch.equal(zs[0], zs[1])
+    zo = M.apply(r_h)
+    assert np.abs(host(zs[0]) - zo).max() <= 1e-12 * np.abs(zo).max()
+    xs = []
+    for pv in (0, 1):
+        B.gdsw_set_launch(g.h, -1, -1, -1, pv)
+        x = torch.zeros_like(r)
+        g.solve(dev(pr.b), x, krylov=B.KRYLOV_GMRES_SR, restart=30, fixed_iters=12)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
     g.close()
