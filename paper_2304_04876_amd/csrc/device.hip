@@ -130,7 +130,8 @@ struct Device {
     int64_t *blk_poff = nullptr;   // first restriction partial of every block
     int32_t *tile_blk = nullptr, *tile_l0 = nullptr, *tile_l1 = nullptr;   // restriction tiles of the big blocks
     int64_t *tile_poff = nullptr;
-    int ntiles = 0;
+    int32_t *wk_tile = nullptr, *wk_s0 = nullptr;   // restriction work items: (tile, first column)
+    int ntiles = 0, nwork = 0;
     int32_t *dof_blk = nullptr, *dof_lr = nullptr;
     double *partial = nullptr, *r0 = nullptr, *z0 = nullptr;
     double *A0 = nullptr;     // assembled coarse matrix
@@ -483,6 +484,18 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         D.red_idx = D.upload(ridx, s);
         D.blk_poff = D.upload(poff, s);
         D.ntiles = int(tb.size());
+        std::vector<int32_t> wt, ws;
+        for (int t = 0; t < D.ntiles; ++t) {
+            const int g = tb[size_t(t)];
+            const int64_t k = B.col_ptr[g + 1] - B.col_ptr[g];
+            for (int64_t c = 0; c < std::max<int64_t>(k, 1); c += RT_CK) {
+                wt.push_back(t);
+                ws.push_back(int32_t(c));
+            }
+        }
+        D.nwork = int(wt.size());
+        D.wk_tile = D.upload(wt, s);
+        D.wk_s0 = D.upload(ws, s);
         D.tile_blk = D.upload(tb, s);
         D.tile_l0 = D.upload(tl0, s);
         D.tile_l1 = D.upload(tl1, s);
@@ -836,18 +849,19 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         const PhiBlocks &B = S.blk;
         // blocks with many rows (subdomain interiors) first, then the small ones
         const int nbig = D.nb_big, nsmall = B.nb - nbig;
-        const int nwg = D.ntiles + (nsmall + RT_NT / 64 - 1) / (RT_NT / 64);
+        const int nsw = (nsmall + RT_NT / 64 - 1) / (RT_NT / 64);
+        const int nwg = D.nwork + nsw;
         if (nwg > 0) {
             if (D.phi32)
                 hipLaunchKernelGGL(k_coarse_restrict<float>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.tile_blk,
-                                   D.tile_l0, D.tile_l1, D.tile_poff, D.blk_poff, D.partial, D.ntiles, nbig, B.nb,
-                                   sk);
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.wk_tile, D.wk_s0, D.blk_poff, D.partial,
+                                   D.nwork, nbig, B.nb, sk);
             else
                 hipLaunchKernelGGL(k_coarse_restrict<double>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.tile_blk,
-                                   D.tile_l0, D.tile_l1, D.tile_poff, D.blk_poff, D.partial, D.ntiles, nbig, B.nb,
-                                   sk);
+                                   D.tile_l0, D.tile_l1, D.tile_poff, D.wk_tile, D.wk_s0, D.blk_poff, D.partial,
+                                   D.nwork, nbig, B.nb, sk);
         }
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, sc, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
@@ -857,14 +871,15 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         else
             hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
                                D.cprob, D.r0, D.z0, S.n0, sk);
-        if (split && nwg > 0) {
+        const int nwp = D.ntiles * RT_RPT + nsw;
+        if (split && nwp > 0) {
             const size_t lds = sizeof(double) * size_t(std::max(1, D.max_k_big));
             if (D.phi32)
-                hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwg), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const float *)D.phi32,
                                    D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
             else
-                hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwg), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const double *)D.phi,
                                    D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
         }

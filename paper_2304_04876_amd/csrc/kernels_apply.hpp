@@ -235,19 +235,21 @@ __global__ __launch_bounds__(1024) void k_band_apply(
 // interiors) are cut into tiles of at most 1024 rows, one 256-thread
 // workgroup per tile (4 rows per thread, every load of a pass issued before
 // the sums); small blocks (interface components) take a wavefront each.
-// Up to 8 columns per pass.
-constexpr int RT_NT = 256, RT_RPT = 4, RT_ROWS = RT_NT * RT_RPT, RT_KB = 8;
+// Up to 8 columns per pass; a tile's columns are cut into chunks of RT_CK,
+// one workgroup per chunk (each partial is still formed by one workgroup,
+// in the same order).
+constexpr int RT_NT = 256, RT_RPT = 4, RT_ROWS = RT_NT * RT_RPT, RT_KB = 8, RT_CK = 32;
 
 template <typename PT>
 __device__ __forceinline__ void restrict_tile(const double *__restrict__ r, const int64_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ rows, const int64_t *__restrict__ col_ptr,
                                               const int64_t *__restrict__ val_off, const PT *__restrict__ phi, int g,
-                                              int l0, int l1, int64_t po, double *__restrict__ partial,
-                                              double (*sh)[RT_NT / 64]) {
+                                              int l0, int l1, int64_t po, int sbeg, int send,
+                                              double *__restrict__ partial, double (*sh)[RT_NT / 64]) {
     constexpr int KB = RT_KB, NW = RT_NT / 64;
     const int64_t r0 = row_ptr[g];
     const int nr = int(row_ptr[g + 1] - r0);
-    const int k = int(col_ptr[g + 1] - col_ptr[g]);
+    const int k = min(int(col_ptr[g + 1] - col_ptr[g]), send);
     const PT *Bg = phi + val_off[g];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double x[RT_RPT];
@@ -256,7 +258,7 @@ __device__ __forceinline__ void restrict_tile(const double *__restrict__ r, cons
         const int l = l0 + tid + j * RT_NT;
         x[j] = l < l1 ? r[rows[r0 + l]] : 0.0;
     }
-    for (int s0 = 0; s0 < k; s0 += KB) {
+    for (int s0 = sbeg; s0 < k; s0 += KB) {
         double bv[KB][RT_RPT];
 #pragma unroll
         for (int s = 0; s < KB; ++s)
@@ -316,25 +318,27 @@ __device__ __forceinline__ void restrict_wave(const double *__restrict__ r, cons
     }
 }
 
-// One launch for both kinds: workgroups [0, ntiles) take the tiles of the
-// big blocks, the rest four small blocks each (blocks g_small, g_small+1, ...
+// One launch for both kinds: workgroups [0, nwork) take the column chunks
+// of the tiles of the big blocks (work item b: tile wk_tile[b], columns from
+// wk_s0[b]), the rest four small blocks each (blocks g_small, g_small+1, ...
 // below nb), so the short component blocks run beside the tiles.
 template <typename PT>
 __global__ __launch_bounds__(RT_NT) void k_coarse_restrict(
     const double *__restrict__ r, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
     const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
-    const int64_t *__restrict__ tile_poff, const int64_t *__restrict__ poff, double *__restrict__ partial,
-    int ntiles, int g_small, int nb, Skip sk) {
+    const int64_t *__restrict__ tile_poff, const int32_t *__restrict__ wk_tile, const int32_t *__restrict__ wk_s0,
+    const int64_t *__restrict__ poff, double *__restrict__ partial, int nwork, int g_small, int nb, Skip sk) {
     __shared__ double sh[RT_KB][RT_NT / 64];
     const int b = blockIdx.x;
-    if (b < ntiles) {
-        const int g = tile_blk[b];
+    if (b < nwork) {
+        const int t = wk_tile[b], g = tile_blk[t];
         if (sk.blk(g)) return;
-        restrict_tile<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, tile_l0[b], tile_l1[b], tile_poff[b], partial,
-                          sh);
+        const int s0 = wk_s0[b];
+        restrict_tile<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, tile_l0[t], tile_l1[t], tile_poff[t], s0,
+                          s0 + RT_CK, partial, sh);
     } else {
-        const int g = g_small + (b - ntiles) * (RT_NT / 64) + int(threadIdx.x >> 6);
+        const int g = g_small + (b - nwork) * (RT_NT / 64) + int(threadIdx.x >> 6);
         if (g >= nb || sk.blk(g)) return;
         restrict_wave<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, poff[g], partial);
     }
@@ -435,46 +439,34 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
     const double *__restrict__ z0, double *__restrict__ zc, int ntiles, int g_small, int nb, Skip sk) {
     extern __shared__ double sz[];   // z0 entries of the tile's block (max columns of a big block)
     const int b = blockIdx.x, tid = threadIdx.x;
-    if (b < ntiles) {
-        const int g = tile_blk[b];
+    if (b < ntiles * RT_RPT) {
+        // quarter q of tile t: rows l0 + q * RT_NT + tid, one per thread
+        const int t = b / RT_RPT, q = b % RT_RPT;
+        const int g = tile_blk[t];
         if (sk.blk(g)) return;
         const int64_t r0 = row_ptr[g];
         const int nr = int(row_ptr[g + 1] - r0);
         const int64_t c0 = col_ptr[g];
         const int k = int(col_ptr[g + 1] - c0);
-        const int l0 = tile_l0[b], l1 = tile_l1[b];
+        const int l = tile_l0[t] + q * RT_NT + tid, l1 = tile_l1[t];
+        if (tile_l0[t] + q * RT_NT >= l1) return;   // empty quarter (uniform over the workgroup)
         const PT *Bg = phi + val_off[g];
-        for (int q = tid; q < k; q += RT_NT) sz[q] = z0[cols[c0 + q]];
+        for (int c = tid; c < k; c += RT_NT) sz[c] = z0[cols[c0 + c]];
         __syncthreads();
-        double acc[RT_RPT];
-#pragma unroll
-        for (int j = 0; j < RT_RPT; ++j) acc[j] = 0.0;
-        constexpr int KB = RT_KB;
+        double acc = 0.0;
+        constexpr int KB = 16;
         for (int s0 = 0; s0 < k; s0 += KB) {
-            double bv[KB][RT_RPT];
+            double bv[KB];
 #pragma unroll
             for (int s = 0; s < KB; ++s)
+                bv[s] = (s0 + s < k && l < l1) ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
 #pragma unroll
-                for (int j = 0; j < RT_RPT; ++j) {
-                    const int l = l0 + tid + j * RT_NT;
-                    bv[s][j] = (s0 + s < k && l < l1) ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
-                }
-#pragma unroll
-            for (int s = 0; s < KB; ++s) {
-                if (s0 + s < k) {
-                    const double zz = sz[s0 + s];
-#pragma unroll
-                    for (int j = 0; j < RT_RPT; ++j) acc[j] += bv[s][j] * zz;
-                }
-            }
+            for (int s = 0; s < KB; ++s)
+                if (s0 + s < k) acc += bv[s] * sz[s0 + s];
         }
-#pragma unroll
-        for (int j = 0; j < RT_RPT; ++j) {
-            const int l = l0 + tid + j * RT_NT;
-            if (l < l1) zc[rows[r0 + l]] = acc[j];
-        }
+        if (l < l1) zc[rows[r0 + l]] = acc;
     } else {
-        const int g = g_small + (b - ntiles) * (RT_NT / 64) + (tid >> 6);
+        const int g = g_small + (b - ntiles * RT_RPT) * (RT_NT / 64) + (tid >> 6);
         if (g >= nb || sk.blk(g)) return;
         const int64_t r0 = row_ptr[g];
         const int nr = int(row_ptr[g + 1] - r0);
