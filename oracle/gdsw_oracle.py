@@ -23,7 +23,9 @@ Steps, in the order of the paper's construction:
   O5  interface components Gamma_1..Gamma_nc (Sec. III, item 1)
   O6  partition of unity D = I on disjoint components (Sec. III, item 2)
   O7  null space Z (Sec. III, item 3), supplied by the caller
-  O8  Phi_Gamma_c spans D R_Gamma_c (R_Gamma Z) (Sec. III, item 4)
+  O8  Phi_Gamma_c spans D R_Gamma_c (R_Gamma Z) (Sec. III, item 4); O8r the
+      reduced variant with coarse functions for the vertices only (Sec. III,
+      variants of GDSW)
   O9  energy-minimising extension, eq. (2), with A_II block diagonal
   O10 coarse matrix A_0 = Phi^T A Phi (the paper prints Phi A Phi^T; only
       Phi^T A Phi has the right shape for eq. (1))
@@ -195,10 +197,70 @@ def orthonormal_span(B: np.ndarray, drop_tol: float = 1e-10) -> np.ndarray:
     return np.stack(Q, axis=1)
 
 
+def rgdsw_coarse_nodes(comps: list, S: dict):
+    """O8r (reduced GDSW, Sec. III: coarse functions only for vertices; the
+    construction is only cited there).  Reading: component d is an ancestor
+    of component c when S(c) is a proper subset of S(d); the coarse nodes
+    are the components without an ancestor (with a 27-point coupling on a
+    box partition: the cross points of the subdomains).  A coarse node
+    belongs to itself; any other component belongs to the coarse nodes that
+    are its ancestors.  Returns (coarse node list, owners per component),
+    both ascending."""
+    sets = [frozenset(S[int(c[0])]) for c in comps]
+    coarse = [i for i, s in enumerate(sets) if not any(s < t for t in sets)]
+    is_coarse = set(coarse)
+    owners = []
+    for i, s in enumerate(sets):
+        owners.append([i] if i in is_coarse else [v for v in coarse if s < sets[v]])
+    return coarse, owners
+
+
+def rgdsw_weight(owners_of_component: list) -> float:
+    """O8r: the weight of a component's rows in each coarse function it
+    belongs to: 1 / (number of coarse nodes it belongs to), so that the
+    weights of every interface node add up to one."""
+    return 1.0 / len(owners_of_component)
+
+
+def rgdsw_interface_basis(comps: list, S: dict, Z: np.ndarray, dpn: int, n: int):
+    """O8r: the interface values of the coarse functions of every coarse node
+    v: the null space Z on the components v belongs to, each component's rows
+    weighted by 1 / (number of coarse nodes it belongs to) (a partition of
+    unity on the interface), orthonormalised over that support as in O8.
+    Columns ordered by coarse node.  Returns (Phi_Gamma as n x n0 CSR, the
+    coarse columns touching each component, n0)."""
+    coarse, owners = rgdsw_coarse_nodes(comps, S)
+    support = {v: [] for v in coarse}
+    for i, own in enumerate(owners):
+        for v in own:
+            support[v].append(i)
+    comp_cols = [[] for _ in comps]
+    rows, cols, vals = [], [], []
+    n0 = 0
+    for v in coarse:
+        dofs = np.concatenate([dofs_of(comps[i], dpn) for i in support[v]])
+        w = np.concatenate([np.full(comps[i].size * dpn, rgdsw_weight(owners[i])) for i in support[v]])
+        Q = orthonormal_span(w[:, None] * Z[dofs, :])
+        k = Q.shape[1]
+        for i in support[v]:
+            comp_cols[i].extend(range(n0, n0 + k))
+        if k:
+            rr, cc = np.meshgrid(dofs, np.arange(n0, n0 + k), indexing="ij")
+            rows.append(rr.ravel())
+            cols.append(cc.ravel())
+            vals.append(Q.ravel())
+        n0 += k
+    if rows:
+        phi_g = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n0))
+    else:
+        phi_g = sp.csr_matrix((n, max(n0, 0)))
+    return phi_g, comp_cols, n0
+
+
 @dataclass
 class CoarseSpace:
     comps: list            # node arrays
-    comp_cols: list        # (first column, count) per component
+    comp_cols: list        # per component: the coarse columns that touch it
     phi: sp.csr_matrix     # n x n0
     n0: int
 
@@ -223,12 +285,16 @@ class GDSW:
     ``sweeps`` undamped Jacobi sweeps each, from a zero start; the factors
     are exact ILU(k) factors, or with ``factor_sweeps`` > 0 the FastILU
     approximation after that many sweeps.  coarse = False drops the coarse
-    term (one level).
+    term (one level); coarse_space = "rgdsw" takes the reduced GDSW interface
+    basis of O8r instead of one block per component (O8).
     """
 
     def __init__(self, A, part, dpn: int, n_parts: int, Z=None, overlap: int = 1,
                  coarse: bool = True, local: str = "exact", sweeps: int = 5,
-                 ilu_level: int = 0, factor_sweeps: int = 0):
+                 ilu_level: int = 0, factor_sweeps: int = 0, coarse_space: str = "gdsw"):
+        if coarse_space not in ("gdsw", "rgdsw"):
+            raise ValueError(coarse_space)
+        self.coarse_space = coarse_space
         self.A = sp.csr_matrix(A, dtype=np.float64)
         self.A.sort_indices()
         self.n = self.A.shape[0]
@@ -282,26 +348,30 @@ class GDSW:
     # -- O6-O10, O12 ---------------------------------------------------------
     def _coarse(self):
         dpn = self.dpn
-        rows, cols, vals = [], [], []
-        comp_cols = []
-        n0 = 0
-        for c in self.comps:
-            dofs = dofs_of(c, dpn)
-            Q = orthonormal_span(self.Z[dofs, :])
-            k = Q.shape[1]
-            comp_cols.append((n0, k))
-            if k:
-                rr, cc = np.meshgrid(dofs, np.arange(n0, n0 + k), indexing="ij")
-                rows.append(rr.ravel())
-                cols.append(cc.ravel())
-                vals.append(Q.ravel())
-            n0 += k
+        if self.coarse_space == "rgdsw":
+            phi_g, comp_cols, n0 = rgdsw_interface_basis(self.comps, self.S, self.Z, dpn, self.n)
+        else:
+            rows, cols, vals = [], [], []
+            comp_cols = []
+            n0 = 0
+            for c in self.comps:
+                dofs = dofs_of(c, dpn)
+                Q = orthonormal_span(self.Z[dofs, :])
+                k = Q.shape[1]
+                comp_cols.append(list(range(n0, n0 + k)))
+                if k:
+                    rr, cc = np.meshgrid(dofs, np.arange(n0, n0 + k), indexing="ij")
+                    rows.append(rr.ravel())
+                    cols.append(cc.ravel())
+                    vals.append(Q.ravel())
+                n0 += k
+            if n0:
+                phi_g = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                      shape=(self.n, n0))
         self.n0 = n0
         if n0 == 0:
             self.cs = None
             return
-        phi_g = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                              shape=(self.n, n0))
         gamma_dofs = dofs_of(np.nonzero(self.is_gamma)[0], dpn)
         interior_nodes = np.nonzero(~self.is_gamma)[0]
         # O9: Phi(I_i, :) = -A_{I_i I_i}^{-1} A_{I_i Gamma} Phi_Gamma per subdomain
@@ -378,7 +448,7 @@ class GDSW:
             "comp_of_node": comp_of,
             "n_comp": len(self.comps),
             "n0": getattr(self, "n0", 0),
-            "comp_rank": np.array([k for (_, k) in self.cs.comp_cols], dtype=np.int32)
+            "comp_rank": np.array([len(cc) for cc in self.cs.comp_cols], dtype=np.int32)
             if self.cs is not None else np.zeros(0, np.int32),
         }
 

@@ -220,3 +220,40 @@ def test_mutant_single_reduce_unscaled_direction(monkeypatch):
         return w - Q[:, :j + 1] @ a
     monkeypatch.setattr(O, "sr_next_candidate", bad)
     assert _sr_pins_fail() > 0
+
+
+# reduced GDSW: planted mistakes in the coarse nodes and the weights
+def _rgdsw_pins_fail():
+    from tests import test_oracle_rgdsw_pins as T
+    failures = 0
+    for fn in (lambda: T.test_coarse_nodes_are_interior_cross_points(12, 3),
+               lambda: T.test_null_space_reproduced("elasticity"),
+               lambda: T.test_null_space_reproduced("poisson"),
+               lambda: T.test_reduced_space_inside_gdsw_space("elasticity")):
+        try:
+            fn()
+        except AssertionError:
+            failures += 1
+    return failures
+
+
+def test_rgdsw_pins_pass_unmutated():
+    assert _rgdsw_pins_fail() == 0
+
+
+def test_mutant_rgdsw_missing_coarse_nodes(monkeypatch):
+    # only the components with the largest subdomain sets become coarse nodes
+    real = O.rgdsw_coarse_nodes
+
+    def fewer(comps, S):
+        coarse, owners = real(comps, S)
+        top = max(len(S[int(comps[v][0])]) for v in coarse)
+        keep = [v for v in coarse if len(S[int(comps[v][0])]) == top]
+        return keep, [[v for v in o if v in keep] for o in owners]
+    monkeypatch.setattr(O, "rgdsw_coarse_nodes", fewer)
+    assert _rgdsw_pins_fail() > 0
+
+
+def test_mutant_rgdsw_weights_not_a_partition_of_unity(monkeypatch):
+    monkeypatch.setattr(O, "rgdsw_weight", lambda owners: 1.0)
+    assert _rgdsw_pins_fail() > 0
