@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--gmres", choices=["single_reduce", "classical"], default="single_reduce",
                     help="GMRES variant of the elasticity workload: one reduction per iteration (the "
                          "paper's experiments) or classical Gram-Schmidt applied twice")
+    ap.add_argument("--coarse", choices=["gdsw", "rgdsw"], default=None,
+                    help="coarse space: GDSW, or the reduced GDSW space of the paper's experiments "
+                         "(default: rgdsw for the elasticity workload, gdsw for Poisson)")
     ap.add_argument("--ilu-level", type=int, default=0)
     ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--N", type=int, default=None)
@@ -107,6 +110,7 @@ def main():
     pbytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[args.prec]
     local = B.LOCAL_ILU0 if args.local == "ilu0" else B.LOCAL_EXACT
     elastic = args.workload == "elasticity"
+    coarse_name = args.coarse or ("rgdsw" if elastic else "gdsw")
     if elastic:
         N, Pn = args.N or 48, args.P or 6
         log(f"[bench] building Q1 elasticity {N}^3 with {Pn}^3 boxes")
@@ -129,6 +133,7 @@ def main():
                        B.gdsw_default_options(local=local, local_prec=precs[args.prec],
                                               basis_prec=B.FP64 if args.prec == "fp64" else B.FP32,
                                               ilu_level=args.ilu_level, ilu_factor_sweeps=args.factor_sweeps,
+                                              coarse=B.COARSE_RGDSW if coarse_name == "rgdsw" else B.COARSE_GDSW,
                                               flags=B.FLAG_GRAPHS if args.graphs else 0))
     t_an = time.perf_counter() - t0
     log(f"[bench] analysis {t_an:.2f}s; numerical setup on the GPU")
@@ -208,7 +213,8 @@ def main():
     # ---- elasticity: error against the FP64 oracle (sampled) -------------------------
     err = None
     if elastic and (N, Pn) == (48, 6):
-        gold = np.load(os.path.join(ROOT, "tests", "golden", "elasticity_oracle.npz"))
+        gold = np.load(os.path.join(ROOT, "tests", "golden", "elasticity_oracle.npz" if coarse_name == "gdsw"
+                                    else f"elasticity_{coarse_name}_oracle.npz"))
         idx = torch.from_numpy(gold["idx"]).to(dev)
         xe = torch.zeros_like(r)
         oe = B.gdsw_solve(h, rhs[0], xe, krylov=krylov, restart=30, rtol=1e-8, maxit=2000, stream=stream)
@@ -270,6 +276,7 @@ def main():
         from oracle import gdsw_oracle as O
         with threadpool_limits(limits=1):
             M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local=args.local, ilu_level=args.ilu_level,
+                       coarse_space=coarse_name,
                        factor_sweeps=args.factor_sweeps)
             b0 = rhs[args.warmup].cpu().numpy()
             t0 = time.perf_counter()
@@ -305,9 +312,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
         "data": "synthetic",
-        "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_gdsw_gmres30"
+        "config": {"workload": (f"elasticity_q1_{N}^3_P{Pn}^3_{args.local}_{coarse_name}_gmres30"
                                 f"{'_single_reduce' if args.gmres == 'single_reduce' else ''}" if elastic
-                                else f"poisson{N}^3_P{Pn}^3_{local_name}_gdsw_cg"), "n": n,
+                                else f"poisson{N}^3_P{Pn}^3_{local_name}_{coarse_name}_cg"), "n": n,
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": args.local,
                    "jacobi_sweeps": 5, "ilu_level": args.ilu_level, "ilu_factor_sweeps": args.factor_sweeps,
                    "local_prec": args.prec, "rtol": 1e-8,

@@ -50,8 +50,17 @@ typedef enum {
     GDSW_ERR_INTERNAL = 8
 } gdsw_status;
 
-/* Coarse space of eq. (1): none (one-level) or GDSW (eq. (2)). */
-enum { GDSW_COARSE_NONE = 0, GDSW_COARSE_GDSW = 1 };
+/* Coarse space of eq. (1): none (one-level), GDSW (eq. (2); one block of
+ * the null space per interface component), or the reduced GDSW variant the
+ * paper's experiments use (Sec. III, variants of GDSW; Sec. VII): coarse
+ * functions only for the interface components whose set of meeting
+ * subdomains is not contained in another component's (the cross points of a
+ * box partition with a 27-point coupling); every other component is shared
+ * among the coarse nodes whose sets strictly contain its own, each with
+ * weight 1 / (their number), and each coarse node's functions are the
+ * weighted null space over its support, orthonormalised, then extended by
+ * eq. (2). */
+enum { GDSW_COARSE_NONE = 0, GDSW_COARSE_GDSW = 1, GDSW_COARSE_RGDSW = 2 };
 
 /* Local solver for A_i^{-1}: exact (banded Cholesky, A_i must be SPD;
  * Sec. V-B "Sparse Direct Matrix Factorization") or ILU(0) in the natural

@@ -22,7 +22,7 @@ _LIB = None
 GDSW_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "SINGULAR", 3: "BREAKDOWN", 4: "NOT_CONVERGED",
                 5: "BUDGET", 6: "HIP", 7: "STATE", 8: "INTERNAL"}
-COARSE_NONE, COARSE_GDSW = 0, 1
+COARSE_NONE, COARSE_GDSW, COARSE_RGDSW = 0, 1, 2
 LOCAL_EXACT, LOCAL_ILU0 = 0, 1
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 KRYLOV_CG, KRYLOV_GMRES, KRYLOV_GMRES_SR = 0, 1, 2

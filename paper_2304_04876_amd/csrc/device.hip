@@ -423,7 +423,7 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const PhiBlocks &B = S.blk;
-    if (S.opt.coarse != GDSW_COARSE_GDSW || S.n0 == 0 || B.nb == 0) return;
+    if (S.opt.coarse == GDSW_COARSE_NONE || S.n0 == 0 || B.nb == 0) return;
     const int n0 = S.n0;
     D.blk_row_ptr = D.upload(B.row_ptr, s);
     // interior blocks come first; they (and any block of many rows) take a
@@ -541,8 +541,9 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         int32_t *d = D.upload(S.cpl_stride, s);
         int32_t *e = D.upload(S.cpl_rank, s);
         int32_t *f = D.upload(S.cpl_slot, s);
+        int32_t *fm = D.upload(S.cpl_slotmap, s);
         hipLaunchKernelGGL(k_ext_rhs, dim3(nblocks(nint, 256)), dim3(256), 0, s, D.val, d_int_ptr, S.np, d_ext_off,
-                           a, b, c, d, e, f, d_phig, E, nint);
+                           a, b, c, d, e, f, fm, d_phig, E, nint);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         D.release(a, 8 * S.cpl_ptr.size());
@@ -551,6 +552,7 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         D.release(d, 4 * S.cpl_stride.size());
         D.release(e, 4 * S.cpl_rank.size());
         D.release(f, 4 * S.cpl_slot.size());
+        D.release(fm, 4 * S.cpl_slotmap.size());
     }
     int *d_status = D.alloc<int>(std::max(S.np, 1));
     HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
@@ -597,16 +599,25 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
             int64_t *pa = D.upload(S.pair_apos, s);
             int32_t *plc = D.upload(S.pair_lr_c, s);
             int32_t *pld = D.upload(S.pair_lr_d, s);
-            int64_t *tg = D.upload(S.a0pair_tgt, s);
             const int64_t total = S.pair_off[npairs];
+            double *T2 = D.alloc<double>(total);
             hipLaunchKernelGGL(k_t2, dim3(nblocks(total, 256)), dim3(256), 0, s, D.val, npairs, pc, pd, po, pe, pa,
-                               plc, pld, d_comp_rank, d_phig_off, d_phig, tg, A0raw, total);
+                               plc, pld, d_comp_rank, d_phig_off, d_phig, T2, total);
+            int64_t *st2 = D.upload(S.a0seg2_tgt, s);
+            int64_t *sp2 = D.upload(S.a0seg2_ptr, s);
+            int64_t *ss2 = D.upload(S.a0seg2_src, s);
+            const int64_t nseg2 = int64_t(S.a0seg2_tgt.size());
+            hipLaunchKernelGGL(k_a0_segments, dim3(nblocks(nseg2, 256)), dim3(256), 0, s, st2, sp2, ss2, T2, A0raw,
+                               nseg2);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));
+            D.release(T2, 8 * size_t(total));
+            D.release(st2, 8 * S.a0seg2_tgt.size()); D.release(sp2, 8 * S.a0seg2_ptr.size());
+            D.release(ss2, 8 * S.a0seg2_src.size());
             D.release(pc, 4 * S.pair_c.size()); D.release(pd, 4 * S.pair_d.size());
             D.release(po, 8 * S.pair_off.size()); D.release(pe, 8 * S.pair_eptr.size());
             D.release(pa, 8 * S.pair_apos.size()); D.release(plc, 4 * S.pair_lr_c.size());
-            D.release(pld, 4 * S.pair_lr_d.size()); D.release(tg, 8 * S.a0pair_tgt.size());
+            D.release(pld, 4 * S.pair_lr_d.size());
         }
         const int64_t nt1 = S.t1_off[S.np];
         if (nt1) {

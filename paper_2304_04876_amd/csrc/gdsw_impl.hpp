@@ -56,10 +56,12 @@ struct Symbolic {
     std::vector<int32_t> comp_of_node;  // [nn], -1 interior
     std::vector<int64_t> comp_ptr;      // [nc+1]
     std::vector<int32_t> comp_nodes;
-    std::vector<int32_t> comp_rank;     // coarse columns per component
-    std::vector<int32_t> comp_col0;     // first coarse column
-    std::vector<int64_t> phig_off;      // [nc+1] offsets of the orthonormal blocks
-    std::vector<double> phig;           // column-major (|c|*dpn x r_c) blocks
+    std::vector<int32_t> comp_rank;     // coarse columns touching each component (k_c)
+    std::vector<int64_t> ccol_ptr;      // [nc+1]
+    std::vector<int32_t> ccol;          // those columns, ascending (GDSW: the component's own)
+    std::vector<int32_t> col_comp;      // [n0] component a coarse column belongs to (its coarse node)
+    std::vector<int64_t> phig_off;      // [nc+1] offsets of the interface blocks
+    std::vector<double> phig;           // column-major (|c|*dpn x k_c) blocks
     int32_t nc = 0, n0 = 0;
     int64_t n_gamma_nodes = 0;
 
@@ -74,7 +76,8 @@ struct Symbolic {
     std::vector<int64_t> cpl_phi;   // offset of the Phi_G row of the Gamma dof
     std::vector<int32_t> cpl_stride;// rows of that component block
     std::vector<int32_t> cpl_rank;  // columns of that component block
-    std::vector<int32_t> cpl_slot;  // first slot of those columns in scol of i
+    std::vector<int32_t> cpl_slot;  // start in cpl_slotmap of the slots of those columns in scol of i
+    std::vector<int32_t> cpl_slotmap;   // per (subdomain, adjacent component): slot of each block column
     // extension value offsets (column-major n_Ii x k_i per subdomain)
     std::vector<int64_t> ext_off;   // [np+1]
 
@@ -127,6 +130,9 @@ struct Symbolic {
     std::vector<int64_t> a0seg_ptr;           // [nseg+1]
     std::vector<int64_t> a0seg_src;           // index into the T1 buffer
     std::vector<int64_t> a0pair_tgt;          // target of every T2 value (same order as values)
+    std::vector<int64_t> a0seg2_tgt;          // T2 values added by target (several pairs may
+    std::vector<int64_t> a0seg2_ptr;          //   share a target when components share
+    std::vector<int64_t> a0seg2_src;          //   coarse columns), ascending pair order
 
     // ---- independent problems packed in one handle (block-diagonal A) ----------
     int32_t nprob = 1;

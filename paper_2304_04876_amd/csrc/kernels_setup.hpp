@@ -491,8 +491,8 @@ __global__ void k_ext_rhs(const double *__restrict__ Aval, const int64_t *__rest
                           const int64_t *__restrict__ ext_off, const int64_t *__restrict__ cpl_ptr,
                           const int64_t *__restrict__ cpl_apos, const int64_t *__restrict__ cpl_phi,
                           const int32_t *__restrict__ cpl_stride, const int32_t *__restrict__ cpl_rank,
-                          const int32_t *__restrict__ cpl_slot, const double *__restrict__ phig,
-                          double *__restrict__ E, int64_t nint) {
+                          const int32_t *__restrict__ cpl_slot, const int32_t *__restrict__ slotmap,
+                          const double *__restrict__ phig, double *__restrict__ E, int64_t nint) {
     const int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (q >= nint) return;
     int lo = 0, hi = np;   // subdomain with int_ptr[i] <= q < int_ptr[i+1]
@@ -508,7 +508,7 @@ __global__ void k_ext_rhs(const double *__restrict__ Aval, const int64_t *__rest
         const double a = Aval[cpl_apos[e]];
         const double *ph = phig + cpl_phi[e];
         const int st = cpl_stride[e], rk = cpl_rank[e], sl = cpl_slot[e];
-        for (int j = 0; j < rk; ++j) Ei[(sl + j) * nr + l] += a * ph[int64_t(j) * st];
+        for (int j = 0; j < rk; ++j) Ei[int64_t(slotmap[sl + j]) * nr + l] += a * ph[int64_t(j) * st];
     }
 }
 
@@ -567,15 +567,15 @@ __global__ void k_t1(const int64_t *__restrict__ int_ptr, const int64_t *__restr
 }
 
 // Interface-interface part of A_0: for every component pair (c, d) with
-// couplings in A, A0[c-cols, d-cols] = Phi_Gc^T A_{cd} Phi_Gd, one thread per
-// entry, couplings in a fixed order.
+// couplings in A, the entries of Phi_Gc^T A_{cd} Phi_Gd, one thread per
+// entry, couplings in a fixed order, into T2 (added into A_0 by target,
+// k_a0_segments: components may share coarse columns).
 __global__ void k_t2(const double *__restrict__ Aval, int npairs, const int32_t *__restrict__ pair_c,
                      const int32_t *__restrict__ pair_d, const int64_t *__restrict__ pair_off,
                      const int64_t *__restrict__ pair_eptr, const int64_t *__restrict__ pair_apos,
                      const int32_t *__restrict__ pair_lr_c, const int32_t *__restrict__ pair_lr_d,
                      const int32_t *__restrict__ comp_rank, const int64_t *__restrict__ phig_off,
-                     const double *__restrict__ phig, const int64_t *__restrict__ tgt,
-                     double *__restrict__ A0, int64_t total) {
+                     const double *__restrict__ phig, double *__restrict__ T2, int64_t total) {
     const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (t >= total) return;
     int lo = 0, hi = npairs;   // pair with pair_off[q] <= t < pair_off[q+1]
@@ -595,7 +595,7 @@ __global__ void k_t2(const double *__restrict__ Aval, int npairs, const int32_t 
     double acc = 0.0;
     for (int64_t e = pair_eptr[q]; e < pair_eptr[q + 1]; ++e)
         acc += pc[pair_lr_c[e]] * Aval[pair_apos[e]] * pd[pair_lr_d[e]];
-    A0[tgt[t]] = acc;
+    T2[t] = acc;
 }
 
 // A0[tgt] += sum of the subdomain contributions of the segment, ascending

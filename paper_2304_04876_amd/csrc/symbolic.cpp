@@ -25,6 +25,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <queue>
@@ -63,7 +64,8 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
     gdsw_options o;
     if (opt) o = *opt; else gdsw_default_options(&o);
     if (o.overlap < 0 || o.overlap > 64) fail(GDSW_ERR_INVALID_ARG, "overlap out of range");
-    if (o.coarse != GDSW_COARSE_NONE && o.coarse != GDSW_COARSE_GDSW) fail(GDSW_ERR_INVALID_ARG, "coarse");
+    if (o.coarse != GDSW_COARSE_NONE && o.coarse != GDSW_COARSE_GDSW && o.coarse != GDSW_COARSE_RGDSW)
+        fail(GDSW_ERR_INVALID_ARG, "coarse");
     if (o.local != GDSW_LOCAL_EXACT && o.local != GDSW_LOCAL_ILU0) fail(GDSW_ERR_INVALID_ARG, "local");
     if (o.jacobi_sweeps < 1 || o.jacobi_sweeps > 1000) fail(GDSW_ERR_INVALID_ARG, "jacobi_sweeps");
     if (o.local_prec < GDSW_FP64 || o.local_prec > GDSW_FP16) fail(GDSW_ERR_INVALID_ARG, "local_prec");
@@ -109,7 +111,7 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
         s.Z.assign(s.n, 1.0);
     }
     // the coarse assembly and the Cholesky local solver use symmetry of A
-    if (o.coarse == GDSW_COARSE_GDSW || o.local == GDSW_LOCAL_EXACT) {
+    if (o.coarse != GDSW_COARSE_NONE || o.local == GDSW_LOCAL_EXACT) {
         for (int64_t i = 0; i < s.n; ++i)
             for (int64_t p = s.rowptr[i]; p < s.rowptr[i + 1]; ++p) {
                 int32_t j = s.col[p];
@@ -300,24 +302,19 @@ void build_interface(Symbolic &s) {
         ++nc;
     }
     s.nc = nc;
-    // interface basis: orthonormalise Z restricted to each component
+    // interface basis
     const int dpn = s.dpn, nz = s.n_null;
-    s.comp_rank.assign(nc, 0);
-    s.comp_col0.assign(nc, 0);
-    s.phig_off.assign(nc + 1, 0);
-    std::vector<std::vector<double>> blocks(nc);
-#pragma omp parallel for schedule(dynamic)
-    for (int32_t c = 0; c < nc; ++c) {
-        int64_t m = (s.comp_ptr[c + 1] - s.comp_ptr[c]) * dpn;
-        std::vector<double> Q;   // kept columns, each m long
+    // Gram-Schmidt of the columns of a (m x nz) block given by value(r, j),
+    // twice per column, dropping a column whose remainder is <= 1e-10 of its
+    // norm; returns the kept orthonormal columns (column-major, m each)
+    auto orthonormalise = [&](int64_t m, const std::function<double(int64_t, int)> &value, int &kept) {
+        std::vector<double> Q;
         std::vector<double> v(m);
-        int kept = 0;
+        kept = 0;
         for (int j = 0; j < nz; ++j) {
             double nb = 0.0;
             for (int64_t r = 0; r < m; ++r) {
-                int64_t node = s.comp_nodes[s.comp_ptr[c] + r / dpn];
-                int64_t dof = node * dpn + r % dpn;
-                v[r] = s.Z[int64_t(j) * s.n + dof];
+                v[r] = value(r, j);
                 nb += v[r] * v[r];
             }
             nb = std::sqrt(nb);
@@ -336,16 +333,118 @@ void build_interface(Symbolic &s) {
             for (int64_t r = 0; r < m; ++r) Q.push_back(v[r] / nv);
             ++kept;
         }
-        s.comp_rank[c] = kept;
-        blocks[c] = std::move(Q);
+        return Q;
+    };
+    auto zval = [&](int32_t c, int64_t r, int j) {   // Z at row r of component c's block
+        int64_t node = s.comp_nodes[s.comp_ptr[c] + r / dpn];
+        return s.Z[int64_t(j) * s.n + node * dpn + r % dpn];
+    };
+    s.comp_rank.assign(nc, 0);
+    s.ccol_ptr.assign(nc + 1, 0);
+    s.ccol.clear();
+    s.col_comp.clear();
+    s.phig_off.assign(nc + 1, 0);
+    std::vector<std::vector<double>> blocks(nc);
+    if (s.opt.coarse != GDSW_COARSE_RGDSW) {
+        // GDSW: Z restricted to each component, orthonormalised
+#pragma omp parallel for schedule(dynamic)
+        for (int32_t c = 0; c < nc; ++c) {
+            const int64_t m = (s.comp_ptr[c + 1] - s.comp_ptr[c]) * dpn;
+            int kept = 0;
+            blocks[c] = orthonormalise(m, [&](int64_t r, int j) { return zval(c, r, j); }, kept);
+            s.comp_rank[c] = kept;
+        }
+        for (int32_t c = 0; c < nc; ++c) {
+            for (int32_t j = 0; j < s.comp_rank[c]; ++j) {
+                s.ccol.push_back(int32_t(s.col_comp.size()));
+                s.col_comp.push_back(c);
+            }
+            s.ccol_ptr[c + 1] = int64_t(s.ccol.size());
+        }
+    } else {
+        // reduced GDSW (coarse functions for the vertices only): component d
+        // is an ancestor of c when S(c) is a proper subset of S(d); the
+        // coarse nodes are the components without an ancestor; a coarse node
+        // owns itself, any other component is owned by its coarse-node
+        // ancestors and carries the weight 1 / (number of owners) in each of
+        // their functions; a coarse node's functions are Z on its support,
+        // weighted, orthonormalised over the support
+        std::vector<const std::vector<int32_t> *> cset(nc);
+        for (int32_t c = 0; c < nc; ++c) cset[c] = &S[s.comp_nodes[s.comp_ptr[c]]];
+        std::vector<std::vector<int32_t>> comps_of_sub(s.np);
+        for (int32_t c = 0; c < nc; ++c) comps_of_sub[(*cset[c])[0]].push_back(c);
+        for (int32_t c = 0; c < nc; ++c)
+            for (size_t t = 1; t < cset[c]->size(); ++t) comps_of_sub[(*cset[c])[t]].push_back(c);
+        auto strict_subset = [&](int32_t a, int32_t b) {   // S(a) proper subset of S(b)
+            const auto &x = *cset[a], &y = *cset[b];
+            return x.size() < y.size() && std::includes(y.begin(), y.end(), x.begin(), x.end());
+        };
+        std::vector<char> is_coarse(nc, 1);
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t d : comps_of_sub[(*cset[c])[0]])
+                if (strict_subset(c, d)) { is_coarse[c] = 0; break; }
+        std::vector<std::vector<int32_t>> owners(nc);
+        for (int32_t c = 0; c < nc; ++c) {
+            if (is_coarse[c]) { owners[c].push_back(c); continue; }
+            for (int32_t d : comps_of_sub[(*cset[c])[0]])
+                if (is_coarse[d] && strict_subset(c, d)) owners[c].push_back(d);
+            std::sort(owners[c].begin(), owners[c].end());
+        }
+        std::vector<std::vector<int32_t>> support(nc);   // of each coarse node, ascending
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t v : owners[c]) support[v].push_back(c);
+        std::vector<int32_t> coarse_nodes;
+        for (int32_t c = 0; c < nc; ++c)
+            if (is_coarse[c]) coarse_nodes.push_back(c);
+        const int32_t nv = int32_t(coarse_nodes.size());
+        std::vector<std::vector<double>> vblocks(nv);
+        std::vector<int> vrank(nv, 0);
+        std::vector<std::vector<int64_t>> vrow0(nv);   // first support row of each supporting component
+#pragma omp parallel for schedule(dynamic)
+        for (int32_t t = 0; t < nv; ++t) {
+            const int32_t v = coarse_nodes[t];
+            const auto &sup = support[v];
+            std::vector<int64_t> r0(sup.size() + 1, 0);
+            for (size_t q = 0; q < sup.size(); ++q)
+                r0[q + 1] = r0[q] + (s.comp_ptr[sup[q] + 1] - s.comp_ptr[sup[q]]) * dpn;
+            const int64_t m = r0.back();
+            auto value = [&](int64_t r, int j) {
+                const size_t q = size_t(std::upper_bound(r0.begin(), r0.end(), r) - r0.begin()) - 1;
+                const int32_t c = sup[q];
+                return zval(c, r - r0[q], j) / double(owners[c].size());
+            };
+            int kept = 0;
+            vblocks[t] = orthonormalise(m, value, kept);
+            vrank[t] = kept;
+            vrow0[t] = std::move(r0);
+        }
+        std::vector<int32_t> vcol0(nv + 1, 0), vidx(nc, -1);
+        for (int32_t t = 0; t < nv; ++t) {
+            vcol0[t + 1] = vcol0[t] + vrank[t];
+            vidx[coarse_nodes[t]] = t;
+            for (int j = 0; j < vrank[t]; ++j) s.col_comp.push_back(coarse_nodes[t]);
+        }
+        // per component: the columns of its owners (ascending) and their
+        // values on its rows
+        for (int32_t c = 0; c < nc; ++c) {
+            const int64_t m = (s.comp_ptr[c + 1] - s.comp_ptr[c]) * dpn;
+            for (int32_t v : owners[c]) {
+                const int32_t t = vidx[v];
+                const auto &sup = support[v];
+                const size_t q = size_t(std::lower_bound(sup.begin(), sup.end(), c) - sup.begin());
+                const int64_t off = vrow0[t][q], mv = vrow0[t].back();
+                for (int j = 0; j < vrank[t]; ++j) {
+                    s.ccol.push_back(vcol0[t] + j);
+                    const double *src = vblocks[t].data() + int64_t(j) * mv + off;
+                    blocks[c].insert(blocks[c].end(), src, src + m);
+                }
+                s.comp_rank[c] += vrank[t];
+            }
+            s.ccol_ptr[c + 1] = int64_t(s.ccol.size());
+        }
     }
-    int32_t col = 0;
-    for (int32_t c = 0; c < nc; ++c) {
-        s.comp_col0[c] = col;
-        col += s.comp_rank[c];
-        s.phig_off[c + 1] = s.phig_off[c] + int64_t(blocks[c].size());
-    }
-    s.n0 = (s.opt.coarse == GDSW_COARSE_GDSW) ? col : 0;
+    for (int32_t c = 0; c < nc; ++c) s.phig_off[c + 1] = s.phig_off[c] + int64_t(blocks[c].size());
+    s.n0 = (s.opt.coarse != GDSW_COARSE_NONE) ? int32_t(s.col_comp.size()) : 0;
     s.phig.resize(s.phig_off[nc]);
     for (int32_t c = 0; c < nc; ++c) std::copy(blocks[c].begin(), blocks[c].end(), s.phig.begin() + s.phig_off[c]);
 }
@@ -628,13 +727,15 @@ void build_coarse(Symbolic &s) {
         for (int64_t q = s.comp_ptr[c]; q < s.comp_ptr[c + 1]; ++q)
             for (int k = 0; k < dpn; ++k)
                 comp_lr[int64_t(s.comp_nodes[q]) * dpn + k] = int32_t((q - s.comp_ptr[c]) * dpn + k);
-    const bool coarse = s.opt.coarse == GDSW_COARSE_GDSW && s.n0 > 0;
+    const bool coarse = s.opt.coarse != GDSW_COARSE_NONE && s.n0 > 0;
     // adjacent coarse columns of each interior block and the couplings
     s.scol_ptr.assign(np + 1, 0);
     s.scol.clear();
     s.cpl_ptr.assign(nint + 1, 0);
     s.cpl_apos.clear(); s.cpl_phi.clear(); s.cpl_stride.clear(); s.cpl_rank.clear(); s.cpl_slot.clear();
-    std::vector<int32_t> slot_of_comp(s.nc, -1);
+    s.cpl_slotmap.clear();
+    std::vector<int32_t> slot_of_comp(s.nc, -1);   // start of the component's slots in cpl_slotmap
+    std::vector<int32_t> slot_of_col(coarse ? s.n0 : 0, -1);
     for (int i = 0; i < np; ++i) {
         std::vector<int32_t> comps;
         for (int64_t q = s.int_ptr[i]; q < s.int_ptr[i + 1]; ++q) {
@@ -647,12 +748,18 @@ void build_coarse(Symbolic &s) {
         }
         std::sort(comps.begin(), comps.end());
         comps.erase(std::unique(comps.begin(), comps.end()), comps.end());
-        int32_t slot = 0;
+        // the coarse columns of the adjacent components, ascending, each once
+        const size_t sc0 = s.scol.size();
+        for (int32_t c : comps)
+            for (int64_t q = s.ccol_ptr[c]; q < s.ccol_ptr[c + 1]; ++q) s.scol.push_back(s.ccol[q]);
+        std::sort(s.scol.begin() + sc0, s.scol.end());
+        s.scol.erase(std::unique(s.scol.begin() + sc0, s.scol.end()), s.scol.end());
+        for (size_t q = sc0; q < s.scol.size(); ++q) slot_of_col[s.scol[q]] = int32_t(q - sc0);
         for (int32_t c : comps) {
-            slot_of_comp[c] = slot;
-            for (int32_t j = 0; j < s.comp_rank[c]; ++j) s.scol.push_back(s.comp_col0[c] + j);
-            slot += s.comp_rank[c];
+            slot_of_comp[c] = int32_t(s.cpl_slotmap.size());
+            for (int64_t q = s.ccol_ptr[c]; q < s.ccol_ptr[c + 1]; ++q) s.cpl_slotmap.push_back(slot_of_col[s.ccol[q]]);
         }
+        for (size_t q = sc0; q < s.scol.size(); ++q) slot_of_col[s.scol[q]] = -1;
         s.scol_ptr[i + 1] = int64_t(s.scol.size());
         for (int64_t q = s.int_ptr[i]; q < s.int_ptr[i + 1]; ++q) {
             int32_t d = s.int_idx[q];
@@ -736,7 +843,7 @@ void build_coarse(Symbolic &s) {
             if (k == 0) continue;
             for (int64_t q = s.comp_ptr[c]; q < s.comp_ptr[c + 1]; ++q)
                 for (int kk = 0; kk < dpn; ++kk) B.rows.push_back(int32_t(int64_t(s.comp_nodes[q]) * dpn + kk));
-            for (int32_t j = 0; j < k; ++j) B.cols.push_back(s.comp_col0[c] + j);
+            for (int64_t q = s.ccol_ptr[c]; q < s.ccol_ptr[c + 1]; ++q) B.cols.push_back(s.ccol[q]);
             int64_t nr = (s.comp_ptr[c + 1] - s.comp_ptr[c]) * dpn;
             B.row_ptr.push_back(int64_t(B.rows.size()));
             B.col_ptr.push_back(int64_t(B.cols.size()));
@@ -758,10 +865,11 @@ void build_coarse(Symbolic &s) {
             return int32_t(std::upper_bound(s.prob_ptr.begin(), s.prob_ptr.end(), d) - s.prob_ptr.begin() - 1);
         };
         std::vector<int32_t> cnt(s.nprob, 0);
-        for (int32_t c = 0; c < s.nc && coarse; ++c) {
+        for (int32_t col = 0; col < n0; ++col) {
+            const int32_t c = s.col_comp[col];
             const int32_t k = prob_of_dof(int64_t(s.comp_nodes[s.comp_ptr[c]]) * dpn);
-            for (int32_t j = 0; j < s.comp_rank[c]; ++j) s.cprob[s.comp_col0[c] + j] = k;
-            cnt[k] += s.comp_rank[c];
+            s.cprob[col] = k;
+            cnt[k] += 1;
         }
         for (int32_t c = 1; c < n0; ++c)
             if (s.cprob[c] < s.cprob[c - 1]) fail(GDSW_ERR_INTERNAL, "coarse columns of a problem not contiguous");
@@ -828,8 +936,25 @@ void build_coarse(Symbolic &s) {
             s.pair_off.push_back(s.pair_off.back() + rc * rd);
             for (int64_t a = 0; a < rc; ++a)
                 for (int64_t b = 0; b < rd; ++b)
-                    s.a0pair_tgt.push_back(a0_index(int32_t(s.comp_col0[c] + a), int32_t(s.comp_col0[d] + b)));
+                    s.a0pair_tgt.push_back(a0_index(s.ccol[s.ccol_ptr[c] + a], s.ccol[s.ccol_ptr[d] + b]));
         }
+    }
+    // T2 values by target, ascending pair order (one value per target unless
+    // components share coarse columns)
+    s.a0seg2_tgt.clear(); s.a0seg2_ptr.assign(1, 0); s.a0seg2_src.clear();
+    {
+        std::vector<int64_t> order(s.a0pair_tgt.size());
+        std::iota(order.begin(), order.end(), int64_t(0));
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t x, int64_t y) { return s.a0pair_tgt[x] < s.a0pair_tgt[y]; });
+        for (size_t q = 0; q < order.size(); ++q) {
+            if (q == 0 || s.a0pair_tgt[order[q]] != s.a0pair_tgt[order[q - 1]]) {
+                if (q) s.a0seg2_ptr.push_back(int64_t(q));
+                s.a0seg2_tgt.push_back(s.a0pair_tgt[order[q]]);
+            }
+            s.a0seg2_src.push_back(order[q]);
+        }
+        if (!order.empty()) s.a0seg2_ptr.push_back(int64_t(order.size()));
     }
     // subdomain terms E_i^T X_i: segments by target, ascending subdomain
     for (int i = 0; i < np; ++i) {

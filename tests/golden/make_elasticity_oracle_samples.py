@@ -1,6 +1,7 @@
-"""Writes elasticity_oracle.npz: the FP64 oracle on the Q1 elasticity
-workload (48^3 elements, 6^3 boxes, 6 rigid-body modes, exact local solves,
-GDSW coarse space), sampled, for the full-size GPU parity test.
+"""Writes elasticity_oracle.npz (GDSW coarse space) or, with the argument
+`rgdsw`, elasticity_rgdsw_oracle.npz (the reduced GDSW space): the FP64
+oracle on the Q1 elasticity workload (48^3 elements, 6^3 boxes, 6 rigid-body
+modes, exact local solves), sampled, for the full-size GPU parity test.
 
 Calls only the oracle and the seeded input generators.  Stored:
   idx       4096 sampled dof indices (seed 11)
@@ -24,10 +25,11 @@ from oracle import gdsw_oracle as O  # noqa: E402
 
 
 def main():
+    coarse = sys.argv[1] if len(sys.argv) > 1 else "gdsw"
     pr = P.workload_elasticity()
     Z = P.rigid_body_modes(pr)
     t = time.time()
-    M = O.GDSW(pr.A, pr.part, 3, pr.n_parts, Z=Z, local="exact")
+    M = O.GDSW(pr.A, pr.part, 3, pr.n_parts, Z=Z, local="exact", coarse_space=coarse)
     print("oracle setup", time.time() - t, flush=True)
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(pr.n, 4096, replace=False))
@@ -35,7 +37,8 @@ def main():
     t = time.time()
     res = O.gmres(pr.A, pr.b, M, rtol=1e-8, restart=30)
     print("gmres", res.iters, time.time() - t, flush=True)
-    np.savez_compressed(os.path.join(HERE, "elasticity_oracle.npz"), idx=idx, z=z[idx], z_norm=np.abs(z).max(),
+    name = "elasticity_oracle.npz" if coarse == "gdsw" else f"elasticity_{coarse}_oracle.npz"
+    np.savez_compressed(os.path.join(HERE, name), idx=idx, z=z[idx], z_norm=np.abs(z).max(),
                         n0=M.A0.shape[0], a0_diag=np.diag(M.A0).copy(), gm_iters=res.iters, x_gm=res.x[idx],
                         x_norm=np.abs(res.x).max())
 

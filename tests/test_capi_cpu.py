@@ -36,11 +36,12 @@ def test_status_strings_and_defaults():
     assert (o.overlap, o.coarse, o.local, o.jacobi_sweeps, o.local_prec) == (1, 1, 0, 5, 0)
 
 
-def _maps_equal(pr, Z=None, overlap=1, local="exact"):
+def _maps_equal(pr, Z=None, overlap=1, local="exact", coarse="gdsw"):
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
-                       B.gdsw_default_options(overlap=overlap, local=0 if local == "exact" else 1))
+                       B.gdsw_default_options(overlap=overlap, local=0 if local == "exact" else 1,
+                                              coarse=B.COARSE_RGDSW if coarse == "rgdsw" else B.COARSE_GDSW))
     try:
-        M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, overlap=overlap, local=local)
+        M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, overlap=overlap, local=local, coarse_space=coarse)
         m = M.maps()
         ov_ptr = np.concatenate([[0], np.cumsum([r.size for r in M.R])])
         assert np.array_equal(B.gdsw_copy_map(h, B.MAP_OV_PTR), ov_ptr)
@@ -91,6 +92,21 @@ def test_maps_elasticity_three_boxes():
 def test_maps_diffusion():
     spec = P.batch_diffusion_specs(3)[1]
     _maps_equal(P.batch_diffusion_problem(spec))
+
+
+@pytest.mark.parametrize("case", ["poisson20", "poisson12", "elasticity6", "elasticity9", "diffusion"])
+def test_maps_reduced_coarse_space(case):
+    """Reduced GDSW: the coarse dimension, the columns touching each
+    component and Phi's column pattern equal the oracle's."""
+    if case == "poisson20":
+        _maps_equal(P.poisson3d(20, 2), coarse="rgdsw")
+    elif case == "poisson12":
+        _maps_equal(P.poisson3d(12, 3), coarse="rgdsw")
+    elif case.startswith("elasticity"):
+        pr = P.elasticity_q1(int(case[10:]), 2 if case == "elasticity6" else 3)
+        _maps_equal(pr, P.rigid_body_modes(pr), coarse="rgdsw")
+    else:
+        _maps_equal(P.batch_diffusion_problem(P.batch_diffusion_specs(3)[1]), coarse="rgdsw")
 
 
 def test_closed_form_counts_small_workload():

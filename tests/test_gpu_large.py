@@ -114,3 +114,38 @@ def test_elasticity_full_size(prec):
     xs = x.cpu().numpy()[ref["idx"]]
     assert np.abs(xs - ref["x_gm"]).max() <= 1e-5 * float(ref["x_norm"])
     g.close()
+
+
+ELAST_R = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "elasticity_rgdsw_oracle.npz")
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_elasticity_full_size_reduced_coarse_space(prec):
+    """The same workload with the reduced GDSW space of the paper's
+    experiments and the single-reduce GMRES(30): FP64 matches the oracle's
+    apply (bound as above) and iteration count."""
+    print(f"[large] elasticity 48^3 rgdsw prec={prec}", file=sys.stderr, flush=True)
+    ref = np.load(ELAST_R)
+    pr = P.workload_elasticity()
+    Z = P.rigid_body_modes(pr)
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 3, Z, local=B.LOCAL_EXACT, local_prec=prec,
+               basis_prec=B.FP64 if prec == B.FP64 else B.FP32, coarse=B.COARSE_RGDSW)
+    assert g.info()["n0"] == int(ref["n0"])
+    a0 = g.map(B.MAP_A0).reshape(int(ref["n0"]), int(ref["n0"]))
+    if prec == B.FP64:
+        assert np.abs(np.diag(a0) - ref["a0_diag"]).max() <= 1e-12 * np.abs(ref["a0_diag"]).max()
+    b = torch.from_numpy(pr.b).cuda()
+    z = torch.zeros_like(b)
+    g.apply(b, z)
+    zs = z.cpu().numpy()[ref["idx"]]
+    err = np.abs(zs - ref["z"]).max() / float(ref["z_norm"])
+    if prec == B.FP64:
+        assert err <= 1e-11, err
+    x = torch.zeros_like(b)
+    out = g.solve(b, x, krylov=B.KRYLOV_GMRES_SR, restart=30, rtol=1e-8)
+    assert out["converged"] and out["rel_res_true"] <= 1e-7
+    slack = {B.FP64: 1, B.FP32: 2}[prec]
+    assert abs(out["iterations"] - int(ref["gm_iters"])) <= slack, (out, int(ref["gm_iters"]))
+    xs = x.cpu().numpy()[ref["idx"]]
+    assert np.abs(xs - ref["x_gm"]).max() <= 1e-5 * float(ref["x_norm"])
+    g.close()
