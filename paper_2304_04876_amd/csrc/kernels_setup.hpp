@@ -326,18 +326,20 @@ __device__ __forceinline__ void band_stage_triangle(const VT *__restrict__ L, in
     }
 }
 
+// The staged triangle is zero in rows kb..63 (pivot included), so the steps
+// s >= kb leave the lanes below kb unchanged: no per-step test, which lets
+// the unrolled steps read their LDS entries eight at a time ahead of the
+// dependent arithmetic.
 template <typename AT>
 __device__ __forceinline__ void band_block_fwd(const AT *sT, AT *y, int k0, int kb, int lane) {
     AT yt = lane < kb ? y[k0 + lane] : AT(0);
     const AT *row = sT + lane * BS_LD;
 #pragma unroll 8
     for (int s = 0; s < BS_NB; ++s) {
-        if (s < kb) {
-            const AT l = row[s];
-            if (lane == s) yt *= l;
-            const AT ys = lane_read(yt, s);
-            if (lane > s) yt -= l * ys;
-        }
+        const AT l = row[s];
+        if (lane == s) yt *= l;
+        const AT ys = lane_read(yt, s);
+        if (lane > s) yt -= l * ys;
     }
     if (lane < kb) y[k0 + lane] = yt;
 }
@@ -347,12 +349,10 @@ __device__ __forceinline__ void band_block_bwd(const AT *sT, AT *y, int k0, int 
     AT yt = lane < kb ? y[k0 + lane] : AT(0);
 #pragma unroll 8
     for (int s = BS_NB - 1; s >= 0; --s) {
-        if (s < kb) {
-            const AT l = sT[s * BS_LD + lane];   // L(k0+s, k0+lane), or the reciprocal pivot at s = lane
-            if (lane == s) yt *= l;
-            const AT zs = lane_read(yt, s);
-            if (lane < s) yt -= l * zs;
-        }
+        const AT l = sT[s * BS_LD + lane];   // L(k0+s, k0+lane), or the reciprocal pivot at s = lane
+        if (lane == s) yt *= l;
+        const AT zs = lane_read(yt, s);
+        if (lane < s) yt -= l * zs;
     }
     if (lane < kb) y[k0 + lane] = yt;
 }
