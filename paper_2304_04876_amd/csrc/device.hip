@@ -161,6 +161,7 @@ struct Device {
     int max_n0 = 0;         // largest coarse block
     int nb_big = 0;         // leading coarse-basis blocks restricted by a workgroup each
     int max_k_big = 0;      // most columns of a big block
+    int band_kinds = 0;     // band solve instances the subdomains need (bit 0 substitution, bit 1 inverse)
     bool split_rule = false;   // prolongation's coarse part by blocks under the fixed rule
     int prolong_split = -1;    // -1: rule, 0: per dof, 1: by blocks (k_coarse_prolong into zc)
     double *zc = nullptr;      // coarse part of the prolongation, by blocks
@@ -304,6 +305,34 @@ static void check_status(Device &D, int *d_status, int count, hipStream_t s, con
                                                          std::to_string(i) + " at row " + std::to_string(st[i] - 1)};
 }
 
+
+// Replaces the 64x64 diagonal blocks of the band factors of every subdomain
+// whose band holds whole triangles by their inverses (k_band_invert_diag);
+// rows_h: host row offsets of the subdomains, bw_h: host bandwidths.
+// (per subdomain: band_inverted(b)); returns which solve instances the
+// subdomains need: bit 0 the substitution one, bit 1 the inverse one.
+static int invert_diagonal_blocks(Device &D, double *band, const int64_t *off, const int32_t *bw, const int64_t *rptr,
+                                  const std::vector<int64_t> &rows_h, const std::vector<int32_t> &bw_h, int np,
+                                  hipStream_t s) {
+    std::vector<int64_t> bp(size_t(np) + 1, 0);
+    int kinds = 0;
+    for (int i = 0; i < np; ++i) {
+        const int64_t n = rows_h[i + 1] - rows_h[i];
+        const bool inv = band_inverted(bw_h[i]);
+        if (n > 0) kinds |= inv ? 2 : 1;
+        bp[i + 1] = bp[i] + (inv ? (n + BS_NB - 1) / BS_NB : 0);
+    }
+    if (bp[np] == 0) return kinds;
+    const size_t lds = sizeof(double) * 2 * BS_NB * (BS_NB + 1);
+    if (lds > D.max_lds) throw DevError{GDSW_ERR_INTERNAL, "LDS too small for the diagonal-block inverses"};
+    int64_t *d_bp = D.upload(bp, s);
+    hipLaunchKernelGGL(k_band_invert_diag, dim3(unsigned(bp[np])), dim3(64), lds, s, band, off, bw, rptr, d_bp, np);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    D.release(d_bp, sizeof(int64_t) * bp.size());
+    return kinds;
+}
+
 static void factor_local(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
@@ -399,6 +428,7 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
                            d_status);
         HIPCHK(hipGetLastError());
         check_status(D, d_status, S.np, s, "banded Cholesky");
+        D.band_kinds = invert_diagonal_blocks(D, band64, D.band_off, D.bw, D.ov_ptr, S.ov_ptr, S.bw, S.np, s);
         D.release(d_src, sizeof(int64_t) * S.bscat_src.size());
         D.release(d_dst, sizeof(int64_t) * S.bscat_dst.size());
         if (prec == GDSW_FP64) {
@@ -572,10 +602,15 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         hipLaunchKernelGGL(k_band_chol<256>, dim3(S.np), dim3(256), lds, s, iband, d_ioff, d_ibw, d_int_ptr, d_status);
         HIPCHK(hipGetLastError());
         check_status(D, d_status, S.np, s, "interior Cholesky");
+        const int ikinds = invert_diagonal_blocks(D, iband, d_ioff, d_ibw, d_int_ptr, S.int_ptr, S.ibw, S.np, s);
         const size_t lds2 = sizeof(double) * (size_t(std::max(S.max_nii, 1)) + BS_NB * BS_LD);
         if (lds2 > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "interior block too large for LDS"};
-        hipLaunchKernelGGL(k_ext_solve<512>, dim3(S.np), dim3(512), lds2, s, iband, d_ioff, d_ibw, d_int_ptr,
-                           d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
+        if (ikinds & 2)
+            hipLaunchKernelGGL((k_ext_solve<512, true>), dim3(S.np), dim3(512), lds2, s, iband, d_ioff, d_ibw,
+                               d_int_ptr, d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
+        if (ikinds & 1)
+            hipLaunchKernelGGL((k_ext_solve<512, false>), dim3(S.np), dim3(512), lds2, s, iband, d_ioff, d_ibw,
+                               d_int_ptr, d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         D.release(iband, sizeof(double) * size_t(nb));
@@ -798,8 +833,12 @@ static bool launch_band(const Symbolic &S, Device &D, const double *r, const Ski
     using AT = typename AccOf<VT>::type;
     const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
     if (lds > D.max_lds) return false;
-    hipLaunchKernelGGL((k_band_apply<NT, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
-                       (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
+    if (D.band_kinds & 2)
+        hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
+    if (D.band_kinds & 1)
+        hipLaunchKernelGGL((k_band_apply<NT, VT, false>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
     return true;
 }
 

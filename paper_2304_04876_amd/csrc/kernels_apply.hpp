@@ -200,13 +200,13 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
 // workgroup per subdomain, vector in LDS, gather and scatter fused.
 // (compiled for up to 1024 threads whatever NT is: that register budget
 // keeps the unrolled triangle solve from spilling)
-template <int NT, typename VT>
+template <int NT, typename VT, bool INV>
 __global__ __launch_bounds__(1024) void k_band_apply(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
     const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (sk.sub(blockIdx.x)) return;
+    if (sk.sub(blockIdx.x) || band_inverted(bw[blockIdx.x]) != INV) return;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *sT = y + maxrows;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(1024) void k_band_apply(
         y[l] = AT(x);
     }
     __syncthreads();
-    band_llt_solve<VT, AT, NT>(band + band_off[i], ni, bw[i], y, sT);
+    band_llt_solve<VT, AT, NT, INV>(band + band_off[i], ni, bw[i], y, sT);
     for (int l = threadIdx.x; l < ni; l += NT) {
         double v = double(y[l]);
         if (dscale) v *= dscale[ov_idx[o + l]];

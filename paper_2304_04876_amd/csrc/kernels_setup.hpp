@@ -279,6 +279,59 @@ __global__ __launch_bounds__(NT) void k_band_chol(double *__restrict__ band, con
     }
 }
 
+// Partitioned inverse of the diagonal blocks of a band Cholesky factor
+// (FP64, before any cast): the 64x64 diagonal block L_kk of rows k0 ..
+// k0+kb-1 is replaced in place by X = L_kk^{-1} (lower triangular; its
+// diagonal, 1/L_tt, is what the band already holds there), so that the
+// triangle solves of the block become products with X.  Only for bands of
+// at least BS_NB - 1, where the whole triangle lies inside the band.  One
+// 64-thread workgroup per diagonal block (block q of subdomain i with
+// blk_ptr[i] <= q < blk_ptr[i+1]); thread c forms column c of X by forward
+// substitution, X(t, c) = -(1/L_tt) sum_{c <= s < t} L(t, s) X(s, c).
+constexpr int BS_NB_INV = 64;
+__global__ __launch_bounds__(64) void k_band_invert_diag(double *__restrict__ band, const int64_t *__restrict__ off,
+                                                         const int32_t *__restrict__ bwid,
+                                                         const int64_t *__restrict__ rptr,
+                                                         const int64_t *__restrict__ blk_ptr, int np) {
+    extern __shared__ double smem[];
+    constexpr int NB = BS_NB_INV, LD = NB + 1;
+    double *sT = smem;             // NB x LD: the block of L
+    double *sX = smem + NB * LD;   // NB x LD: its inverse
+    const int64_t q = blockIdx.x;
+    int lo = 0, hi = np;   // subdomain with blk_ptr[i] <= q < blk_ptr[i+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blk_ptr[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int i = lo;
+    const int b = bwid[i];
+    if (b < NB - 1) return;   // (the host gives narrow bands no blocks)
+    const int n = int(rptr[i + 1] - rptr[i]);
+    const int k0 = int(q - blk_ptr[i]) * NB;
+    const int kb = min(NB, n - k0);
+    const int64_t w = b + 1;
+    double *L = band + off[i];
+    const int c = threadIdx.x;
+    for (int e = c; e < NB * NB; e += 64) {
+        const int t = e / NB, s2 = e % NB;
+        sT[t * LD + s2] = (t < kb && s2 <= t) ? L[int64_t(k0 + t) * w + (s2 - t + b)] : 0.0;
+    }
+    __syncthreads();
+    if (c < kb) {
+        sX[c * LD + c] = sT[c * LD + c];
+        for (int t = c + 1; t < kb; ++t) {
+            double acc = 0.0;
+            for (int s2 = c; s2 < t; ++s2) acc += sT[t * LD + s2] * sX[s2 * LD + c];
+            sX[t * LD + c] = -acc * sT[t * LD + t];
+        }
+    }
+    __syncthreads();
+    for (int e = c; e < NB * NB; e += 64) {
+        const int t = e / NB, s2 = e % NB;
+        if (t < kb && s2 < t) L[int64_t(k0 + t) * w + (s2 - t + b)] = sX[t * LD + s2];
+    }
+}
+
 // Casts a band (FP64) into the storage precision of the local factors.
 template <typename VT>
 __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int64_t cnt) {
@@ -301,6 +354,14 @@ __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int
 //   threads, consecutive addresses), and wavefront 0 solves block k-1's
 //   transposed triangle (lane t = column t).
 constexpr int BS_NB = 64;
+static_assert(BS_NB == BS_NB_INV, "the inverted diagonal blocks are the solve's blocks");
+
+// A band of width b holds whole 64x64 triangles, and so gets its diagonal
+// blocks inverted (k_band_invert_diag), when b >= 63.  The choice depends
+// on the subdomain alone, so a problem's results do not depend on what it
+// is packed with; the solve kernels come in one instance per choice, each
+// leaving the other kind's subdomains alone.
+__host__ __device__ constexpr bool band_inverted(int b) { return b >= BS_NB - 1; }
 constexpr int BS_LD = BS_NB + 1;
 
 __device__ __forceinline__ float lane_read(float v, int l) {
@@ -324,6 +385,27 @@ __device__ __forceinline__ void band_stage_triangle(const VT *__restrict__ L, in
         if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
         sT[t * BS_LD + s] = v;
     }
+}
+
+// The same block solves with the inverted diagonal block staged (bands of at
+// least BS_NB - 1): lane t forms row t of X y (forward) or of X^T y
+// (backward) in one pass of products; entries outside the triangle are zero
+// in the staging, and the clamp keeps the reads inside the block.
+template <typename AT>
+__device__ __forceinline__ void band_block_fwd_inv(const AT *sT, AT *y, int k0, int kb, int lane) {
+    const AT *row = sT + lane * BS_LD;
+    AT acc = 0;
+#pragma unroll 8
+    for (int s = 0; s < BS_NB; ++s) acc += row[s] * y[k0 + min(s, kb - 1)];
+    if (lane < kb) y[k0 + lane] = acc;
+}
+
+template <typename AT>
+__device__ __forceinline__ void band_block_bwd_inv(const AT *sT, AT *y, int k0, int kb, int lane) {
+    AT acc = 0;
+#pragma unroll 8
+    for (int s = 0; s < BS_NB; ++s) acc += sT[s * BS_LD + lane] * y[k0 + min(s, kb - 1)];
+    if (lane < kb) y[k0 + lane] = acc;
 }
 
 // The staged triangle is zero in rows kb..63 (pivot included), so the steps
@@ -385,10 +467,13 @@ __device__ __forceinline__ void band_store_triangle(const AT (&tv)[tri_per_threa
     }
 }
 
-template <typename VT, typename AT, int NT>
+// INV: the diagonal blocks hold their inverses (band_inverted(b)), so each
+// triangle solve is one product with the staged block.
+template <typename VT, typename AT, int NT, bool INV>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
     if (n <= 0) return;   // an empty subdomain or interior (uniform over the workgroup)
     constexpr bool F64 = sizeof(AT) == 8;
+    constexpr bool inv = INV;
     constexpr int G = F64 ? 8 : 32;   // loads in flight per thread and group (backward)
     // triangle loads overlapped with the updates where the register budget
     // holds the extra values (FP32 accumulation from 512 threads, FP64 at 1024)
@@ -399,7 +484,10 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
     // ---- forward
     band_stage_triangle<VT, AT, NT>(L, w, b, 0, min(BS_NB, n), sT);
     __syncthreads();
-    if (tid < 64) band_block_fwd(sT, y, 0, min(BS_NB, n), lane);
+    if (tid < 64) {
+        if constexpr (inv) band_block_fwd_inv(sT, y, 0, min(BS_NB, n), lane);
+        else band_block_fwd(sT, y, 0, min(BS_NB, n), lane);
+    }
     __syncthreads();
     // rows below a solved block: 16 lanes per row, lane q takes the block's
     // columns q, q+16, q+32, q+48 (consecutive lanes, consecutive addresses)
@@ -444,7 +532,10 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         if constexpr (PREF) band_store_triangle<AT, NT>(tv, sT);
         else band_stage_triangle<VT, AT, NT>(L, w, b, k1, kb1, sT);
         __syncthreads();
-        if (tid < 64) band_block_fwd(sT, y, k1, kb1, lane);
+        if (tid < 64) {
+            if constexpr (inv) band_block_fwd_inv(sT, y, k1, kb1, lane);
+            else band_block_fwd(sT, y, k1, kb1, lane);
+        }
         __syncthreads();
     }
     // ---- backward
@@ -452,7 +543,10 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         const int k0 = (nblk - 1) * BS_NB, kb = n - k0;
         band_stage_triangle<VT, AT, NT>(L, w, b, k0, kb, sT);
         __syncthreads();
-        if (tid < 64) band_block_bwd(sT, y, k0, kb, lane);
+        if (tid < 64) {
+            if constexpr (inv) band_block_bwd_inv(sT, y, k0, kb, lane);
+            else band_block_bwd(sT, y, k0, kb, lane);
+        }
         __syncthreads();
     }
     for (int blk = nblk - 1; blk > 0; --blk) {
@@ -478,7 +572,10 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
         if constexpr (PREF) band_store_triangle<AT, NT>(tv, sT);
         else band_stage_triangle<VT, AT, NT>(L, w, b, p0, BS_NB, sT);
         __syncthreads();
-        if (tid < 64) band_block_bwd(sT, y, p0, BS_NB, lane);
+        if (tid < 64) {
+            if constexpr (inv) band_block_bwd_inv(sT, y, p0, BS_NB, lane);
+            else band_block_bwd(sT, y, p0, BS_NB, lane);
+        }
         __syncthreads();
     }
 }
@@ -515,7 +612,7 @@ __global__ void k_ext_rhs(const double *__restrict__ Aval, const int64_t *__rest
 // Phi_{I_i} = -A_{I_i I_i}^{-1} E_i, one workgroup per subdomain, one right
 // hand side at a time through LDS, written into the subdomain's interior
 // block of Phi.
-template <int NT>
+template <int NT, bool INV>
 __global__ __launch_bounds__(1024) void k_ext_solve(const double *__restrict__ iband,
                                                   const int64_t *__restrict__ iband_off,
                                                   const int32_t *__restrict__ ibw,
@@ -531,7 +628,7 @@ __global__ __launch_bounds__(1024) void k_ext_solve(const double *__restrict__ i
     const int n = int(int_ptr[i + 1] - int_ptr[i]);
     const int k = int(scol_ptr[i + 1] - scol_ptr[i]);
     const int g = sub_blk[i];
-    if (n == 0 || k == 0 || g < 0) return;
+    if (n == 0 || k == 0 || g < 0 || band_inverted(ibw[i]) != INV) return;
     double *y = smem;
     double *sT = smem + n;
     const double *L = iband + iband_off[i];
@@ -539,7 +636,7 @@ __global__ __launch_bounds__(1024) void k_ext_solve(const double *__restrict__ i
         const double *e = E + ext_off[i] + int64_t(s) * n;
         for (int l = threadIdx.x; l < n; l += NT) y[l] = e[l];
         __syncthreads();
-        band_llt_solve<double, double, NT>(L, n, ibw[i], y, sT);
+        band_llt_solve<double, double, NT, INV>(L, n, ibw[i], y, sT);
         double *out = phi + blk_val_off[g] + int64_t(s) * n;
         for (int l = threadIdx.x; l < n; l += NT) out[l] = -y[l];
         __syncthreads();
