@@ -122,7 +122,7 @@ struct Device {
     int64_t *ell_off = nullptr;
     // ---- coarse ----
     int64_t *blk_row_ptr = nullptr, *blk_col_ptr = nullptr, *blk_val_off = nullptr;
-    int32_t *blk_rows = nullptr, *blk_cols = nullptr;
+    int32_t *blk_rows = nullptr;
     double *phi = nullptr;    // FP64 coarse-basis values
     float *phi32 = nullptr;   // FP32 copy when basis_prec == FP32
     int64_t *red_ptr = nullptr;
@@ -134,6 +134,11 @@ struct Device {
     int ntiles = 0, nwork = 0;
     int32_t *dof_blk = nullptr, *dof_lr = nullptr;
     double *partial = nullptr, *r0 = nullptr, *z0 = nullptr;
+    // z0 repeated in the column order of the coarse basis blocks, and the
+    // positions of each coarse column there
+    double *zg = nullptr;
+    int64_t *cpos_ptr = nullptr;
+    int32_t *cpos = nullptr;
     double *A0 = nullptr;     // assembled coarse matrix
     double *A0inv = nullptr;  // its inverse (dense blocks, one per problem)
     int32_t *cprob = nullptr, *prob_c0 = nullptr;
@@ -470,7 +475,6 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     D.blk_col_ptr = D.upload(B.col_ptr, s);
     D.blk_val_off = D.upload(B.val_off, s);
     D.blk_rows = D.upload(B.rows, s);
-    D.blk_cols = D.upload(B.cols, s);
     // restriction partials: block g has ntile(g) tiles of k(g) partials each
     // (one tile unless it is a big block of more than RT_ROWS rows); the
     // reduction of column c adds them by ascending block, then tile
@@ -537,6 +541,9 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     D.dof_lr = D.upload(S.dof_lr, s);
     D.r0 = D.alloc<double>(n0);
     D.z0 = D.alloc<double>(n0);
+    D.zg = D.alloc<double>(int64_t(B.cols.size()));
+    D.cpos_ptr = D.upload(S.red_ptr, s);
+    D.cpos = D.upload(S.red_idx, s);
     const int64_t nphi = B.val_off[B.nb];
     D.phi = D.alloc<double>(nphi);
     D.phi_entries = nphi;
@@ -917,21 +924,21 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
                            D.partial, D.r0, S.n0, sk);
         if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
             hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
-                               D.r0, D.z0, S.n0, sk);
+                               D.r0, D.z0, D.cpos_ptr, D.cpos, D.zg, S.n0, sk);
         else
             hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
-                               D.cprob, D.r0, D.z0, S.n0, sk);
+                               D.cprob, D.r0, D.z0, D.cpos_ptr, D.cpos, D.zg, S.n0, sk);
         const int nwp = D.ntiles * RT_RPT + nsw;
         if (split && nwp > 0) {
             const size_t lds = sizeof(double) * size_t(std::max(1, D.max_k_big));
             if (D.phi32)
                 hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const float *)D.phi32,
-                                   D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32,
+                                   D.tile_blk, D.tile_l0, D.tile_l1, D.zg, D.zc, D.ntiles, nbig, B.nb, sk);
             else
                 hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
-                                   D.blk_rows, D.blk_col_ptr, D.blk_cols, D.blk_val_off, (const double *)D.phi,
-                                   D.tile_blk, D.tile_l0, D.tile_l1, D.z0, D.zc, D.ntiles, nbig, B.nb, sk);
+                                   D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi,
+                                   D.tile_blk, D.tile_l0, D.tile_l1, D.zg, D.zc, D.ntiles, nbig, B.nb, sk);
         }
     }
     if (local) {
@@ -954,20 +961,20 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
     if (dot_r) {
         if (D.phi32)
             hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const float *)D.phi32, D.z0, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
+                               (const float *)D.phi32, D.zg, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
         else
             hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                               (const double *)D.phi, D.z0, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
+                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
+                               (const double *)D.phi, D.zg, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
     } else if (D.phi32) {
         hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                           D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const float *)D.phi32, D.z0, zc, z, S.n, sk);
+                           D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
+                           (const float *)D.phi32, D.zg, zc, z, S.n, sk);
     } else {
         hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
-                           D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_cols, D.blk_val_off,
-                           (const double *)D.phi, D.z0, zc, z, S.n, sk);
+                           D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
+                           (const double *)D.phi, D.zg, zc, z, S.n, sk);
     }
     HIPCHK(hipGetLastError());
 }

@@ -364,11 +364,16 @@ __global__ void k_coarse_reduce(const int64_t *__restrict__ red_ptr, const int32
 }
 
 // z0 = A_0^{-1} r0 with A_0^{-1} block diagonal over the problems of the
-// handle (row-major dense blocks): one wavefront per row
+// handle (row-major dense blocks): one wavefront per row.  Each result is
+// also written to zg at every position where its column appears in the
+// column lists of the coarse basis blocks (cpos_ptr/cpos), so that the
+// prolongation reads z0 in block-column order without the index gather.
 __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ Ainv, const int64_t *__restrict__ a0_off,
                                                     const int32_t *__restrict__ prob_c0,
                                                     const int32_t *__restrict__ cprob, const double *__restrict__ x,
-                                                    double *__restrict__ y, int n0, Skip sk) {
+                                                    double *__restrict__ y, const int64_t *__restrict__ cpos_ptr,
+                                                    const int32_t *__restrict__ cpos, double *__restrict__ zg, int n0,
+                                                    Skip sk) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n0 || sk.col(row)) return;
@@ -392,13 +397,16 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
     }
     acc = wave_sum(acc);
     if (lane == 0) y[row] = acc;
+    for (int64_t p = cpos_ptr[row] + lane; p < cpos_ptr[row + 1]; p += 64) zg[cpos[p]] = acc;
 }
 
 // Same with one workgroup (4 wavefronts) per row, for blocks of large order.
 __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict__ Ainv, const int64_t *__restrict__ a0_off,
                                                        const int32_t *__restrict__ prob_c0,
                                                        const int32_t *__restrict__ cprob, const double *__restrict__ x,
-                                                       double *__restrict__ y, int n0, Skip sk) {
+                                                       double *__restrict__ y, const int64_t *__restrict__ cpos_ptr,
+                                                       const int32_t *__restrict__ cpos, double *__restrict__ zg,
+                                                       int n0, Skip sk) {
     __shared__ double sh[4];
     const int row = blockIdx.x;
     if (sk.col(row)) return;
@@ -422,10 +430,12 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
     }
     acc = block_sum<double, 256>(acc, sh);
     if (threadIdx.x == 0) y[row] = acc;
+    for (int64_t p = cpos_ptr[row] + threadIdx.x; p < cpos_ptr[row + 1]; p += 256) zg[cpos[p]] = acc;
 }
 
 // Coarse part of the prolongation by blocks, for coarse bases with many
-// columns per block: zc[rows of B_g] = B_g z0(cols_g).  A tile of a big
+// columns per block: zc[rows of B_g] = B_g z0(cols_g), z0(cols_g) read from
+// the gathered copy zg.  A tile of a big
 // block per workgroup (RT_RPT rows per thread, the block's z0 entries staged
 // in LDS, columns in passes of RT_KB with every load of a pass issued first)
 // and a wavefront per small block.  Each row adds its products in column
@@ -434,9 +444,9 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
 template <typename PT>
 __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ rows, const int64_t *__restrict__ col_ptr,
-    const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    const int32_t *__restrict__ tile_blk, const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1,
-    const double *__restrict__ z0, double *__restrict__ zc, int ntiles, int g_small, int nb, Skip sk) {
+    const int64_t *__restrict__ val_off, const PT *__restrict__ phi, const int32_t *__restrict__ tile_blk,
+    const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1, const double *__restrict__ zg,
+    double *__restrict__ zc, int ntiles, int g_small, int nb, Skip sk) {
     extern __shared__ double sz[];   // z0 entries of the tile's block (max columns of a big block)
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b < ntiles * RT_RPT) {
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
         const int l = tile_l0[t] + q * RT_NT + tid, l1 = tile_l1[t];
         if (tile_l0[t] + q * RT_NT >= l1) return;   // empty quarter (uniform over the workgroup)
         const PT *Bg = phi + val_off[g];
-        for (int c = tid; c < k; c += RT_NT) sz[c] = z0[cols[c0 + c]];
+        for (int c = tid; c < k; c += RT_NT) sz[c] = zg[c0 + c];
         __syncthreads();
         double acc = 0.0;
         constexpr int KB = 16;
@@ -475,23 +485,23 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
         const PT *Bg = phi + val_off[g];
         for (int l = tid & 63; l < nr; l += 64) {
             double acc = 0.0;
-            for (int s = 0; s < k; ++s) acc += double(to_acc(Bg[int64_t(s) * nr + l])) * z0[cols[c0 + s]];
+            for (int s = 0; s < k; ++s) acc += double(to_acc(Bg[int64_t(s) * nr + l])) * zg[c0 + s];
             zc[rows[r0 + l]] = acc;
         }
     }
 }
 
 // z[d] = sum over the local rows holding d (ascending subdomain) of zloc
-//        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part)
+//        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part;
+//        z0 read in block-column order from zg)
 // zc != nullptr: the coarse part was formed by blocks (k_coarse_prolong).
 template <typename PT>
 __device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_t *__restrict__ t_ptr,
                                               const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
                                               const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr,
                                               const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ col_ptr,
-                                              const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
-                                              const PT *__restrict__ phi, const double *__restrict__ z0,
-                                              const double *__restrict__ zc) {
+                                              const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+                                              const double *__restrict__ zg, const double *__restrict__ zc) {
     double acc = 0.0;
     if (which & 1)
         for (int p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
@@ -512,7 +522,7 @@ __device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     bv[u] = q0 + u < k ? double(to_acc(Bg[(q0 + u) * nr])) : 0.0;
-                    zv[u] = q0 + u < k ? z0[cols[c0 + q0 + u]] : 0.0;
+                    zv[u] = q0 + u < k ? zg[c0 + q0 + u] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
@@ -528,14 +538,12 @@ template <typename PT>
 __global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
                           const double *__restrict__ zloc, const int32_t *__restrict__ dof_blk,
                           const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
-                          const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols,
-                          const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-                          const double *__restrict__ z0, const double *__restrict__ zc, double *__restrict__ z,
-                          int64_t n, Skip sk) {
+                          const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off,
+                          const PT *__restrict__ phi, const double *__restrict__ zg, const double *__restrict__ zc,
+                          double *__restrict__ z, int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (d >= n || sk.dof(d)) return;
-    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0,
-                           zc);
+    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
@@ -545,9 +553,8 @@ template <typename PT>
 __global__ __launch_bounds__(256) void k_prolong_dot(
     int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
     const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
-    const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ cols, const int64_t *__restrict__ val_off,
-    const PT *__restrict__ phi, const double *__restrict__ z0, const double *__restrict__ zc, double *__restrict__ z,
-    Skip sk, const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
+    const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
+    const double *__restrict__ zg, const double *__restrict__ zc, double *__restrict__ z, Skip sk, const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
     double *__restrict__ partial) {
     __shared__ double sh[4];
     const int blk = blockIdx.x;
@@ -556,8 +563,7 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     double dot = 0.0;
     for (int d = row0 + threadIdx.x; d < row1; d += 256) {
         const double v =
-            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, cols, val_off, phi, z0,
-                            zc);
+            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
         z[d] = v;
         dot += rvec[d] * v;
     }
