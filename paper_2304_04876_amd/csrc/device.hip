@@ -1039,12 +1039,12 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     // p = z + beta p fused into the product with A
     hipLaunchKernelGGL(k_cg_spmv_dot_p, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
                        (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
-    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
     hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, pnew, D.kq, D.kpart2, D.kst, all);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, D.kdone), s, D.kr);   // also the partials of r.z
     // stop test on ||r||^2 (partials from the update), then beta from r.z
-    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR_BETA), 0,
+    hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RR_BETA), 0,
                        D.kpart2);
     D.cg_par ^= 1;
 }
@@ -1099,11 +1099,11 @@ static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, 
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(KNT), 0, s, x, D.kr, b, kb);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BB), pbase,
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_BB), pbase,
                        (const double *)nullptr);
     launch_apply(h, D.kr, D.kz, 3, make_skip(S, D, k < 0 ? D.kdone : D.kmask), s);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kr, D.kz, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase,
+    hipLaunchKernelGGL(k_cg_finish, dim3(pn), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_RHO), pbase,
                        (const double *)nullptr);
     // p_old = z with beta = 0: the first product takes p = z
     hipLaunchKernelGGL(k_cg_start_p, dim3((nb + UPB - 1) / UPB), dim3(KNT), 0, s, D.cg_par ? D.kp2 : D.kp, D.kz,
@@ -1121,7 +1121,7 @@ static void queue_true_residual(gdsw_handle_s *h, const double *b, const double 
     hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst,
+    hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst,
                        (int *)nullptr, int(KF_RED), k < 0 ? 0 : k, (const double *)nullptr);
 }
 
@@ -1264,7 +1264,7 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     KState ks{};
     HIPCHK(hipMemcpyAsync(D.kst, &ks, sizeof(KState), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_dot, dim3(D.nkb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, all);
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KNT), 0, s, D.kpart, D.pb_ptr, D.kst, (int *)nullptr, int(KF_BB), 0,
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, (int *)nullptr, int(KF_BB), 0,
                        (const double *)nullptr);
     HIPCHK(hipMemcpyAsync(&ks, D.kst, sizeof(KState), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, x, 0.0, n);

@@ -250,17 +250,65 @@ enum {
     KF_RR_BETA = 6  // KF_RR with the total of partial2 (r.r), then KF_BETA with t (r.z)
 };
 
-__global__ __launch_bounds__(KNT) void k_cg_finish(const double *__restrict__ partial, const int32_t *__restrict__ pb_ptr,
-                                                   KState *st, int *__restrict__ kdone, int op, int base,
-                                                   const double *__restrict__ partial2) {
+// Totals of partials [lo, hi) of a and, if b != nullptr, of b, each in
+// index order, by one workgroup of NT threads: eight independent chains per
+// thread, so that a problem of up to 8 NT row blocks needs one round of
+// loads; the order depends only on hi - lo.
+template <int NT>
+__device__ __forceinline__ void sum_partials_pair(const double *__restrict__ a, const double *__restrict__ b, int lo,
+                                                  int hi, double *sh, double &ta, double &tb) {
+    constexpr int C = 8;
+    double va[C], vb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) va[c] = vb[c] = 0.0;
+    int q = lo + int(threadIdx.x);
+    for (; q + (C - 1) * NT < hi; q += C * NT) {
+        double xa[C], xb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            xa[c] = a[q + c * NT];
+            xb[c] = b ? b[q + c * NT] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            va[c] += xa[c];
+            vb[c] += xb[c];
+        }
+    }
+    for (; q < hi; q += NT) {
+        va[0] += a[q];
+        if (b) vb[0] += b[q];
+    }
+    double sa = ((va[0] + va[1]) + (va[2] + va[3])) + ((va[4] + va[5]) + (va[6] + va[7]));
+    double sb = ((vb[0] + vb[1]) + (vb[2] + vb[3])) + ((vb[4] + vb[5]) + (vb[6] + vb[7]));
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        sh[w] = sa;
+        sh[NT / 64 + w] = sb;
+    }
+    __syncthreads();
+    ta = tb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+        ta += sh[k];
+        tb += sh[NT / 64 + k];
+    }
+}
+
+constexpr int KFIN_NT = 1024;   // threads of k_cg_finish
+__global__ __launch_bounds__(KFIN_NT) void k_cg_finish(const double *__restrict__ partial,
+                                                       const int32_t *__restrict__ pb_ptr, KState *st,
+                                                       int *__restrict__ kdone, int op, int base,
+                                                       const double *__restrict__ partial2) {
     const int k = base + blockIdx.x;
     KState &S = st[k];
     if ((op == KF_ALPHA || op == KF_RR || op == KF_BETA || op == KF_RR_BETA) && S.done) return;
-    __shared__ double sh[KNT / 64];
-    double t = sum_partials(partial, pb_ptr[k], pb_ptr[k + 1], sh);
+    __shared__ double sh[2 * KFIN_NT / 64];
+    double t, t2;
+    sum_partials_pair<KFIN_NT>(partial, op == KF_RR_BETA ? partial2 : nullptr, pb_ptr[k], pb_ptr[k + 1], sh, t, t2);
     if (op == KF_RR_BETA) {
-        __syncthreads();   // sh is reused
-        const double t2 = sum_partials(partial2, pb_ptr[k], pb_ptr[k + 1], sh);
         if (threadIdx.x != 0) return;
         if (!cg_rr_step(S, t2)) cg_beta_step(S, t);
         if (kdone) kdone[k] = S.done;
