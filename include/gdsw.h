@@ -315,6 +315,22 @@ gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *st
 gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant,
                             int32_t apply_streams, int32_t prolong_variant, void *stream);
 
+/* Timing of the local solves where they run (Sec. VII times the local-solver
+ * phase of the apply on its own).  With enable != 0 every later apply of the
+ * handle, those inside the solvers included, records a pair of HIP events on
+ * its stream just before and just after the local-solve launch, for up to
+ * GDSW_PROFILE_MAX applies (later ones are not recorded), except while the
+ * stream is being captured into a graph; enable != 0 also clears earlier
+ * records, enable == 0 stops recording and keeps them.  Creates the events on
+ * first use. */
+#define GDSW_PROFILE_MAX 1024
+gdsw_status gdsw_profile_local(gdsw_handle h, int32_t enable);
+
+/* Waits for the recorded event pairs and writes the elapsed milliseconds of
+ * the first min(count recorded, max) of them to ms (host, max floats);
+ * *count receives the number recorded. */
+gdsw_status gdsw_profile_read(gdsw_handle h, float *ms, int32_t max, int32_t *count);
+
 /* Dof offsets of the problems of a handle: offsets[count+1] (host). */
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);
 

@@ -37,7 +37,8 @@ EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refacto
             "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
-            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch")
+            "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch",
+            "gdsw_profile_local", "gdsw_profile_read")
 
 
 class Options(ctypes.Structure):
@@ -109,6 +110,8 @@ def lib():
         "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
         "gdsw_autotune": (ctypes.c_int, [vp, i32, vp, vp]),
         "gdsw_set_launch": (ctypes.c_int, [vp, i32, i32, i32, i32, vp]),
+        "gdsw_profile_local": (ctypes.c_int, [vp, i32]),
+        "gdsw_profile_read": (ctypes.c_int, [vp, vp, i32, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -318,6 +321,21 @@ def gdsw_autotune(h, reps=10, stream=None) -> list:
 def gdsw_set_launch(h, local_variant=-1, gemv_variant=-1, apply_streams=-1, prolong_variant=-1, stream=None):
     _check(h, lib().gdsw_set_launch(h, int(local_variant), int(gemv_variant), int(apply_streams),
                                     int(prolong_variant), _stream(stream)))
+
+
+PROFILE_MAX = 1024
+
+
+def gdsw_profile_local(h, enable=True):
+    _check(h, lib().gdsw_profile_local(h, 1 if enable else 0))
+
+
+def gdsw_profile_read(h) -> np.ndarray:
+    """Milliseconds of each recorded local-solve launch (waits for them)."""
+    ms = np.zeros(PROFILE_MAX, dtype=np.float32)
+    count = ctypes.c_int32(0)
+    _check(h, lib().gdsw_profile_read(h, ms.ctypes.data, PROFILE_MAX, ctypes.byref(count)))
+    return ms[:min(count.value, PROFILE_MAX)].astype(np.float64)
 
 
 def gdsw_problem_offsets(h) -> np.ndarray:

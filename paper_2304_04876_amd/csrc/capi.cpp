@@ -82,6 +82,16 @@ gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_v
     return gdsw::set_launch(h, local_variant, gemv_variant, apply_streams, prolong_variant, stream);
 }
 
+gdsw_status gdsw_profile_local(gdsw_handle h, int32_t enable) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::profile_local(h, enable);
+}
+
+gdsw_status gdsw_profile_read(gdsw_handle h, float *ms, int32_t max, int32_t *count) {
+    if (!h || !count || max < 0 || (max > 0 && !ms)) return GDSW_ERR_INVALID_ARG;
+    return gdsw::profile_read(h, ms, max, count);
+}
+
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
     if (!h || !offsets) return GDSW_ERR_INVALID_ARG;
     if (!h->analyzed) return GDSW_ERR_STATE;

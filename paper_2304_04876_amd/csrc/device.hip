@@ -91,8 +91,14 @@ struct Device {
         hipGraphExec_t exec;
     };
     std::vector<CgGraph> cg_graphs;
+    // timing of the local solves inside applies (gdsw_profile_local): event
+    // pair i brackets the local-solve launch of the i-th recorded apply
+    bool prof_on = false;
+    int prof_n = 0;
+    std::vector<hipEvent_t> prof_ev;
 
     ~Device() {
+        for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
         for (auto &g : cg_graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap) (void)hipStreamDestroy(cap);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -942,11 +948,23 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         }
     }
     if (local) {
+        // optional timing of the local solves where they run
+        bool prof = D.prof_on && D.prof_n < GDSW_PROFILE_MAX;
+        if (prof) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            HIPCHK(hipStreamIsCapturing(s, &cs));
+            prof = cs == hipStreamCaptureStatusNone;
+        }
+        if (prof) HIPCHK(hipEventRecord(D.prof_ev[size_t(2 * D.prof_n)], s));
         switch (S.opt.local_prec) {
             case GDSW_FP64: launch_local<double>(S, D, r, sk, s); break;
             case GDSW_FP32: launch_local<float>(S, D, r, sk, s); break;
             case GDSW_BF16: launch_local<bf16>(S, D, r, sk, s); break;
             default: launch_local<fp16>(S, D, r, sk, s); break;
+        }
+        if (prof) {
+            HIPCHK(hipEventRecord(D.prof_ev[size_t(2 * D.prof_n + 1)], s));
+            ++D.prof_n;
         }
     }
     if (fork) {
@@ -1631,6 +1649,48 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
     } catch (const DevError &e) {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+gdsw_status profile_local(gdsw_handle_s *h, int enable) {
+    if (!h->factored || !h->dev) {
+        h->err = "profile_local before factor";
+        return GDSW_ERR_STATE;
+    }
+    Device &D = *h->dev;
+    try {
+        if (enable && D.prof_ev.empty()) {
+            D.prof_ev.assign(size_t(2 * GDSW_PROFILE_MAX), nullptr);
+            for (hipEvent_t &e : D.prof_ev) HIPCHK(hipEventCreate(&e));
+        }
+    } catch (const DevError &e) {
+        for (hipEvent_t &ev : D.prof_ev)
+            if (ev) (void)hipEventDestroy(ev);
+        D.prof_ev.clear();
+        h->err = e.msg;
+        return e.st;
+    }
+    if (enable) D.prof_n = 0;
+    D.prof_on = enable != 0;
+    return GDSW_OK;
+}
+
+gdsw_status profile_read(gdsw_handle_s *h, float *ms, int max, int *count) {
+    if (!h->factored || !h->dev) {
+        h->err = "profile_read before factor";
+        return GDSW_ERR_STATE;
+    }
+    Device &D = *h->dev;
+    *count = D.prof_n;
+    try {
+        for (int i = 0; i < std::min(max, D.prof_n); ++i) {
+            HIPCHK(hipEventSynchronize(D.prof_ev[size_t(2 * i + 1)]));
+            HIPCHK(hipEventElapsedTime(&ms[i], D.prof_ev[size_t(2 * i)], D.prof_ev[size_t(2 * i + 1)]));
+        }
+    } catch (const DevError &e) {
         h->err = e.msg;
         return e.st;
     }

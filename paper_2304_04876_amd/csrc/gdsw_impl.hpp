@@ -178,6 +178,8 @@ gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream);
 gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream);
 gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream);
 gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream);
+gdsw_status profile_local(gdsw_handle_s *h, int enable);
+gdsw_status profile_read(gdsw_handle_s *h, float *ms, int max, int *count);
 gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, int prolong_variant,
                        void *stream);
 int tuned_variant(const gdsw_handle_s *h, int which);

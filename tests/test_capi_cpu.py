@@ -1,6 +1,7 @@
 """C ABI checks that need no GPU: the library loads, exports every entry
 point declared in include/gdsw.h, and its host symbolic analysis (phase (a))
 reproduces the oracle's integer maps bit for bit."""
+import ctypes
 import os
 import re
 
@@ -167,6 +168,25 @@ def test_set_launch_before_factor_state_error():
     assert "factor" in B.gdsw_last_error(h)
     assert B.lib().gdsw_set_launch(None, 0, 0, 1, 0, None) == 1
     B.gdsw_destroy(h)
+
+
+def test_profile_before_factor_state_error():
+    pr = P.poisson3d(6, 2)
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 1)
+    assert B.lib().gdsw_profile_local(h, 1) == 7
+    assert "factor" in B.gdsw_last_error(h)
+    count = ctypes.c_int32(-1)
+    assert B.lib().gdsw_profile_read(h, None, 0, ctypes.byref(count)) == 7
+    assert B.lib().gdsw_profile_read(h, None, 4, ctypes.byref(count)) == 1   # ms missing
+    assert B.lib().gdsw_profile_read(h, None, 0, None) == 1                  # count missing
+    assert B.lib().gdsw_profile_local(None, 1) == 1
+    B.gdsw_destroy(h)
+
+
+def test_profile_max_matches_header():
+    text = open(os.path.join(ROOT, "include", "gdsw.h")).read()
+    m = re.search(r"#define GDSW_PROFILE_MAX (\d+)", text)
+    assert m and int(m.group(1)) == B.PROFILE_MAX
 
 
 @pytest.mark.parametrize("level", [0, 1, 2])
