@@ -125,6 +125,7 @@ struct Device {
     int32_t *bw = nullptr;
     void *Lv = nullptr, *Uv = nullptr, *dinv = nullptr;   // ILU(0): sweep layout
     uint16_t *Lc = nullptr, *Uc = nullptr;
+    uint32_t *Cp = nullptr;   // the columns packed by row (register-resident sweeps only)
     int64_t *ell_off = nullptr;
     // ---- coarse ----
     int64_t *blk_row_ptr = nullptr, *blk_col_ptr = nullptr, *blk_val_off = nullptr;
@@ -289,8 +290,8 @@ static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *
                      const double *d_lval, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
-    const bool small = S.KL <= 3 && S.KU <= 3;
-    const int KL = small ? 3 : std::max(S.KL, 1), KU = small ? 3 : std::max(S.KU, 1);
+    const bool small = S.KL <= ILU_KL && S.KU <= ILU_KU;
+    const int KL = small ? ILU_KL : std::max(S.KL, 1), KU = small ? ILU_KU : std::max(S.KU, 1);
     D.KLp = KL;
     D.KUp = KU;
     D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows);
@@ -298,11 +299,12 @@ static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *
     D.dinv = D.alloc<VT>(S.ell_rows);
     D.Lc = D.alloc<uint16_t>(int64_t(KL) * S.ell_rows);
     D.Uc = D.alloc<uint16_t>(int64_t(KU) * S.ell_rows);
+    if (small) D.Cp = D.alloc<uint32_t>(int64_t(ILU_CW) * S.ell_rows);
     int64_t maxpad = 0;
     for (int i = 0; i < S.np; ++i) maxpad = std::max(maxpad, S.ell_off[i + 1] - S.ell_off[i]);
     dim3 grid(nblocks(maxpad, 256), S.np);
     hipLaunchKernelGGL(k_ilu_pack<VT>, grid, dim3(256), 0, s, D.ov_ptr, D.ell_off, d_lrowptr, d_lcol, d_ldiag,
-                       d_lval, S.ell_rows, KL, KU, (VT *)D.Lv, D.Lc, (VT *)D.Uv, D.Uc, (VT *)D.dinv);
+                       d_lval, S.ell_rows, KL, KU, (VT *)D.Lv, D.Lc, (VT *)D.Uv, D.Uc, (VT *)D.dinv, D.Cp);
     HIPCHK(hipGetLastError());
     D.local_entries = int64_t(KL + KU + 1) * S.ell_rows;
 }
@@ -799,7 +801,7 @@ constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 3;
 
 template <typename VT, int NT>
 static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
-    if (D.KLp != 3 || D.KUp != 3) return false;
+    if (D.KLp != ILU_KL || D.KUp != ILU_KU || !D.Cp) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
     const int need = (S.max_ni + NT - 1) / NT;
     using AT = typename AccOf<VT>::type;
@@ -807,9 +809,9 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
     if (need <= RR) {                                                                                        \
         const size_t lds = (3 * sizeof(AT) + (f64 ? 0 : sizeof(double))) * NT * RR;                          \
         if (lds > D.max_lds) return false;                                                                   \
-        hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, 3, 3, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx,     \
-                           D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc, \
-                           (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, sk);                   \
+        hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT>), dim3(S.np), dim3(NT), lds, s, r,      \
+                           D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, (const VT *)D.Uv,     \
+                           D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, sk);             \
         return true;                                                                                         \
     }
     // the row counts per thread whose factor entries stay in registers

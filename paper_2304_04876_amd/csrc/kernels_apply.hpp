@@ -27,10 +27,13 @@ template <int NT, int R, int KL, int KU, typename VT>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
-    const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
-    const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
-    double *__restrict__ zloc, Skip sk) {
+    const VT *__restrict__ Uv, const uint32_t *__restrict__ Cp, const VT *__restrict__ dinv,
+    const double *__restrict__ dscale, int sweeps, double *__restrict__ zloc, Skip sk) {
     using AT = typename AccOf<VT>::type;
+    constexpr int CW = (KL + KU + 1) / 2;   // 32-bit words of packed columns per row
+    // FP64 factors are never scaled (dscale is null for them), and their LDS
+    // holds no scale slots
+    constexpr bool scaled = !std::is_same<VT, double>::value;
     if (sk.sub(blockIdx.x)) return;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *bufA = reinterpret_cast<AT *>(smraw);
@@ -44,36 +47,46 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const int npad = int(ell_off[i + 1] - eo);
     const int tid = threadIdx.x;
 
+    if (ni == 0) return;   // (the whole workgroup)
+    const int last_r = ni - 1, last_p = npad - 1;
     AT rr[R];
     AT lv[R][KL], uv[R][KU];
-    uint16_t lc[R][KL], uc[R][KU];
+    uint32_t cw[R][CW];   // local column of L slot s: half s, of U slot s: half KL + s
+    int dof[R];
+    // Every load of the thread's rows is issued before any loaded value is
+    // used, with no branches between them: the restriction indices, then the
+    // factor slots, the gathered r and the pivots.  Rows past the subdomain
+    // read its last row (in bounds) and are never used.
+#pragma unroll
+    for (int m = 0; m < R; ++m) dof[m] = ov_idx[o + min(tid + m * NT, last_r)];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int l = tid + m * NT;
-        rr[m] = 0;
-        if (l < ni) {
-            const int d = ov_idx[o + l];
-            double x = r[d];
-            if (dscale) {
-                const double sc = dscale[d];
-                sscale[l] = sc;
-                x *= sc;
-            }
-            rr[m] = AT(x);
-            sdinv[l] = to_acc(dinv[eo + l]);
-        }
-        const bool ok = l < npad;
+        const int64_t e = eo + min(tid + m * NT, last_p);
 #pragma unroll
-        for (int s = 0; s < KL; ++s) {
-            lv[m][s] = ok ? to_acc(Lv[s * ell_rows + eo + l]) : AT(0);
-            lc[m][s] = ok ? Lc[s * ell_rows + eo + l] : uint16_t(0);
-        }
+        for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(Lv[s * ell_rows + e]);
 #pragma unroll
-        for (int s = 0; s < KU; ++s) {
-            uv[m][s] = ok ? to_acc(Uv[s * ell_rows + eo + l]) : AT(0);
-            uc[m][s] = ok ? Uc[s * ell_rows + eo + l] : uint16_t(0);
-        }
+        for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(Uv[s * ell_rows + e]);
+#pragma unroll
+        for (int w = 0; w < CW; ++w) cw[m][w] = Cp[e * CW + w];
     }
+    // the gathered r (scaled for reduced-precision factors) and the pivots,
+    // written to LDS for every slot of the thread (rows past the subdomain
+    // included: they are never read)
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        double x = r[dof[m]];
+        if (scaled && dscale) {
+            const double sc = dscale[dof[m]];
+            x *= sc;
+            sscale[tid + m * NT] = sc;
+        }
+        rr[m] = AT(x);
+    }
+    AT dv[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) dv[m] = to_acc(dinv[eo + min(tid + m * NT, last_r)]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) sdinv[tid + m * NT] = dv[m];
     AT *cur = bufA, *nxt = bufB;
     // first L sweep from zero: y^1 = r
 #pragma unroll
@@ -89,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
             if (l < ni) {
                 AT acc = rr[m];
 #pragma unroll
-                for (int s = 0; s < KL; ++s) acc -= lv[m][s] * cur[lc[m][s]];
+                for (int s = 0; s < KL; ++s) acc -= lv[m][s] * cur[(cw[m][s >> 1] >> (16 * (s & 1))) & 0xffffu];
                 nxt[l] = acc;
             }
         }
@@ -114,7 +127,10 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
             if (l < ni) {
                 AT acc = rr[m];
 #pragma unroll
-                for (int s = 0; s < KU; ++s) acc -= uv[m][s] * cur[uc[m][s]];
+                for (int s = 0; s < KU; ++s) {
+                    const int k = KL + s;
+                    acc -= uv[m][s] * cur[(cw[m][k >> 1] >> (16 * (k & 1))) & 0xffffu];
+                }
                 nxt[l] = acc;
             }
         }
@@ -126,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
         const int l = tid + m * NT;
         if (l < ni) {
             double v = double(cur[l]);
-            if (dscale) v *= sscale[l];
+            if (scaled && dscale) v *= sscale[l];
             zloc[o + l] = v;
         }
     }

@@ -137,13 +137,17 @@ __global__ void k_ilu0_factor(const int64_t *__restrict__ ov_ptr, const int64_t 
 // the strictly lower part L at [s * ell_rows + R], of the strictly upper part
 // scaled by the pivot (U_lj / U_ll) likewise, and 1 / U_ll.  Unused slots
 // hold 0 with column 0.
+// Slots of the register-resident ILU(0) sweeps: three L and three U entries
+// per row; their local columns packed two per 32-bit word.
+constexpr int ILU_KL = 3, ILU_KU = 3, ILU_CW = (ILU_KL + ILU_KU + 1) / 2;
+
 template <typename VT>
 __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__restrict__ ell_off,
                            const int64_t *__restrict__ lrowptr, const int32_t *__restrict__ lcol,
                            const int32_t *__restrict__ ldiag, const double *__restrict__ lval,
                            int64_t ell_rows, int KL, int KU, VT *__restrict__ Lv,
                            uint16_t *__restrict__ Lc, VT *__restrict__ Uv, uint16_t *__restrict__ Uc,
-                           VT *__restrict__ dinv) {
+                           VT *__restrict__ dinv, uint32_t *__restrict__ Cp) {
     const int i = blockIdx.y;
     const int64_t o = ov_ptr[i], ni = ov_ptr[i + 1] - o;
     const int64_t npad = ell_off[i + 1] - ell_off[i];
@@ -178,6 +182,19 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
     for (; su < KU; ++su) {
         Uv[su * ell_rows + R] = from_double<VT>(0.0);
         Uc[su * ell_rows + R] = 0;
+    }
+    // Cp != nullptr: the row's L then U columns again, two per 32-bit word
+    // (low half first), ILU_CW words per row, for the register-resident sweeps
+    if (Cp) {
+        for (int w = 0; w < ILU_CW; ++w) {
+            uint32_t v = 0;
+            for (int h = 0; h < 2; ++h) {
+                const int k = 2 * w + h;
+                const uint32_t c = k < KL ? Lc[k * ell_rows + R] : (k < KL + KU ? Uc[(k - KL) * ell_rows + R] : 0u);
+                v |= c << (16 * h);
+            }
+            Cp[R * ILU_CW + w] = v;
+        }
     }
 }
 
