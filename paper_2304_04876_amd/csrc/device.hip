@@ -889,6 +889,39 @@ static void launch_local(const Symbolic &S, Device &D, const double *r, const Sk
     throw DevError{GDSW_ERR_INVALID_ARG, "no local-solve kernel fits this subdomain size"};
 }
 
+// The prolongation kernels for the parts w (bit 0 one-level, bit 1 coarse)
+// and the form of the coarse part (zc != nullptr: formed by blocks).
+template <typename PT, int W, bool BLK>
+static void launch_prolong_inst(const Symbolic &S, Device &D, const double *zc, double *z, const Skip &sk,
+                                hipStream_t s, const double *dot_r) {
+    const PT *phi = std::is_same<PT, float>::value ? (const PT *)D.phi32 : (const PT *)D.phi;
+    if (dot_r)
+        hipLaunchKernelGGL((k_prolong_dot<PT, W, BLK>), dim3(D.nkb), dim3(256), 0, s, D.t_ptr, D.t_pos, D.zloc,
+                           D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off, phi, D.zg, zc, z, sk,
+                           D.kb_row0, D.kb_row1, dot_r, D.kpart);
+    else
+        hipLaunchKernelGGL((k_prolong<PT, W, BLK>), dim3(nblocks(S.n, 256)), dim3(256), 0, s, D.t_ptr, D.t_pos,
+                           D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off, phi, D.zg, zc,
+                           z, S.n, sk);
+}
+
+template <typename PT>
+static void launch_prolong(const Symbolic &S, Device &D, int w, const double *zc, double *z, const Skip &sk,
+                           hipStream_t s, const double *dot_r) {
+    if (w == 0)   // neither part (the coarse part of a handle without one): z = 0
+        launch_prolong_inst<PT, 0, false>(S, D, nullptr, z, sk, s, dot_r);
+    else if (w == 1)
+        launch_prolong_inst<PT, 1, false>(S, D, nullptr, z, sk, s, dot_r);
+    else if (w == 2 && zc)
+        launch_prolong_inst<PT, 2, true>(S, D, zc, z, sk, s, dot_r);
+    else if (w == 2)
+        launch_prolong_inst<PT, 2, false>(S, D, nullptr, z, sk, s, dot_r);
+    else if (zc)
+        launch_prolong_inst<PT, 3, true>(S, D, zc, z, sk, s, dot_r);
+    else
+        launch_prolong_inst<PT, 3, false>(S, D, nullptr, z, sk, s, dot_r);
+}
+
 // z = M^{-1} r (which = 3), or one part of it; with dot_r the prolongation
 // also writes the Krylov-block partials of dot_r . z into the partial buffer.
 static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk, hipStream_t s,
@@ -978,24 +1011,10 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         return;
     }
     const int w = (which & 1) | (coarse ? 2 : 0);
-    if (dot_r) {
-        if (D.phi32)
-            hipLaunchKernelGGL(k_prolong_dot<float>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
-                               (const float *)D.phi32, D.zg, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
-        else
-            hipLaunchKernelGGL(k_prolong_dot<double>, dim3(D.nkb), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                               D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
-                               (const double *)D.phi, D.zg, zc, z, sk, D.kb_row0, D.kb_row1, dot_r, D.kpart);
-    } else if (D.phi32) {
-        hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos, D.zloc,
-                           D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
-                           (const float *)D.phi32, D.zg, zc, z, S.n, sk);
-    } else {
-        hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks(S.n, 256)), dim3(256), 0, s, w, D.t_ptr, D.t_pos,
-                           D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off,
-                           (const double *)D.phi, D.zg, zc, z, S.n, sk);
-    }
+    if (D.phi32)
+        launch_prolong<float>(S, D, w, zc, z, sk, s, dot_r);
+    else
+        launch_prolong<double>(S, D, w, zc, z, sk, s, dot_r);
     HIPCHK(hipGetLastError());
 }
 

@@ -268,11 +268,21 @@ __device__ __forceinline__ void restrict_tile(const double *__restrict__ r, cons
     const int k = min(int(col_ptr[g + 1] - col_ptr[g]), send);
     const PT *Bg = phi + val_off[g];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // rows past the tile and columns past the block read the tile's last row
+    // and the block's last column (in bounds, no branch between the loads);
+    // x is zero there, so they add nothing to the columns that are written
+    if (l1 <= l0) {   // an empty tile (the whole workgroup): zero partials
+        for (int s = sbeg + tid; s < k; s += RT_NT) partial[po + s] = 0.0;
+        return;
+    }
+    int ri[RT_RPT];
+#pragma unroll
+    for (int j = 0; j < RT_RPT; ++j) ri[j] = rows[r0 + min(l0 + tid + j * RT_NT, l1 - 1)];
     double x[RT_RPT];
 #pragma unroll
     for (int j = 0; j < RT_RPT; ++j) {
-        const int l = l0 + tid + j * RT_NT;
-        x[j] = l < l1 ? r[rows[r0 + l]] : 0.0;
+        const double v = r[ri[j]];
+        x[j] = l0 + tid + j * RT_NT < l1 ? v : 0.0;
     }
     for (int s0 = sbeg; s0 < k; s0 += KB) {
         double bv[KB][RT_RPT];
@@ -280,8 +290,8 @@ __device__ __forceinline__ void restrict_tile(const double *__restrict__ r, cons
         for (int s = 0; s < KB; ++s)
 #pragma unroll
             for (int j = 0; j < RT_RPT; ++j) {
-                const int l = l0 + tid + j * RT_NT;
-                bv[s][j] = (s0 + s < k && l < l1) ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
+                const int l = min(l0 + tid + j * RT_NT, l1 - 1);
+                bv[s][j] = double(to_acc(Bg[int64_t(min(s0 + s, k - 1)) * nr + l]));
             }
         double acc[KB];
 #pragma unroll
@@ -322,9 +332,12 @@ __device__ __forceinline__ void restrict_wave(const double *__restrict__ r, cons
         for (int s = 0; s < KB; ++s) acc[s] = 0.0;
         for (int l = lane; l < nr; l += 64) {
             const double x = r[rows[r0 + l]];
+            double b[KB];   // the row's entries, all loads before the products
+#pragma unroll
+            for (int s = 0; s < KB; ++s) b[s] = s0 + s < k ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
 #pragma unroll
             for (int s = 0; s < KB; ++s)
-                if (s0 + s < k) acc[s] += double(to_acc(Bg[int64_t(s0 + s) * nr + l])) * x;
+                if (s0 + s < k) acc[s] += b[s] * x;
         }
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
@@ -508,41 +521,82 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
 }
 
 // z[d] = sum over the local rows holding d (ascending subdomain) of zloc
-//        + Phi(d, :) z0       (which: bit 0 one-level part, bit 1 coarse part;
+//        + Phi(d, :) z0       (W: bit 0 one-level part, bit 1 coarse part;
 //        z0 read in block-column order from zg)
-// zc != nullptr: the coarse part was formed by blocks (k_coarse_prolong).
-template <typename PT>
-__device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_t *__restrict__ t_ptr,
+// BLK: the coarse part was formed by blocks (k_coarse_prolong) into zc.
+// The parts and the form are template arguments, so that the loads below
+// form straight-line code the compiler can issue in three waves, each before
+// anything waits for it: (1) where the local rows of d start and end, the
+// block and row of d in the coarse basis; (2) the first local row and the
+// block's shape; (3) the first local result, the first chunk of d's row of
+// the basis and of z0.
+template <typename PT, int W, bool BLK>
+__device__ __forceinline__ double prolong_one(int64_t d, const int32_t *__restrict__ t_ptr,
                                               const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
                                               const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr,
                                               const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ col_ptr,
                                               const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
                                               const double *__restrict__ zg, const double *__restrict__ zc) {
+    constexpr bool one = (W & 1) != 0, two = (W & 2) != 0, by_dof = two && !BLK;
+    constexpr int U = 8;   // columns per chunk
+    int p0 = 0, p1 = 0, g = -1, lr = 0;
+    if constexpr (one) {
+        p0 = t_ptr[d];
+        p1 = t_ptr[d + 1];
+    }
+    if constexpr (two) g = dof_blk[d];
+    if constexpr (by_dof) lr = dof_lr[d];
+    // (every dof lies in at least one overlapping subdomain, and a coarse
+    // part means at least one block: the loads stay in bounds; values read
+    // for a dof outside the coarse basis, g < 0, are not used)
+    const int gg = max(g, 0);
+    int64_t rp0 = 0, rp1 = 0, c0 = 0, c1 = 0, vo = 0;
+    if constexpr (by_dof) {
+        rp0 = row_ptr[gg];
+        rp1 = row_ptr[gg + 1];
+        c0 = col_ptr[gg];
+        c1 = col_ptr[gg + 1];
+        vo = val_off[gg];
+    }
+    double z_first = 0.0, zc_d = 0.0;
+    if constexpr (one) z_first = zloc[t_pos[p0]];
+    if constexpr (two && BLK) zc_d = zc[d];
+    const int64_t nr = rp1 - rp0;
+    const int k = g >= 0 ? int(c1 - c0) : 0;
+    const PT *Bg = phi + vo + lr;
+    double bv[U], zv[U];
+    if constexpr (by_dof) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bv[u] = u < k ? double(to_acc(Bg[u * nr])) : 0.0;
+            zv[u] = u < k ? zg[c0 + u] : 0.0;
+        }
+    }
+    // sums: the local results in ascending subdomain, then the coarse part
+    // (its products in column order)
     double acc = 0.0;
-    if (which & 1)
-        for (int p = t_ptr[d]; p < t_ptr[d + 1]; ++p) acc += zloc[t_pos[p]];
-    if (which & 2) {
-        const int g = dof_blk[d];
-        if (g >= 0 && zc) {
-            acc += zc[d];
-        } else if (g >= 0) {
-            const int64_t nr = row_ptr[g + 1] - row_ptr[g];
-            const int64_t c0 = col_ptr[g];
-            const int k = int(col_ptr[g + 1] - c0);
-            const PT *Bg = phi + val_off[g] + dof_lr[d];
-            // columns in chunks of 8, loads first, products added in order
-            constexpr int U = 8;
+    if constexpr (one) {
+        acc += z_first;
+        for (int p = p0 + 1; p < p1; ++p) acc += zloc[t_pos[p]];
+    }
+    if constexpr (two && BLK) {
+        if (g >= 0) acc += zc_d;
+    }
+    if constexpr (by_dof) {
+        if (g >= 0) {
             double s = 0.0;
-            for (int q0 = 0; q0 < k; q0 += U) {
-                double bv[U], zv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (u < k) s += bv[u] * zv[u];
+            for (int q = U; q < k; q += U) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    bv[u] = q0 + u < k ? double(to_acc(Bg[(q0 + u) * nr])) : 0.0;
-                    zv[u] = q0 + u < k ? zg[c0 + q0 + u] : 0.0;
+                    bv[u] = q + u < k ? double(to_acc(Bg[(q + u) * nr])) : 0.0;
+                    zv[u] = q + u < k ? zg[c0 + q + u] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (q0 + u < k) s += bv[u] * zv[u];
+                    if (q + u < k) s += bv[u] * zv[u];
             }
             acc += s;
         }
@@ -550,8 +604,8 @@ __device__ __forceinline__ double prolong_one(int which, int64_t d, const int32_
     return acc;
 }
 
-template <typename PT>
-__global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
+template <typename PT, int W, bool BLK>
+__global__ void k_prolong(const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos,
                           const double *__restrict__ zloc, const int32_t *__restrict__ dof_blk,
                           const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
                           const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off,
@@ -559,18 +613,19 @@ __global__ void k_prolong(int which, const int32_t *__restrict__ t_ptr, const in
                           double *__restrict__ z, int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (d >= n || sk.dof(d)) return;
-    z[d] = prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
+    z[d] = prolong_one<PT, W, BLK>(d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
 // [row0[b], row1[b]) of one problem), also writing the block's partial of
 // r . z for the next CG step.
-template <typename PT>
+template <typename PT, int W, bool BLK>
 __global__ __launch_bounds__(256) void k_prolong_dot(
-    int which, const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
+    const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
     const int32_t *__restrict__ dof_blk, const int32_t *__restrict__ dof_lr, const int64_t *__restrict__ row_ptr,
     const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ val_off, const PT *__restrict__ phi,
-    const double *__restrict__ zg, const double *__restrict__ zc, double *__restrict__ z, Skip sk, const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
+    const double *__restrict__ zg, const double *__restrict__ zc, double *__restrict__ z, Skip sk,
+    const int32_t *__restrict__ kb_row0, const int32_t *__restrict__ kb_row1, const double *__restrict__ rvec,
     double *__restrict__ partial) {
     __shared__ double sh[4];
     const int blk = blockIdx.x;
@@ -579,7 +634,7 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     double dot = 0.0;
     for (int d = row0 + threadIdx.x; d < row1; d += 256) {
         const double v =
-            prolong_one<PT>(which, d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
+            prolong_one<PT, W, BLK>(d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
         z[d] = v;
         dot += rvec[d] * v;
     }

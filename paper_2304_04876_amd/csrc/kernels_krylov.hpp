@@ -73,7 +73,9 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
     const int64_t base = A.off[sl] + lane;
     const int w = A.width[sl];
     // slots in chunks of 8: all loads of a chunk are issued before the
-    // products are added (in slot order)
+    // products are added (in slot order); slots past the slice's width
+    // re-read its last slot (in bounds, no branch between the loads) and are
+    // not added
     constexpr int U = 8;
     double acc = 0.0;
     for (int j0 = 0; j0 < w; j0 += U) {
@@ -81,13 +83,13 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
         double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t e = base + int64_t(j0 + u) * SELL_C;
-            c[u] = j0 + u < w ? A.col[e] : 0;
-            v[u] = j0 + u < w ? A.val[e] : 0.0;
+            const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
+            c[u] = A.col[e];
+            v[u] = A.val[e];
         }
         double xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = j0 + u < w ? x[c[u]] : 0.0;
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (j0 + u < w) acc += v[u] * xv[u];
@@ -118,16 +120,16 @@ __device__ __forceinline__ double sell_row_p(const Sell &A, int i, const double 
         int c[U];
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t e = base + int64_t(j0 + u) * SELL_C;
-            c[u] = j0 + u < w ? A.col[e] : 0;
-            v[u] = j0 + u < w ? A.val[e] : 0.0;
+        for (int u = 0; u < U; ++u) {   // (as in sell_row)
+            const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
+            c[u] = A.col[e];
+            v[u] = A.val[e];
         }
         double zv[U], pv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            zv[u] = j0 + u < w ? z[c[u]] : 0.0;
-            pv[u] = j0 + u < w ? pold[c[u]] : 0.0;
+            zv[u] = z[c[u]];
+            pv[u] = pold[c[u]];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
