@@ -801,7 +801,8 @@ constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 3;
 
 template <typename VT, int NT>
 static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
-    if (D.KLp != ILU_KL || D.KUp != ILU_KU || !D.Cp) return false;
+    // (one sweep per triangle needs no factor entries: the streaming kernel)
+    if (D.KLp != ILU_KL || D.KUp != ILU_KU || !D.Cp || S.opt.jacobi_sweeps < 2) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
     const int need = (S.max_ni + NT - 1) / NT;
     using AT = typename AccOf<VT>::type;

@@ -48,30 +48,32 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const int tid = threadIdx.x;
 
     if (ni == 0) return;   // (the whole workgroup)
+    __builtin_assume(sweeps >= 2);   // (the launcher takes another kernel for one sweep)
     const int last_r = ni - 1, last_p = npad - 1;
     AT rr[R];
     AT lv[R][KL], uv[R][KU];
     uint32_t cw[R][CW];   // local column of L slot s: half s, of U slot s: half KL + s
     int dof[R];
     // Every load of the thread's rows is issued before any loaded value is
-    // used, with no branches between them: the restriction indices, then the
-    // factor slots, the gathered r and the pivots.  Rows past the subdomain
-    // read its last row (in bounds) and are never used.
+    // used, with no branches between them, in the order the values are
+    // needed: the restriction indices, the pivots, the L slots and the
+    // columns, the gathered r, and last the U slots, which are only waited
+    // for after the L sweeps.  Rows past the subdomain read its last row (in
+    // bounds) and are never used.
 #pragma unroll
     for (int m = 0; m < R; ++m) dof[m] = ov_idx[o + min(tid + m * NT, last_r)];
+    AT dv[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) dv[m] = to_acc(dinv[eo + min(tid + m * NT, last_r)]);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int64_t e = eo + min(tid + m * NT, last_p);
 #pragma unroll
         for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(Lv[s * ell_rows + e]);
 #pragma unroll
-        for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(Uv[s * ell_rows + e]);
-#pragma unroll
         for (int w = 0; w < CW; ++w) cw[m][w] = Cp[e * CW + w];
     }
-    // the gathered r (scaled for reduced-precision factors) and the pivots,
-    // written to LDS for every slot of the thread (rows past the subdomain
-    // included: they are never read)
+    // the gathered r (scaled for reduced-precision factors)
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         double x = r[dof[m]];
@@ -82,70 +84,91 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
         }
         rr[m] = AT(x);
     }
-    AT dv[R];
+    // (kept after the loads above by the scheduler barrier)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int m = 0; m < R; ++m) dv[m] = to_acc(dinv[eo + min(tid + m * NT, last_r)]);
+    for (int m = 0; m < R; ++m) {
+        const int64_t e = eo + min(tid + m * NT, last_p);
+#pragma unroll
+        for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(Uv[s * ell_rows + e]);
+    }
+    // pivots to LDS for every slot of the thread (rows past the subdomain
+    // included: they are never read)
 #pragma unroll
     for (int m = 0; m < R; ++m) sdinv[tid + m * NT] = dv[m];
+    // The sweeps run over every slot of the thread, rows past the subdomain
+    // included (their columns point inside the LDS vectors; no row of the
+    // subdomain reads them), so that all LDS reads of a sweep go out before
+    // the first product waits.
     AT *cur = bufA, *nxt = bufB;
     // first L sweep from zero: y^1 = r
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int l = tid + m * NT;
-        if (l < ni) cur[l] = rr[m];
-    }
+    for (int m = 0; m < R; ++m) cur[tid + m * NT] = rr[m];
     __syncthreads();
+    // rows in groups of SG: the LDS reads of a group are issued together
+    constexpr int SG = 4;
     for (int k = 1; k < sweeps; ++k) {
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int l = tid + m * NT;
-            if (l < ni) {
-                AT acc = rr[m];
+        for (int m0 = 0; m0 < R; m0 += SG) {
+            AT v[SG][KL];
 #pragma unroll
-                for (int s = 0; s < KL; ++s) acc -= lv[m][s] * cur[(cw[m][s >> 1] >> (16 * (s & 1))) & 0xffffu];
-                nxt[l] = acc;
-            }
+            for (int g = 0; g < SG; ++g)
+#pragma unroll
+                for (int s = 0; s < KL; ++s)
+                    if (m0 + g < R) v[g][s] = cur[(cw[m0 + g][s >> 1] >> (16 * (s & 1))) & 0xffffu];
+#pragma unroll
+            for (int g = 0; g < SG; ++g)
+                if (m0 + g < R) {
+                    AT acc = rr[m0 + g];
+#pragma unroll
+                    for (int s = 0; s < KL; ++s) acc -= lv[m0 + g][s] * v[g][s];
+                    nxt[tid + (m0 + g) * NT] = acc;
+                }
         }
         __syncthreads();
         AT *t = cur; cur = nxt; nxt = t;
     }
-    // c = D^{-1} y^K (kept in rr), first U sweep from zero: w^1 = c
+    // c = D^{-1} y^K (kept in rr), first U sweep from zero: w^1 = c (all
+    // reads before the writes)
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int l = tid + m * NT;
-        if (l < ni) {
-            rr[m] = sdinv[l] * cur[l];
-            nxt[l] = rr[m];
-        }
-    }
+    for (int m = 0; m < R; ++m) rr[m] = sdinv[tid + m * NT] * cur[tid + m * NT];
+#pragma unroll
+    for (int m = 0; m < R; ++m) nxt[tid + m * NT] = rr[m];
     __syncthreads();
     { AT *t = cur; cur = nxt; nxt = t; }
     for (int k = 1; k < sweeps; ++k) {
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int l = tid + m * NT;
-            if (l < ni) {
-                AT acc = rr[m];
+        for (int m0 = 0; m0 < R; m0 += SG) {
+            AT v[SG][KU];
+#pragma unroll
+            for (int g = 0; g < SG; ++g)
 #pragma unroll
                 for (int s = 0; s < KU; ++s) {
-                    const int k = KL + s;
-                    acc -= uv[m][s] * cur[(cw[m][k >> 1] >> (16 * (k & 1))) & 0xffffu];
+                    const int h = KL + s;
+                    if (m0 + g < R) v[g][s] = cur[(cw[m0 + g][h >> 1] >> (16 * (h & 1))) & 0xffffu];
                 }
-                nxt[l] = acc;
-            }
+#pragma unroll
+            for (int g = 0; g < SG; ++g)
+                if (m0 + g < R) {
+                    AT acc = rr[m0 + g];
+#pragma unroll
+                    for (int s = 0; s < KU; ++s) acc -= uv[m0 + g][s] * v[g][s];
+                    nxt[tid + (m0 + g) * NT] = acc;
+                }
         }
         __syncthreads();
         AT *t = cur; cur = nxt; nxt = t;
     }
+    // the result: all LDS reads, then the stores of the subdomain's rows
+    double out[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int l = tid + m * NT;
-        if (l < ni) {
-            double v = double(cur[l]);
-            if (scaled && dscale) v *= sscale[l];
-            zloc[o + l] = v;
-        }
+        out[m] = double(cur[tid + m * NT]);
+        if (scaled && dscale) out[m] *= sscale[tid + m * NT];
     }
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+        if (tid + m * NT < ni) zloc[o + tid + m * NT] = out[m];
 }
 
 // Same sweeps for any slot counts and subdomain sizes: factors are read from
