@@ -252,18 +252,46 @@ __global__ __launch_bounds__(1024) void k_band_apply(
     const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
-    for (int l = threadIdx.x; l < ni; l += NT) {
-        const int d = ov_idx[o + l];
-        double x = r[d];
-        if (dscale) x *= dscale[d];
-        y[l] = AT(x);
+    // gathers and stores in batches of GB rows per thread, every load of a
+    // batch issued before the first use (rows past the end re-read the last)
+    constexpr int GB = 4;
+    for (int l0 = threadIdx.x; l0 < ni; l0 += GB * NT) {
+        int d[GB];
+#pragma unroll
+        for (int b = 0; b < GB; ++b) d[b] = ov_idx[o + min(l0 + b * NT, ni - 1)];
+        double x[GB];
+#pragma unroll
+        for (int b = 0; b < GB; ++b) x[b] = r[d[b]];
+        if (dscale) {
+            double sc[GB];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) sc[b] = dscale[d[b]];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) x[b] *= sc[b];
+        }
+#pragma unroll
+        for (int b = 0; b < GB; ++b)
+            if (l0 + b * NT < ni) y[l0 + b * NT] = AT(x[b]);
     }
     __syncthreads();
     band_llt_solve<VT, AT, NT, INV>(band + band_off[i], ni, bw[i], y, sT);
-    for (int l = threadIdx.x; l < ni; l += NT) {
-        double v = double(y[l]);
-        if (dscale) v *= dscale[ov_idx[o + l]];
-        zloc[o + l] = v;
+    for (int l0 = threadIdx.x; l0 < ni; l0 += GB * NT) {
+        double v[GB];
+#pragma unroll
+        for (int b = 0; b < GB; ++b) v[b] = double(y[min(l0 + b * NT, ni - 1)]);
+        if (dscale) {
+            int d[GB];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) d[b] = ov_idx[o + min(l0 + b * NT, ni - 1)];
+            double sc[GB];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) sc[b] = dscale[d[b]];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) v[b] *= sc[b];
+        }
+#pragma unroll
+        for (int b = 0; b < GB; ++b)
+            if (l0 + b * NT < ni) zloc[o + l0 + b * NT] = v[b];
     }
 }
 
