@@ -27,12 +27,61 @@ template <> __device__ __forceinline__ float from_double<float>(double x) { retu
 template <> __device__ __forceinline__ fp16 from_double<fp16>(double x) { return __float2half(float(x)); }
 template <> __device__ __forceinline__ bf16 from_double<bf16>(double x) { return __float2bfloat16(float(x)); }
 
-// Sum over a wavefront with a fixed butterfly order (every lane gets it).
+// Lane moves without the LDS crossbar: DPP within rows of 16 lanes (quad
+// permutations, mirrors of 8 and of 16 lanes), a swizzle across the halves
+// of 32 lanes, and reads of one lane.  64-bit values move as two halves.
+constexpr int DPP_QUAD_1032 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int SWZ_XOR16 = 0x1F | (0x10 << 10);   // bit mode: and 0x1f, or 0, xor 0x10
+
+template <int CTRL>
+__device__ __forceinline__ float lane_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), SWZ_XOR16));
+}
+__device__ __forceinline__ double lane_xor16(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), SWZ_XOR16);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), SWZ_XOR16);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_read(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_read(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes, with a fixed order; every lane of the row
+// gets the same bits (each step adds a value and its partner's, and the two
+// partners' sums commute).  All lanes of the wavefront must be active.
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+    v += lane_move<DPP_QUAD_1032>(v);
+    v += lane_move<DPP_QUAD_2301>(v);
+    v += lane_move<DPP_ROW_HALF_MIRROR>(v);
+    v += lane_move<DPP_ROW_MIRROR>(v);
+    return v;
+}
+
+// Sum over a wavefront with a fixed order (every lane gets it): rows of 16,
+// pairs of rows, then the two halves of the wavefront.  All lanes active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = row16_sum(v);
+    v += lane_xor16(v);
+    return lane_read(v, 0) + lane_read(v, 32);
 }
 
 // Workgroup sum with a fixed order; `sh` must hold NT/64 values.  Every

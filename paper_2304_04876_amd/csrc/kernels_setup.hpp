@@ -381,15 +381,6 @@ static_assert(BS_NB == BS_NB_INV, "the inverted diagonal blocks are the solve's 
 __host__ __device__ constexpr bool band_inverted(int b) { return b >= BS_NB - 1; }
 constexpr int BS_LD = BS_NB + 1;
 
-__device__ __forceinline__ float lane_read(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double lane_read(double v, int l) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane(int(u >> 32), l);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
 
 // sT(t, s) = L(k0+t, k0+s) for s < t, 1/L(k0+t, k0+t) for s = t (all threads)
 template <typename VT, typename AT, int NT>
@@ -510,6 +501,7 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
     // columns q, q+16, q+32, q+48 (consecutive lanes, consecutive addresses)
     // and the 16 partial products are summed across the lanes
     constexpr int LPR = 16, RPI = NT / LPR;
+    static_assert(LPR == 16, "the row sums use rows of 16 lanes");
     const int sub = tid & (LPR - 1), rg = tid / LPR;
     for (int blk = 0; blk + 1 < nblk; ++blk) {
         const int k0 = blk * BS_NB;
@@ -541,8 +533,7 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
                 AT acc = 0;
 #pragma unroll
                 for (int q = 0; q < BS_NB / LPR; ++q) acc += v[it][q] * yq[q];
-#pragma unroll
-                for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, LPR);
+                acc = row16_sum(acc);   // (LPR = 16 lanes per row)
                 if (r < rend && sub == 0) y[r] -= acc;
             }
         }
