@@ -965,7 +965,7 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, sc, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
         if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
-            hipLaunchKernelGGL(k_block_gemv_wg, dim3(S.n0), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
+            hipLaunchKernelGGL(k_block_gemv_wg, dim3((S.n0 + GW_R - 1) / GW_R), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
                                D.r0, D.z0, D.cpos_ptr, D.cpos, D.zg, S.n0, sk);
         else
             hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,

@@ -480,37 +480,83 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
     for (int64_t p = cpos_ptr[row] + lane; p < cpos_ptr[row + 1]; p += 64) zg[cpos[p]] = acc;
 }
 
-// Same with one workgroup (4 wavefronts) per row, for blocks of large order.
+// Same with one workgroup (4 wavefronts) per row, for blocks of large order:
+// GW_R consecutive rows per workgroup, which read each entry of r0 once for
+// all of them when they belong to one problem.  Each row's products are
+// added per thread in column order and then summed over the workgroup as
+// for a single row, so the rows do not change each other's bits.
+constexpr int GW_R = 4;
 __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict__ Ainv, const int64_t *__restrict__ a0_off,
                                                        const int32_t *__restrict__ prob_c0,
                                                        const int32_t *__restrict__ cprob, const double *__restrict__ x,
                                                        double *__restrict__ y, const int64_t *__restrict__ cpos_ptr,
                                                        const int32_t *__restrict__ cpos, double *__restrict__ zg,
                                                        int n0, Skip sk) {
-    __shared__ double sh[4];
-    const int row = blockIdx.x;
-    if (sk.col(row)) return;
-    const int k = cprob[row];
-    const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
-    const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
-    const double *xk = x + c0;
-    constexpr int U = 16;
-    double acc = 0.0;
-    for (int c0 = threadIdx.x; c0 < nk; c0 += U * 256) {
-        double av[U], xv[U];
+    __shared__ double sh[GW_R][4];
+    const int r0 = blockIdx.x * GW_R;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int row[GW_R];
+    bool act[GW_R];
+    bool any = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = c0 + u * 256;
-            av[u] = c < nk ? a[c] : 0.0;
-            xv[u] = c < nk ? xk[c] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (c0 + u * 256 < nk) acc += av[u] * xv[u];
+    for (int j = 0; j < GW_R; ++j) {
+        row[j] = min(r0 + j, n0 - 1);
+        act[j] = r0 + j < n0 && !sk.col(row[j]);
+        any |= act[j];
     }
-    acc = block_sum<double, 256>(acc, sh);
-    if (threadIdx.x == 0) y[row] = acc;
-    for (int64_t p = cpos_ptr[row] + threadIdx.x; p < cpos_ptr[row + 1]; p += 256) zg[cpos[p]] = acc;
+    if (!any) return;   // (the whole workgroup)
+    const int k0 = cprob[row[0]];
+    bool same = true;
+#pragma unroll
+    for (int j = 1; j < GW_R; ++j) same &= cprob[row[j]] == k0;
+    constexpr int U = 12;
+    double acc[GW_R];
+#pragma unroll
+    for (int j = 0; j < GW_R; ++j) acc[j] = 0.0;
+    if (same) {
+        const int c0 = prob_c0[k0], nk = prob_c0[k0 + 1] - c0;
+        const double *xk = x + c0;
+        const double *a0 = Ainv + a0_off[k0];
+        for (int cc = tid; cc < nk; cc += U * 256) {
+            double xv[U], av[GW_R][U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = cc + u * 256 < nk ? xk[cc + u * 256] : 0.0;
+#pragma unroll
+            for (int j = 0; j < GW_R; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    av[j][u] = cc + u * 256 < nk ? a0[int64_t(row[j] - c0) * nk + cc + u * 256] : 0.0;
+#pragma unroll
+            for (int j = 0; j < GW_R; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (cc + u * 256 < nk) acc[j] += av[j][u] * xv[u];
+        }
+    } else {   // rows of different problems (problem boundaries of a batch)
+#pragma unroll
+        for (int j = 0; j < GW_R; ++j) {
+            const int k = cprob[row[j]];
+            const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
+            const double *a = Ainv + a0_off[k] + int64_t(row[j] - c0) * nk;
+            for (int c = tid; c < nk; c += 256) acc[j] += a[c] * x[c0 + c];
+        }
+    }
+    // the workgroup sums, as block_sum for each row
+#pragma unroll
+    for (int j = 0; j < GW_R; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) sh[j][wv] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < GW_R; ++j) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) t += sh[j][w];
+        if (!act[j]) continue;
+        if (tid == 0) y[row[j]] = t;
+        for (int64_t p = cpos_ptr[row[j]] + tid; p < cpos_ptr[row[j] + 1]; p += 256) zg[cpos[p]] = t;
+    }
 }
 
 // Coarse part of the prolongation by blocks, for coarse bases with many
