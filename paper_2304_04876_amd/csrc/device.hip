@@ -233,7 +233,26 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         D.sell.off = D.upload(off, s);
         D.sell.width = D.upload(wid, s);
         D.sell.val = D.upload(sv, s);
-        D.sell.col = D.upload(sc, s);
+        // 16-bit column offsets when every entry lies within 32767 of its row
+        bool near = true;
+        for (int64_t i = 0; i < S.n && near; ++i)
+            for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p)
+                if (std::abs(int64_t(S.col[p]) - i) > 32767) {
+                    near = false;
+                    break;
+                }
+        std::vector<int16_t> sd;
+        if (near) {
+            sd.resize(sc.size());
+            for (int64_t sl = 0; sl < nsl; ++sl)
+                for (int64_t j = 0; j < int64_t(wid[sl]) * SELL_C; ++j) {
+                    const int64_t e = off[sl] + j, i = sl * SELL_C + j % SELL_C;
+                    sd[size_t(e)] = int16_t(i < S.n ? sc[size_t(e)] - i : 0);
+                }
+            D.sell.dcol = D.upload(sd, s);
+        } else {
+            D.sell.col = D.upload(sc, s);
+        }
         HIPCHK(hipStreamSynchronize(s));
     }
     D.t_pos = D.upload(S.t_pos, s);
@@ -1044,8 +1063,12 @@ gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream) {
     }
     if (!x || !y || x == y) return GDSW_ERR_INVALID_ARG;
     const int n = int(h->sym.n);
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
-                       x, y, n);
+    if (h->dev->sell.dcol)
+        hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
+                           x, y, n);
+    else
+        hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
+                           x, y, n);
     return hipGetLastError() == hipSuccess ? GDSW_OK : GDSW_ERR_HIP;
 }
 
@@ -1077,8 +1100,12 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     const int nkb = D.nkb, np = S.nprob;
     double *pold = D.cg_par ? D.kp2 : D.kp, *pnew = D.cg_par ? D.kp : D.kp2;
     // p = z + beta p fused into the product with A
-    hipLaunchKernelGGL(k_cg_spmv_dot_p, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
-                       (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
+    if (D.sell.dcol)
+        hipLaunchKernelGGL(k_cg_spmv_dot_p<true>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
+                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
+    else
+        hipLaunchKernelGGL(k_cg_spmv_dot_p<false>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
+                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
     hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, pnew, D.kq, D.kpart2, D.kst, all);
@@ -1158,7 +1185,10 @@ static void queue_true_residual(gdsw_handle_s *h, const double *b, const double 
     const int base = k < 0 ? 0 : D.h_pb_ptr[k];
     const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
+    if (D.sell.dcol)
+        hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
+    else
+        hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
     hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst,
@@ -1332,7 +1362,10 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     while (single_reduce) {
         // u = r = b - A x; step 0 forms ||r|| in its reduction
         hipLaunchKernelGGL(k_sr_cycle_start, dim3(1), dim3(1024), 0, s, st);
-        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+        if (D.sell.dcol)
+            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+        else
+            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
         int queued = 0, chunk = 4;
         while (true) {
@@ -1342,7 +1375,10 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
                 const bool last = j == m;   // completes column m-1 only
                 if (!last) {
                     launch_apply(h, r, t, 3, gsk, s);
-                    hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
+                    if (D.sell.dcol)
+                        hipLaunchKernelGGL(k_gm_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
+                    else
+                        hipLaunchKernelGGL(k_gm_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
                 }
                 hipLaunchKernelGGL(k_sr_reduce, dim3(sr_nb), dim3(KNT), 0, s, V, r, last ? nullptr : w, n, j,
                                    D.gm_part, st);
@@ -1370,7 +1406,10 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     }
     while (!single_reduce) {
         // r = b - A x
-        hipLaunchKernelGGL(k_spmv, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+        if (D.sell.dcol)
+            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+        else
+            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
         hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, r, n, D.gm_part, st, 1);
         hipLaunchKernelGGL(k_gm_start_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st);
@@ -1381,7 +1420,10 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
             for (int k = 0; k < c; ++k) {
                 hipLaunchKernelGGL(k_gm_get, dim3(nblocks(n, 256, 65536)), dim3(256), 0, s, V, v, n, st);
                 launch_apply(h, v, t, 3, gsk, s);
-                hipLaunchKernelGGL(k_gm_spmv, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
+                if (D.sell.dcol)
+                    hipLaunchKernelGGL(k_gm_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
+                else
+                    hipLaunchKernelGGL(k_gm_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, t, w, int(n), st);
                 for (int pass = 0; pass < 2; ++pass) {
                     hipLaunchKernelGGL(k_gm_dots, dim3(gr), dim3(KNT), 0, s, V, w, n, D.gm_part, st);
                     hipLaunchKernelGGL(k_gm_dots_finish, dim3(1), dim3(GM_FIN_NT), 0, s, D.gm_part, gr, st, pass);

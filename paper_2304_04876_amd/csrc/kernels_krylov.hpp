@@ -59,15 +59,29 @@ __device__ __forceinline__ double sum_partials(const double *partial, int lo, in
 
 // A in sliced ELL form for the SpMV: slices of SELL_C consecutive rows, each
 // slice padded to its longest row and stored slot-major, so that
-// consecutive threads (rows) read consecutive addresses.
+// consecutive threads (rows) read consecutive addresses.  The columns are
+// stored as 16-bit offsets from the row (dcol) when every entry lies within
+// 32767 of the diagonal (banded orderings: the 7-point and the Q1 elasticity
+// matrices here), else as 32-bit indices (col); the kernels take the form as
+// a template argument D16.
 constexpr int SELL_C = 256;
 struct Sell {
     const int64_t *off;    // [nslices+1] value offsets of the slices
     const int32_t *width;  // [nslices] slots of each slice
     const double *val;
-    const int32_t *col;
+    const int32_t *col;    // 32-bit columns (null with dcol)
+    const int16_t *dcol;   // column - row (null with col)
 };
 
+template <bool D16>
+__device__ __forceinline__ int sell_col(const Sell &A, int i, int64_t e) {
+    if constexpr (D16)
+        return i + int(A.dcol[e]);
+    else
+        return A.col[e];
+}
+
+template <bool D16>
 __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *__restrict__ x) {
     const int sl = i / SELL_C, lane = i % SELL_C;
     const int64_t base = A.off[sl] + lane;
@@ -84,7 +98,7 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
-            c[u] = A.col[e];
+            c[u] = sell_col<D16>(A, i, e);
             v[u] = A.val[e];
         }
         double xv[U];
@@ -97,10 +111,11 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
     return acc;
 }
 
+template <bool D16>
 __global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y, int n) {
     const int i = blockIdx.x * KNT + threadIdx.x;
     if (i >= n) return;
-    y[i] = sell_row(A, i, x);
+    y[i] = sell_row<D16>(A, i, x);
 }
 
 // One row of A (z + beta p_old): the vector is formed on the fly from z and
@@ -109,6 +124,7 @@ __global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__
 // writes as its own p_new.
 __device__ __forceinline__ double p_next(double beta, double pold, double z) { return __builtin_fma(beta, pold, z); }
 
+template <bool D16>
 __device__ __forceinline__ double sell_row_p(const Sell &A, int i, const double *__restrict__ z,
                                              const double *__restrict__ pold, double beta) {
     const int sl = i / SELL_C, lane = i % SELL_C;
@@ -122,7 +138,7 @@ __device__ __forceinline__ double sell_row_p(const Sell &A, int i, const double 
 #pragma unroll
         for (int u = 0; u < U; ++u) {   // (as in sell_row)
             const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
-            c[u] = A.col[e];
+            c[u] = sell_col<D16>(A, i, e);
             v[u] = A.val[e];
         }
         double zv[U], pv[U];
@@ -151,6 +167,7 @@ __global__ __launch_bounds__(KNT) void k_cg_init(double *__restrict__ x, double 
 // The update p = z + beta p fused into the next product: p_new = z + beta
 // p_old (written by each row for itself), q = A p_new and the partials of
 // p_new . q.  At the start of CG p_old = z and beta = 0, so p_new = z.
+template <bool D16>
 __global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__restrict__ z,
                                                        const double *__restrict__ pold, double *__restrict__ pnew,
                                                        double *__restrict__ q, double *__restrict__ partial,
@@ -162,7 +179,7 @@ __global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__r
     const double beta = S.beta;
     double dot = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
-        const double acc = sell_row_p(A, i, z, pold, beta);
+        const double acc = sell_row_p<D16>(A, i, z, pold, beta);
         const double pi = p_next(beta, pold[i], z[i]);
         pnew[i] = pi;
         q[i] = acc;
@@ -435,12 +452,13 @@ __device__ void sum_partial_values(const double *__restrict__ p, int64_t sv, int
 }
 
 // w = A t (skipped once the cycle has stopped)
+template <bool D16>
 __global__ __launch_bounds__(KNT) void k_gm_spmv(Sell A, const double *__restrict__ t, double *__restrict__ w, int n,
                                                  const GState *st) {
     if (st->cycle_done) return;
     const int i = blockIdx.x * KNT + threadIdx.x;
     if (i >= n) return;
-    w[i] = sell_row(A, i, t);
+    w[i] = sell_row<D16>(A, i, t);
 }
 
 // v = V_j (j from the state), the vector the preconditioner is applied to
