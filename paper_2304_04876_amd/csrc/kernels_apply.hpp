@@ -381,14 +381,31 @@ __device__ __forceinline__ void restrict_wave(const double *__restrict__ r, cons
         double acc[KB];
 #pragma unroll
         for (int s = 0; s < KB; ++s) acc[s] = 0.0;
-        for (int l = lane; l < nr; l += 64) {
-            const double x = r[rows[r0 + l]];
-            double b[KB];   // the row's entries, all loads before the products
+        // rows in batches of WB per lane, every load of a batch issued before
+        // the products (rows past the block re-read its last row, with x = 0);
+        // each column adds its rows in the order l = lane, lane + 64, ...
+        constexpr int WB = 4;
+        for (int l0 = lane; l0 < nr; l0 += WB * 64) {
+            int ri[WB];
 #pragma unroll
-            for (int s = 0; s < KB; ++s) b[s] = s0 + s < k ? double(to_acc(Bg[int64_t(s0 + s) * nr + l])) : 0.0;
+            for (int j = 0; j < WB; ++j) ri[j] = rows[r0 + min(l0 + j * 64, nr - 1)];
+            double bv[WB][KB];
 #pragma unroll
-            for (int s = 0; s < KB; ++s)
-                if (s0 + s < k) acc[s] += b[s] * x;
+            for (int j = 0; j < WB; ++j)
+#pragma unroll
+                for (int s = 0; s < KB; ++s)
+                    bv[j][s] = s0 + s < k ? double(to_acc(Bg[int64_t(s0 + s) * nr + min(l0 + j * 64, nr - 1)])) : 0.0;
+            double x[WB];
+#pragma unroll
+            for (int j = 0; j < WB; ++j) {
+                const double v = r[ri[j]];
+                x[j] = l0 + j * 64 < nr ? v : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < WB; ++j)
+#pragma unroll
+                for (int s = 0; s < KB; ++s)
+                    if (s0 + s < k) acc[s] += bv[j][s] * x[j];
         }
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
