@@ -64,14 +64,14 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     for (int m = 0; m < R; ++m) dof[m] = ov_idx[o + min(tid + m * NT, last_r)];
     AT dv[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) dv[m] = to_acc(dinv[eo + min(tid + m * NT, last_r)]);
+    for (int m = 0; m < R; ++m) dv[m] = to_acc(ld_once(&dinv[eo + min(tid + m * NT, last_r)]));
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int64_t e = eo + min(tid + m * NT, last_p);
 #pragma unroll
-        for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(Lv[s * ell_rows + e]);
+        for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(ld_once(&Lv[s * ell_rows + e]));
 #pragma unroll
-        for (int w = 0; w < CW; ++w) cw[m][w] = Cp[e * CW + w];
+        for (int w = 0; w < CW; ++w) cw[m][w] = ld_once(&Cp[e * CW + w]);
     }
     // the gathered r (scaled for reduced-precision factors)
 #pragma unroll
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     for (int m = 0; m < R; ++m) {
         const int64_t e = eo + min(tid + m * NT, last_p);
 #pragma unroll
-        for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(Uv[s * ell_rows + e]);
+        for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(ld_once(&Uv[s * ell_rows + e]));
     }
     // pivots to LDS for every slot of the thread (rows past the subdomain
     // included: they are never read)
