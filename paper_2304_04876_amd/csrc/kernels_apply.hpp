@@ -485,7 +485,7 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = c0 + u * 64;
-            av[u] = c < nk ? a[c] : 0.0;
+            av[u] = c < nk ? ld_once(&a[c]) : 0.0;
             xv[u] = c < nk ? xk[c] : 0.0;
         }
 #pragma unroll
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
             for (int j = 0; j < GW_R; ++j)
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    av[j][u] = cc + u * 256 < nk ? a0[int64_t(row[j] - c0) * nk + cc + u * 256] : 0.0;
+                    av[j][u] = cc + u * 256 < nk ? ld_once(&a0[int64_t(row[j] - c0) * nk + cc + u * 256]) : 0.0;
 #pragma unroll
             for (int j = 0; j < GW_R; ++j)
 #pragma unroll
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
             const int k = cprob[row[j]];
             const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
             const double *a = Ainv + a0_off[k] + int64_t(row[j] - c0) * nk;
-            for (int c = tid; c < nk; c += 256) acc[j] += a[c] * x[c0 + c];
+            for (int c = tid; c < nk; c += 256) acc[j] += ld_once(&a[c]) * x[c0 + c];
         }
     }
     // the workgroup sums, as block_sum for each row

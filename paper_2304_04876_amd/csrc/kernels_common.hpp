@@ -27,9 +27,10 @@ template <> __device__ __forceinline__ float from_double<float>(double x) { retu
 template <> __device__ __forceinline__ fp16 from_double<fp16>(double x) { return __float2half(float(x)); }
 template <> __device__ __forceinline__ bf16 from_double<bf16>(double x) { return __float2bfloat16(float(x)); }
 
-// Loads of data read once per launch (factor entries), marked non-temporal
-// so that they do not displace data that later kernels of the same apply
-// read again from the caches (the coarse basis, the vectors).
+// Loads of data read once per launch (factor entries, matrix entries, the
+// coarse inverse), marked non-temporal so that they do not displace data
+// that later kernels of the same iteration read again from the caches (the
+// coarse basis, the vectors).
 template <typename T>
 __device__ __forceinline__ T ld_once(const T *p) { return *p; }
 template <>
@@ -38,6 +39,10 @@ template <>
 __device__ __forceinline__ float ld_once<float>(const float *p) { return __builtin_nontemporal_load(p); }
 template <>
 __device__ __forceinline__ uint32_t ld_once<uint32_t>(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+template <>
+__device__ __forceinline__ int32_t ld_once<int32_t>(const int32_t *p) { return __builtin_nontemporal_load(p); }
+template <>
+__device__ __forceinline__ int16_t ld_once<int16_t>(const int16_t *p) { return __builtin_nontemporal_load(p); }
 
 // Lane moves without the LDS crossbar: DPP within rows of 16 lanes (quad
 // permutations, mirrors of 8 and of 16 lanes), a swizzle across the halves

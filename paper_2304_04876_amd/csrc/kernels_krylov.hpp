@@ -76,9 +76,9 @@ struct Sell {
 template <bool D16>
 __device__ __forceinline__ int sell_col(const Sell &A, int i, int64_t e) {
     if constexpr (D16)
-        return i + int(A.dcol[e]);
+        return i + int(ld_once(&A.dcol[e]));
     else
-        return A.col[e];
+        return ld_once(&A.col[e]);
 }
 
 template <bool D16>
@@ -99,7 +99,7 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
         for (int u = 0; u < U; ++u) {
             const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
             c[u] = sell_col<D16>(A, i, e);
-            v[u] = A.val[e];
+            v[u] = ld_once(&A.val[e]);
         }
         double xv[U];
 #pragma unroll
@@ -139,7 +139,7 @@ __device__ __forceinline__ double sell_row_p(const Sell &A, int i, const double 
         for (int u = 0; u < U; ++u) {   // (as in sell_row)
             const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
             c[u] = sell_col<D16>(A, i, e);
-            v[u] = A.val[e];
+            v[u] = ld_once(&A.val[e]);
         }
         double zv[U], pv[U];
 #pragma unroll

@@ -373,6 +373,18 @@ __global__ void k_cast(const double *__restrict__ src, VT *__restrict__ dst, int
 constexpr int BS_NB = 64;
 static_assert(BS_NB == BS_NB_INV, "the inverted diagonal blocks are the solve's blocks");
 
+// Loads of band entries: non-temporal for 8-byte entries (each band is
+// streamed once per pass in whole cache lines); 4- and 2-byte entries use
+// plain loads, since a row's 64-entry segment then fills only part of a
+// line and the rest of the line is read by the next load.
+template <typename VT>
+__device__ __forceinline__ VT band_ld(const VT *p) {
+    if constexpr (sizeof(VT) == 8)
+        return ld_once(p);
+    else
+        return *p;
+}
+
 // A band of width b holds whole 64x64 triangles, and so gets its diagonal
 // blocks inverted (k_band_invert_diag), when b >= 63.  The choice depends
 // on the subdomain alone, so a problem's results do not depend on what it
@@ -390,7 +402,7 @@ __device__ __forceinline__ void band_stage_triangle(const VT *__restrict__ L, in
     for (int e = threadIdx.x; e < BS_NB * BS_NB; e += NT) {
         const int t = e / BS_NB, s = e % BS_NB;
         AT v = 0;
-        if (t < kb && s <= t && t - s <= b) v = to_acc(L[int64_t(k0 + t) * w + (s - t + b)]);
+        if (t < kb && s <= t && t - s <= b) v = to_acc(band_ld(&L[int64_t(k0 + t) * w + (s - t + b)]));
         sT[t * BS_LD + s] = v;
     }
 }
@@ -461,7 +473,7 @@ __device__ __forceinline__ void band_load_triangle(const VT *__restrict__ L, int
     for (int c = 0; c < tri_per_thread<NT>(); ++c) {
         const int e = int(threadIdx.x) + c * NT;
         const int t = e / BS_NB, s = e % BS_NB;
-        tv[c] = (e < BS_NB * BS_NB && t < kb && s <= t && t - s <= b) ? to_acc(L[int64_t(k0 + t) * w + (s - t + b)])
+        tv[c] = (e < BS_NB * BS_NB && t < kb && s <= t && t - s <= b) ? to_acc(band_ld(&L[int64_t(k0 + t) * w + (s - t + b)]))
                                                                       : AT(0);
     }
 }
@@ -524,7 +536,7 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
 #pragma unroll
                 for (int q = 0; q < BS_NB / LPR; ++q) {
                     const int s = sub + q * LPR;
-                    v[it][q] = (r < rend && s >= s0) ? to_acc(row[s]) : AT(0);
+                    v[it][q] = (r < rend && s >= s0) ? to_acc(band_ld(&row[s])) : AT(0);
                 }
             }
 #pragma unroll
@@ -571,7 +583,7 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
             for (int g = 0; g < BS_NB; g += G) {
                 AT v[G];
 #pragma unroll
-                for (int q = 0; q < G; ++q) v[q] = (g + q < smax) ? to_acc(col[int64_t(g + q) * (w - 1)]) : AT(0);
+                for (int q = 0; q < G; ++q) v[q] = (g + q < smax) ? to_acc(band_ld(&col[int64_t(g + q) * (w - 1)])) : AT(0);
 #pragma unroll
                 for (int q = 0; q < G; ++q) acc += v[q] * y[k0 + min(g + q, kb - 1)];
             }
