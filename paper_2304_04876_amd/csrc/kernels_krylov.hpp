@@ -182,7 +182,7 @@ __global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__r
         const double acc = sell_row_p<D16>(A, i, z, pold, beta);
         const double pi = p_next(beta, pold[i], z[i]);
         pnew[i] = pi;
-        q[i] = acc;
+        __builtin_nontemporal_store(acc, &q[i]);   // (read once, by the update)
         dot += pi * acc;
     }
     dot = block_sum<double, KNT>(dot, sh);
@@ -202,8 +202,9 @@ __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, do
     const double alpha = S.alpha;
     double v = 0.0;
     for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
+        // x and q are read once here (x again only in the next update)
+        __builtin_nontemporal_store(ld_once(&x[i]) + alpha * p[i], &x[i]);
+        const double ri = r[i] - alpha * ld_once(&q[i]);
         r[i] = ri;
         v += ri * ri;
     }
