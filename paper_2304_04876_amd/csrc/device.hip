@@ -981,7 +981,7 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
                                    D.tile_l0, D.tile_l1, D.tile_poff, D.wk_tile, D.wk_s0, D.blk_poff, D.partial,
                                    D.nwork, nbig, B.nb, sk);
         }
-        hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(S.n0, 256)), dim3(256), 0, sc, D.red_ptr, D.red_idx,
+        hipLaunchKernelGGL(k_coarse_reduce, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
         if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
             hipLaunchKernelGGL(k_block_gemv_wg, dim3((S.n0 + GW_R - 1) / GW_R), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,

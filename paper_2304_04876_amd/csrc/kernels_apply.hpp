@@ -442,22 +442,20 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_restrict(
 }
 
 // r0[c] = sum of the partials of coarse column c (ascending block order)
-__global__ void k_coarse_reduce(const int64_t *__restrict__ red_ptr, const int32_t *__restrict__ red_idx,
-                                const double *__restrict__ partial, double *__restrict__ r0, int n0, Skip sk) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n0 || sk.col(c)) return;
-    constexpr int U = 8;
-    double acc = 0.0;
+// One wavefront per column: lane j adds partials j, j + 64, ... of the
+// column's list, then the wavefront sum (a fixed order that depends only on
+// the column's list).
+__global__ __launch_bounds__(256) void k_coarse_reduce(const int64_t *__restrict__ red_ptr,
+                                                       const int32_t *__restrict__ red_idx,
+                                                       const double *__restrict__ partial, double *__restrict__ r0,
+                                                       int n0, Skip sk) {
+    const int c = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= n0 || sk.col(c)) return;   // (the whole wavefront)
     const int64_t q1 = red_ptr[c + 1];
-    for (int64_t q0 = red_ptr[c]; q0 < q1; q0 += U) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = q0 + u < q1 ? partial[red_idx[q0 + u]] : 0.0;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (q0 + u < q1) acc += v[u];
-    }
-    r0[c] = acc;
+    double acc = 0.0;
+    for (int64_t q = red_ptr[c] + lane; q < q1; q += 64) acc += partial[red_idx[q]];
+    acc = wave_sum(acc);
+    if (lane == 0) r0[c] = acc;
 }
 
 // z0 = A_0^{-1} r0 with A_0^{-1} block diagonal over the problems of the
