@@ -104,6 +104,10 @@ def test_one_level_and_single_subdomain():
     zd = torch.zeros(pr.n, dtype=torch.float64, device="cuda")
     g.apply(dev(r), zd)
     assert rel_max(host(zd), M.apply(r)) <= 1e-12
+    # the coarse part of a handle without a coarse space is zero
+    zd.fill_(7.0)
+    g.apply_part(dev(r), zd, 2)
+    assert not host(zd).any()
     g.close()
     say("[solve] single subdomain")
     pr = P.poisson3d(9, 1)
