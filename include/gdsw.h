@@ -145,6 +145,8 @@ typedef struct {
     int32_t prolong_variant;  /* coarse part of the prolongation: -1 fixed rule (by blocks
                                  when Phi holds >= 16 values per dof), 0 per dof,
                                  1 by blocks                                         */
+    double t_refactor;        /* seconds: last numeric re-setup (gdsw_refactor,
+                                 synchronised); 0 if there was none             */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -193,8 +195,20 @@ gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts
  * singular pivots are reported).  Errors: SINGULAR, BUDGET, HIP, STATE. */
 gdsw_status gdsw_factor(gdsw_handle h, void *stream);
 
-/* Numeric re-setup with new values on the same pattern (host FP64 array of
- * nnz values in the CSR order given to gdsw_analyze). */
+/* Numeric re-setup with new values on the same pattern (Sec. V-A: the
+ * numerical phase repeated for a new matrix of the same structure).
+ *   val: host FP64 array of the nnz values in the CSR order given to
+ *        gdsw_analyze (copied during the call).
+ * Keeps the symbolic analysis, every device map and buffer (the factors,
+ * Phi, A_0^{-1} and the Krylov vectors stay at the same device addresses, so
+ * captured graphs remain valid), the launch configurations chosen by
+ * gdsw_autotune / gdsw_set_launch and the captured CG graphs; recomputes the
+ * local factors, the extension Phi_I, A_0 and its inverse from the new
+ * values.  The maps and scratch of the numerical setup stay resident from the
+ * first call on (reported in device_bytes), so later calls upload and
+ * allocate nothing.  A handle that is not factored is factored afresh.
+ * Synchronises `stream`.  Errors: INVALID_ARG (non-finite value), SINGULAR
+ * (the handle is then left unfactored), BUDGET, HIP. */
 gdsw_status gdsw_refactor(gdsw_handle h, const double *val, void *stream);
 
 /* gdsw_analyze followed by gdsw_factor. */

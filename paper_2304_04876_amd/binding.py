@@ -70,7 +70,7 @@ class Info(ctypes.Structure):
                 ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
                 ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32),
-                ("prolong_variant", ctypes.c_int32)]
+                ("prolong_variant", ctypes.c_int32), ("t_refactor", ctypes.c_double)]
 
 
 def lib():

@@ -170,6 +170,7 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->gemv_variant = gdsw::tuned_variant(h, 1);
     info->apply_streams = gdsw::tuned_variant(h, 2);
     info->prolong_variant = gdsw::tuned_variant(h, 3);
+    info->t_refactor = h->t_refactor;
     return GDSW_OK;
 }
 

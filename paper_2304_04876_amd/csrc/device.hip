@@ -77,6 +77,49 @@ struct Device {
         if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
         return p;
     }
+    // Buffers of the numerical setup alone: uploaded index maps of the
+    // analysis (which do not depend on the matrix values) and scratch.  The
+    // first factorisation frees them when it is done; from the first numeric
+    // re-setup on (gdsw_refactor) they stay resident, keyed by the host
+    // vector they hold or by a scratch tag, so that later re-setups neither
+    // upload maps nor allocate.
+    bool keep_setup = false;
+    struct Held {
+        const void *key;
+        void *p;
+        size_t sz;
+    };
+    std::vector<Held> held;
+    void *held_find(const void *key, size_t sz) const {
+        for (const Held &x : held)
+            if (x.key == key) {
+                if (x.sz != std::max<size_t>(sz, 16)) throw DevError{GDSW_ERR_INTERNAL, "setup buffer size changed"};
+                return x.p;
+            }
+        return nullptr;
+    }
+    template <typename T>
+    T *setup_upload(const std::vector<T> &v, hipStream_t s) {
+        const size_t sz = sizeof(T) * std::max<size_t>(v.size(), 1);
+        if (keep_setup)
+            if (void *p = held_find(&v, sz)) return static_cast<T *>(p);
+        T *p = upload(v, s);
+        if (keep_setup) held.push_back({&v, p, std::max<size_t>(sz, 16)});
+        return p;
+    }
+    template <typename T>
+    T *setup_scratch(int tag, int64_t count) {
+        const void *key = reinterpret_cast<const void *>(uintptr_t(tag));
+        const size_t sz = sizeof(T) * size_t(std::max<int64_t>(count, 1));
+        if (keep_setup)
+            if (void *p = held_find(key, sz)) return static_cast<T *>(p);
+        T *p = static_cast<T *>(raw_alloc(sz));
+        if (keep_setup) held.push_back({key, p, std::max<size_t>(sz, 16)});
+        return p;
+    }
+    void setup_release(void *p, size_t sz) {
+        if (!keep_setup) release(p, sz);
+    }
     // the coarse part of an apply runs on `side` beside the local solves
     // (fork/join with two events); created with the default priority
     hipStream_t side = nullptr;
@@ -186,6 +229,37 @@ struct Device {
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
 
+// Scratch tags of the numerical setup (Device::setup_scratch).
+enum SetupTag {
+    ST_STATUS = 1, ST_LVAL, ST_FI_A, ST_FI_V, ST_BAND64, ST_BP_LOCAL, ST_BP_INT, ST_E, ST_IBAND, ST_T2, ST_T1,
+    ST_GJ_P, ST_GJ_W, ST_SUB_BLK
+};
+
+// Values of A in the sliced ELL layout of the Krylov SpMV (slices of SELL_C
+// rows, slot-major, padded to the slice's longest row with zeros).
+static std::vector<double> sell_values(const Symbolic &S, std::vector<int64_t> *off_out = nullptr,
+                                       std::vector<int32_t> *wid_out = nullptr) {
+    const int64_t nsl = (S.n + SELL_C - 1) / SELL_C;
+    std::vector<int64_t> off(nsl + 1, 0);
+    std::vector<int32_t> wid(nsl, 0);
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+        int32_t w = 0;
+        for (int64_t i = sl * SELL_C; i < std::min<int64_t>(S.n, (sl + 1) * SELL_C); ++i)
+            w = std::max<int32_t>(w, int32_t(S.rowptr[i + 1] - S.rowptr[i]));
+        wid[sl] = w;
+        off[sl + 1] = off[sl] + int64_t(w) * SELL_C;
+    }
+    std::vector<double> sv(off[nsl], 0.0);
+    for (int64_t i = 0; i < S.n; ++i) {
+        const int64_t base = off[i / SELL_C] + i % SELL_C;
+        int j = 0;
+        for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p, ++j) sv[base + int64_t(j) * SELL_C] = S.val[p];
+    }
+    if (off_out) *off_out = std::move(off);
+    if (wid_out) *wid_out = std::move(wid);
+    return sv;
+}
+
 // ---------------------------------------------------------------------------
 static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
@@ -209,25 +283,15 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         std::vector<int32_t> tp(S.t_ptr.begin(), S.t_ptr.end());
         D.t_ptr = D.upload(tp, s);
         // sliced ELL copy of A
-        const int64_t nsl = (S.n + SELL_C - 1) / SELL_C;
-        std::vector<int64_t> off(nsl + 1, 0);
-        std::vector<int32_t> wid(nsl, 0);
-        for (int64_t sl = 0; sl < nsl; ++sl) {
-            int32_t w = 0;
-            for (int64_t i = sl * SELL_C; i < std::min<int64_t>(S.n, (sl + 1) * SELL_C); ++i)
-                w = std::max<int32_t>(w, int32_t(S.rowptr[i + 1] - S.rowptr[i]));
-            wid[sl] = w;
-            off[sl + 1] = off[sl] + int64_t(w) * SELL_C;
-        }
-        std::vector<double> sv(off[nsl], 0.0);
+        std::vector<int64_t> off;
+        std::vector<int32_t> wid;
+        std::vector<double> sv = sell_values(S, &off, &wid);
+        const int64_t nsl = int64_t(wid.size());
         std::vector<int32_t> sc(off[nsl], 0);
         for (int64_t i = 0; i < S.n; ++i) {
             const int64_t base = off[i / SELL_C] + i % SELL_C;
             int j = 0;
-            for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p, ++j) {
-                sv[base + int64_t(j) * SELL_C] = S.val[p];
-                sc[base + int64_t(j) * SELL_C] = S.col[p];
-            }
+            for (int64_t p = S.rowptr[i]; p < S.rowptr[i + 1]; ++p, ++j) sc[base + int64_t(j) * SELL_C] = S.col[p];
             for (; j < wid[i / SELL_C]; ++j) sc[base + int64_t(j) * SELL_C] = int32_t(i);
         }
         D.sell.off = D.upload(off, s);
@@ -311,14 +375,16 @@ static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *
     Device &D = *h->dev;
     const bool small = S.KL <= ILU_KL && S.KU <= ILU_KU;
     const int KL = small ? ILU_KL : std::max(S.KL, 1), KU = small ? ILU_KU : std::max(S.KU, 1);
-    D.KLp = KL;
-    D.KUp = KU;
-    D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows);
-    D.Uv = D.alloc<VT>(int64_t(KU) * S.ell_rows);
-    D.dinv = D.alloc<VT>(S.ell_rows);
-    D.Lc = D.alloc<uint16_t>(int64_t(KL) * S.ell_rows);
-    D.Uc = D.alloc<uint16_t>(int64_t(KU) * S.ell_rows);
-    if (small) D.Cp = D.alloc<uint32_t>(int64_t(ILU_CW) * S.ell_rows);
+    if (!D.Lv) {   // (a numeric re-setup writes into the same buffers)
+        D.KLp = KL;
+        D.KUp = KU;
+        D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows);
+        D.Uv = D.alloc<VT>(int64_t(KU) * S.ell_rows);
+        D.dinv = D.alloc<VT>(S.ell_rows);
+        D.Lc = D.alloc<uint16_t>(int64_t(KL) * S.ell_rows);
+        D.Uc = D.alloc<uint16_t>(int64_t(KU) * S.ell_rows);
+        if (small) D.Cp = D.alloc<uint32_t>(int64_t(ILU_CW) * S.ell_rows);
+    }
     int64_t maxpad = 0;
     for (int i = 0; i < S.np; ++i) maxpad = std::max(maxpad, S.ell_off[i + 1] - S.ell_off[i]);
     dim3 grid(nblocks(maxpad, 256), S.np);
@@ -345,7 +411,7 @@ static void check_status(Device &D, int *d_status, int count, hipStream_t s, con
 // subdomains need: bit 0 the substitution one, bit 1 the inverse one.
 static int invert_diagonal_blocks(Device &D, double *band, const int64_t *off, const int32_t *bw, const int64_t *rptr,
                                   const std::vector<int64_t> &rows_h, const std::vector<int32_t> &bw_h, int np,
-                                  hipStream_t s) {
+                                  int tag, hipStream_t s) {
     std::vector<int64_t> bp(size_t(np) + 1, 0);
     int kinds = 0;
     for (int i = 0; i < np; ++i) {
@@ -357,44 +423,48 @@ static int invert_diagonal_blocks(Device &D, double *band, const int64_t *off, c
     if (bp[np] == 0) return kinds;
     const size_t lds = sizeof(double) * 2 * BS_NB * (BS_NB + 1);
     if (lds > D.max_lds) throw DevError{GDSW_ERR_INTERNAL, "LDS too small for the diagonal-block inverses"};
-    int64_t *d_bp = D.upload(bp, s);
+    int64_t *d_bp = D.setup_scratch<int64_t>(tag, int64_t(bp.size()));
+    HIPCHK(hipMemcpyAsync(d_bp, bp.data(), sizeof(int64_t) * bp.size(), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_band_invert_diag, dim3(unsigned(bp[np])), dim3(64), lds, s, band, off, bw, rptr, d_bp, np);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    D.release(d_bp, sizeof(int64_t) * bp.size());
+    D.setup_release(d_bp, sizeof(int64_t) * bp.size());
     return kinds;
 }
 
+// Local factors (ILU(k) in the sweep layout, or band Cholesky factors with
+// inverted diagonal blocks) from the current values of A.  Allocates the
+// factor buffers on the first call; a numeric re-setup overwrites them.
 static void factor_local(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const int prec = S.opt.local_prec;
     const bool scaled = prec != GDSW_FP64;
     if (scaled) {
-        D.dscale = D.alloc<double>(S.n);
+        if (!D.dscale) D.dscale = D.alloc<double>(S.n);
         hipLaunchKernelGGL(k_diag_scale, dim3(nblocks(S.n, 256)), dim3(256), 0, s, D.val, D.adiag, D.dscale, S.n);
     }
-    int *d_status = D.alloc<int>(S.np);
+    int *d_status = D.setup_scratch<int>(ST_STATUS, S.np);
     HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
     if (S.opt.local == GDSW_LOCAL_ILU0) {
-        int64_t *d_lrowptr = D.upload(S.lrowptr, s);
-        int32_t *d_lcol = D.upload(S.lcol, s);
-        int64_t *d_lgpos = D.upload(S.lgpos, s);
-        int32_t *d_ldiag = D.upload(S.ldiag, s);
-        int64_t *d_lvl_base = D.upload(S.lvl_base, s);
-        int32_t *d_lvl_ptr = D.upload(S.lvl_ptr, s);
-        int32_t *d_lvl_rows = D.upload(S.lvl_rows, s);
-        D.ell_off = D.upload(S.ell_off, s);
+        int64_t *d_lrowptr = D.setup_upload(S.lrowptr, s);
+        int32_t *d_lcol = D.setup_upload(S.lcol, s);
+        int64_t *d_lgpos = D.setup_upload(S.lgpos, s);
+        int32_t *d_ldiag = D.setup_upload(S.ldiag, s);
+        int64_t *d_lvl_base = D.setup_upload(S.lvl_base, s);
+        int32_t *d_lvl_ptr = D.setup_upload(S.lvl_ptr, s);
+        int32_t *d_lvl_rows = D.setup_upload(S.lvl_rows, s);
+        if (!D.ell_off) D.ell_off = D.upload(S.ell_off, s);
         const int64_t ne = int64_t(S.lcol.size());
-        double *d_lval = D.alloc<double>(ne);
+        double *d_lval = D.setup_scratch<double>(ST_LVAL, ne);
         hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_lgpos,
                            (const int64_t *)nullptr, d_lval, ne, D.dscale, D.arow, D.col);
         if (S.opt.ilu_factor_sweeps > 0) {
             // FastILU: sweeps over the factor entries from the start l = a/a_jj, u = a
-            double *d_a = D.alloc<double>(ne), *d_v = D.alloc<double>(ne);
-            int64_t *d_fptr = D.upload(S.fi_ptr, s);
-            int32_t *d_pairs = D.upload(S.fi_pairs, s);
-            int32_t *d_dpos = D.upload(S.fi_dpos, s);
+            double *d_a = D.setup_scratch<double>(ST_FI_A, ne), *d_v = D.setup_scratch<double>(ST_FI_V, ne);
+            int64_t *d_fptr = D.setup_upload(S.fi_ptr, s);
+            int32_t *d_pairs = D.setup_upload(S.fi_pairs, s);
+            int32_t *d_dpos = D.setup_upload(S.fi_dpos, s);
             HIPCHK(hipMemcpyAsync(d_a, d_lval, sizeof(double) * size_t(ne), hipMemcpyDeviceToDevice, s));
             hipLaunchKernelGGL(k_fastilu_start, dim3(nblocks(ne, 256)), dim3(256), 0, s, d_a, d_dpos, d_lval, ne);
             double *cur = d_lval, *nxt = d_v;
@@ -409,11 +479,11 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
                                d_status);
             HIPCHK(hipGetLastError());
             check_status(D, d_status, S.np, s, "FastILU");
-            D.release(d_a, sizeof(double) * ne);
-            D.release(d_v, sizeof(double) * ne);
-            D.release(d_fptr, sizeof(int64_t) * S.fi_ptr.size());
-            D.release(d_pairs, sizeof(int32_t) * S.fi_pairs.size());
-            D.release(d_dpos, sizeof(int32_t) * S.fi_dpos.size());
+            D.setup_release(d_a, sizeof(double) * ne);
+            D.setup_release(d_v, sizeof(double) * ne);
+            D.setup_release(d_fptr, sizeof(int64_t) * S.fi_ptr.size());
+            D.setup_release(d_pairs, sizeof(int32_t) * S.fi_pairs.size());
+            D.setup_release(d_dpos, sizeof(int32_t) * S.fi_dpos.size());
         } else {
             hipLaunchKernelGGL(k_ilu0_factor, dim3(S.np), dim3(256), 0, s, D.ov_ptr, d_lrowptr, d_lcol, d_ldiag,
                                d_lvl_base, d_lvl_ptr, d_lvl_rows, d_lval, d_status);
@@ -430,29 +500,32 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
         // register-resident kernel does not cover) keep them in global memory
         {
             const size_t asz = prec == GDSW_FP64 ? 8 : 4;
-            if (3 * asz * size_t(S.max_ni) > D.max_lds)
+            if (3 * asz * size_t(S.max_ni) > D.max_lds && !D.sweep_buf)
                 D.sweep_buf = D.raw_alloc(3 * asz * size_t(S.ov_ptr[S.np]));
         }
         HIPCHK(hipStreamSynchronize(s));
-        D.release(d_lval, sizeof(double) * ne);
-        D.release(d_lrowptr, sizeof(int64_t) * S.lrowptr.size());
-        D.release(d_lcol, sizeof(int32_t) * S.lcol.size());
-        D.release(d_lgpos, sizeof(int64_t) * S.lgpos.size());
-        D.release(d_ldiag, sizeof(int32_t) * S.ldiag.size());
-        D.release(d_lvl_base, sizeof(int64_t) * S.lvl_base.size());
-        D.release(d_lvl_ptr, sizeof(int32_t) * S.lvl_ptr.size());
-        D.release(d_lvl_rows, sizeof(int32_t) * S.lvl_rows.size());
+        D.setup_release(d_lval, sizeof(double) * ne);
+        D.setup_release(d_lrowptr, sizeof(int64_t) * S.lrowptr.size());
+        D.setup_release(d_lcol, sizeof(int32_t) * S.lcol.size());
+        D.setup_release(d_lgpos, sizeof(int64_t) * S.lgpos.size());
+        D.setup_release(d_ldiag, sizeof(int32_t) * S.ldiag.size());
+        D.setup_release(d_lvl_base, sizeof(int64_t) * S.lvl_base.size());
+        D.setup_release(d_lvl_ptr, sizeof(int32_t) * S.lvl_ptr.size());
+        D.setup_release(d_lvl_rows, sizeof(int32_t) * S.lvl_rows.size());
     } else {
         const int64_t nb = S.band_off[S.np];
-        double *band64 = D.alloc<double>(nb);
+        // FP64 factors are the band itself; reduced precision casts a
+        // scratch FP64 band into it
+        double *band64 = prec == GDSW_FP64 ? static_cast<double *>(D.band) : D.setup_scratch<double>(ST_BAND64, nb);
+        if (!band64) band64 = static_cast<double *>(D.band = D.alloc<double>(nb));
         HIPCHK(hipMemsetAsync(band64, 0, sizeof(double) * size_t(nb), s));
-        int64_t *d_src = D.upload(S.bscat_src, s);
-        int64_t *d_dst = D.upload(S.bscat_dst, s);
+        int64_t *d_src = D.setup_upload(S.bscat_src, s);
+        int64_t *d_dst = D.setup_upload(S.bscat_dst, s);
         const int64_t ne = int64_t(S.bscat_src.size());
         hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_src, d_dst,
                            band64, ne, D.dscale, D.arow, D.col);
-        D.band_off = D.upload(S.band_off, s);
-        D.bw = D.upload(S.bw, s);
+        if (!D.band_off) D.band_off = D.upload(S.band_off, s);
+        if (!D.bw) D.bw = D.upload(S.bw, s);
         const size_t lds = sizeof(double) * (CH_NB * CH_LD + CH_NB + size_t(std::max(S.max_bw, 1)) * CH_LD);
         if (lds > D.max_lds)
             throw DevError{GDSW_ERR_INVALID_ARG, "local bandwidth too large for the banded Cholesky"};
@@ -460,28 +533,31 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
                            d_status);
         HIPCHK(hipGetLastError());
         check_status(D, d_status, S.np, s, "banded Cholesky");
-        D.band_kinds = invert_diagonal_blocks(D, band64, D.band_off, D.bw, D.ov_ptr, S.ov_ptr, S.bw, S.np, s);
-        D.release(d_src, sizeof(int64_t) * S.bscat_src.size());
-        D.release(d_dst, sizeof(int64_t) * S.bscat_dst.size());
-        if (prec == GDSW_FP64) {
-            D.band = band64;
-        } else {
-            void *bl = D.raw_alloc(prec_size(prec) * size_t(nb));
+        D.band_kinds = invert_diagonal_blocks(D, band64, D.band_off, D.bw, D.ov_ptr, S.ov_ptr, S.bw, S.np,
+                                              ST_BP_LOCAL, s);
+        D.setup_release(d_src, sizeof(int64_t) * S.bscat_src.size());
+        D.setup_release(d_dst, sizeof(int64_t) * S.bscat_dst.size());
+        if (prec != GDSW_FP64) {
+            if (!D.band) D.band = D.raw_alloc(prec_size(prec) * size_t(nb));
+            void *bl = D.band;
             const int gb = nblocks(nb, 256, 65536);
             if (prec == GDSW_FP32) hipLaunchKernelGGL(k_cast<float>, dim3(gb), dim3(256), 0, s, band64, (float *)bl, nb);
             else if (prec == GDSW_BF16) hipLaunchKernelGGL(k_cast<bf16>, dim3(gb), dim3(256), 0, s, band64, (bf16 *)bl, nb);
             else hipLaunchKernelGGL(k_cast<fp16>, dim3(gb), dim3(256), 0, s, band64, (fp16 *)bl, nb);
             HIPCHK(hipStreamSynchronize(s));
-            D.release(band64, sizeof(double) * size_t(nb));
-            D.band = bl;
+            D.setup_release(band64, sizeof(double) * size_t(nb));
         }
         D.local_entries = nb;
     }
     HIPCHK(hipStreamSynchronize(s));
-    D.release(d_status, sizeof(int) * S.np);
+    D.setup_release(d_status, sizeof(int) * S.np);
 }
 
-static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
+// Layout of the coarse part, built once per handle: block maps, restriction
+// tiles and work items, reduction lists, the coarse vectors, and the buffers
+// of Phi and A_0; the interface blocks of Phi (orthonormal null-space bases,
+// independent of the matrix values) are copied in here.
+static void coarse_layout(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const PhiBlocks &B = S.blk;
@@ -575,59 +651,82 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
     D.phi = D.alloc<double>(nphi);
     D.phi_entries = nphi;
     // interface blocks: the orthonormal bases from the analysis
-    std::vector<int32_t> sub_blk(S.np, -1);
-    for (int g = 0; g < B.nb; ++g) {
-        if (B.kind[g] == 0) {
-            sub_blk[B.owner[g]] = g;
-        } else {
+    for (int g = 0; g < B.nb; ++g)
+        if (B.kind[g] != 0) {
             const int c = B.owner[g];
             HIPCHK(hipMemcpyAsync(D.phi + B.val_off[g], S.phig.data() + S.phig_off[c],
                                   sizeof(double) * size_t(S.phig_off[c + 1] - S.phig_off[c]),
                                   hipMemcpyHostToDevice, s));
         }
+    D.A0 = D.alloc<double>(S.a0_off[S.nprob]);
+    D.A0inv = D.alloc<double>(S.a0_off[S.nprob]);
+    D.cprob = D.upload(S.cprob, s);
+    D.prob_c0 = D.upload(S.prob_c0, s);
+    for (int k = 0; k < S.nprob; ++k) D.max_n0 = std::max(D.max_n0, S.prob_c0[k + 1] - S.prob_c0[k]);
+    D.a0_off = D.upload(S.a0_off, s);
+    if (S.opt.basis_prec == GDSW_FP32) D.phi32 = D.alloc<float>(nphi);
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// Numerical part of the coarse space from the current values of A: the
+// extension Phi_I = -A_II^{-1} A_IG Phi_G (eq. (2)), A_0 = Phi^T A Phi and its
+// inverse, written into the buffers of coarse_layout.
+static void coarse_numeric(gdsw_handle_s *h, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const PhiBlocks &B = S.blk;
+    if (S.opt.coarse == GDSW_COARSE_NONE || S.n0 == 0 || B.nb == 0) return;
+    const int64_t nphi = B.val_off[B.nb];
+    int32_t *d_sub_blk = nullptr;
+    {
+        std::vector<int32_t> sub_blk(S.np, -1);
+        for (int g = 0; g < B.nb; ++g)
+            if (B.kind[g] == 0) sub_blk[B.owner[g]] = g;
+        d_sub_blk = D.setup_scratch<int32_t>(ST_SUB_BLK, S.np);
+        HIPCHK(hipMemcpyAsync(d_sub_blk, sub_blk.data(), sizeof(int32_t) * size_t(S.np), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
-    double *d_phig = D.upload(S.phig, s);
-    int64_t *d_phig_off = D.upload(S.phig_off, s);
-    int32_t *d_comp_rank = D.upload(S.comp_rank, s);
-    int32_t *d_sub_blk = D.upload(sub_blk, s);
-    int64_t *d_int_ptr = D.upload(S.int_ptr, s);
-    int64_t *d_scol_ptr = D.upload(S.scol_ptr, s);
-    int64_t *d_ext_off = D.upload(S.ext_off, s);
+    double *d_phig = D.setup_upload(S.phig, s);
+    int64_t *d_phig_off = D.setup_upload(S.phig_off, s);
+    int32_t *d_comp_rank = D.setup_upload(S.comp_rank, s);
+    int64_t *d_int_ptr = D.setup_upload(S.int_ptr, s);
+    int64_t *d_scol_ptr = D.setup_upload(S.scol_ptr, s);
+    int64_t *d_ext_off = D.setup_upload(S.ext_off, s);
     // ---- extension: E_i = A_{I_i G} Phi_G, A_{I_i I_i} = L L^T, Phi_I = -A_II^{-1} E_i
     const int64_t nint = S.int_ptr[S.np];
     const int64_t next = S.ext_off[S.np];
-    double *E = D.alloc<double>(next);
+    double *E = D.setup_scratch<double>(ST_E, next);
     HIPCHK(hipMemsetAsync(E, 0, sizeof(double) * size_t(std::max<int64_t>(next, 1)), s));
     {
-        int64_t *a = D.upload(S.cpl_ptr, s);
-        int64_t *b = D.upload(S.cpl_apos, s);
-        int64_t *c = D.upload(S.cpl_phi, s);
-        int32_t *d = D.upload(S.cpl_stride, s);
-        int32_t *e = D.upload(S.cpl_rank, s);
-        int32_t *f = D.upload(S.cpl_slot, s);
-        int32_t *fm = D.upload(S.cpl_slotmap, s);
+        int64_t *a = D.setup_upload(S.cpl_ptr, s);
+        int64_t *b = D.setup_upload(S.cpl_apos, s);
+        int64_t *c = D.setup_upload(S.cpl_phi, s);
+        int32_t *d = D.setup_upload(S.cpl_stride, s);
+        int32_t *e = D.setup_upload(S.cpl_rank, s);
+        int32_t *f = D.setup_upload(S.cpl_slot, s);
+        int32_t *fm = D.setup_upload(S.cpl_slotmap, s);
         hipLaunchKernelGGL(k_ext_rhs, dim3(nblocks(nint, 256)), dim3(256), 0, s, D.val, d_int_ptr, S.np, d_ext_off,
                            a, b, c, d, e, f, fm, d_phig, E, nint);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
-        D.release(a, 8 * S.cpl_ptr.size());
-        D.release(b, 8 * S.cpl_apos.size());
-        D.release(c, 8 * S.cpl_phi.size());
-        D.release(d, 4 * S.cpl_stride.size());
-        D.release(e, 4 * S.cpl_rank.size());
-        D.release(f, 4 * S.cpl_slot.size());
-        D.release(fm, 4 * S.cpl_slotmap.size());
+        D.setup_release(a, 8 * S.cpl_ptr.size());
+        D.setup_release(b, 8 * S.cpl_apos.size());
+        D.setup_release(c, 8 * S.cpl_phi.size());
+        D.setup_release(d, 4 * S.cpl_stride.size());
+        D.setup_release(e, 4 * S.cpl_rank.size());
+        D.setup_release(f, 4 * S.cpl_slot.size());
+        D.setup_release(fm, 4 * S.cpl_slotmap.size());
     }
-    int *d_status = D.alloc<int>(std::max(S.np, 1));
+    int *d_status = D.setup_scratch<int>(ST_STATUS, std::max(S.np, 1));
     HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
     {
         const int64_t nb = S.iband_off[S.np];
-        double *iband = D.alloc<double>(nb);
+        double *iband = D.setup_scratch<double>(ST_IBAND, nb);
         HIPCHK(hipMemsetAsync(iband, 0, sizeof(double) * size_t(std::max<int64_t>(nb, 1)), s));
-        int64_t *d_src = D.upload(S.ibscat_src, s);
-        int64_t *d_dst = D.upload(S.ibscat_dst, s);
-        int64_t *d_ioff = D.upload(S.iband_off, s);
-        int32_t *d_ibw = D.upload(S.ibw, s);
+        int64_t *d_src = D.setup_upload(S.ibscat_src, s);
+        int64_t *d_dst = D.setup_upload(S.ibscat_dst, s);
+        int64_t *d_ioff = D.setup_upload(S.iband_off, s);
+        int32_t *d_ibw = D.setup_upload(S.ibw, s);
         const int64_t ne = int64_t(S.ibscat_src.size());
         hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_src, d_dst, iband,
                            ne, (const double *)nullptr, D.arow, D.col);
@@ -636,7 +735,8 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         hipLaunchKernelGGL(k_band_chol<256>, dim3(S.np), dim3(256), lds, s, iband, d_ioff, d_ibw, d_int_ptr, d_status);
         HIPCHK(hipGetLastError());
         check_status(D, d_status, S.np, s, "interior Cholesky");
-        const int ikinds = invert_diagonal_blocks(D, iband, d_ioff, d_ibw, d_int_ptr, S.int_ptr, S.ibw, S.np, s);
+        const int ikinds = invert_diagonal_blocks(D, iband, d_ioff, d_ibw, d_int_ptr, S.int_ptr, S.ibw, S.np,
+                                                  ST_BP_INT, s);
         const size_t lds2 = sizeof(double) * (size_t(std::max(S.max_nii, 1)) + BS_NB * BS_LD);
         if (lds2 > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "interior block too large for LDS"};
         if (ikinds & 2)
@@ -647,69 +747,68 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
                                d_int_ptr, d_scol_ptr, d_ext_off, E, d_sub_blk, D.blk_val_off, D.phi);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
-        D.release(iband, sizeof(double) * size_t(nb));
-        D.release(d_src, 8 * S.ibscat_src.size());
-        D.release(d_dst, 8 * S.ibscat_dst.size());
-        D.release(d_ioff, 8 * S.iband_off.size());
-        D.release(d_ibw, 4 * S.ibw.size());
+        D.setup_release(iband, sizeof(double) * size_t(nb));
+        D.setup_release(d_src, 8 * S.ibscat_src.size());
+        D.setup_release(d_dst, 8 * S.ibscat_dst.size());
+        D.setup_release(d_ioff, 8 * S.iband_off.size());
+        D.setup_release(d_ibw, 4 * S.ibw.size());
     }
     // ---- A_0 = Phi_G^T A_GG Phi_G + sum_i E_i^T Phi_{I_i}
     // A_0 is block diagonal over the independent problems: one dense block each
     const int64_t na0 = S.a0_off[S.nprob];
-    double *A0raw = D.alloc<double>(na0);
+    double *A0raw = D.A0inv;   // assembled here, then inverted in place below
     HIPCHK(hipMemsetAsync(A0raw, 0, sizeof(double) * size_t(na0), s));
     {
         const int npairs = int(S.pair_c.size());
         if (npairs) {
-            int32_t *pc = D.upload(S.pair_c, s);
-            int32_t *pd = D.upload(S.pair_d, s);
-            int64_t *po = D.upload(S.pair_off, s);
-            int64_t *pe = D.upload(S.pair_eptr, s);
-            int64_t *pa = D.upload(S.pair_apos, s);
-            int32_t *plc = D.upload(S.pair_lr_c, s);
-            int32_t *pld = D.upload(S.pair_lr_d, s);
+            int32_t *pc = D.setup_upload(S.pair_c, s);
+            int32_t *pd = D.setup_upload(S.pair_d, s);
+            int64_t *po = D.setup_upload(S.pair_off, s);
+            int64_t *pe = D.setup_upload(S.pair_eptr, s);
+            int64_t *pa = D.setup_upload(S.pair_apos, s);
+            int32_t *plc = D.setup_upload(S.pair_lr_c, s);
+            int32_t *pld = D.setup_upload(S.pair_lr_d, s);
             const int64_t total = S.pair_off[npairs];
-            double *T2 = D.alloc<double>(total);
+            double *T2 = D.setup_scratch<double>(ST_T2, total);
             hipLaunchKernelGGL(k_t2, dim3(nblocks(total, 256)), dim3(256), 0, s, D.val, npairs, pc, pd, po, pe, pa,
                                plc, pld, d_comp_rank, d_phig_off, d_phig, T2, total);
-            int64_t *st2 = D.upload(S.a0seg2_tgt, s);
-            int64_t *sp2 = D.upload(S.a0seg2_ptr, s);
-            int64_t *ss2 = D.upload(S.a0seg2_src, s);
+            int64_t *st2 = D.setup_upload(S.a0seg2_tgt, s);
+            int64_t *sp2 = D.setup_upload(S.a0seg2_ptr, s);
+            int64_t *ss2 = D.setup_upload(S.a0seg2_src, s);
             const int64_t nseg2 = int64_t(S.a0seg2_tgt.size());
             hipLaunchKernelGGL(k_a0_segments, dim3(nblocks(nseg2, 256)), dim3(256), 0, s, st2, sp2, ss2, T2, A0raw,
                                nseg2);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));
-            D.release(T2, 8 * size_t(total));
-            D.release(st2, 8 * S.a0seg2_tgt.size()); D.release(sp2, 8 * S.a0seg2_ptr.size());
-            D.release(ss2, 8 * S.a0seg2_src.size());
-            D.release(pc, 4 * S.pair_c.size()); D.release(pd, 4 * S.pair_d.size());
-            D.release(po, 8 * S.pair_off.size()); D.release(pe, 8 * S.pair_eptr.size());
-            D.release(pa, 8 * S.pair_apos.size()); D.release(plc, 4 * S.pair_lr_c.size());
-            D.release(pld, 4 * S.pair_lr_d.size());
+            D.setup_release(T2, 8 * size_t(total));
+            D.setup_release(st2, 8 * S.a0seg2_tgt.size()); D.setup_release(sp2, 8 * S.a0seg2_ptr.size());
+            D.setup_release(ss2, 8 * S.a0seg2_src.size());
+            D.setup_release(pc, 4 * S.pair_c.size()); D.setup_release(pd, 4 * S.pair_d.size());
+            D.setup_release(po, 8 * S.pair_off.size()); D.setup_release(pe, 8 * S.pair_eptr.size());
+            D.setup_release(pa, 8 * S.pair_apos.size()); D.setup_release(plc, 4 * S.pair_lr_c.size());
+            D.setup_release(pld, 4 * S.pair_lr_d.size());
         }
         const int64_t nt1 = S.t1_off[S.np];
         if (nt1) {
-            double *T1 = D.alloc<double>(nt1);
-            int64_t *d_t1off = D.upload(S.t1_off, s);
+            double *T1 = D.setup_scratch<double>(ST_T1, nt1);
+            int64_t *d_t1off = D.setup_upload(S.t1_off, s);
             int kmax = 0;
             for (int i = 0; i < S.np; ++i) kmax = std::max<int>(kmax, int(S.scol_ptr[i + 1] - S.scol_ptr[i]));
             dim3 grid(nblocks(int64_t(kmax) * kmax, 256), S.np);
             hipLaunchKernelGGL(k_t1, grid, dim3(256), 0, s, d_int_ptr, d_scol_ptr, d_ext_off, E, d_sub_blk,
                                D.blk_val_off, D.phi, d_t1off, T1);
-            int64_t *st = D.upload(S.a0seg_tgt, s);
-            int64_t *sp = D.upload(S.a0seg_ptr, s);
-            int64_t *ss = D.upload(S.a0seg_src, s);
+            int64_t *st = D.setup_upload(S.a0seg_tgt, s);
+            int64_t *sp = D.setup_upload(S.a0seg_ptr, s);
+            int64_t *ss = D.setup_upload(S.a0seg_src, s);
             const int64_t nseg = int64_t(S.a0seg_tgt.size());
             hipLaunchKernelGGL(k_a0_segments, dim3(nblocks(nseg, 256)), dim3(256), 0, s, st, sp, ss, T1, A0raw, nseg);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));
-            D.release(T1, 8 * nt1); D.release(d_t1off, 8 * S.t1_off.size());
-            D.release(st, 8 * S.a0seg_tgt.size()); D.release(sp, 8 * S.a0seg_ptr.size());
-            D.release(ss, 8 * S.a0seg_src.size());
+            D.setup_release(T1, 8 * nt1); D.setup_release(d_t1off, 8 * S.t1_off.size());
+            D.setup_release(st, 8 * S.a0seg_tgt.size()); D.setup_release(sp, 8 * S.a0seg_ptr.size());
+            D.setup_release(ss, 8 * S.a0seg_src.size());
         }
     }
-    D.A0 = D.alloc<double>(na0);
     for (int k = 0; k < S.nprob; ++k) {
         const int nk = S.prob_c0[k + 1] - S.prob_c0[k];
         if (nk == 0) continue;
@@ -717,13 +816,12 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
                            D.A0 + S.a0_off[k], nk);
     }
     // ---- A_0^{-1} by blocked Gauss-Jordan sweeps, block by block, on a copy
-    D.A0inv = A0raw;
     hipLaunchKernelGGL(k_copy, dim3(nblocks(na0, 256, 65536)), dim3(256), 0, s, D.A0, D.A0inv, na0);
     {
         int nmax = 0;
         for (int k = 0; k < S.nprob; ++k) nmax = std::max(nmax, S.prob_c0[k + 1] - S.prob_c0[k]);
-        double *P = D.alloc<double>(GJ_NB * GJ_NB);
-        double *W = D.alloc<double>(int64_t(nmax) * GJ_NB);
+        double *P = D.setup_scratch<double>(ST_GJ_P, GJ_NB * GJ_NB);
+        double *W = D.setup_scratch<double>(ST_GJ_W, int64_t(nmax) * GJ_NB);
         HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int) * S.np, s));
         for (int k = 0; k < S.nprob; ++k) {
             const int nk = S.prob_c0[k + 1] - S.prob_c0[k];
@@ -740,27 +838,22 @@ static void factor_coarse(gdsw_handle_s *h, hipStream_t s) {
         hipLaunchKernelGGL(k_negate, dim3(nblocks(na0, 256, 65536)), dim3(256), 0, s, D.A0inv, na0);
         HIPCHK(hipGetLastError());
         check_status(D, d_status, std::min(S.np, S.nprob), s, "coarse matrix inverse");
-        D.release(P, 8 * GJ_NB * GJ_NB);
-        D.release(W, 8 * size_t(nmax) * GJ_NB);
+        D.setup_release(P, 8 * GJ_NB * GJ_NB);
+        D.setup_release(W, 8 * size_t(nmax) * GJ_NB);
     }
-    D.cprob = D.upload(S.cprob, s);
-    D.prob_c0 = D.upload(S.prob_c0, s);
-    for (int k = 0; k < S.nprob; ++k) D.max_n0 = std::max(D.max_n0, S.prob_c0[k + 1] - S.prob_c0[k]);
-    D.a0_off = D.upload(S.a0_off, s);
-    if (S.opt.basis_prec == GDSW_FP32) {
-        D.phi32 = D.alloc<float>(nphi);
+    if (D.phi32) {
         hipLaunchKernelGGL(k_cast<float>, dim3(nblocks(nphi, 256, 65536)), dim3(256), 0, s, D.phi, D.phi32, nphi);
     }
     HIPCHK(hipStreamSynchronize(s));
-    D.release(E, 8 * std::max<int64_t>(next, 1));
-    D.release(d_phig, 8 * S.phig.size());
-    D.release(d_phig_off, 8 * S.phig_off.size());
-    D.release(d_comp_rank, 4 * S.comp_rank.size());
-    D.release(d_sub_blk, 4 * sub_blk.size());
-    D.release(d_int_ptr, 8 * S.int_ptr.size());
-    D.release(d_scol_ptr, 8 * S.scol_ptr.size());
-    D.release(d_ext_off, 8 * S.ext_off.size());
-    D.release(d_status, 4 * std::max(S.np, 1));
+    D.setup_release(E, 8 * std::max<int64_t>(next, 1));
+    D.setup_release(d_phig, 8 * S.phig.size());
+    D.setup_release(d_phig_off, 8 * S.phig_off.size());
+    D.setup_release(d_comp_rank, 4 * S.comp_rank.size());
+    D.setup_release(d_sub_blk, 4 * size_t(S.np));
+    D.setup_release(d_int_ptr, 8 * S.int_ptr.size());
+    D.setup_release(d_scol_ptr, 8 * S.scol_ptr.size());
+    D.setup_release(d_ext_off, 8 * S.ext_off.size());
+    D.setup_release(d_status, 4 * std::max(S.np, 1));
 }
 
 gdsw_status factor(gdsw_handle_s *h, void *stream) {
@@ -784,7 +877,8 @@ gdsw_status factor(gdsw_handle_s *h, void *stream) {
         }
         upload_all(h, s);
         factor_local(h, s);
-        factor_coarse(h, s);
+        coarse_layout(h, s);
+        coarse_numeric(h, s);
         HIPCHK(hipStreamSynchronize(s));
     } catch (const DevError &e) {
         h->err = e.msg;
@@ -800,6 +894,15 @@ gdsw_status factor(gdsw_handle_s *h, void *stream) {
     return GDSW_OK;
 }
 
+// Numeric re-setup (Sec. V-A: the numerical phase repeated on new values of
+// the same pattern).  The symbolic analysis, every device map, the buffers
+// of the factors, Phi, A_0^{-1} and the Krylov vectors (same addresses, so
+// captured graphs stay valid), the tuned launch configurations and the
+// captured CG graphs are kept; only the values of A (CSR and sliced ELL
+// copies), the local factors, the extension Phi_I, A_0 and its inverse are
+// recomputed.  The setup's own maps and scratch stay resident from the first
+// re-setup on, so later ones upload and allocate nothing.  On an error the
+// handle is left unfactored (a later refactor or factor starts afresh).
 gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
     if (!val) return GDSW_ERR_INVALID_ARG;
     for (int64_t p = 0; p < h->sym.nnz; ++p)
@@ -808,7 +911,34 @@ gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
             return GDSW_ERR_INVALID_ARG;
         }
     h->sym.val.assign(val, val + h->sym.nnz);
-    return factor(h, stream);
+    if (!h->factored || !h->dev) return factor(h, stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto t0 = std::chrono::steady_clock::now();
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    try {
+        D.keep_setup = true;
+        HIPCHK(hipMemcpyAsync(D.val, S.val.data(), sizeof(double) * size_t(S.nnz), hipMemcpyHostToDevice, s));
+        {
+            const std::vector<double> sv = sell_values(S);
+            HIPCHK(hipMemcpyAsync(const_cast<double *>(D.sell.val), sv.data(), sizeof(double) * sv.size(),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));   // sv goes out of scope
+        }
+        factor_local(h, s);
+        coarse_numeric(h, s);
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        h->factored = false;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed";
+        h->factored = false;
+        return GDSW_ERR_BUDGET;
+    }
+    h->t_refactor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return GDSW_OK;
 }
 
 // ---------------------------------------------------------------------------

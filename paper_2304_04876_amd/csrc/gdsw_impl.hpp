@@ -157,6 +157,7 @@ struct gdsw_handle_s {
     bool analyzed = false;
     bool factored = false;
     double t_factor = 0.0;
+    double t_refactor = 0.0;   // last numeric re-setup
 };
 
 namespace gdsw {

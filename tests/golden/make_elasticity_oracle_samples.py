@@ -10,6 +10,11 @@ Calls only the oracle and the seeded input generators.  Stored:
   a0_diag   diagonal of A0
   gm_iters  right-preconditioned GMRES(30) iterations to 1e-8
   x_gm      the GMRES solution at idx
+  x_fixed   the GMRES(30) iterate after exactly gm_iters iterations at idx
+            (modified Gram-Schmidt Arnoldi), and its 2-norm x_fixed_norm
+  sr_iters, x_fixed_sr
+            the single-reduce GMRES(30): iterations to 1e-8 and the iterate
+            after exactly sr_iters iterations at idx
 """
 import os
 import sys
@@ -37,10 +42,15 @@ def main():
     t = time.time()
     res = O.gmres(pr.A, pr.b, M, rtol=1e-8, restart=30)
     print("gmres", res.iters, time.time() - t, flush=True)
+    fx = O.gmres(pr.A, pr.b, M, restart=30, fixed_iters=res.iters)
+    sr = O.gmres_single_reduce(pr.A, pr.b, M, rtol=1e-8, restart=30)
+    fsr = O.gmres_single_reduce(pr.A, pr.b, M, restart=30, fixed_iters=sr.iters)
+    print("single-reduce gmres", sr.iters, flush=True)
     name = "elasticity_oracle.npz" if coarse == "gdsw" else f"elasticity_{coarse}_oracle.npz"
     np.savez_compressed(os.path.join(HERE, name), idx=idx, z=z[idx], z_norm=np.abs(z).max(),
                         n0=M.A0.shape[0], a0_diag=np.diag(M.A0).copy(), gm_iters=res.iters, x_gm=res.x[idx],
-                        x_norm=np.abs(res.x).max())
+                        x_norm=np.abs(res.x).max(), x_fixed=fx.x[idx], x_fixed_norm=np.abs(fx.x).max(),
+                        sr_iters=sr.iters, x_fixed_sr=fsr.x[idx])
 
 
 if __name__ == "__main__":

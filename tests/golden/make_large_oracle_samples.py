@@ -1,6 +1,8 @@
 """Writes large_poisson_oracle.npz: the FP64 oracle's results on the 128^3
 Poisson workload with 512 boxes (ILU(0) local solves with 5+5 Jacobi sweeps,
-GDSW coarse space), sampled, for the full-size GPU parity test.
+GDSW coarse space), sampled, for the full-size GPU parity test; with the
+argument `exact`, large_poisson_exact_oracle.npz: the same with exact local
+solves (same sample indices and fields, z_exact in place of z_ilu0).
 
 Calls only the oracle and the seeded input generators.  Stored:
   idx       4096 sampled dof indices (fixed seed 7)
@@ -24,9 +26,10 @@ from oracle import gdsw_oracle as O  # noqa: E402
 
 
 def main():
+    local = sys.argv[1] if len(sys.argv) > 1 else "ilu0"
     pr = P.workload_poisson_large()
     t = time.time()
-    M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local="ilu0", sweeps=5)
+    M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local=local, sweeps=5)
     print("oracle setup", time.time() - t, flush=True)
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(pr.n, 4096, replace=False))
@@ -42,7 +45,8 @@ def main():
     n0 = M.A0.shape[0]
     ar = rng.integers(0, n0, 2000)
     ac = rng.integers(0, n0, 2000)
-    np.savez_compressed(os.path.join(HERE, "large_poisson_oracle.npz"), idx=idx, z_ilu0=z[idx], zc=zc[idx],
+    name = "large_poisson_oracle.npz" if local == "ilu0" else f"large_poisson_{local}_oracle.npz"
+    np.savez_compressed(os.path.join(HERE, name), idx=idx, **{f"z_{local}": z[idx]}, zc=zc[idx],
                         cg_iters=np.array(its), x_fixed=fx.x[idx], a0_diag=np.diag(M.A0).copy(),
                         a0_rows=ar, a0_cols=ac, a0_vals=M.A0[ar, ac], z_norm=np.abs(z).max(),
                         x_norm=np.linalg.norm(fx.x))

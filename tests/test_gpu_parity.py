@@ -9,9 +9,12 @@ Tolerances (FP64 throughout unless stated):
   well-conditioned operator (condition numbers below 1e4 here).
 * coarse basis and coarse matrix: 1e-12 relative to their largest entry.
 * CG: iteration counts within +-1; iterates after the same fixed number of
-  iterations within 1e-10 relative (2-norm), or, where CG's growth of
-  rounding differences is larger than that (ILU(0)-Jacobi), within 10% of
-  the distance of the oracle's iterate to the exact solution.
+  iterations within 1e-10 relative (2-norm) wherever the oracle's own
+  iterate is determined that closely.  With ILU(0)-Jacobi local solves on
+  the 20^3 workload the oracle's iterate past iteration 25 moves by up to
+  1e-10..1e-8 under rounding-level changes of the operator
+  (tests/test_oracle_cg_sensitivity.py); there the bound is ten times that
+  spread, measured for the same right-hand side.
 * reduced-precision local factors: the iteration count stays within a few
   of FP64 and the final error is bounded by kappa-style growth of the
   tolerance (checked against a direct solve).
@@ -140,6 +143,26 @@ def test_coarse_basis_and_matrix(case):
     g.close()
 
 
+def _perturbed_spread(A, b, M, k, eps, seeds=(100, 101, 102)):
+    """Largest relative distance between the oracle's k-th CG iterate and the
+    same iterate with every apply multiplied entry-wise by 1 + eps u, u
+    seeded uniform(-1, 1) (the rounding noise of the oracle's own iterate;
+    tests/test_oracle_cg_sensitivity.py)."""
+    x = O.pcg(A, b, M, fixed_iters=k).x
+    worst = 0.0
+    for s in seeds:
+        rng = np.random.default_rng(s)
+
+        class Pert:
+            def apply(self, r):
+                z = M.apply(r)
+                return z * (1.0 + eps * rng.uniform(-1.0, 1.0, z.size))
+
+        y = O.pcg(A, b, Pert(), fixed_iters=k).x
+        worst = max(worst, float(np.linalg.norm(y - x) / np.linalg.norm(x)))
+    return worst
+
+
 @pytest.mark.parametrize("local", ["exact", "ilu0"])
 def test_cg_matches_oracle_small_workload(local):
     pr = P.workload_poisson_small()
@@ -154,19 +177,34 @@ def test_cg_matches_oracle_small_workload(local):
         out = g.solve(bd, xd, rtol=1e-8)
         assert abs(out["iterations"] - ref.iters) <= 1, (out, ref.iters)
         assert out["converged"] and out["rel_res_true"] <= 2e-8
-        k = ref.iters
-        fx = O.pcg(pr.A, b, M, fixed_iters=k)
-        g.solve(bd, xd, fixed_iters=k)
-        x = host(xd)
-        # CG amplifies rounding differences of the operator over the
-        # iterations, strongly so with ILU(0)-Jacobi local solves (on the CPU
-        # a random relative perturbation of 1e-16 in every apply moves the
-        # 43rd iterate by 1.5e-9, against 6e-15 with exact local solves); the
-        # two iterates must agree far more closely than either agrees with
-        # the exact solution
-        xs = spla.spsolve(pr.A.tocsc(), b)
-        bound = max(1e-10 * np.linalg.norm(fx.x), 0.1 * np.linalg.norm(fx.x - xs))
-        assert np.linalg.norm(x - fx.x) <= bound
+        # the apply difference that the iterates below start from
+        zd = torch.zeros_like(bd)
+        g.apply(bd, zd)
+        d_apply = rel_max(host(zd), M.apply(b))
+        # FP64 parity of the iterates at 1e-10 where the oracle's own iterate
+        # is determined that closely: every iteration with exact local
+        # solves; with ILU(0)-Jacobi up to iteration 25, after which the
+        # oracle's iterate itself moves by 1e-10 under rounding-level
+        # changes of the operator (tests/test_oracle_cg_sensitivity.py)
+        ks = [ref.iters] if local == "exact" else [15, 25]
+        for k in ks:
+            fx = O.pcg(pr.A, b, M, fixed_iters=k)
+            g.solve(bd, xd, fixed_iters=k)
+            err = float(np.linalg.norm(host(xd) - fx.x) / np.linalg.norm(fx.x))
+            say(f"  seed {seed} k {k}: iterate diff {err:.2e} (apply diff {d_apply:.1e})")
+            assert err <= 1e-10
+        if local == "ilu0":
+            # at the converged count: within ten times the oracle's own
+            # spread under per-apply perturbations of 1e-15 (above the
+            # measured apply difference d_apply)
+            assert d_apply <= 1e-15
+            k = ref.iters
+            spread = _perturbed_spread(pr.A, b, M, k, 1e-15)
+            fx = O.pcg(pr.A, b, M, fixed_iters=k)
+            g.solve(bd, xd, fixed_iters=k)
+            err = float(np.linalg.norm(host(xd) - fx.x) / np.linalg.norm(fx.x))
+            say(f"  seed {seed} k {k}: iterate diff {err:.2e}, oracle spread {spread:.2e}")
+            assert err <= 10.0 * spread
     g.close()
 
 
@@ -298,18 +336,61 @@ def test_autotune_keeps_results(local, prec):
     g.close()
 
 
-def test_refactor_with_new_values():
-    pr = P.poisson3d(12, 3)
-    say("[refactor]")
-    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0)
-    r = dev(P.rhs_uniform(pr.n, 1))
-    z1 = torch.zeros_like(r)
-    g.apply(r, z1)
-    B.gdsw_refactor(g.h, 2.0 * pr.A.tocsr().data)
-    z2 = torch.zeros_like(r)
-    g.apply(r, z2)
-    # M^{-1} of 2A is half of M^{-1} of A (every step is linear in A's scale)
-    assert float((z2 - 0.5 * z1).abs().max()) <= 1e-13 * float(z1.abs().max())
+@pytest.mark.parametrize("local", ["exact", "ilu0"])
+def test_refactor_new_coefficients_matches_fresh_oracle(local):
+    """Numeric re-setup to different coefficients on the same pattern
+    (diffusion kappa -> kappa', which changes the extension Phi_I and A_0):
+    the apply, its coarse term and a CG solve match a fresh oracle of the new
+    matrix; the tuned launch configuration, the buffers (device bytes after
+    the first re-setup) and a captured CG graph are kept; a re-setup to
+    values with a zero row (a zero pivot) reports SINGULAR and leaves the handle
+    unfactored until a good re-setup."""
+    N, Pn = 14, 3
+    k1 = np.exp(np.random.default_rng(71).standard_normal((N + 1) ** 3))
+    k2 = np.exp(2.0 * np.random.default_rng(72).standard_normal((N + 1) ** 3))
+    p1, p2 = P.diffusion3d(N, k1, Pn), P.diffusion3d(N, k2, Pn)
+    assert np.array_equal(p1.A.indptr, p2.A.indptr) and np.array_equal(p1.A.indices, p2.A.indices)
+    say(f"[refactor] diffusion {N}^3 local={local}")
+    lo = 0 if local == "exact" else 1
+    g = B.Gdsw(p1.A, p1.part, p1.n_parts, 1, local=lo, flags=B.FLAG_GRAPHS)
+    B.gdsw_set_launch(g.h, local_variant=0 if local == "exact" else 2, gemv_variant=1, apply_streams=2)
+    b = dev(P.rhs_uniform(p1.n, 3))
+    x = torch.zeros_like(b)
+    g.solve(b, x, rtol=1e-8)          # captures the CG graphs on the old values
+    M2 = O.GDSW(p2.A, p2.part, 1, p2.n_parts, local=local)
+    z = torch.zeros_like(b)
+    for rep in range(2):
+        B.gdsw_refactor(g.h, p2.A.tocsr().data)
+        inf = g.info()
+        assert (inf["local_variant"], inf["gemv_variant"], inf["apply_streams"]) == (0 if local == "exact" else 2, 1, 2)
+        assert inf["t_refactor"] > 0
+        if rep == 0:
+            bytes_after_first = inf["device_bytes"]
+        else:
+            assert inf["device_bytes"] == bytes_after_first
+        g.apply(b, z)
+        zr = M2.apply(host(b))
+        assert rel_max(host(z), zr) <= 1e-12
+        g.apply_part(b, z, 2)
+        assert rel_max(host(z), M2.coarse_apply(host(b))) <= 1e-12
+        ref = O.pcg(p2.A, host(b), M2, rtol=1e-8)
+        out = g.solve(b, x, rtol=1e-8)
+        assert abs(out["iterations"] - ref.iters) <= 1, (out, ref.iters)
+        assert out["converged"] and out["rel_res_true"] <= 2e-8
+    # the old coefficients' operator is gone: it differs from the new one
+    M1 = O.GDSW(p1.A, p1.part, 1, p1.n_parts, local=local)
+    assert rel_max(M1.apply(host(b)), zr) > 1e-3
+    # a failing re-setup, then a good one
+    bad = p2.A.tocsr().copy()
+    bad.data[bad.indptr[5]:bad.indptr[6]] = 0.0
+    with pytest.raises(B.GdswError) as ei:
+        B.gdsw_refactor(g.h, bad.data)
+    assert ei.value.status == 2
+    with pytest.raises(B.GdswError):
+        g.apply(b, z)
+    B.gdsw_refactor(g.h, p1.A.tocsr().data)
+    g.apply(b, z)
+    assert rel_max(host(z), M1.apply(host(b))) <= 1e-12
     g.close()
 
 
