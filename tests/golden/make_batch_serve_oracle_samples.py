@@ -14,7 +14,8 @@ ones padded with -1 / 0):
   batch_z[j]        (M^{-1} b_k)[idx], b_k the problem's right-hand side
   batch_z_norm[j]   max |M^{-1} b_k|
   batch_iters[j]    CG iterations to 1e-8
-  batch_x[j]        the CG solution at idx, batch_x_norm[j] its max-norm
+  batch_x[j]        the CG solution at idx, batch_x_norm[j] its max-norm,
+                    batch_x_norm2[j] its 2-norm
   batch_xf[j]       the CG iterate after exactly batch_iters[j] iterations
 
 Serving (Poisson operators N = 32, 59, 96 with P = round(N/16); ILU(0) local
@@ -22,7 +23,7 @@ solves with 5+5 Jacobi sweeps in FP64, GDSW): one request each, right-hand
 side rhs_uniform(n, rid) with rid = 1000, 1001, 1002:
   serve_N[j], serve_rid[j], serve_idx[j] (512 samples, seed 200 + j),
   serve_iters[j], serve_x[j] (CG solution to 1e-8 at idx),
-  serve_x_norm[j]
+  serve_x_norm[j] (max-norm), serve_x_norm2[j] (2-norm)
 """
 import os
 import sys
@@ -59,7 +60,7 @@ def main():
     specs = P.batch_diffusion_specs(256)
     ks = chosen_batch_problems(specs)
     out = {k: [] for k in ("batch_k", "batch_idx", "batch_z", "batch_z_norm", "batch_iters", "batch_x",
-                           "batch_x_norm", "batch_xf")}
+                           "batch_x_norm", "batch_x_norm2", "batch_xf")}
     for k in ks:
         t = time.time()
         pr = P.batch_diffusion_problem(specs[k])
@@ -75,10 +76,11 @@ def main():
         out["batch_iters"].append(res.iters)
         out["batch_x"].append(res.x[idx])
         out["batch_x_norm"].append(np.abs(res.x).max())
+        out["batch_x_norm2"].append(np.linalg.norm(res.x))
         out["batch_xf"].append(fx.x[idx])
         print(f"batch problem {k}: N={specs[k]['N']} P={specs[k]['P']} iters={res.iters} "
               f"({time.time() - t:.1f} s)", flush=True)
-    sv = {k: [] for k in ("serve_N", "serve_rid", "serve_idx", "serve_iters", "serve_x", "serve_x_norm")}
+    sv = {k: [] for k in ("serve_N", "serve_rid", "serve_idx", "serve_iters", "serve_x", "serve_x_norm", "serve_x_norm2")}
     for j, (N, rid) in enumerate(((32, 1000), (59, 1001), (96, 1002))):
         t = time.time()
         pr = P.serve_operator(N)
@@ -92,6 +94,7 @@ def main():
         sv["serve_iters"].append(res.iters)
         sv["serve_x"].append(res.x[idx])
         sv["serve_x_norm"].append(np.abs(res.x).max())
+        sv["serve_x_norm2"].append(np.linalg.norm(res.x))
         print(f"serve N={N} rid={rid}: iters={res.iters} ({time.time() - t:.1f} s)", flush=True)
     np.savez_compressed(os.path.join(HERE, "batch_serve_oracle.npz"),
                         **{k: np.array(v) for k, v in out.items()}, **{k: np.array(v) for k, v in sv.items()})

@@ -1,5 +1,6 @@
 """The serving loop: resident operators, continuous batching of requests that
 arrive while others run, and each result identical alone and in the mix."""
+import os
 import sys
 
 import numpy as np
@@ -55,3 +56,42 @@ def test_budget_admission():
     srv.close()
     with pytest.raises(B.GdswError):
         SV.Server(ops, hbm_budget_bytes=1000, local=B.LOCAL_ILU0)
+
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_serve_oracle.npz")
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP16])
+def test_served_results_against_oracle(prec):
+    """Three operators of the serving stream (Poisson N = 32, 59, 96 with
+    P = round(N/16), ILU(0) + 5+5 Jacobi sweeps, GDSW), one request each,
+    served together: FP64 local factors reproduce the oracle's iteration
+    counts; with the stream's FP16 factors (FP32 arithmetic) the iteration
+    counts stay within the reduced-precision slack and each result's error
+    against the FP64 oracle's solution is stated and bounded by what two
+    solutions with relative residuals <= 1e-8 can differ by."""
+    ref = np.load(GOLD)
+    Ns = [int(v) for v in ref["serve_N"]]
+    ops = [P.serve_operator(N) for N in Ns]
+    print(f"[serve] oracle samples N={Ns} prec={prec}", file=sys.stderr, flush=True)
+    srv = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=prec,
+                    basis_prec=B.FP64 if prec == B.FP64 else B.FP32, step_iters=4)
+    reqs = [SV.Request(rid=int(ref["serve_rid"][j]), op=j, arrival=0.0,
+                       b=P.rhs_uniform(ops[j].n, int(ref["serve_rid"][j]))) for j in range(len(ops))]
+    reqs, sols = srv.run(reqs, keep_solutions=True)
+    srv.close()
+    for j, r in enumerate(sorted(reqs, key=lambda q: q.op)):
+        N = Ns[r.op]
+        xs = sols[r.rid].cpu().numpy()[ref["serve_idx"][r.op]]
+        err = np.abs(xs - ref["serve_x"][r.op]).max() / float(ref["serve_x_norm2"][r.op])
+        oit = int(ref["serve_iters"][r.op])
+        print(f"  N={N}: iterations {r.iterations} (oracle {oit}), solution diff vs the FP64 oracle "
+              f"{err:.1e} of its 2-norm", file=sys.stderr, flush=True)
+        assert r.status == 0 and r.rel_res_true <= 1.5e-8
+        assert abs(r.iterations - oit) <= (1 if prec == B.FP64 else 4)
+        # true residuals <= 1.5e-8 ||b|| here and about 1e-8 ||b|| in the
+        # oracle: ||x - x_oracle|| <= 3e-8 ||A^-1|| ||b||, with
+        # ||A^-1|| = 1 / (12 sin^2(pi / (2 (N + 1)))) for this stencil
+        lam_min = 12.0 * np.sin(np.pi / (2 * (N + 1))) ** 2
+        bound = 3e-8 * np.linalg.norm(r.b) / lam_min / float(ref["serve_x_norm2"][r.op])
+        assert err <= bound, (N, err, bound)
