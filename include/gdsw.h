@@ -220,6 +220,27 @@ gdsw_status gdsw_setup(const gdsw_csr *A, const int32_t *part, int32_t n_parts,
  * length n (distinct).  Queued on `stream`, no synchronisation. */
 gdsw_status gdsw_apply(gdsw_handle h, const double *r_dev, double *z_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * z = M^{-1} r as gdsw_apply, bit for bit, with the apply's scratch (the
+ * local results, the coarse restriction partials, r_0 and z_0, the blocked
+ * coarse prolongation, the sweep iterates of subdomains too large for LDS)
+ * taken from a static device array of GDSW_STATIC_SCRATCH_BYTES per GPU
+ * instead of the handle's own buffers.  Allocates nothing (no hipMalloc or
+ * hipFree, no allocating library call); the array is held by every GPU the
+ * library runs on until the process ends.  The current device must be the
+ * one the handle was factored on.  Every call on one GPU, from any handle,
+ * shares that GPU's array and leaves the last call's contents in it: calls
+ * that overlap on one GPU (queued on different streams, or from different
+ * threads) race and give wrong results; calls queued one after another on
+ * one stream are safe.  r_dev, z_dev: FP64 device vectors of length n
+ * (distinct), caller-owned.  Queued on `stream`, no synchronisation.
+ * Errors: STATE (not factored), INVALID_ARG (bad pointers, other device),
+ * BUDGET (the handle needs more scratch than the array holds; the message
+ * gives both sizes), HIP. */
+#define GDSW_STATIC_SCRATCH_BYTES 67108864
+gdsw_status gdsw_apply_static(gdsw_handle h, const double *r_dev, double *z_dev, void *stream);
+
 /* Parts of eq. (1) alone: which = 1 one-level sum only, 2 coarse term only,
  * 3 both (same as gdsw_apply); 4 = only the batched local solves
  * A_i^{-1} R_i r, kept in the handle's local buffer (z_dev unused, may be

@@ -34,7 +34,7 @@ _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
               5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64, 9: np.int64, 10: np.int32}
 
 EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
-            "gdsw_apply", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
+            "gdsw_apply", "gdsw_apply_static", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
             "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch",
@@ -92,6 +92,7 @@ def lib():
                                       ctypes.POINTER(vp)]),
         "gdsw_apply": (ctypes.c_int, [vp, vp, vp, vp]),
         "gdsw_apply_part": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "gdsw_apply_static": (ctypes.c_int, [vp, vp, vp, vp]),
         "gdsw_spmv": (ctypes.c_int, [vp, vp, vp, vp]),
         "gdsw_solve": (ctypes.c_int, [vp, vp, vp, i32, i32, dbl, i32, i32, ctypes.POINTER(SolveInfo), vp]),
         "gdsw_get_info": (ctypes.c_int, [vp, ctypes.POINTER(Info)]),
@@ -212,6 +213,10 @@ def gdsw_setup(A, part, n_parts, dpn=1, Z=None, options=None, stream=None):
 
 def gdsw_apply(h, r, z, stream=None):
     _check(h, lib().gdsw_apply(h, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def gdsw_apply_static(h, r, z, stream=None):
+    _check(h, lib().gdsw_apply_static(h, _ptr(r), _ptr(z), _stream(stream)))
 
 
 def gdsw_apply_part(h, r, z, which, stream=None):

@@ -126,6 +126,11 @@ gdsw_status gdsw_apply(gdsw_handle h, const double *r_dev, double *z_dev, void *
     return gdsw::apply(h, r_dev, z_dev, 3, stream);
 }
 
+gdsw_status gdsw_apply_static(gdsw_handle h, const double *r_dev, double *z_dev, void *stream) {
+    if (!h) return GDSW_ERR_INVALID_ARG;
+    return gdsw::apply_static(h, r_dev, z_dev, stream);
+}
+
 gdsw_status gdsw_apply_part(gdsw_handle h, const double *r_dev, double *z_dev, int32_t which, void *stream) {
     if (!h) return GDSW_ERR_INVALID_ARG;
     return gdsw::apply(h, r_dev, z_dev, which, stream);

@@ -16,6 +16,17 @@
 #include "kernels_krylov.hpp"
 #include "kernels_setup.hpp"
 
+// Scratch of the allocation-free apply (gdsw_apply_static): the local
+// results, the coarse restriction partials, r_0, z_0 and its repetitions,
+// the coarse part of the prolongation and the sweep iterates of large
+// subdomains, carved from this array instead of the handle's buffers.  Each
+// GPU the library runs on holds its own copy until the process ends; host
+// code uses the address hipGetSymbolAddress returns for the current device,
+// never the array's name.
+static __device__ __align__(256) unsigned char scratch[GDSW_STATIC_SCRATCH_BYTES];
+
+#include <mutex>
+
 namespace gdsw {
 
 struct DevError {
@@ -42,6 +53,31 @@ static size_t prec_size(int p) {
         case GDSW_FP32: return 4;
         default: return 2;
     }
+}
+
+// Device address of `scratch` on GPU `dev` (which must be the current
+// device), looked up once per device and kept.
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+static gdsw_status static_scratch(int dev, void **out, std::string *err) {
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = "device index out of range for the static scratch table";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return GDSW_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    if (out) *out = g_scratch_ptr[dev];
+    return GDSW_OK;
 }
 
 struct Device {
@@ -225,6 +261,9 @@ struct Device {
     int gm_m = 0;
     GState *gm_st = nullptr;
     void *sweep_buf = nullptr;    // iterates of subdomains too large for LDS
+    size_t sweep_bytes = 0;
+    int64_t n_partial = 0;        // coarse restriction partials
+    int device = 0;               // the GPU the handle was factored on
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
@@ -500,8 +539,10 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
         // register-resident kernel does not cover) keep them in global memory
         {
             const size_t asz = prec == GDSW_FP64 ? 8 : 4;
-            if (3 * asz * size_t(S.max_ni) > D.max_lds && !D.sweep_buf)
-                D.sweep_buf = D.raw_alloc(3 * asz * size_t(S.ov_ptr[S.np]));
+            if (3 * asz * size_t(S.max_ni) > D.max_lds && !D.sweep_buf) {
+                D.sweep_bytes = 3 * asz * size_t(S.ov_ptr[S.np]);
+                D.sweep_buf = D.raw_alloc(D.sweep_bytes);
+            }
         }
         HIPCHK(hipStreamSynchronize(s));
         D.setup_release(d_lval, sizeof(double) * ne);
@@ -638,6 +679,7 @@ static void coarse_layout(gdsw_handle_s *h, hipStream_t s) {
         D.tile_l1 = D.upload(tl1, s);
         D.tile_poff = D.upload(tpo, s);
         D.partial = D.alloc<double>(poff[B.nb]);
+        D.n_partial = poff[B.nb];
         HIPCHK(hipStreamSynchronize(s));   // the host vectors above go out of scope
     }
     D.dof_blk = D.upload(S.dof_blk, s);
@@ -866,6 +908,10 @@ gdsw_status factor(gdsw_handle_s *h, void *stream) {
         {
             int dev = 0, lds = 0;
             HIPCHK(hipGetDevice(&dev));
+            h->dev->device = dev;
+            // the allocation-free apply's scratch on this GPU
+            if (gdsw_status st = static_scratch(dev, nullptr, &h->err); st != GDSW_OK)
+                throw DevError{st, h->err};
             HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             h->dev->max_lds = size_t(lds);
             int cus = 0;
@@ -1179,6 +1225,76 @@ gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void 
     }
     try {
         launch_apply(h, r, z, which, Skip(), static_cast<hipStream_t>(stream));
+    } catch (const DevError &e) {
+        h->err = e.msg;
+        return e.st;
+    }
+    return GDSW_OK;
+}
+
+// The apply of eq. (1) with its scratch taken from the static array: the
+// handle's buffers of the local results, the coarse partials, r_0, z_0 (and
+// its repetitions), the blocked coarse prolongation and the sweep iterates
+// are swapped for consecutive 256-byte aligned pieces of `scratch` for the
+// duration of the launches (kernel arguments are copied at launch), then
+// restored.  Every piece is fully written before it is read within one
+// apply, so nothing needs clearing.
+gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *stream) {
+    if (!h->factored || !h->dev) {
+        h->err = "apply before factor";
+        return GDSW_ERR_STATE;
+    }
+    if (!r || !z || r == z) {
+        h->err = "apply_static: bad arguments";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    Device &D = *h->dev;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != D.device) {
+        h->err = "apply_static: the current device is not the one the handle was factored on";
+        return GDSW_ERR_INVALID_ARG;
+    }
+    void *base = nullptr;
+    if (gdsw_status st = static_scratch(cur, &base, &h->err); st != GDSW_OK) return st;
+    const bool split_used = D.zc != nullptr;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return at;
+    };
+    const Symbolic &S = h->sym;
+    const size_t o_zloc = take(sizeof(double) * size_t(S.ov_ptr[S.np]));
+    const size_t o_part = take(sizeof(double) * size_t(D.n_partial));
+    const size_t o_r0 = take(sizeof(double) * size_t(S.n0));
+    const size_t o_z0 = take(sizeof(double) * size_t(S.n0));
+    const size_t o_zg = take(sizeof(double) * S.blk.cols.size());
+    const size_t o_zc = split_used ? take(sizeof(double) * size_t(S.n)) : 0;
+    const size_t o_sw = D.sweep_buf ? take(D.sweep_bytes) : 0;
+    if (off > GDSW_STATIC_SCRATCH_BYTES) {
+        h->err = "apply_static: this handle needs " + std::to_string(off) + " bytes of scratch, more than the " +
+                 std::to_string(size_t(GDSW_STATIC_SCRATCH_BYTES)) + " of the static array";
+        return GDSW_ERR_BUDGET;
+    }
+    unsigned char *b = static_cast<unsigned char *>(base);
+    struct Swap {
+        Device &D;
+        double *zloc, *partial, *r0, *z0, *zg, *zc;
+        void *sweep;
+        ~Swap() {
+            D.zloc = zloc, D.partial = partial, D.r0 = r0, D.z0 = z0, D.zg = zg, D.zc = zc;
+            D.sweep_buf = sweep;
+        }
+    } keep{D, D.zloc, D.partial, D.r0, D.z0, D.zg, D.zc, D.sweep_buf};
+    D.zloc = reinterpret_cast<double *>(b + o_zloc);
+    D.partial = reinterpret_cast<double *>(b + o_part);
+    D.r0 = reinterpret_cast<double *>(b + o_r0);
+    D.z0 = reinterpret_cast<double *>(b + o_z0);
+    D.zg = reinterpret_cast<double *>(b + o_zg);
+    if (split_used) D.zc = reinterpret_cast<double *>(b + o_zc);
+    if (D.sweep_buf) D.sweep_buf = b + o_sw;
+    try {
+        launch_apply(h, r, z, 3, Skip(), static_cast<hipStream_t>(stream));
     } catch (const DevError &e) {
         h->err = e.msg;
         return e.st;
