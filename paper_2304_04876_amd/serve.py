@@ -106,7 +106,9 @@ class Server:
 
     def run(self, requests, keep_solutions=False):
         """Serves `requests` (sorted by arrival, seconds from now); returns
-        the requests with their times and results filled in."""
+        the requests with their times and results filled in, and the
+        solutions (device copies) of every request (keep_solutions=True) or
+        of the request ids in the collection keep_solutions."""
         torch = self.torch
         nslot = len(self.slot_op)
         free = {k: [s for s in range(nslot) if self.slot_op[s] == k] for k in range(len(self.ops))}
@@ -149,7 +151,7 @@ class Server:
                     r.iterations = info["iterations"]
                     r.rel_res_true = info["rel_res_true"]
                     r.status = info["status"]
-                    if keep_solutions:
+                    if keep_solutions is True or (keep_solutions and r.rid in keep_solutions):
                         lo, hi = int(self.offs[s]), int(self.offs[s + 1])
                         solutions[r.rid] = self.x[lo:hi].clone()
                     free[self.slot_op[s]].append(s)
