@@ -101,6 +101,19 @@ typedef struct {
                                  the iterative FastILU variant, s Jacobi sweeps
                                  over the factor entries (Sec. V-B; the paper's
                                  experiments use 3); default 0                    */
+    int32_t slots;            /* right-hand-side slots per problem (>= 1; 0 is read
+                                 as 1): the handle keeps one factored operator
+                                 and preconditions `slots` right-hand sides of
+                                 every problem with it.  Vectors passed to
+                                 gdsw_apply, gdsw_spmv, gdsw_solve(_batch) and
+                                 gdsw_slots_begin then hold the slots one after
+                                 another (length slots * n; dof d of slot k at
+                                 k n + d); slot k of problem p is the Krylov
+                                 problem k * n_problems + p (its dof range from
+                                 gdsw_problem_offsets).  Only the per-slot
+                                 vectors and intermediate results are
+                                 allocated per slot; slots * n < 2^31.
+                                 GMRES needs slots = 1.  Default 1.              */
 } gdsw_options;
 
 /* Square sparse matrix in CSR form, HOST pointers: rowptr[n+1] (int64),
@@ -147,6 +160,10 @@ typedef struct {
                                  1 by blocks                                         */
     double t_refactor;        /* seconds: last numeric re-setup (gdsw_refactor,
                                  synchronised); 0 if there was none             */
+    int32_t slots;            /* right-hand-side slots per problem (options.slots) */
+    int64_t slot_bytes;       /* of device_bytes, the bytes held per slot (its
+                                 vectors and intermediate results); the rest is
+                                 the factored operator, held once            */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -366,7 +383,9 @@ gdsw_status gdsw_profile_local(gdsw_handle h, int32_t enable);
  * *count receives the number recorded. */
 gdsw_status gdsw_profile_read(gdsw_handle h, float *ms, int32_t max, int32_t *count);
 
-/* Dof offsets of the problems of a handle: offsets[count+1] (host). */
+/* Dof offsets of the Krylov problems of a handle, offsets[slots * n_problems
+ * + 1] (host): problem p in slot k is entry k * n_problems + p, its rows
+ * k n + (offsets of p). */
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets);
 
 gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info);

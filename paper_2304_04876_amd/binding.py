@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("jacobi_sweeps", ctypes.c_int32), ("local_prec", ctypes.c_int32),
                 ("basis_prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
                 ("flags", ctypes.c_uint64), ("ilu_level", ctypes.c_int32),
-                ("ilu_factor_sweeps", ctypes.c_int32)]
+                ("ilu_factor_sweeps", ctypes.c_int32), ("slots", ctypes.c_int32)]
 
 
 class CSR(ctypes.Structure):
@@ -70,7 +70,8 @@ class Info(ctypes.Structure):
                 ("t_analyze", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
                 ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32),
-                ("prolong_variant", ctypes.c_int32), ("t_refactor", ctypes.c_double)]
+                ("prolong_variant", ctypes.c_int32), ("t_refactor", ctypes.c_double),
+                ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_int64)]
 
 
 def lib():
@@ -285,8 +286,14 @@ def _info_dict(info, st=None):
     return d
 
 
+def _krylov_problems(h):
+    """(slot, problem) pairs of a handle: slots * n_problems."""
+    inf = gdsw_get_info(h)
+    return inf["n_problems"] * max(1, inf["slots"])
+
+
 def gdsw_solve_batch(h, b, x, rtol=1e-8, maxit=1000, stream=None, raise_on_error=True):
-    count = gdsw_get_info(h)["n_problems"]
+    count = _krylov_problems(h)
     infos = (SolveInfo * count)()
     st = lib().gdsw_solve_batch(h, _ptr(b), _ptr(x), float(rtol), int(maxit), infos, _stream(stream))
     if raise_on_error and st != GDSW_OK:
@@ -303,7 +310,7 @@ def gdsw_slot_start(h, slot, stream=None):
 
 
 def gdsw_slots_step(h, iters, stream=None) -> np.ndarray:
-    count = gdsw_get_info(h)["n_problems"]
+    count = _krylov_problems(h)
     state = np.zeros(count, dtype=np.int32)
     _check(h, lib().gdsw_slots_step(h, int(iters), state.ctypes.data, _stream(stream)))
     return state
@@ -344,7 +351,7 @@ def gdsw_profile_read(h) -> np.ndarray:
 
 
 def gdsw_problem_offsets(h) -> np.ndarray:
-    count = gdsw_get_info(h)["n_problems"]
+    count = _krylov_problems(h)
     out = np.zeros(count + 1, dtype=np.int64)
     _check(h, lib().gdsw_problem_offsets(h, out.ctypes.data))
     return out

@@ -1,6 +1,7 @@
 // C ABI entry points (include/gdsw.h): argument checks, error strings and
 // dispatch to the host analysis (symbolic.cpp) and the device phases
 // (device.hip).
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -19,6 +20,7 @@ void gdsw_default_options(gdsw_options *opt) {
     opt->basis_prec = GDSW_FP64;
     opt->hbm_budget_bytes = 0;
     opt->flags = 0;
+    opt->slots = 1;
 }
 
 gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts, int32_t dpn, const double *Z,
@@ -47,7 +49,8 @@ gdsw_status gdsw_analyze_batch(int32_t count, const gdsw_csr *A, const int32_t *
 gdsw_status gdsw_solve_batch(gdsw_handle h, const double *b_dev, double *x_dev, double rtol, int32_t maxit,
                              gdsw_solve_info *infos, void *stream) {
     if (!h) return GDSW_ERR_INVALID_ARG;
-    return gdsw::solve(h, b_dev, x_dev, GDSW_KRYLOV_CG, 0, rtol, maxit, 0, infos, h->sym.nprob, stream);
+    return gdsw::solve(h, b_dev, x_dev, GDSW_KRYLOV_CG, 0, rtol, maxit, 0, infos,
+                       std::max(1, h->sym.opt.slots) * h->sym.nprob, stream);
 }
 
 gdsw_status gdsw_slots_begin(gdsw_handle h, const double *b_dev, double *x_dev, double rtol, int32_t maxit,
@@ -95,7 +98,11 @@ gdsw_status gdsw_profile_read(gdsw_handle h, float *ms, int32_t max, int32_t *co
 gdsw_status gdsw_problem_offsets(gdsw_handle h, int64_t *offsets) {
     if (!h || !offsets) return GDSW_ERR_INVALID_ARG;
     if (!h->analyzed) return GDSW_ERR_STATE;
-    std::memcpy(offsets, h->sym.prob_ptr.data(), sizeof(int64_t) * h->sym.prob_ptr.size());
+    const gdsw::Symbolic &S = h->sym;
+    const int ns = std::max(1, S.opt.slots);
+    for (int k = 0; k < ns; ++k)
+        for (int p = 0; p < S.nprob; ++p) offsets[k * S.nprob + p] = int64_t(k) * S.n + S.prob_ptr[p];
+    offsets[ns * S.nprob] = int64_t(ns) * S.n;
     return GDSW_OK;
 }
 
@@ -176,6 +183,8 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->apply_streams = gdsw::tuned_variant(h, 2);
     info->prolong_variant = gdsw::tuned_variant(h, 3);
     info->t_refactor = h->t_refactor;
+    info->slots = std::max(1, S.opt.slots);
+    info->slot_bytes = gdsw::slot_bytes(h);
     return GDSW_OK;
 }
 

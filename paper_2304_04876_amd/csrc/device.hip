@@ -261,9 +261,14 @@ struct Device {
     int gm_m = 0;
     GState *gm_st = nullptr;
     void *sweep_buf = nullptr;    // iterates of subdomains too large for LDS
-    size_t sweep_bytes = 0;
-    int64_t n_partial = 0;        // coarse restriction partials
+    size_t sweep_bytes = 0;       // (one slot)
+    int64_t n_partial = 0;        // coarse restriction partials (one slot)
     int device = 0;               // the GPU the handle was factored on
+    // right-hand-side slots: ns slots of every problem; the Krylov problems
+    // are the nvp = ns * nprob (slot, problem) pairs over nv = ns * n rows
+    int ns = 1, nvp = 1;
+    int64_t nv = 0;
+    Slots slots{};
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
@@ -359,25 +364,35 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         HIPCHK(hipStreamSynchronize(s));
     }
     D.t_pos = D.upload(S.t_pos, s);
-    D.zloc = D.alloc<double>(S.ov_ptr[S.np]);
-    const int64_t n = S.n;
+    D.ns = std::max(1, S.opt.slots);
+    D.nvp = D.ns * S.nprob;
+    D.nv = int64_t(D.ns) * S.n;
+    if (D.nv >= (int64_t(1) << 31)) throw DevError{GDSW_ERR_INVALID_ARG, "slots * n must stay below 2^31"};
+    D.slots.ns = D.ns;
+    D.slots.n = S.n;
+    D.slots.zl = S.ov_ptr[S.np];
+    D.zloc = D.alloc<double>(D.ns * S.ov_ptr[S.np]);
+    const int64_t n = D.nv;
     D.kr = D.alloc<double>(n);
     D.kz = D.alloc<double>(n);
     D.kp = D.alloc<double>(n);
     D.kp2 = D.alloc<double>(n);
     D.kq = D.alloc<double>(n);
     D.kt = D.alloc<double>(n);
-    // Krylov row blocks: KROWS rows each, never across problems
+    // Krylov row blocks: KROWS rows each, never across problems or slots;
+    // Krylov problem v = k nprob + p is problem p in slot k (rows k n + ...)
     {
         std::vector<int32_t> bp, b0, b1;
-        D.h_pb_ptr.assign(S.nprob + 1, 0);
-        for (int k = 0; k < S.nprob; ++k) {
-            for (int64_t r = S.prob_ptr[k]; r < S.prob_ptr[k + 1]; r += KROWS) {
-                bp.push_back(k);
-                b0.push_back(int32_t(r));
-                b1.push_back(int32_t(std::min<int64_t>(r + KROWS, S.prob_ptr[k + 1])));
+        D.h_pb_ptr.assign(D.nvp + 1, 0);
+        for (int v = 0; v < D.nvp; ++v) {
+            const int k = v / S.nprob, p = v % S.nprob;
+            const int64_t sh = int64_t(k) * S.n;
+            for (int64_t r = S.prob_ptr[p]; r < S.prob_ptr[p + 1]; r += KROWS) {
+                bp.push_back(v);
+                b0.push_back(int32_t(sh + r));
+                b1.push_back(int32_t(sh + std::min<int64_t>(r + KROWS, S.prob_ptr[p + 1])));
             }
-            D.h_pb_ptr[k + 1] = int32_t(bp.size());
+            D.h_pb_ptr[v + 1] = int32_t(bp.size());
         }
         D.nkb = int(bp.size());
         D.kb_prob = D.upload(bp, s);
@@ -388,9 +403,9 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     }
     D.kpart = D.alloc<double>(std::max(D.nkb, 1));
     D.kpart2 = D.alloc<double>(std::max(D.nkb, 1));
-    D.kst = D.alloc<KState>(S.nprob);
-    D.kdone = D.alloc<int>(S.nprob);
-    D.kmask = D.alloc<int>(S.nprob);
+    D.kst = D.alloc<KState>(D.nvp);
+    D.kdone = D.alloc<int>(D.nvp);
+    D.kmask = D.alloc<int>(D.nvp);
     D.sub_prob = D.upload(S.sub_prob, s);
     D.prob_ptr = D.upload(S.prob_ptr, s);
     {
@@ -541,7 +556,7 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
             const size_t asz = prec == GDSW_FP64 ? 8 : 4;
             if (3 * asz * size_t(S.max_ni) > D.max_lds && !D.sweep_buf) {
                 D.sweep_bytes = 3 * asz * size_t(S.ov_ptr[S.np]);
-                D.sweep_buf = D.raw_alloc(D.sweep_bytes);
+                D.sweep_buf = D.raw_alloc(D.sweep_bytes * size_t(D.ns));
             }
         }
         HIPCHK(hipStreamSynchronize(s));
@@ -615,7 +630,7 @@ static void coarse_layout(gdsw_handle_s *h, hipStream_t s) {
     // many columns per row of Phi (elasticity: ~90): the per-dof form reads
     // them with scattered loads, the block form streams each block once
     D.split_rule = B.val_off[size_t(B.nb)] >= 16 * S.n && sizeof(double) * size_t(D.max_k_big) <= D.max_lds;
-    if (D.split_rule) D.zc = D.alloc<double>(S.n);
+    if (D.split_rule) D.zc = D.alloc<double>(D.ns * S.n);
     D.blk_col_ptr = D.upload(B.col_ptr, s);
     D.blk_val_off = D.upload(B.val_off, s);
     D.blk_rows = D.upload(B.rows, s);
@@ -678,15 +693,18 @@ static void coarse_layout(gdsw_handle_s *h, hipStream_t s) {
         D.tile_l0 = D.upload(tl0, s);
         D.tile_l1 = D.upload(tl1, s);
         D.tile_poff = D.upload(tpo, s);
-        D.partial = D.alloc<double>(poff[B.nb]);
+        D.partial = D.alloc<double>(D.ns * poff[B.nb]);
         D.n_partial = poff[B.nb];
+        D.slots.part = poff[B.nb];
         HIPCHK(hipStreamSynchronize(s));   // the host vectors above go out of scope
     }
     D.dof_blk = D.upload(S.dof_blk, s);
     D.dof_lr = D.upload(S.dof_lr, s);
-    D.r0 = D.alloc<double>(n0);
-    D.z0 = D.alloc<double>(n0);
-    D.zg = D.alloc<double>(int64_t(B.cols.size()));
+    D.r0 = D.alloc<double>(D.ns * n0);
+    D.z0 = D.alloc<double>(D.ns * n0);
+    D.zg = D.alloc<double>(D.ns * int64_t(B.cols.size()));
+    D.slots.n0 = n0;
+    D.slots.cols = int64_t(B.cols.size());
     D.cpos_ptr = D.upload(S.red_ptr, s);
     D.cpos = D.upload(S.red_idx, s);
     const int64_t nphi = B.val_off[B.nb];
@@ -1001,13 +1019,22 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
     constexpr bool f64 = std::is_same<VT, double>::value;
     const int need = (S.max_ni + NT - 1) / NT;
     using AT = typename AccOf<VT>::type;
+    // with several right-hand-side slots, one workgroup takes every slot of
+    // its subdomain with the factor entries loaded once
 #define GDSW_ILU_CASE(RR)                                                                                    \
     if (need <= RR) {                                                                                        \
         const size_t lds = (3 * sizeof(AT) + (f64 ? 0 : sizeof(double))) * NT * RR;                          \
         if (lds > D.max_lds) return false;                                                                   \
-        hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT>), dim3(S.np), dim3(NT), lds, s, r,      \
-                           D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, (const VT *)D.Uv,     \
-                           D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, sk);             \
+        if (D.ns > 1)                                                                                        \
+            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, true>), dim3(S.np), dim3(NT), lds,  \
+                               s, r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv,            \
+                               (const VT *)D.Uv, D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps,    \
+                               D.zloc, sk);                                                                  \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, false>), dim3(S.np), dim3(NT), lds, \
+                               s, r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv,            \
+                               (const VT *)D.Uv, D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps,    \
+                               D.zloc, sk);                                                                  \
         return true;                                                                                         \
     }
     // the row counts per thread whose factor entries stay in registers
@@ -1033,7 +1060,7 @@ static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, con
         gbuf = D.sweep_buf;
         lds = 0;
     }
-    hipLaunchKernelGGL((k_ilu_jacobi_generic<NT, VT>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+    hipLaunchKernelGGL((k_ilu_jacobi_generic<NT, VT>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                        D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc,
                        (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, S.max_ni, gbuf, sk);
     return true;
@@ -1045,10 +1072,10 @@ static bool launch_band(const Symbolic &S, Device &D, const double *r, const Ski
     const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
     if (lds > D.max_lds) return false;
     if (D.band_kinds & 2)
-        hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+        hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                            (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
     if (D.band_kinds & 1)
-        hipLaunchKernelGGL((k_band_apply<NT, VT, false>), dim3(S.np), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+        hipLaunchKernelGGL((k_band_apply<NT, VT, false>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                            (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
     return true;
 }
@@ -1096,7 +1123,7 @@ static void launch_prolong_inst(const Symbolic &S, Device &D, const double *zc, 
                            D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off, phi, D.zg, zc, z, sk,
                            D.kb_row0, D.kb_row1, dot_r, D.kpart);
     else
-        hipLaunchKernelGGL((k_prolong<PT, W, BLK>), dim3(nblocks(S.n, 256)), dim3(256), 0, s, D.t_ptr, D.t_pos,
+        hipLaunchKernelGGL((k_prolong<PT, W, BLK>), dim3(nblocks(S.n, 256), D.ns), dim3(256), 0, s, D.t_ptr, D.t_pos,
                            D.zloc, D.dof_blk, D.dof_lr, D.blk_row_ptr, D.blk_col_ptr, D.blk_val_off, phi, D.zg, zc,
                            z, S.n, sk);
 }
@@ -1120,10 +1147,13 @@ static void launch_prolong(const Symbolic &S, Device &D, int w, const double *zc
 
 // z = M^{-1} r (which = 3), or one part of it; with dot_r the prolongation
 // also writes the Krylov-block partials of dot_r . z into the partial buffer.
-static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk, hipStream_t s,
+static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which, const Skip &sk_in, hipStream_t s,
                          const double *dot_r = nullptr) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
+    Skip sk = sk_in;
+    sk.sl = D.slots;
+    if (!sk.flag) sk.nprob = S.nprob;
     const bool local = (which & 1) || which == 4;
     const bool coarse = (which & 2) && D.A0inv != nullptr;
     // the coarse chain (restriction, reduction, GEMV) and the local solves
@@ -1147,33 +1177,33 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
         const int nwg = D.nwork + nsw;
         if (nwg > 0) {
             if (D.phi32)
-                hipLaunchKernelGGL(k_coarse_restrict<float>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_restrict<float>, dim3(nwg, D.ns), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32, D.tile_blk,
                                    D.tile_l0, D.tile_l1, D.tile_poff, D.wk_tile, D.wk_s0, D.blk_poff, D.partial,
                                    D.nwork, nbig, B.nb, sk);
             else
-                hipLaunchKernelGGL(k_coarse_restrict<double>, dim3(nwg), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_restrict<double>, dim3(nwg, D.ns), dim3(RT_NT), 0, sc, r, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi, D.tile_blk,
                                    D.tile_l0, D.tile_l1, D.tile_poff, D.wk_tile, D.wk_s0, D.blk_poff, D.partial,
                                    D.nwork, nbig, B.nb, sk);
         }
-        hipLaunchKernelGGL(k_coarse_reduce, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.red_ptr, D.red_idx,
+        hipLaunchKernelGGL(k_coarse_reduce, dim3((S.n0 + 3) / 4, D.ns), dim3(256), 0, sc, D.red_ptr, D.red_idx,
                            D.partial, D.r0, S.n0, sk);
         if (D.gemv_variant == 1 || (D.gemv_variant < 0 && D.max_n0 >= 1024))
-            hipLaunchKernelGGL(k_block_gemv_wg, dim3((S.n0 + GW_R - 1) / GW_R), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
+            hipLaunchKernelGGL(k_block_gemv_wg, dim3((S.n0 + GW_R - 1) / GW_R, D.ns), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0, D.cprob,
                                D.r0, D.z0, D.cpos_ptr, D.cpos, D.zg, S.n0, sk);
         else
-            hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
+            hipLaunchKernelGGL(k_block_gemv, dim3((S.n0 + 3) / 4, D.ns), dim3(256), 0, sc, D.A0inv, D.a0_off, D.prob_c0,
                                D.cprob, D.r0, D.z0, D.cpos_ptr, D.cpos, D.zg, S.n0, sk);
         const int nwp = D.ntiles * RT_RPT + nsw;
         if (split && nwp > 0) {
             const size_t lds = sizeof(double) * size_t(std::max(1, D.max_k_big));
             if (D.phi32)
-                hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_prolong<float>, dim3(nwp, D.ns), dim3(RT_NT), lds, sc, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const float *)D.phi32,
                                    D.tile_blk, D.tile_l0, D.tile_l1, D.zg, D.zc, D.ntiles, nbig, B.nb, sk);
             else
-                hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwp), dim3(RT_NT), lds, sc, D.blk_row_ptr,
+                hipLaunchKernelGGL(k_coarse_prolong<double>, dim3(nwp, D.ns), dim3(RT_NT), lds, sc, D.blk_row_ptr,
                                    D.blk_rows, D.blk_col_ptr, D.blk_val_off, (const double *)D.phi,
                                    D.tile_blk, D.tile_l0, D.tile_l1, D.zg, D.zc, D.ntiles, nbig, B.nb, sk);
         }
@@ -1264,13 +1294,14 @@ gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *str
         return at;
     };
     const Symbolic &S = h->sym;
-    const size_t o_zloc = take(sizeof(double) * size_t(S.ov_ptr[S.np]));
-    const size_t o_part = take(sizeof(double) * size_t(D.n_partial));
-    const size_t o_r0 = take(sizeof(double) * size_t(S.n0));
-    const size_t o_z0 = take(sizeof(double) * size_t(S.n0));
-    const size_t o_zg = take(sizeof(double) * S.blk.cols.size());
-    const size_t o_zc = split_used ? take(sizeof(double) * size_t(S.n)) : 0;
-    const size_t o_sw = D.sweep_buf ? take(D.sweep_bytes) : 0;
+    const size_t ns = size_t(D.ns);   // every right-hand-side slot
+    const size_t o_zloc = take(ns * sizeof(double) * size_t(S.ov_ptr[S.np]));
+    const size_t o_part = take(ns * sizeof(double) * size_t(D.n_partial));
+    const size_t o_r0 = take(ns * sizeof(double) * size_t(S.n0));
+    const size_t o_z0 = take(ns * sizeof(double) * size_t(S.n0));
+    const size_t o_zg = take(ns * sizeof(double) * S.blk.cols.size());
+    const size_t o_zc = split_used ? take(ns * sizeof(double) * size_t(S.n)) : 0;
+    const size_t o_sw = D.sweep_buf ? take(ns * D.sweep_bytes) : 0;
     if (off > GDSW_STATIC_SCRATCH_BYTES) {
         h->err = "apply_static: this handle needs " + std::to_string(off) + " bytes of scratch, more than the " +
                  std::to_string(size_t(GDSW_STATIC_SCRATCH_BYTES)) + " of the static array";
@@ -1308,13 +1339,13 @@ gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream) {
         return GDSW_ERR_STATE;
     }
     if (!x || !y || x == y) return GDSW_ERR_INVALID_ARG;
-    const int n = int(h->sym.n);
+    const int n = int(h->dev->nv), pn = int(h->sym.n);   // every right-hand-side slot
     if (h->dev->sell.dcol)
         hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
-                           x, y, n);
+                           x, y, n, pn);
     else
         hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(n, KNT)), dim3(KNT), 0, static_cast<hipStream_t>(stream), h->dev->sell,
-                           x, y, n);
+                           x, y, n, pn);
     return hipGetLastError() == hipSuccess ? GDSW_OK : GDSW_ERR_HIP;
 }
 
@@ -1343,15 +1374,15 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
-    const int nkb = D.nkb, np = S.nprob;
+    const int nkb = D.nkb, np = D.nvp;
     double *pold = D.cg_par ? D.kp2 : D.kp, *pnew = D.cg_par ? D.kp : D.kp2;
     // p = z + beta p fused into the product with A
     if (D.sell.dcol)
         hipLaunchKernelGGL(k_cg_spmv_dot_p<true>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
-                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
+                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n));
     else
         hipLaunchKernelGGL(k_cg_spmv_dot_p<false>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
-                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all);
+                           (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n));
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
     hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, pnew, D.kq, D.kpart2, D.kst, all);
@@ -1408,7 +1439,7 @@ static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, 
     Device &D = *h->dev;
     const int base = k < 0 ? 0 : D.h_pb_ptr[k];
     const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
-    const int pbase = k < 0 ? 0 : k, pn = k < 0 ? S.nprob : 1;
+    const int pbase = k < 0 ? 0 : k, pn = k < 0 ? D.nvp : 1;
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(KNT), 0, s, x, D.kr, b, kb);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, b, b, D.kpart, D.kst, 0, kb);
@@ -1427,17 +1458,17 @@ static void queue_cg_start(gdsw_handle_s *h, const double *b, double *x, int k, 
 static void queue_true_residual(gdsw_handle_s *h, const double *b, const double *x, int k, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
-    const int n = int(S.n);
+    const int n = int(D.nv);
     const int base = k < 0 ? 0 : D.h_pb_ptr[k];
     const int nb = k < 0 ? D.nkb : D.h_pb_ptr[k + 1] - D.h_pb_ptr[k];
     const KBlk kb{D.kb_prob, D.kb_row0, D.kb_row1, base};
     if (D.sell.dcol)
-        hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
+        hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n, int(S.n));
     else
-        hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n);
+        hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(n, KNT)), dim3(KNT), 0, s, D.sell, x, D.kt, n, int(S.n));
     hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, D.kt, n);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(KNT), 0, s, D.kt, D.kt, D.kpart, D.kst, 0, kb);
-    hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? S.nprob : 1), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst,
+    hipLaunchKernelGGL(k_cg_finish, dim3(k < 0 ? D.nvp : 1), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst,
                        (int *)nullptr, int(KF_RED), k < 0 ? 0 : k, (const double *)nullptr);
 }
 
@@ -1453,9 +1484,8 @@ static void fill_info(const KState &f, gdsw_solve_info *info) {
 // per chunk, kernels of finished problems return immediately.
 static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double rtol, int maxit, int fixed,
                             gdsw_solve_info *infos, int ninfo, hipStream_t s) {
-    Symbolic &S = h->sym;
     Device &D = *h->dev;
-    const int np = S.nprob;
+    const int np = D.nvp;   // every (slot, problem) pair
     std::vector<KState> hs(np);
     for (auto &k : hs) {
         k = KState{};
@@ -1533,8 +1563,8 @@ gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int 
         if (krylov == GDSW_KRYLOV_CG) {
             st = solve_cg(h, b, x, rtol, maxit, fixed_iters, info, info ? ninfo : 0, s);
         } else {
-            if (h->sym.nprob != 1) {
-                h->err = "GMRES needs a handle with one problem";
+            if (h->sym.nprob != 1 || h->dev->ns != 1) {
+                h->err = "GMRES needs a handle with one problem and one right-hand-side slot";
                 return GDSW_ERR_INVALID_ARG;
             }
             st = solve_gmres(h, b, x, restart, rtol, maxit, fixed_iters, krylov == GDSW_KRYLOV_GMRES_SR, info, s);
@@ -1609,9 +1639,9 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
         // u = r = b - A x; step 0 forms ||r|| in its reduction
         hipLaunchKernelGGL(k_sr_cycle_start, dim3(1), dim3(1024), 0, s, st);
         if (D.sell.dcol)
-            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n), int(n));
         else
-            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n), int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
         int queued = 0, chunk = 4;
         while (true) {
@@ -1653,9 +1683,9 @@ gdsw_status solve_gmres(gdsw_handle_s *h, const double *b, double *x, int restar
     while (!single_reduce) {
         // r = b - A x
         if (D.sell.dcol)
-            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+            hipLaunchKernelGGL(k_spmv<true>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n), int(n));
         else
-            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n));
+            hipLaunchKernelGGL(k_spmv<false>, dim3(g), dim3(KNT), 0, s, D.sell, x, r, int(n), int(n));
         hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, b, r, int(n));
         hipLaunchKernelGGL(k_gm_sqnorm, dim3(gr), dim3(KNT), 0, s, r, n, D.gm_part, st, 1);
         hipLaunchKernelGGL(k_gm_start_finish, dim3(1), dim3(KNT), 0, s, D.gm_part, gr, st);
@@ -1737,7 +1767,7 @@ gdsw_status slots_begin(gdsw_handle_s *h, const double *b, double *x, double rto
     }
     Device &D = *h->dev;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int np = h->sym.nprob;
+    const int np = h->dev->nvp;   // every (slot, problem) pair
     D.slot_b = b;
     D.slot_x = x;
     D.h_state.assign(np, KState{});
@@ -1765,7 +1795,7 @@ gdsw_status slot_start(gdsw_handle_s *h, int slot, void *stream) {
         return GDSW_ERR_STATE;
     }
     Device &D = *h->dev;
-    const int np = h->sym.nprob;
+    const int np = h->dev->nvp;   // every (slot, problem) pair
     if (slot < 0 || slot >= np) return GDSW_ERR_INVALID_ARG;
     if (D.h_state[slot].status != KS_IDLE) {
         h->err = "slot is busy";
@@ -1802,7 +1832,7 @@ gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream
         return GDSW_ERR_STATE;
     }
     Device &D = *h->dev;
-    const int np = h->sym.nprob;
+    const int np = h->dev->nvp;   // every (slot, problem) pair
     hipStream_t s = static_cast<hipStream_t>(stream);
     try {
         bool any = false;
@@ -1830,7 +1860,7 @@ gdsw_status slots_step(gdsw_handle_s *h, int iters, int32_t *state, void *stream
 gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void *stream) {
     if (!h->dev || !h->dev->slot_x) return GDSW_ERR_STATE;
     Device &D = *h->dev;
-    if (slot < 0 || slot >= h->sym.nprob) return GDSW_ERR_INVALID_ARG;
+    if (slot < 0 || slot >= D.nvp) return GDSW_ERR_INVALID_ARG;
     if (D.h_state[slot].status == KS_IDLE || !D.h_state[slot].done) {
         h->err = "slot has no finished result";
         return GDSW_ERR_STATE;
@@ -1869,7 +1899,8 @@ template <typename VT>
 static float time_local(gdsw_handle_s *h, int v, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
-    const Skip none;
+    Skip none;
+    none.sl = D.slots;
     if (!launch_local_variant<VT>(S, D, v, D.kr, none, s)) return -1.0f;
     HIPCHK(hipEventRecord(e0, s));
     for (int k = 0; k < reps; ++k) launch_local_variant<VT>(S, D, v, D.kr, none, s);
@@ -1892,7 +1923,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
     try {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(S.n, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, S.n);
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
         const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
         float best = -1.0f;
         int bv = -1;
@@ -1939,7 +1970,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
             // coarse part of the prolongation per dof or by blocks
             const size_t lds = sizeof(double) * size_t(D.max_k_big);
             if (lds <= D.max_lds) {
-                if (!D.zc) D.zc = D.alloc<double>(S.n);
+                if (!D.zc) D.zc = D.alloc<double>(D.ns * S.n);
                 float tp[2];
                 for (int v = 0; v < 2; ++v) {
                     D.prolong_split = v;
@@ -2029,8 +2060,9 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
         hipStream_t s = static_cast<hipStream_t>(stream);
         bool fits = false;
         try {
-            hipLaunchKernelGGL(k_fill, dim3(nblocks(S.n, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, S.n);
-            const Skip none;
+            hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
+            Skip none;
+            none.sl = D.slots;
             switch (S.opt.local_prec) {
                 case GDSW_FP64: fits = launch_local_variant<double>(S, D, local_variant, D.kr, none, s); break;
                 case GDSW_FP32: fits = launch_local_variant<float>(S, D, local_variant, D.kr, none, s); break;
@@ -2050,7 +2082,7 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
     }
     if (prolong_variant == 1 && !D.zc && D.A0inv) {
         try {
-            D.zc = D.alloc<double>(S.n);
+            D.zc = D.alloc<double>(D.ns * S.n);
         } catch (const DevError &e) {
             h->err = e.msg;
             return e.st;
@@ -2078,6 +2110,22 @@ void destroy_device(gdsw_handle_s *h) {
 }
 
 int64_t device_bytes(const gdsw_handle_s *h) { return h->dev ? h->dev->bytes : 0; }
+
+// Device bytes held per right-hand-side slot (the six Krylov vectors, the
+// local results, the coarse partials, r_0, z_0 and its repetitions, the
+// blocked coarse prolongation, the sweep iterates, the Krylov row-block
+// tables, partial sums and states of the slot's problems); the rest of
+// device_bytes is the operator itself, held once.
+int64_t slot_bytes(const gdsw_handle_s *h) {
+    if (!h->dev) return 0;
+    const Device &D = *h->dev;
+    const Symbolic &S = h->sym;
+    const int64_t cols = D.zg ? D.slots.cols : 0, n0 = D.z0 ? S.n0 : 0, nkb = D.nkb / D.ns;
+    return int64_t(sizeof(double)) * (6 * S.n + S.ov_ptr[S.np] + D.n_partial + 2 * n0 + cols + (D.zc ? S.n : 0) +
+                                      2 * nkb) +
+           int64_t(D.sweep_bytes) + int64_t(sizeof(int32_t)) * (3 * nkb + S.nprob) +
+           int64_t(sizeof(KState) + 2 * sizeof(int)) * S.nprob;
+}
 
 gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out) {
     if (!h->factored || !h->dev) return GDSW_ERR_STATE;

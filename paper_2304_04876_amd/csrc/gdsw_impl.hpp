@@ -172,6 +172,7 @@ gdsw_status factor(gdsw_handle_s *h, void *stream);
 gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream);
 gdsw_status apply(gdsw_handle_s *h, const double *r, double *z, int which, void *stream);
 gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *stream);
+int64_t slot_bytes(const gdsw_handle_s *h);
 gdsw_status spmv(gdsw_handle_s *h, const double *x, double *y, void *stream);
 gdsw_status solve(gdsw_handle_s *h, const double *b, double *x, int krylov, int restart,
                   double rtol, int maxit, int fixed_iters, gdsw_solve_info *info, int ninfo, void *stream);

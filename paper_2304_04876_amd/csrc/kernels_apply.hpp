@@ -23,7 +23,10 @@ namespace gdsw {
 // restriction gather (with the optional diagonal scaling of the
 // reduced-precision factors) and the write of the local result are fused
 // in.  LDS: 3 NT R accumulator values (+ NT R doubles with scaling).
-template <int NT, int R, int KL, int KU, typename VT>
+// MS: every right-hand-side slot of the subdomain in one workgroup, one
+// after another, with the factor entries loaded once for all of them (the
+// slots' sweeps reuse the registers); otherwise the slot is blockIdx.y.
+template <int NT, int R, int KL, int KU, typename VT, bool MS>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
@@ -34,7 +37,13 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     // FP64 factors are never scaled (dscale is null for them), and their LDS
     // holds no scale slots
     constexpr bool scaled = !std::is_same<VT, double>::value;
-    if (sk.sub(blockIdx.x)) return;
+    int slot = MS ? 0 : int(blockIdx.y);
+    if constexpr (MS) {
+        while (slot < sk.sl.ns && sk.sub(blockIdx.x, slot)) ++slot;
+        if (slot == sk.sl.ns) return;
+    } else if (sk.sub(blockIdx.x, slot)) {
+        return;
+    }
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *bufA = reinterpret_cast<AT *>(smraw);
     AT *bufB = bufA + NT * R;
@@ -76,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     // the gathered r (scaled for reduced-precision factors)
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        double x = r[dof[m]];
+        double x = r[slot * sk.sl.n + dof[m]];
         if (scaled && dscale) {
             const double sc = dscale[dof[m]];
             x *= sc;
@@ -101,6 +110,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     // subdomain reads them), so that all LDS reads of a sweep go out before
     // the first product waits.
     AT *cur = bufA, *nxt = bufB;
+    for (;;) {   // the right-hand-side slots (one pass unless MS)
     // first L sweep from zero: y^1 = r
 #pragma unroll
     for (int m = 0; m < R; ++m) cur[tid + m * NT] = rr[m];
@@ -168,7 +178,24 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     }
 #pragma unroll
     for (int m = 0; m < R; ++m)
-        if (tid + m * NT < ni) zloc[o + tid + m * NT] = out[m];
+        if (tid + m * NT < ni) zloc[slot * sk.sl.zl + o + tid + m * NT] = out[m];
+    if constexpr (!MS) {
+        break;
+    } else {
+        // the next slot that runs: its gathered r, after every thread is
+        // done with the LDS vectors of this one
+        ++slot;
+        while (slot < sk.sl.ns && sk.sub(blockIdx.x, slot)) ++slot;
+        if (slot == sk.sl.ns) break;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            double x = r[slot * sk.sl.n + dof[m]];
+            if (scaled && dscale) x *= sscale[tid + m * NT];
+            rr[m] = AT(x);
+        }
+        __syncthreads();
+    }
+    }
 }
 
 // Same sweeps for any slot counts and subdomain sizes: factors are read from
@@ -182,14 +209,17 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
     double *__restrict__ zloc, int maxrows, void *__restrict__ gbuf, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (sk.sub(blockIdx.x)) return;
+    const int slot = blockIdx.y;
+    if (sk.sub(blockIdx.x, slot)) return;
+    r += slot * sk.sl.n;
+    zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
     const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
     // the three vectors live in LDS, or (subdomains too large for it) in a
-    // per-subdomain slice of global memory, which stays in L2
-    AT *rb = gbuf ? reinterpret_cast<AT *>(gbuf) + 3 * o : reinterpret_cast<AT *>(smraw);
+    // per-subdomain slice of global memory (per slot), which stays in L2
+    AT *rb = gbuf ? reinterpret_cast<AT *>(gbuf) + 3 * (slot * sk.sl.zl + o) : reinterpret_cast<AT *>(smraw);
     const int64_t stride = gbuf ? ni : maxrows;
     AT *cur = rb + stride, *nxt = cur + stride;
     const int64_t eo = ell_off[i];
@@ -245,7 +275,10 @@ __global__ __launch_bounds__(1024) void k_band_apply(
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
     const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    if (sk.sub(blockIdx.x) || band_inverted(bw[blockIdx.x]) != INV) return;
+    const int slot = blockIdx.y;
+    if (sk.sub(blockIdx.x, slot) || band_inverted(bw[blockIdx.x]) != INV) return;
+    r += slot * sk.sl.n;
+    zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *sT = y + maxrows;
@@ -427,16 +460,18 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_restrict(
     const int64_t *__restrict__ tile_poff, const int32_t *__restrict__ wk_tile, const int32_t *__restrict__ wk_s0,
     const int64_t *__restrict__ poff, double *__restrict__ partial, int nwork, int g_small, int nb, Skip sk) {
     __shared__ double sh[RT_KB][RT_NT / 64];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x, slot = blockIdx.y;
+    r += slot * sk.sl.n;
+    partial += slot * sk.sl.part;
     if (b < nwork) {
         const int t = wk_tile[b], g = tile_blk[t];
-        if (sk.blk(g)) return;
+        if (sk.blk(g, slot)) return;
         const int s0 = wk_s0[b];
         restrict_tile<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, tile_l0[t], tile_l1[t], tile_poff[t], s0,
                           s0 + RT_CK, partial, sh);
     } else {
         const int g = g_small + (b - nwork) * (RT_NT / 64) + int(threadIdx.x >> 6);
-        if (g >= nb || sk.blk(g)) return;
+        if (g >= nb || sk.blk(g, slot)) return;
         restrict_wave<PT>(r, row_ptr, rows, col_ptr, val_off, phi, g, poff[g], partial);
     }
 }
@@ -449,8 +484,10 @@ __global__ __launch_bounds__(256) void k_coarse_reduce(const int64_t *__restrict
                                                        const int32_t *__restrict__ red_idx,
                                                        const double *__restrict__ partial, double *__restrict__ r0,
                                                        int n0, Skip sk) {
-    const int c = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (c >= n0 || sk.col(c)) return;   // (the whole wavefront)
+    const int c = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63, slot = blockIdx.y;
+    if (c >= n0 || sk.col(c, slot)) return;   // (the whole wavefront)
+    partial += slot * sk.sl.part;
+    r0 += slot * sk.sl.n0;
     const int64_t q1 = red_ptr[c + 1];
     double acc = 0.0;
     for (int64_t q = red_ptr[c] + lane; q < q1; q += 64) acc += partial[red_idx[q]];
@@ -470,8 +507,11 @@ __global__ __launch_bounds__(256) void k_block_gemv(const double *__restrict__ A
                                                     const int32_t *__restrict__ cpos, double *__restrict__ zg, int n0,
                                                     Skip sk) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= n0 || sk.col(row)) return;
+    const int lane = threadIdx.x & 63, slot = blockIdx.y;
+    if (row >= n0 || sk.col(row, slot)) return;
+    x += slot * sk.sl.n0;
+    y += slot * sk.sl.n0;
+    zg += slot * sk.sl.cols;
     const int k = cprob[row];
     const int c0 = prob_c0[k], nk = prob_c0[k + 1] - c0;
     const double *a = Ainv + a0_off[k] + int64_t(row - c0) * nk;
@@ -508,7 +548,7 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
                                                        const int32_t *__restrict__ cpos, double *__restrict__ zg,
                                                        int n0, Skip sk) {
     __shared__ double sh[GW_R][4];
-    const int r0 = blockIdx.x * GW_R;
+    const int r0 = blockIdx.x * GW_R, slot = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int row[GW_R];
     bool act[GW_R];
@@ -516,10 +556,13 @@ __global__ __launch_bounds__(256) void k_block_gemv_wg(const double *__restrict_
 #pragma unroll
     for (int j = 0; j < GW_R; ++j) {
         row[j] = min(r0 + j, n0 - 1);
-        act[j] = r0 + j < n0 && !sk.col(row[j]);
+        act[j] = r0 + j < n0 && !sk.col(row[j], slot);
         any |= act[j];
     }
     if (!any) return;   // (the whole workgroup)
+    x += slot * sk.sl.n0;
+    y += slot * sk.sl.n0;
+    zg += slot * sk.sl.cols;
     const int k0 = cprob[row[0]];
     bool same = true;
 #pragma unroll
@@ -589,12 +632,14 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
     const int32_t *__restrict__ tile_l0, const int32_t *__restrict__ tile_l1, const double *__restrict__ zg,
     double *__restrict__ zc, int ntiles, int g_small, int nb, Skip sk) {
     extern __shared__ double sz[];   // z0 entries of the tile's block (max columns of a big block)
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int b = blockIdx.x, tid = threadIdx.x, slot = blockIdx.y;
+    zg += slot * sk.sl.cols;
+    zc += slot * sk.sl.n;
     if (b < ntiles * RT_RPT) {
         // quarter q of tile t: rows l0 + q * RT_NT + tid, one per thread
         const int t = b / RT_RPT, q = b % RT_RPT;
         const int g = tile_blk[t];
-        if (sk.blk(g)) return;
+        if (sk.blk(g, slot)) return;
         const int64_t r0 = row_ptr[g];
         const int nr = int(row_ptr[g + 1] - r0);
         const int64_t c0 = col_ptr[g];
@@ -618,7 +663,7 @@ __global__ __launch_bounds__(RT_NT) void k_coarse_prolong(
         if (l < l1) zc[rows[r0 + l]] = acc;
     } else {
         const int g = g_small + (b - ntiles * RT_RPT) * (RT_NT / 64) + (tid >> 6);
-        if (g >= nb || sk.blk(g)) return;
+        if (g >= nb || sk.blk(g, slot)) return;
         const int64_t r0 = row_ptr[g];
         const int nr = int(row_ptr[g + 1] - r0);
         const int64_t c0 = col_ptr[g];
@@ -724,13 +769,16 @@ __global__ void k_prolong(const int32_t *__restrict__ t_ptr, const int32_t *__re
                           const PT *__restrict__ phi, const double *__restrict__ zg, const double *__restrict__ zc,
                           double *__restrict__ z, int64_t n, Skip sk) {
     const int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (d >= n || sk.dof(d)) return;
-    z[d] = prolong_one<PT, W, BLK>(d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
+    const int slot = blockIdx.y;
+    if (d >= n || sk.dof(d, slot)) return;
+    z[slot * sk.sl.n + d] = prolong_one<PT, W, BLK>(d, t_ptr, t_pos, zloc + slot * sk.sl.zl, dof_blk, dof_lr, row_ptr,
+                                                    col_ptr, val_off, phi, zg + slot * sk.sl.cols,
+                                                    zc + slot * sk.sl.n);
 }
 
 // The same over the row blocks of the Krylov iteration (256 threads, rows
-// [row0[b], row1[b]) of one problem), also writing the block's partial of
-// r . z for the next CG step.
+// [row0[b], row1[b]) of one problem in one slot: rows of slot k are
+// k n + d), also writing the block's partial of r . z for the next CG step.
 template <typename PT, int W, bool BLK>
 __global__ __launch_bounds__(256) void k_prolong_dot(
     const int32_t *__restrict__ t_ptr, const int32_t *__restrict__ t_pos, const double *__restrict__ zloc,
@@ -742,13 +790,19 @@ __global__ __launch_bounds__(256) void k_prolong_dot(
     __shared__ double sh[4];
     const int blk = blockIdx.x;
     const int row0 = kb_row0[blk], row1 = kb_row1[blk];
-    if (sk.dof(row0)) return;
+    const int slot = sk.sl.ns > 1 ? int(row0 / sk.sl.n) : 0;
+    const int64_t base = slot * sk.sl.n;
+    if (sk.dof(row0 - base, slot)) return;
+    zloc += slot * sk.sl.zl;
+    zg += slot * sk.sl.cols;
+    zc += base;
     double dot = 0.0;
-    for (int d = row0 + threadIdx.x; d < row1; d += 256) {
-        const double v =
+    for (int v = row0 + threadIdx.x; v < row1; v += 256) {
+        const int64_t d = v - base;
+        const double val =
             prolong_one<PT, W, BLK>(d, t_ptr, t_pos, zloc, dof_blk, dof_lr, row_ptr, col_ptr, val_off, phi, zg, zc);
-        z[d] = v;
-        dot += rvec[d] * v;
+        z[v] = val;
+        dot += rvec[v] * val;
     }
     dot = block_sum<double, 256>(dot, sh);
     if (threadIdx.x == 0) partial[blk] = dot;

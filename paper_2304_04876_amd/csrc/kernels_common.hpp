@@ -116,10 +116,29 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     return t;
 }
 
+// Right-hand-side slots: a handle may hold `ns` right-hand sides of every
+// problem, all preconditioned with the one factored operator.  The vectors
+// of the apply and the Krylov iteration hold the slots one after another
+// (dof d of slot k at k n + d), and every buffer of per-slot intermediate
+// results (local results, coarse partials, r_0, z_0 and its repetitions,
+// the coarse part of the prolongation) is laid out the same way with the
+// strides below.  Kernels over the operator's work items take the slot as
+// blockIdx.y (or loop over the slots where the operator's values are held
+// in registers).
+struct Slots {
+    int ns = 1;
+    int64_t n = 0;       // dofs of one slot (the operator's dimension)
+    int64_t zl = 0;      // local rows
+    int64_t part = 0;    // coarse restriction partials
+    int64_t n0 = 0;      // coarse columns
+    int64_t cols = 0;    // repetitions of z_0 in block-column order
+};
+
 // Which parts of a launch to skip: a handle may pack several independent
-// problems (block-diagonal A); `flag[k]` != 0 means problem k is finished or
-// idle and its subdomains, coarse blocks, coarse columns and dofs are left
-// alone.  flag == nullptr: nothing is skipped.
+// problems (block-diagonal A), each with `ns` slots; `flag[k nprob + p]` !=
+// 0 means problem p in slot k is finished or idle and its subdomains,
+// coarse blocks, coarse columns and dofs are left alone in that slot.
+// flag == nullptr: nothing is skipped.
 struct Skip {
     const int *flag = nullptr;
     const int32_t *sub_prob = nullptr;   // subdomain -> problem
@@ -127,18 +146,26 @@ struct Skip {
     const int32_t *cprob = nullptr;      // coarse column -> problem
     const int64_t *prob_ptr = nullptr;   // dof offsets of the problems
     int nprob = 1;
-    __device__ __forceinline__ bool sub(int i) const { return flag && flag[nprob > 1 ? sub_prob[i] : 0]; }
-    __device__ __forceinline__ bool blk(int g) const { return flag && flag[nprob > 1 ? blk_prob[g] : 0]; }
-    __device__ __forceinline__ bool col(int c) const { return flag && flag[nprob > 1 ? cprob[c] : 0]; }
-    __device__ __forceinline__ bool dof(int64_t d) const {
+    Slots sl;
+    __device__ __forceinline__ bool sub(int i, int k = 0) const {
+        return flag && flag[k * nprob + (nprob > 1 ? sub_prob[i] : 0)];
+    }
+    __device__ __forceinline__ bool blk(int g, int k = 0) const {
+        return flag && flag[k * nprob + (nprob > 1 ? blk_prob[g] : 0)];
+    }
+    __device__ __forceinline__ bool col(int c, int k = 0) const {
+        return flag && flag[k * nprob + (nprob > 1 ? cprob[c] : 0)];
+    }
+    // d: a dof of the operator (0 <= d < n), in slot k
+    __device__ __forceinline__ bool dof(int64_t d, int k = 0) const {
         if (!flag) return false;
-        if (nprob == 1) return flag[0];
+        if (nprob == 1) return flag[k];
         int lo = 0, hi = nprob;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (prob_ptr[mid] <= d) lo = mid; else hi = mid;
         }
-        return flag[lo];
+        return flag[k * nprob + lo];
     }
 };
 

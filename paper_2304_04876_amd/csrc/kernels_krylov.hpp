@@ -111,11 +111,16 @@ __device__ __forceinline__ double sell_row(const Sell &A, int i, const double *_
     return acc;
 }
 
+// y = A x on n rows; with right-hand-side slots (n a multiple of the
+// operator's dimension pn) row k pn + i of slot k is row i of A applied to
+// slot k of x
 template <bool D16>
-__global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y, int n) {
+__global__ __launch_bounds__(KNT) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y, int n,
+                                              int pn) {
     const int i = blockIdx.x * KNT + threadIdx.x;
     if (i >= n) return;
-    y[i] = sell_row<D16>(A, i, x);
+    const int base = pn < n ? (i / pn) * pn : 0;
+    y[i] = sell_row<D16>(A, i - base, x + base);
 }
 
 // One row of A (z + beta p_old): the vector is formed on the fly from z and
@@ -171,15 +176,18 @@ template <bool D16>
 __global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__restrict__ z,
                                                        const double *__restrict__ pold, double *__restrict__ pnew,
                                                        double *__restrict__ q, double *__restrict__ partial,
-                                                       const KState *st, KBlk kb) {
+                                                       const KState *st, KBlk kb, int pn) {
     const int blk = kb.base + blockIdx.x;
     const KState &S = st[kb.prob[blk]];
     if (S.done) return;
     __shared__ double sh[KNT / 64];
     const double beta = S.beta;
+    // rows of right-hand-side slot k are k pn + i (a block never crosses a slot)
+    const int row0 = kb.row0[blk];
+    const int base = row0 >= pn ? (row0 / pn) * pn : 0;
     double dot = 0.0;
-    for (int i = kb.row0[blk] + threadIdx.x; i < kb.row1[blk]; i += KNT) {
-        const double acc = sell_row_p<D16>(A, i, z, pold, beta);
+    for (int i = row0 + threadIdx.x; i < kb.row1[blk]; i += KNT) {
+        const double acc = sell_row_p<D16>(A, i - base, z + base, pold + base, beta);
         const double pi = p_next(beta, pold[i], z[i]);
         pnew[i] = pi;
         __builtin_nontemporal_store(acc, &q[i]);   // (read once, by the update)

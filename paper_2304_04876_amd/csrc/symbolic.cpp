@@ -73,6 +73,8 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
     if (o.flags & ~uint64_t(GDSW_FLAG_GRAPHS)) fail(GDSW_ERR_INVALID_ARG, "unknown flags");
     if (o.ilu_level < 0 || o.ilu_level > 8) fail(GDSW_ERR_INVALID_ARG, "ilu_level out of range");
     if (o.ilu_factor_sweeps < 0 || o.ilu_factor_sweeps > 100) fail(GDSW_ERR_INVALID_ARG, "ilu_factor_sweeps");
+    if (o.slots == 0) o.slots = 1;
+    if (o.slots < 0 || o.slots > 4096) fail(GDSW_ERR_INVALID_ARG, "slots out of range");
     if (Z == nullptr && n_null > 1) fail(GDSW_ERR_INVALID_ARG, "Z == NULL needs n_null <= 1");
     if (Z != nullptr && (n_null <= 0 || n_null > 64)) fail(GDSW_ERR_INVALID_ARG, "n_null out of range");
     s.opt = o;

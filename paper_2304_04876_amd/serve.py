@@ -1,16 +1,21 @@
 """Serving loop: factored GDSW preconditioners stay resident on the GPU and
 incoming right-hand sides are solved with continuous batching.
 
-Every operator owns a number of *slots* (copies of the operator packed in
-one batch handle of the library).  A request names an operator and a
-right-hand side; it waits in that operator's queue until one of its slots is
-free, is then loaded into the slot and started, and from there on advances
-together with every other running slot: each step runs ``step_iters`` CG
-iterations of all running slots in shared kernel launches.  A slot that
-converges returns its result at the next step boundary and takes the next
-queued request at once.  The number of slots per operator is chosen to fit
-an HBM budget.  Each slot's arithmetic is independent of what the other
-slots hold, so a result is bit-identical alone and in the mix.
+All operators sit in one handle of the library, factored once; the handle
+holds S right-hand-side *slots* of every operator (its `slots` option): per
+slot only the Krylov vectors and the apply's intermediate results, while
+the local factors, the coarse basis, A_0^{-1} and the matrix are shared by
+all slots of an operator (the register-resident local solves read each
+factor entry once for all slots of a subdomain).  A request names an
+operator and a right-hand side; it waits in that operator's queue until one
+of its slots is free, is then loaded into the slot and started, and from
+there on advances together with every other running slot: each step runs
+``step_iters`` CG iterations of all running slots in shared kernel
+launches.  A slot that converges returns its result at the next step
+boundary and takes the next queued request at once.  S comes from an HBM
+budget: the operators' resident bytes plus S slot workspaces (the library
+reports both) must fit it.  Each slot's arithmetic is independent of what
+the other slots hold, so a result is bit-identical alone and in the mix.
 
 This module is driver code over the C ABI (``binding``): all numerical work
 runs in the library's kernels.
@@ -65,39 +70,47 @@ class Server:
         self.opts = dict(local=local, local_prec=local_prec, basis_prec=basis_prec,
                          flags=B.FLAG_GRAPHS if graphs else 0)
         self.stream = stream
+        self.hbm_budget_bytes = int(hbm_budget_bytes)
         if slots_per_op is None:
             slots_per_op = self._slots_for_budget(hbm_budget_bytes)
         if slots_per_op < 1:
             raise B.GdswError(5, "HBM budget too small for one slot per operator")
         self.slots_per_op = slots_per_op
-        probs = []
-        self.slot_op = []
-        for k, op in enumerate(operators):
-            for _ in range(slots_per_op):
-                probs.append((op.A, op.part, op.n_parts))
-                self.slot_op.append(k)
-        self.h = B.gdsw_analyze_batch(probs, options=B.gdsw_default_options(**self.opts))
+        nops = len(operators)
+        self.h = B.gdsw_analyze_batch([(op.A, op.part, op.n_parts) for op in operators],
+                                      options=B.gdsw_default_options(slots=slots_per_op, **self.opts))
         B.gdsw_factor(self.h, stream)
+        # Krylov problem v = k * nops + p: operator p in slot k
         self.offs = B.gdsw_problem_offsets(self.h)
+        self.slot_op = [v % nops for v in range(slots_per_op * nops)]
         n = int(self.offs[-1])
         self.b = torch.zeros(n, dtype=torch.float64, device="cuda")
         self.x = torch.zeros_like(self.b)
         B.gdsw_slots_begin(self.h, self.b, self.x, rtol, maxit, stream)
-        self.device_bytes = B.gdsw_get_info(self.h)["device_bytes"] + 2 * 8 * n
+        info = B.gdsw_get_info(self.h)
+        # device bytes: the handle (operators once + per-slot workspaces)
+        # and the right-hand sides and solutions of every slot
+        self.device_bytes = info["device_bytes"] + 2 * 8 * n
+        self.operator_bytes = info["device_bytes"] - slots_per_op * info["slot_bytes"]
+        self.slot_workspace_bytes = info["slot_bytes"] + 2 * 8 * n // slots_per_op
 
     def _slots_for_budget(self, budget):
         """Slots per operator that fit `budget` device bytes (0: four): the
-        footprint of one slot per operator is measured on a probe handle."""
+        operators' resident bytes and one slot's workspace are read from a
+        one-slot probe handle."""
         if not budget:
             return 4
         probe = B.gdsw_analyze_batch([(op.A, op.part, op.n_parts) for op in self.ops],
-                                     options=B.gdsw_default_options(**self.opts))
+                                     options=B.gdsw_default_options(slots=1, **self.opts))
         try:
             B.gdsw_factor(probe, self.stream)
-            per_slot = B.gdsw_get_info(probe)["device_bytes"] + 2 * 8 * sum(op.n for op in self.ops)
+            info = B.gdsw_get_info(probe)
         finally:
             B.gdsw_destroy(probe)
-        return int(budget // per_slot)
+        n = sum(op.n for op in self.ops)
+        resident = info["device_bytes"] - info["slot_bytes"]
+        per_slot = info["slot_bytes"] + 2 * 8 * n
+        return int((budget - resident) // per_slot)
 
     def close(self):
         if getattr(self, "h", None):

@@ -46,13 +46,18 @@ def test_served_results_equal_alone():
 
 def test_budget_admission():
     ops = [P.poisson3d(10, 2), P.poisson3d(12, 2)]
-    # a budget that holds exactly one slot per operator
     probe = SV.Server(ops, slots_per_op=1, local=B.LOCAL_ILU0, local_prec=B.FP16, basis_prec=B.FP32)
+    resident, per_slot = probe.operator_bytes, probe.slot_workspace_bytes
     one = probe.device_bytes
     probe.close()
-    srv = SV.Server(ops, hbm_budget_bytes=int(1.5 * one), local=B.LOCAL_ILU0, local_prec=B.FP16,
-                    basis_prec=B.FP32)
-    assert srv.slots_per_op == 1
+    # the operators are held once, each slot adds only its workspace
+    assert 0 < per_slot < resident
+    assert one == resident + per_slot
+    # a budget for the operators and two and a half slot workspaces
+    srv = SV.Server(ops, hbm_budget_bytes=int(resident + 2.5 * per_slot), local=B.LOCAL_ILU0,
+                    local_prec=B.FP16, basis_prec=B.FP32)
+    assert srv.slots_per_op == 2
+    assert srv.device_bytes == resident + 2 * per_slot
     srv.close()
     with pytest.raises(B.GdswError):
         SV.Server(ops, hbm_budget_bytes=1000, local=B.LOCAL_ILU0)
