@@ -372,6 +372,8 @@ def main():
     ap.add_argument("--workload", choices=["all", "poisson", "elasticity", "batch", "serve"], default="all",
                     help="all (default): the headline line with the other workloads as sub-records")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-seq-stride", type=int, default=1,
+                    help="batch workload: time the sequential FP64 reference on every k-th problem")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--graphs", action="store_true", help="queue CG iterations as captured HIP graphs")
@@ -394,7 +396,7 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch":
-        print(json.dumps(bench_batch(args)), flush=True)
+        print(json.dumps(bench_batch(args, sequential_stride=args.batch_seq_stride)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)

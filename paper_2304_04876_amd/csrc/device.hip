@@ -269,6 +269,7 @@ struct Device {
     int ns = 1, nvp = 1;
     int64_t nv = 0;
     Slots slots{};
+    int32_t *sub_order = nullptr;   // local-solve launch order (decreasing size), or null
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
@@ -408,6 +409,18 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
     D.kmask = D.alloc<int>(D.nvp);
     D.sub_prob = D.upload(S.sub_prob, s);
     D.prob_ptr = D.upload(S.prob_ptr, s);
+    {
+        // the local solves start with the largest subdomains (a stable sort
+        // by decreasing size; none when all have one size)
+        std::vector<int32_t> ord(S.np);
+        for (int i = 0; i < S.np; ++i) ord[i] = i;
+        auto sz = [&](int i) { return S.ov_ptr[i + 1] - S.ov_ptr[i]; };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sz(a) > sz(b); });
+        bool uniform = true;
+        for (int i = 1; i < S.np && uniform; ++i) uniform = sz(i) == sz(0);
+        if (!uniform) D.sub_order = D.upload(ord, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
     {
         std::vector<int32_t> bprob(std::max<int32_t>(S.blk.nb, 1), 0);
         for (int g = 0; g < S.blk.nb; ++g)
@@ -1153,6 +1166,7 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
     Device &D = *h->dev;
     Skip sk = sk_in;
     sk.sl = D.slots;
+    sk.order = D.sub_order;
     if (!sk.flag) sk.nprob = S.nprob;
     const bool local = (which & 1) || which == 4;
     const bool coarse = (which & 2) && D.A0inv != nullptr;
@@ -1901,6 +1915,7 @@ static float time_local(gdsw_handle_s *h, int v, int reps, hipStream_t s, hipEve
     Device &D = *h->dev;
     Skip none;
     none.sl = D.slots;
+    none.order = D.sub_order;
     if (!launch_local_variant<VT>(S, D, v, D.kr, none, s)) return -1.0f;
     HIPCHK(hipEventRecord(e0, s));
     for (int k = 0; k < reps; ++k) launch_local_variant<VT>(S, D, v, D.kr, none, s);
@@ -2063,6 +2078,7 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
             hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
             Skip none;
             none.sl = D.slots;
+            none.order = D.sub_order;
             switch (S.opt.local_prec) {
                 case GDSW_FP64: fits = launch_local_variant<double>(S, D, local_variant, D.kr, none, s); break;
                 case GDSW_FP32: fits = launch_local_variant<float>(S, D, local_variant, D.kr, none, s); break;

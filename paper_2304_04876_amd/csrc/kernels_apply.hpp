@@ -37,11 +37,12 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     // FP64 factors are never scaled (dscale is null for them), and their LDS
     // holds no scale slots
     constexpr bool scaled = !std::is_same<VT, double>::value;
+    const int i = sk.sub_at(blockIdx.x);
     int slot = MS ? 0 : int(blockIdx.y);
     if constexpr (MS) {
-        while (slot < sk.sl.ns && sk.sub(blockIdx.x, slot)) ++slot;
+        while (slot < sk.sl.ns && sk.sub(i, slot)) ++slot;
         if (slot == sk.sl.ns) return;
-    } else if (sk.sub(blockIdx.x, slot)) {
+    } else if (sk.sub(i, slot)) {
         return;
     }
     extern __shared__ __align__(16) unsigned char smraw[];
@@ -49,7 +50,6 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     AT *bufB = bufA + NT * R;
     AT *sdinv = bufB + NT * R;
     double *sscale = reinterpret_cast<double *>(sdinv + NT * R);   // used with dscale only
-    const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
     const int64_t eo = ell_off[i];
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
         // the next slot that runs: its gathered r, after every thread is
         // done with the LDS vectors of this one
         ++slot;
-        while (slot < sk.sl.ns && sk.sub(blockIdx.x, slot)) ++slot;
+        while (slot < sk.sl.ns && sk.sub(i, slot)) ++slot;
         if (slot == sk.sl.ns) break;
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -209,12 +209,11 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
     double *__restrict__ zloc, int maxrows, void *__restrict__ gbuf, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    const int slot = blockIdx.y;
-    if (sk.sub(blockIdx.x, slot)) return;
+    const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
+    if (sk.sub(i, slot)) return;
     r += slot * sk.sl.n;
     zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
     // the three vectors live in LDS, or (subdomains too large for it) in a
@@ -275,14 +274,13 @@ __global__ __launch_bounds__(1024) void k_band_apply(
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
     const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
     using AT = typename AccOf<VT>::type;
-    const int slot = blockIdx.y;
-    if (sk.sub(blockIdx.x, slot) || band_inverted(bw[blockIdx.x]) != INV) return;
+    const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
+    if (sk.sub(i, slot) || band_inverted(bw[i]) != INV) return;
     r += slot * sk.sl.n;
     zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *sT = y + maxrows;
-    const int i = blockIdx.x;
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
     // gathers and stores in batches of GB rows per thread, every load of a

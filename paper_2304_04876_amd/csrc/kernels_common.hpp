@@ -147,6 +147,12 @@ struct Skip {
     const int64_t *prob_ptr = nullptr;   // dof offsets of the problems
     int nprob = 1;
     Slots sl;
+    // launch order of the local solves: workgroup b takes subdomain
+    // order[b] (subdomains by decreasing size, so that the largest start
+    // first and the hardware dispatcher, handing each free compute unit the
+    // next workgroup, packs the smaller ones behind them); null: b itself
+    const int32_t *order = nullptr;
+    __device__ __forceinline__ int sub_at(int b) const { return order ? order[b] : b; }
     __device__ __forceinline__ bool sub(int i, int k = 0) const {
         return flag && flag[k * nprob + (nprob > 1 ? sub_prob[i] : 0)];
     }

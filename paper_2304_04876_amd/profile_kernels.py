@@ -7,7 +7,10 @@ rocprofv3 (kernel trace, FETCH_SIZE / WRITE_SIZE passes):
   boxes, banded Cholesky), ``--reps`` times;
 * the full preconditioner apply once;
 * a plain device copy of a known size (``--copy-mib`` MiB read and written),
-  ``--reps`` times, to calibrate the byte counters.
+  ``--reps`` times, to calibrate the byte counters;
+* with ``--setup-only``, only the numerical setup (band Cholesky, inverted
+  diagonal blocks, extension, coarse matrix and its Gauss-Jordan inverse),
+  for the arithmetic counters of the dense setup kernels.
 
 Usage: python -m paper_2304_04876_amd.profile_kernels [--local ilu0|exact]
 """
@@ -28,6 +31,8 @@ def main():
     ap.add_argument("--elasticity", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the launch configurations first "
                     "(as the benchmark does), so the counters see the configuration it times")
+    ap.add_argument("--setup-only", action="store_true", help="only the numerical setup (local factors, "
+                    "extension, coarse matrix and its inverse), for counters of the setup kernels")
     a = ap.parse_args()
 
     import torch
@@ -45,6 +50,11 @@ def main():
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                local=B.LOCAL_ILU0 if a.local == "ilu0" else B.LOCAL_EXACT, local_prec=precs[a.prec],
                basis_prec=B.FP64 if a.prec == "fp64" else B.FP32)
+    torch.cuda.synchronize()
+    if a.setup_only:
+        g.close()
+        print("[profile] done", file=sys.stderr, flush=True)
+        return
     r = torch.from_numpy(P.rhs_uniform(pr.n, 0)).cuda()
     z = torch.zeros_like(r)
     torch.cuda.synchronize()
