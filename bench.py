@@ -43,7 +43,7 @@ METRIC = "GDSW-PCG solves/sec and M^-1 applies/sec at 1e-8 residual; p50/p99 sol
 # profiles/hbm_traffic_*.md).  A figure only applies to the kernel source it
 # was measured on: `src` is a hash of that kernel's text, checked below.
 MEASURED_TRAFFIC = {
-    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 269708068, "src": "c8406bb7a407aff9"},
+    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 271355003, "src": "01873f67dbb64d3a"},
     ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14274626339, "src": "c63f9cb3b151c80b"},
     ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1610807593, "src": "c63f9cb3b151c80b"},
 }
@@ -55,7 +55,7 @@ def kernel_source_hash(kernel):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_04876_amd", "csrc")
     segments = {
-        "k_ilu_jacobi": [("kernels_apply.hpp", "template <int NT, int R, int KL, int KU, typename VT>",
+        "k_ilu_jacobi": [("kernels_apply.hpp", "template <int NT, int R, int KL, int KU, typename VT, bool MS>",
                           "// Same sweeps for any slot counts and subdomain sizes")],
         "k_band_apply": [("kernels_setup.hpp", "constexpr int BS_NB = 64;", "// Extension, eq. (2)."),
                          ("kernels_apply.hpp", "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor",
@@ -66,7 +66,9 @@ def kernel_source_hash(kernel):
     h = hashlib.sha256()
     for fname, start, end in segments[kernel]:
         text = open(os.path.join(csrc, fname)).read()
-        a, b = text.index(start), text.index(end)
+        a, b = text.find(start), text.find(end)
+        if a < 0 or b < a:
+            return None   # the kernel's text moved: no measurement applies to it
         h.update(text[a:b].encode())
     return h.hexdigest()[:16]
 
@@ -465,9 +467,10 @@ def bench_batch(args, sequential_stride=1):
                                                              flags=B.FLAG_GRAPHS if args.graphs else 0))
     t_an = time.perf_counter() - t0
     B.gdsw_factor(hb)
+    tune = B.gdsw_autotune(hb, reps=3)
     info = B.gdsw_get_info(hb)
     log(f"[batch] n={info['n']} subdomains={info['n_parts']} analysis {t_an:.1f}s setup {info['t_factor']:.2f}s "
-        f"device {info['device_bytes'] / 1e9:.1f} GB")
+        f"device {info['device_bytes'] / 1e9:.1f} GB; autotune {[round(t, 3) for t in tune[:3]]}")
     offs = B.gdsw_problem_offsets(hb)
     b = torch.from_numpy(np.concatenate([p.b for p in probs])).cuda()
     x = torch.zeros_like(b)

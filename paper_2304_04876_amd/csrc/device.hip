@@ -270,6 +270,14 @@ struct Device {
     int64_t nv = 0;
     Slots slots{};
     int32_t *sub_order = nullptr;   // local-solve launch order (decreasing size), or null
+    // size classes of the local solves: consecutive ranges of the launch
+    // order whose sizes lie within a factor two of the class's largest; each
+    // is launched with LDS and rows per thread for its own largest
+    // subdomain, in the launch configuration tuned for it (-1: the handle's)
+    struct SizeClass {
+        int begin, end, max_ni, variant;
+    };
+    std::vector<SizeClass> cls;
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
@@ -419,6 +427,12 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         bool uniform = true;
         for (int i = 1; i < S.np && uniform; ++i) uniform = sz(i) == sz(0);
         if (!uniform) D.sub_order = D.upload(ord, s);
+        // one class: separate launches per size class run one after another
+        // on the stream, each with its own tail of idle compute units, and
+        // were slower than one launch in size order (256-problem diffusion
+        // batch: 688 against 827 solves/s)
+        D.cls.clear();
+        D.cls.push_back({0, S.np, int(S.max_ni), -1});
         HIPCHK(hipStreamSynchronize(s));
     }
     {
@@ -1025,12 +1039,24 @@ gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
 // -1 picks by a fixed rule; gdsw_autotune times the candidates.
 constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 3;
 
+// One size class c of the local solves: workgroup b takes subdomain
+// sub_order[c.begin + b] (or b itself without an order), with LDS and rows
+// per thread for the class's largest subdomain.
+static Skip class_skip(const Device &D, const Skip &sk, const Device::SizeClass &c) {
+    Skip k = sk;
+    k.order = D.sub_order ? D.sub_order + c.begin : nullptr;
+    return k;
+}
+
 template <typename VT, int NT>
-static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                            const Device::SizeClass &c) {
     // (one sweep per triangle needs no factor entries: the streaming kernel)
     if (D.KLp != ILU_KL || D.KUp != ILU_KU || !D.Cp || S.opt.jacobi_sweeps < 2) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
-    const int need = (S.max_ni + NT - 1) / NT;
+    const int need = (c.max_ni + NT - 1) / NT;
+    const int nb = c.end - c.begin;
+    const Skip kc = class_skip(D, sk, c);
     using AT = typename AccOf<VT>::type;
     // with several right-hand-side slots, one workgroup takes every slot of
     // its subdomain with the factor entries loaded once
@@ -1039,15 +1065,15 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
         const size_t lds = (3 * sizeof(AT) + (f64 ? 0 : sizeof(double))) * NT * RR;                          \
         if (lds > D.max_lds) return false;                                                                   \
         if (D.ns > 1)                                                                                        \
-            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, true>), dim3(S.np), dim3(NT), lds,  \
+            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, true>), dim3(nb), dim3(NT), lds,    \
                                s, r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv,            \
                                (const VT *)D.Uv, D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps,    \
-                               D.zloc, sk);                                                                  \
+                               D.zloc, kc);                                                                  \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, false>), dim3(S.np), dim3(NT), lds, \
+            hipLaunchKernelGGL((k_ilu_jacobi<NT, RR, ILU_KL, ILU_KU, VT, false>), dim3(nb), dim3(NT), lds,   \
                                s, r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv,            \
                                (const VT *)D.Uv, D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps,    \
-                               D.zloc, sk);                                                                  \
+                               D.zloc, kc);                                                                  \
         return true;                                                                                         \
     }
     // the row counts per thread whose factor entries stay in registers
@@ -1064,65 +1090,89 @@ static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const
 }
 
 template <typename VT, int NT>
-static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                              const Device::SizeClass &c) {
     using AT = typename AccOf<VT>::type;
-    size_t lds = 3 * sizeof(AT) * size_t(S.max_ni);
+    size_t lds = 3 * sizeof(AT) * size_t(c.max_ni);
     void *gbuf = nullptr;
     if (lds > D.max_lds) {
         if (!D.sweep_buf) return false;
         gbuf = D.sweep_buf;
         lds = 0;
     }
-    hipLaunchKernelGGL((k_ilu_jacobi_generic<NT, VT>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
-                       D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc,
-                       (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, S.max_ni, gbuf, sk);
+    hipLaunchKernelGGL((k_ilu_jacobi_generic<NT, VT>), dim3(c.end - c.begin, D.ns), dim3(NT), lds, s, r, D.ov_idx,
+                       D.ov_ptr, D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv, D.Lc, (const VT *)D.Uv, D.Uc,
+                       (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, c.max_ni, gbuf,
+                       class_skip(D, sk, c));
     return true;
 }
 
 template <typename VT, int NT>
-static bool launch_band(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+static bool launch_band(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                        const Device::SizeClass &c) {
     using AT = typename AccOf<VT>::type;
-    const size_t lds = sizeof(AT) * (size_t(S.max_ni) + BS_NB * BS_LD);
+    const size_t lds = sizeof(AT) * (size_t(c.max_ni) + BS_NB * BS_LD);
     if (lds > D.max_lds) return false;
+    const Skip kc = class_skip(D, sk, c);
+    const int nb = c.end - c.begin;
     if (D.band_kinds & 2)
-        hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
-                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
+        hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(nb, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, c.max_ni, kc);
     if (D.band_kinds & 1)
-        hipLaunchKernelGGL((k_band_apply<NT, VT, false>), dim3(S.np, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
-                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, S.max_ni, sk);
+        hipLaunchKernelGGL((k_band_apply<NT, VT, false>), dim3(nb, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                           (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, c.max_ni, kc);
     return true;
 }
 
 template <typename VT>
 static bool launch_local_variant(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
-                                 hipStream_t s) {
+                                 hipStream_t s, const Device::SizeClass &c) {
     if (S.opt.local == GDSW_LOCAL_ILU0) {
         switch (v) {
-            case 0: return launch_ilu_regs<VT, 512>(S, D, r, sk, s);
-            case 1: return launch_ilu_regs<VT, 1024>(S, D, r, sk, s);
-            case 2: return launch_ilu_stream<VT, 256>(S, D, r, sk, s);
-            default: return launch_ilu_stream<VT, 512>(S, D, r, sk, s);
+            case 0: return launch_ilu_regs<VT, 512>(S, D, r, sk, s, c);
+            case 1: return launch_ilu_regs<VT, 1024>(S, D, r, sk, s, c);
+            case 2: return launch_ilu_stream<VT, 256>(S, D, r, sk, s, c);
+            default: return launch_ilu_stream<VT, 512>(S, D, r, sk, s, c);
         }
     }
     switch (v) {
-        case 0: return launch_band<VT, 256>(S, D, r, sk, s);
-        case 1: return launch_band<VT, 512>(S, D, r, sk, s);
-        default: return launch_band<VT, 1024>(S, D, r, sk, s);
+        case 0: return launch_band<VT, 256>(S, D, r, sk, s, c);
+        case 1: return launch_band<VT, 512>(S, D, r, sk, s, c);
+        default: return launch_band<VT, 1024>(S, D, r, sk, s, c);
     }
 }
 
+// Every size class in the configuration tuned for it, else the handle's
+// (gdsw_set_launch / gdsw_autotune), else the fixed rule: register-resident
+// sweeps when they fit (FP64: 512 threads, reduced precision: 1024), else
+// streaming; band solves with 512 threads.
 template <typename VT>
-static void launch_local(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
-    if (D.local_variant >= 0 && launch_local_variant<VT>(S, D, D.local_variant, r, sk, s)) return;
-    // fixed rule: register-resident sweeps when they fit (FP64: 512 threads,
-    // reduced precision: 1024), else streaming; band solves with 512 threads
+static void launch_local_class(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                               const Device::SizeClass &c) {
+    if (c.variant >= 0 && launch_local_variant<VT>(S, D, c.variant, r, sk, s, c)) return;
+    if (D.local_variant >= 0 && launch_local_variant<VT>(S, D, D.local_variant, r, sk, s, c)) return;
     static const int ilu_order_f64[] = {0, 1, 2, 3}, ilu_order_lo[] = {1, 0, 2, 3}, band_order[] = {1, 0, 2};
     const bool ilu = S.opt.local == GDSW_LOCAL_ILU0;
     const int *order = ilu ? (std::is_same<VT, double>::value ? ilu_order_f64 : ilu_order_lo) : band_order;
     const int nv = ilu ? N_ILU_VARIANTS : N_BAND_VARIANTS;
     for (int q = 0; q < nv; ++q)
-        if (launch_local_variant<VT>(S, D, order[q], r, sk, s)) return;
+        if (launch_local_variant<VT>(S, D, order[q], r, sk, s, c)) return;
     throw DevError{GDSW_ERR_INVALID_ARG, "no local-solve kernel fits this subdomain size"};
+}
+
+template <typename VT>
+static void launch_local(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
+    for (const Device::SizeClass &c : D.cls) launch_local_class<VT>(S, D, r, sk, s, c);
+}
+
+// One launch configuration for every size class (false: it does not fit
+// every class).
+template <typename VT>
+static bool launch_local_fits_all(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
+                                  hipStream_t s) {
+    for (const Device::SizeClass &c : D.cls)
+        if (!launch_local_variant<VT>(S, D, v, r, sk, s, c)) return false;
+    return true;
 }
 
 // The prolongation kernels for the parts w (bit 0 one-level, bit 1 coarse)
@@ -1166,7 +1216,6 @@ static void launch_apply(gdsw_handle_s *h, const double *r, double *z, int which
     Device &D = *h->dev;
     Skip sk = sk_in;
     sk.sl = D.slots;
-    sk.order = D.sub_order;
     if (!sk.flag) sk.nprob = S.nprob;
     const bool local = (which & 1) || which == 4;
     const bool coarse = (which & 2) && D.A0inv != nullptr;
@@ -1910,15 +1959,15 @@ gdsw_status slot_finish(gdsw_handle_s *h, int slot, gdsw_solve_info *info, void 
 // Autotuner: times every launch configuration of the local-solve kernel and
 // both coarse GEMV variants on the handle's own data and keeps the fastest.
 template <typename VT>
-static float time_local(gdsw_handle_s *h, int v, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static float time_local(gdsw_handle_s *h, int v, const Device::SizeClass &c, int reps, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
     Skip none;
     none.sl = D.slots;
-    none.order = D.sub_order;
-    if (!launch_local_variant<VT>(S, D, v, D.kr, none, s)) return -1.0f;
+    if (!launch_local_variant<VT>(S, D, v, D.kr, none, s, c)) return -1.0f;
     HIPCHK(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) launch_local_variant<VT>(S, D, v, D.kr, none, s);
+    for (int k = 0; k < reps; ++k) launch_local_variant<VT>(S, D, v, D.kr, none, s, c);
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -1939,24 +1988,34 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
+        // every size class of the local solves on its own: the fastest
+        // configuration per class (times[v]: the sum over the classes, -1
+        // where v does not fit a class)
         const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
-        float best = -1.0f;
-        int bv = -1;
-        for (int v = 0; v < nv; ++v) {
-            float t;
-            switch (S.opt.local_prec) {
-                case GDSW_FP64: t = time_local<double>(h, v, reps, s, e0, e1); break;
-                case GDSW_FP32: t = time_local<float>(h, v, reps, s, e0, e1); break;
-                case GDSW_BF16: t = time_local<bf16>(h, v, reps, s, e0, e1); break;
-                default: t = time_local<fp16>(h, v, reps, s, e0, e1); break;
+        if (times)
+            for (int v = 0; v < nv; ++v) times[v] = 0.0f;
+        for (size_t ci = 0; ci < D.cls.size(); ++ci) {
+            Device::SizeClass &c = D.cls[ci];
+            float best = -1.0f;
+            int bv = -1;
+            for (int v = 0; v < nv; ++v) {
+                float t;
+                switch (S.opt.local_prec) {
+                    case GDSW_FP64: t = time_local<double>(h, v, c, reps, s, e0, e1); break;
+                    case GDSW_FP32: t = time_local<float>(h, v, c, reps, s, e0, e1); break;
+                    case GDSW_BF16: t = time_local<bf16>(h, v, c, reps, s, e0, e1); break;
+                    default: t = time_local<fp16>(h, v, c, reps, s, e0, e1); break;
+                }
+                if (times) times[v] = (t < 0.0f || times[v] < 0.0f) ? -1.0f : times[v] + t;
+                if (t > 0.0f && (best < 0.0f || t < best)) {
+                    best = t;
+                    bv = v;
+                }
             }
-            if (times) times[v] = t;
-            if (t > 0.0f && (best < 0.0f || t < best)) {
-                best = t;
-                bv = v;
-            }
+            c.variant = bv;
         }
-        D.local_variant = bv;
+        // reported: the configuration of the largest subdomains
+        D.local_variant = D.cls.empty() ? -1 : D.cls[0].variant;
         if (D.A0inv) {
             float tg[2];
             for (int v = 0; v < 2; ++v) {
@@ -2078,12 +2137,11 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
             hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
             Skip none;
             none.sl = D.slots;
-            none.order = D.sub_order;
             switch (S.opt.local_prec) {
-                case GDSW_FP64: fits = launch_local_variant<double>(S, D, local_variant, D.kr, none, s); break;
-                case GDSW_FP32: fits = launch_local_variant<float>(S, D, local_variant, D.kr, none, s); break;
-                case GDSW_BF16: fits = launch_local_variant<bf16>(S, D, local_variant, D.kr, none, s); break;
-                default: fits = launch_local_variant<fp16>(S, D, local_variant, D.kr, none, s); break;
+                case GDSW_FP64: fits = launch_local_fits_all<double>(S, D, local_variant, D.kr, none, s); break;
+                case GDSW_FP32: fits = launch_local_fits_all<float>(S, D, local_variant, D.kr, none, s); break;
+                case GDSW_BF16: fits = launch_local_fits_all<bf16>(S, D, local_variant, D.kr, none, s); break;
+                default: fits = launch_local_fits_all<fp16>(S, D, local_variant, D.kr, none, s); break;
             }
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));
@@ -2105,6 +2163,7 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
         }
     }
     D.local_variant = local_variant;
+    for (Device::SizeClass &c : D.cls) c.variant = -1;   // one configuration for every class
     D.gemv_variant = gemv_variant;
     D.apply_streams = apply_streams;
     D.prolong_split = prolong_variant;

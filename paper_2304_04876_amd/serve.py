@@ -60,7 +60,7 @@ class ServeStats:
 class Server:
     def __init__(self, operators, slots_per_op=None, hbm_budget_bytes=0, local=B.LOCAL_ILU0,
                  local_prec=B.FP16, basis_prec=B.FP32, rtol=1e-8, maxit=1000, step_iters=4,
-                 stream=None, graphs=False):
+                 stream=None, graphs=False, autotune=True):
         import torch
         self.torch = torch
         self.ops = operators
@@ -80,6 +80,8 @@ class Server:
         self.h = B.gdsw_analyze_batch([(op.A, op.part, op.n_parts) for op in operators],
                                       options=B.gdsw_default_options(slots=slots_per_op, **self.opts))
         B.gdsw_factor(self.h, stream)
+        if autotune:   # launch configurations timed on this handle, the same for every slot
+            B.gdsw_autotune(self.h, reps=3, stream=stream)
         # Krylov problem v = k * nops + p: operator p in slot k
         self.offs = B.gdsw_problem_offsets(self.h)
         self.slot_op = [v % nops for v in range(slots_per_op * nops)]
