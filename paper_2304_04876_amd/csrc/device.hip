@@ -1439,13 +1439,23 @@ static void queue_cg_iteration(gdsw_handle_s *h, double *x, hipStream_t s) {
     const KBlk all{D.kb_prob, D.kb_row0, D.kb_row1, 0};
     const int nkb = D.nkb, np = D.nvp;
     double *pold = D.cg_par ? D.kp2 : D.kp, *pnew = D.cg_par ? D.kp : D.kp2;
-    // p = z + beta p fused into the product with A
-    if (D.sell.dcol)
+    // p = z + beta p fused into the product with A (with several
+    // right-hand-side slots, each matrix entry is loaded once for them)
+    if (D.ns > 1) {
+        const int nkb1 = nkb / D.ns;
+        if (D.sell.dcol)
+            hipLaunchKernelGGL(k_cg_spmv_dot_p_ms<true>, dim3(nkb1), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
+                               (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n), D.ns, nkb1);
+        else
+            hipLaunchKernelGGL(k_cg_spmv_dot_p_ms<false>, dim3(nkb1), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
+                               (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n), D.ns, nkb1);
+    } else if (D.sell.dcol) {
         hipLaunchKernelGGL(k_cg_spmv_dot_p<true>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
                            (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n));
-    else
+    } else {
         hipLaunchKernelGGL(k_cg_spmv_dot_p<false>, dim3(nkb), dim3(KNT), 0, s, D.sell, (const double *)D.kz,
                            (const double *)pold, pnew, D.kq, D.kpart, D.kst, all, int(S.n));
+    }
     hipLaunchKernelGGL(k_cg_finish, dim3(np), dim3(KFIN_NT), 0, s, D.kpart, D.pb_ptr, D.kst, D.kdone, int(KF_ALPHA), 0,
                        (const double *)nullptr);
     hipLaunchKernelGGL(k_cg_update_xr, dim3(nkb), dim3(KNT), 0, s, x, D.kr, pnew, D.kq, D.kpart2, D.kst, all);

@@ -197,6 +197,85 @@ __global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p(Sell A, const double *__r
     if (threadIdx.x == 0) partial[blk] = dot;
 }
 
+// The same for right-hand-side slots: one workgroup per row block of the
+// operator takes that block in every slot, loading each matrix entry once
+// for up to SG slots at a time (slot k's Krylov block is k nkb1 + b, its
+// rows k pn + i).  Each slot's row sums, products and block partials are
+// formed in the order of the one-slot kernel above, so the results are the
+// same bits.
+template <bool D16>
+__global__ __launch_bounds__(KNT) void k_cg_spmv_dot_p_ms(Sell A, const double *__restrict__ z,
+                                                          const double *__restrict__ pold, double *__restrict__ pnew,
+                                                          double *__restrict__ q, double *__restrict__ partial,
+                                                          const KState *st, KBlk kb, int pn, int ns, int nkb1) {
+    constexpr int SG = 4, U = 8;
+    __shared__ double sh[KNT / 64];
+    const int b = blockIdx.x;
+    const int row0 = kb.row0[b], row1 = kb.row1[b];
+    for (int g0 = 0; g0 < ns; g0 += SG) {
+        const int ng = min(SG, ns - g0);
+        bool act[SG];
+        double beta[SG], dot[SG];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+            const KState *S = j < ng ? &st[kb.prob[(g0 + j) * nkb1 + b]] : nullptr;
+            act[j] = S && !S->done;
+            beta[j] = act[j] ? S->beta : 0.0;
+            dot[j] = 0.0;
+            any |= act[j];
+        }
+        if (!any) continue;   // (the whole workgroup)
+        for (int i = row0 + threadIdx.x; i < row1; i += KNT) {
+            const int sl = i / SELL_C, lane = i % SELL_C;
+            const int64_t base = A.off[sl] + lane;
+            const int w = A.width[sl];
+            double acc[SG];
+#pragma unroll
+            for (int j = 0; j < SG; ++j) acc[j] = 0.0;
+            for (int j0 = 0; j0 < w; j0 += U) {
+                int c[U];
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {   // (as in sell_row)
+                    const int64_t e = base + int64_t(min(j0 + u, w - 1)) * SELL_C;
+                    c[u] = sell_col<D16>(A, i, e);
+                    v[u] = ld_once(&A.val[e]);
+                }
+#pragma unroll
+                for (int j = 0; j < SG; ++j) {
+                    if (!act[j]) continue;
+                    const int64_t so = int64_t(g0 + j) * pn;
+                    double zv[U], pv[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        zv[u] = z[so + c[u]];
+                        pv[u] = pold[so + c[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (j0 + u < w) acc[j] += v[u] * p_next(beta[j], pv[u], zv[u]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                if (!act[j]) continue;
+                const int64_t o = int64_t(g0 + j) * pn + i;
+                const double pi = p_next(beta[j], pold[o], z[o]);
+                pnew[o] = pi;
+                __builtin_nontemporal_store(acc[j], &q[o]);
+                dot[j] += pi * acc[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+            if (j >= ng) break;   // (uniform)
+            const double t = block_sum<double, KNT>(dot[j], sh);
+            if (threadIdx.x == 0 && act[j]) partial[(g0 + j) * nkb1 + b] = t;
+        }
+    }
+}
+
 // x += alpha p; r -= alpha q; partials of r.r (the stop test is taken
 // together with beta after the apply)
 __global__ __launch_bounds__(KNT) void k_cg_update_xr(double *__restrict__ x, double *__restrict__ r,
