@@ -334,17 +334,19 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
 /* Autotuner: times every launch configuration of the local-solve kernel
  * (ILU(0): register-resident sweeps with 512 or 1024 threads, streaming
  * sweeps with 256 or 512 threads; exact: band solves with 256, 512 or 1024
- * threads), both coarse GEMV variants, and the whole apply with the coarse
- * part on the caller's stream after the local solves or on a second stream
- * beside them, on the handle's own factors, `reps` launches each, and keeps
- * the fastest for all later applies; also the coarse part of the
- * prolongation z += Phi z0 per dof (each dof reads its row of Phi) or by
- * blocks (each block of Phi times z0 streamed once on the coarse chain, the
- * per-dof pass then adds one value).  times_ms (optional, host, 10 floats)
- * receives the average milliseconds per launch (-1 for configurations that
- * do not fit): [0..3] local variants, [4..5] GEMV variants, [6..7] apply in
- * one stream / two streams, [8..9] apply with the prolongation per dof / by
- * blocks.  Synchronises `stream`. */
+ * threads, one workgroup per subdomain or as persistent workgroups drawing
+ * subdomains from a work counter), both coarse GEMV variants, and the whole
+ * apply with the coarse part on the caller's stream after the local solves
+ * or on a second stream beside them, on the handle's own factors, `reps`
+ * launches each, and keeps the fastest for all later applies; also the
+ * coarse part of the prolongation z += Phi z0 per dof (each dof reads its row
+ * of Phi) or by blocks (each block of Phi times z0 streamed once on the
+ * coarse chain, the per-dof pass then adds one value).  times_ms (optional,
+ * host, 16 floats) receives the average milliseconds per launch (-1 for
+ * configurations that do not fit): [0..7] local variants (ILU(0): 0..3,
+ * exact: 0..5), [8..9] GEMV variants, [10..11] apply in one stream / two
+ * streams, [12..13] apply with the prolongation per dof / by blocks.
+ * Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
 /* Pins the launch configurations gdsw_autotune chooses from, for callers

@@ -325,7 +325,7 @@ def gdsw_slot_finish(h, slot, stream=None) -> dict:
 
 
 def gdsw_autotune(h, reps=10, stream=None) -> list:
-    times = np.full(10, -1.0, dtype=np.float32)
+    times = np.full(16, -1.0, dtype=np.float32)
     _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
     return times.tolist()
 

@@ -55,6 +55,8 @@ static size_t prec_size(int p) {
     }
 }
 
+constexpr int QUEUE_HALF = 4096;   // work counters per band-solve kind (one per slot)
+
 // Device address of `scratch` on GPU `dev` (which must be the current
 // device), looked up once per device and kept.
 constexpr int MAX_DEVICES = 64;
@@ -270,6 +272,7 @@ struct Device {
     int64_t nv = 0;
     Slots slots{};
     int32_t *sub_order = nullptr;   // local-solve launch order (decreasing size), or null
+    int *queue = nullptr;           // work counters of the persistent band solves (QUEUE_HALF per kind)
     // size classes of the local solves: consecutive ranges of the launch
     // order whose sizes lie within a factor two of the class's largest; each
     // is launched with LDS and rows per thread for its own largest
@@ -609,6 +612,7 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
                            band64, ne, D.dscale, D.arow, D.col);
         if (!D.band_off) D.band_off = D.upload(S.band_off, s);
         if (!D.bw) D.bw = D.upload(S.bw, s);
+        if (!D.queue) D.queue = D.alloc<int>(2 * QUEUE_HALF);
         const size_t lds = sizeof(double) * (CH_NB * CH_LD + CH_NB + size_t(std::max(S.max_bw, 1)) * CH_LD);
         if (lds > D.max_lds)
             throw DevError{GDSW_ERR_INVALID_ARG, "local bandwidth too large for the banded Cholesky"};
@@ -1035,9 +1039,11 @@ gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream) {
 // ---------------------------------------------------------------------------
 // Launch configurations of the local-solve kernels.  ILU(0): 0 = registers,
 // 512 threads; 1 = registers, 1024 threads; 2 = streaming, 256 threads;
-// 3 = streaming, 512 threads.  Exact: 0 = 256 threads, 1 = 512, 2 = 1024.
-// -1 picks by a fixed rule; gdsw_autotune times the candidates.
-constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 3;
+// 3 = streaming, 512 threads.  Exact: 0 = 256 threads, 1 = 512, 2 = 1024,
+// one workgroup per subdomain; 3, 4, 5 = the same as persistent workgroups
+// (as many as fit the compute units at once) drawing subdomains from a work
+// counter.  -1 picks by a fixed rule; gdsw_autotune times the candidates.
+constexpr int N_ILU_VARIANTS = 4, N_BAND_VARIANTS = 6;
 
 // One size class c of the local solves: workgroup b takes subdomain
 // sub_order[c.begin + b] (or b itself without an order), with LDS and rows
@@ -1109,12 +1115,33 @@ static bool launch_ilu_stream(const Symbolic &S, Device &D, const double *r, con
 
 template <typename VT, int NT>
 static bool launch_band(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
-                        const Device::SizeClass &c) {
+                        const Device::SizeClass &c, bool persistent) {
     using AT = typename AccOf<VT>::type;
     const size_t lds = sizeof(AT) * (size_t(c.max_ni) + BS_NB * BS_LD);
     if (lds > D.max_lds) return false;
     const Skip kc = class_skip(D, sk, c);
     const int nb = c.end - c.begin;
+    if (persistent) {
+        // as many workgroups as are resident at once: 2048 threads and the
+        // LDS of a compute unit
+        const int per_cu = std::max<int>(1, std::min<int>(2048 / NT, int(D.max_lds / lds)));
+        const int g = std::max(1, std::min(nb, per_cu * D.n_cu));
+        for (int kind = 0; kind < 2; ++kind) {
+            const bool inv = kind == 0;
+            if (!(D.band_kinds & (inv ? 2 : 1))) continue;
+            int *q = D.queue + (inv ? 0 : QUEUE_HALF);
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, q, 0, D.ns);
+            if (inv)
+                hipLaunchKernelGGL((k_band_apply_pers<NT, VT, true>), dim3(g, D.ns), dim3(NT), lds, s, r, D.ov_idx,
+                                   D.ov_ptr, (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, c.max_ni, kc, q,
+                                   nb);
+            else
+                hipLaunchKernelGGL((k_band_apply_pers<NT, VT, false>), dim3(g, D.ns), dim3(NT), lds, s, r, D.ov_idx,
+                                   D.ov_ptr, (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, c.max_ni, kc, q,
+                                   nb);
+        }
+        return true;
+    }
     if (D.band_kinds & 2)
         hipLaunchKernelGGL((k_band_apply<NT, VT, true>), dim3(nb, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                            (const VT *)D.band, D.band_off, D.bw, D.dscale, D.zloc, c.max_ni, kc);
@@ -1136,9 +1163,12 @@ static bool launch_local_variant(const Symbolic &S, Device &D, int v, const doub
         }
     }
     switch (v) {
-        case 0: return launch_band<VT, 256>(S, D, r, sk, s, c);
-        case 1: return launch_band<VT, 512>(S, D, r, sk, s, c);
-        default: return launch_band<VT, 1024>(S, D, r, sk, s, c);
+        case 0: return launch_band<VT, 256>(S, D, r, sk, s, c, false);
+        case 1: return launch_band<VT, 512>(S, D, r, sk, s, c, false);
+        case 2: return launch_band<VT, 1024>(S, D, r, sk, s, c, false);
+        case 3: return launch_band<VT, 256>(S, D, r, sk, s, c, true);
+        case 4: return launch_band<VT, 512>(S, D, r, sk, s, c, true);
+        default: return launch_band<VT, 1024>(S, D, r, sk, s, c, true);
     }
 }
 
@@ -1151,7 +1181,8 @@ static void launch_local_class(const Symbolic &S, Device &D, const double *r, co
                                const Device::SizeClass &c) {
     if (c.variant >= 0 && launch_local_variant<VT>(S, D, c.variant, r, sk, s, c)) return;
     if (D.local_variant >= 0 && launch_local_variant<VT>(S, D, D.local_variant, r, sk, s, c)) return;
-    static const int ilu_order_f64[] = {0, 1, 2, 3}, ilu_order_lo[] = {1, 0, 2, 3}, band_order[] = {1, 0, 2};
+    static const int ilu_order_f64[N_ILU_VARIANTS] = {0, 1, 2, 3}, ilu_order_lo[N_ILU_VARIANTS] = {1, 0, 2, 3},
+                     band_order[N_BAND_VARIANTS] = {1, 0, 2, 4, 3, 5};
     const bool ilu = S.opt.local == GDSW_LOCAL_ILU0;
     const int *order = ilu ? (std::is_same<VT, double>::value ? ilu_order_f64 : ilu_order_lo) : band_order;
     const int nv = ilu ? N_ILU_VARIANTS : N_BAND_VARIANTS;
@@ -2036,7 +2067,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
                 HIPCHK(hipEventElapsedTime(&tg[v], e0, e1));
-                if (times) times[4 + v] = tg[v] / reps;
+                if (times) times[8 + v] = tg[v] / reps;
             }
             D.gemv_variant = tg[1] < tg[0] ? 1 : 0;
             float ta[2];
@@ -2048,7 +2079,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
                 HIPCHK(hipEventElapsedTime(&ta[v], e0, e1));
-                if (times) times[6 + v] = ta[v] / reps;
+                if (times) times[10 + v] = ta[v] / reps;
             }
             D.apply_streams = ta[1] < ta[0] ? 2 : 1;
             // coarse part of the prolongation per dof or by blocks
@@ -2064,7 +2095,7 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     HIPCHK(hipEventElapsedTime(&tp[v], e0, e1));
-                    if (times) times[8 + v] = tp[v] / reps;
+                    if (times) times[12 + v] = tp[v] / reps;
                 }
                 D.prolong_split = tp[1] < tp[0] ? 1 : 0;
             }

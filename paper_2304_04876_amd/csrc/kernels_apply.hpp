@@ -266,18 +266,13 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
 // ---------------------------------------------------------------------------
 // Exact local solve A_i^{-1} r_i with the banded Cholesky factor, one
 // workgroup per subdomain, vector in LDS, gather and scatter fused.
-// (compiled for up to 1024 threads whatever NT is: that register budget
-// keeps the unrolled triangle solve from spilling)
 template <int NT, typename VT, bool INV>
-__global__ __launch_bounds__(1024) void k_band_apply(
-    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
-    const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
-    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
+__device__ __forceinline__ void band_apply_one(int i, const double *__restrict__ r, const int32_t *__restrict__ ov_idx,
+                                               const int64_t *__restrict__ ov_ptr, const VT *__restrict__ band,
+                                               const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
+                                               const double *__restrict__ dscale, double *__restrict__ zloc,
+                                               int maxrows) {
     using AT = typename AccOf<VT>::type;
-    const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
-    if (sk.sub(i, slot) || band_inverted(bw[i]) != INV) return;
-    r += slot * sk.sl.n;
-    zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *sT = y + maxrows;
@@ -323,6 +318,45 @@ __global__ __launch_bounds__(1024) void k_band_apply(
 #pragma unroll
         for (int b = 0; b < GB; ++b)
             if (l0 + b * NT < ni) zloc[o + l0 + b * NT] = v[b];
+    }
+}
+
+// (compiled for up to 1024 threads whatever NT is: that register budget
+// keeps the unrolled triangle solve from spilling)
+template <int NT, typename VT, bool INV>
+__global__ __launch_bounds__(1024) void k_band_apply(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
+    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
+    const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
+    if (sk.sub(i, slot) || band_inverted(bw[i]) != INV) return;
+    band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
+                                zloc + slot * sk.sl.zl, maxrows);
+}
+
+// The same as a persistent loop: gridDim.x workgroups per slot take the
+// launch order's subdomains from a work counter (queue[slot], zeroed by the
+// launcher before the launch) until all `nitems` are taken; with the order
+// by decreasing size this is a largest-first list scheduled dynamically.
+template <int NT, typename VT, bool INV>
+__global__ __launch_bounds__(1024) void k_band_apply_pers(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
+    const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk, int *__restrict__ queue,
+    int nitems) {
+    __shared__ int s_t;
+    const int slot = blockIdx.y;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(&queue[slot], 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();   // (every thread has read the ticket before the next is drawn)
+        if (t >= nitems) break;   // (the whole workgroup)
+        const int i = sk.sub_at(t);
+        if (!sk.sub(i, slot) && band_inverted(bw[i]) == INV)
+            band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
+                                        zloc + slot * sk.sl.zl, maxrows);
+        __syncthreads();   // (the LDS vector is free for the next subdomain)
     }
 }
 

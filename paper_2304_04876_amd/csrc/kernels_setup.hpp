@@ -76,6 +76,10 @@ __global__ void k_diag_scale(const double *__restrict__ val, const int64_t *__re
     if (d < n) scale[d] = 1.0 / sqrt(val[adiag[d]]);
 }
 
+__global__ void k_fill_i32(int *__restrict__ x, int v, int n) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) x[p] = v;
+}
+
 __global__ void k_fill(double *__restrict__ x, double v, int64_t n) {
     for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < n;
          p += int64_t(gridDim.x) * blockDim.x)
