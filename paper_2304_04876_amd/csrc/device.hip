@@ -1602,10 +1602,20 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
     HIPCHK(hipMemcpyAsync(D.kdone, zeros.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     queue_cg_start(h, b, x, -1, s);
     const int limit = fixed > 0 ? fixed : maxit;
+    const bool graphs = (h->sym.opt.flags & GDSW_FLAG_GRAPHS) != 0;
+    // residual of every problem at the previous host check
+    std::vector<double> rr_prev(np, -1.0);
+    std::vector<int> it_prev(np, 0);
     int queued = 0, chunk = 4;
     while (queued < limit) {
         const int c = std::min(chunk, limit - queued);
-        queue_cg_chunk(h, x, c, s);
+        if (graphs) {
+            // as captured chunks of 32, 16, ..., 1 iterations (few distinct graphs)
+            for (int p = 32; p >= 1; p >>= 1)   // (c <= 32)
+                if (c & p) queue_cg_chunk(h, x, p, s);
+        } else {
+            queue_cg_chunk(h, x, c, s);
+        }
         queued += c;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hs.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));
@@ -1613,7 +1623,30 @@ static gdsw_status solve_cg(gdsw_handle_s *h, const double *b, double *x, double
         bool all = true;
         for (auto &k : hs) all = all && k.done;
         if (all) break;
-        chunk = std::min(chunk * 2, 32);
+        // The next chunk: the iterations the slowest running problem needs at
+        // the residual reduction per iteration it showed since the last check
+        // (plus one), so that few iterations are queued after convergence;
+        // doubling when there is no estimate (first check, no reduction, or
+        // a fixed iteration count).  Only how many iterations are queued
+        // between two checks changes, never an iterate.
+        int est = 0;
+        bool ok = fixed <= 0;
+        for (int k = 0; k < np && ok; ++k) {
+            const KState &f = hs[k];
+            if (f.done) continue;
+            if (rr_prev[k] > 0.0 && f.iters > it_prev[k] && f.rr > 0.0 && f.bb > 0.0 && f.rr < rr_prev[k]) {
+                const double q = std::log(f.rr / rr_prev[k]) / double(f.iters - it_prev[k]);   // < 0
+                const double need = std::log(f.rtol2 * f.bb / f.rr) / q;
+                est = std::max(est, need <= 0.0 ? 1 : int(std::ceil(need)));
+            } else {
+                ok = false;
+            }
+        }
+        for (int k = 0; k < np; ++k) {
+            rr_prev[k] = hs[k].rr;
+            it_prev[k] = hs[k].iters;
+        }
+        chunk = ok && est > 0 ? std::min(est + 1, 32) : std::min(chunk * 2, 32);
     }
     queue_true_residual(h, b, x, -1, s);
     HIPCHK(hipMemcpyAsync(hs.data(), D.kst, sizeof(KState) * np, hipMemcpyDeviceToHost, s));

@@ -25,7 +25,7 @@ namespace gdsw {
 // in.  LDS: 3 NT R accumulator values (+ NT R doubles with scaling).
 // MS: every right-hand-side slot of the subdomain in one workgroup, one
 // after another, with the factor entries loaded once for all of them (the
-// slots' sweeps reuse the registers); otherwise the slot is blockIdx.y.
+// slots' sweeps reuse the registers); otherwise the handle has one slot.
 template <int NT, int R, int KL, int KU, typename VT, bool MS>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
@@ -38,11 +38,13 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi(
     // holds no scale slots
     constexpr bool scaled = !std::is_same<VT, double>::value;
     const int i = sk.sub_at(blockIdx.x);
-    int slot = MS ? 0 : int(blockIdx.y);
+    // (the one-slot form is launched for handles with one slot only: there
+    // the slot is the constant 0)
+    int slot = 0;
     if constexpr (MS) {
         while (slot < sk.sl.ns && sk.sub(i, slot)) ++slot;
         if (slot == sk.sl.ns) return;
-    } else if (sk.sub(i, slot)) {
+    } else if (sk.sub(i, 0)) {
         return;
     }
     extern __shared__ __align__(16) unsigned char smraw[];
