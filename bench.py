@@ -37,6 +37,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GDSW-PCG solves/sec and M^-1 applies/sec at 1e-8 residual; p50/p99 solve latency"
+# options.exact_order by name (values of the enum in include/gdsw.h)
+ORDERS = {"natural": 0, "nd": 1, "auto": 2}
 
 # HBM traffic of the dominant kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (calibrated by a device copy of known size; see
@@ -83,7 +85,7 @@ GOLD = os.path.join(ROOT, "tests", "golden")
 
 def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=None, gmres="single_reduce",
            ilu_level=0, factor_sweeps=0, graphs=False, steps=10, warmup=2, kernel_reps=50, autotune=True,
-           with_graph_apply=True):
+           with_graph_apply=True, order="natural"):
     """One workload on one handle: setup, autotune, `warmup` + `steps` timed
     solves, applies/s from a graph-replayed apply, the dominant kernel timed
     where it runs, and the error against FP64 oracle samples where the
@@ -120,7 +122,8 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                                               basis_prec=B.FP64 if prec == "fp64" else B.FP32,
                                               ilu_level=ilu_level, ilu_factor_sweeps=factor_sweeps,
                                               coarse=B.COARSE_RGDSW if coarse_name == "rgdsw" else B.COARSE_GDSW,
-                                              flags=B.FLAG_GRAPHS if graphs else 0))
+                                              flags=B.FLAG_GRAPHS if graphs else 0,
+                                              exact_order=ORDERS[order]))
     t_an = time.perf_counter() - t0
     log(f"[bench] analysis {t_an:.2f}s; numerical setup on the GPU")
     B.gdsw_factor(h, stream)
@@ -265,17 +268,21 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
     torch.cuda.synchronize()
     k_ms_alone = e0.elapsed_time(e1) / kernel_reps
     nloc = info["sum_overlap_dofs"]
+    # algorithmic bytes of one local-solve launch, from the library: ILU(0):
+    # every stored off-diagonal factor entry once (value + 16-bit local
+    # column) and the inverse pivot per local row; exact: the band twice
+    # (forward, backward), or the supernodal panels' lower parts twice and
+    # their gather lists and struct rows once; and per local row the
+    # restriction index (4 B), the gathered r (8 B), the local result (8 B)
+    alg_bytes = info["local_solve_bytes"]
     if local == "ilu0":
-        # every stored off-diagonal factor entry once (value + 16-bit local
-        # column), the inverse pivot per local row, and per local row the
-        # restriction index (4 B), the gathered r (8 B), the local result (8 B)
-        offdiag = info["local_factor_entries"] - nloc
-        alg_bytes = offdiag * (pbytes + 2) + nloc * pbytes + nloc * (4 + 8 + 8)
         kname = "k_ilu_jacobi" if info["local_variant"] in (0, 1) else "k_ilu_jacobi_generic"
-    else:
-        # band factor read twice (forward and backward) + vectors
-        alg_bytes = 2 * info["local_factor_entries"] * pbytes + nloc * (4 + 8 + 8)
+    elif info["nd_subdomains"] == pr.n_parts:
+        kname = "k_nd_apply"
+    elif info["nd_subdomains"] == 0:
         kname = "k_band_apply"
+    else:
+        kname = "k_band_apply+k_nd_apply"
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     # the whole apply (graph-replayed): local solves, coarse restriction
     # (Phi once + row index and r per row), A_0^{-1} GEMV, prolongation
@@ -294,6 +301,8 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                 "alg_bytes_per_launch": int(alg_bytes), "avg_launch_ms": round(k_ms, 5),
                 "avg_launch_ms_back_to_back": round(k_ms_alone, 5)}
     local_name = local
+    if local == "exact" and order != "natural":
+        local_name = f"exact_{order}"
     if local == "ilu0" and (ilu_level or factor_sweeps):
         local_name = f"ilu{ilu_level}" + (f"_fast{factor_sweeps}" if factor_sweeps else "")
     out = {
@@ -307,6 +316,8 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                    "n_parts": pr.n_parts, "n0": info["n0"], "overlap": 1, "local": local,
                    "jacobi_sweeps": 5, "ilu_level": ilu_level, "ilu_factor_sweeps": factor_sweeps,
                    "local_prec": prec, "rtol": 1e-8,
+                   "exact_order": order if local == "exact" else None,
+                   "nd_subdomains": info["nd_subdomains"],
                    "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"],
                    "tuned_apply_streams": info["apply_streams"], "tuned_prolong_variant": info["prolong_variant"],
                    "graphs": bool(graphs)},
@@ -362,11 +373,12 @@ def cpu_baseline(kind="poisson", N=128, Pn=8, local="ilu0", coarse="gdsw", gmres
 
 
 def sub(d, keys=("value", "ms_per_step", "dtype", "applies_per_sec", "p50_ms", "p99_ms", "iterations",
-                 "rel_res_true_max", "setup_s", "error_vs_oracle")):
+                 "rel_res_true_max", "setup_s", "device_bytes", "error_vs_oracle")):
     out = {k: d[k] for k in keys if k in d and d[k] is not None}
     out["workload"] = d["config"]["workload"]
     out["unit"] = "solves/s"
-    out["roofline"] = {k: d["roofline"][k] for k in ("kernel", "achieved", "frac", "avg_launch_ms")}
+    out["roofline"] = {k: d["roofline"][k] for k in ("kernel", "achieved", "frac", "avg_launch_ms",
+                                                     "alg_bytes_per_launch")}
     if d.get("apply_roofline"):
         out["apply_roofline_frac"] = d["apply_roofline"]["frac"]
     return out
@@ -380,6 +392,9 @@ def main():
     ap.add_argument("--local", choices=["ilu0", "exact"], default=None,
                     help="local solver (default: ilu0 for Poisson, exact for elasticity)")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default="fp64")
+    ap.add_argument("--exact-order", choices=["natural", "nd", "auto"], default="natural",
+                    help="exact local solves: band Cholesky in the natural order, the supernodal Cholesky "
+                         "after nested dissection, or per subdomain the one with fewer factor values")
     ap.add_argument("--workload", choices=["all", "poisson", "elasticity", "batch", "serve"], default="all",
                     help="all (default): the headline line with the other workloads as sub-records")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -416,7 +431,8 @@ def main():
     if args.local is None:
         args.local = "exact" if kind == "elasticity" else "ilu0"
     d = single(kind, args.N, args.P, args.local, args.prec, args.coarse, args.gmres, args.ilu_level,
-               args.factor_sweeps, args.graphs, args.steps, args.warmup, args.kernel_reps)
+               args.factor_sweeps, args.graphs, args.steps, args.warmup, args.kernel_reps,
+               order=args.exact_order)
     line = {
         "metric": METRIC,
         "value": d["value"], "unit": "solves/s", "n_gpus": 1, "steps": d["steps"], "warmup": d["warmup"],
@@ -432,8 +448,12 @@ def main():
                       kernel_reps=20)
         line["mixed_precision_fp16"] = sub(fp16)
         line["mixed_precision_fp16"]["vs_fp64_solves_per_s"] = round(fp16["value"] / d["value"], 3)
+        # exact local solves: the supernodal factor after nested dissection
+        # (the faster form on these 16^3 boxes) and the band beside it
         line["exact_local"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
-                                         kernel_reps=10))
+                                         kernel_reps=10, order="nd"))
+        line["exact_local_band"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
+                                              kernel_reps=10, order="natural"))
         line["elasticity"] = sub(single("elasticity", None, None, "exact", "fp32", None, "single_reduce",
                                         steps=3, warmup=1, kernel_reps=10))
         bargs = argparse.Namespace(**vars(args))
@@ -473,7 +493,8 @@ def bench_batch(args, sequential_stride=1):
     hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
                               options=B.gdsw_default_options(local=B.LOCAL_EXACT, local_prec=B.FP32,
                                                              basis_prec=B.FP32,
-                                                             flags=B.FLAG_GRAPHS if args.graphs else 0))
+                                                             flags=B.FLAG_GRAPHS if args.graphs else 0,
+                                                             exact_order=ORDERS[args.exact_order]))
     t_an = time.perf_counter() - t0
     B.gdsw_factor(hb)
     tune = B.gdsw_autotune(hb, reps=3)
@@ -510,7 +531,7 @@ def bench_batch(args, sequential_stride=1):
     seq, seq_res, nseq = 0.0, 0.0, 0
     for k in range(0, len(probs), sequential_stride):
         p = probs[k]
-        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_EXACT)
+        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_EXACT, exact_order=ORDERS[args.exact_order])
         bk = b[int(offs[k]):int(offs[k + 1])].clone()
         xk = torch.zeros_like(bk)
         g.solve(bk, xk, rtol=1e-8, maxit=2000)
@@ -530,7 +551,8 @@ def bench_batch(args, sequential_stride=1):
         "dtype": "f64+fp32", "data": "synthetic",
         "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact_fp32_gdsw_cg",
                    "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8,
-                   "graphs": bool(args.graphs)},
+                   "graphs": bool(args.graphs), "exact_order": args.exact_order,
+                   "nd_subdomains": int(info["nd_subdomains"])},
         "iterations_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
         "rel_res_true_max": res,
         "sequential_fp64_solves_per_s": round(seq_rate, 2),

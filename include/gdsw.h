@@ -114,7 +114,24 @@ typedef struct {
                                  vectors and intermediate results are
                                  allocated per slot; slots * n < 2^31.
                                  GMRES needs slots = 1.  Default 1.              */
+    int32_t exact_order;      /* GDSW_LOCAL_EXACT only: GDSW_ORDER_NATURAL (band
+                                 Cholesky in the natural local order),
+                                 GDSW_ORDER_ND (nested dissection by vertex
+                                 separators, supernodal Cholesky; Sec. V-B,
+                                 sparse direct factorization) for every
+                                 subdomain whose two solve vectors fit the
+                                 160 KiB of LDS (16 B per local row for FP64
+                                 factors, 8 otherwise), the band for the
+                                 others, or
+                                 GDSW_ORDER_AUTO (per subdomain whichever of
+                                 the two stores fewer factor values, when its
+                                 two solve vectors fit LDS; the choice depends
+                                 on the subdomain alone, gdsw_info.nd_subdomains
+                                 counts the supernodal ones).  Default NATURAL */
 } gdsw_options;
+
+/* Orderings of the exact local factor (options.exact_order). */
+enum { GDSW_ORDER_NATURAL = 0, GDSW_ORDER_ND = 1, GDSW_ORDER_AUTO = 2 };
 
 /* Square sparse matrix in CSR form, HOST pointers: rowptr[n+1] (int64),
  * col[nnz] (int32, sorted ascending within each row), val[nnz] (FP64). */
@@ -164,6 +181,14 @@ typedef struct {
     int64_t slot_bytes;       /* of device_bytes, the bytes held per slot (its
                                  vectors and intermediate results); the rest is
                                  the factored operator, held once            */
+    int32_t exact_order;      /* options.exact_order                              */
+    int32_t nd_subdomains;    /* subdomains with the supernodal (nested-dissection)
+                                 exact factor; the others keep the band       */
+    int64_t local_solve_bytes;/* algorithmic bytes of one launch of the local
+                                 solves (every stored factor value read once
+                                 per pass, the index data once, per local row
+                                 the restriction index, the gathered r and the
+                                 local result)                                 */
 } gdsw_info;
 
 /* Integer maps that can be copied out for inspection (gdsw_map_size /
@@ -183,7 +208,34 @@ enum {
     GDSW_MAP_LOCAL_ROWPTR = 9, /* int64 [sum_overlap_dofs+1]: CSR row pointers of the
                                   local matrices' patterns (ILU(k) patterns with fill
                                   for GDSW_LOCAL_ILU0), subdomains one after another */
-    GDSW_MAP_LOCAL_COL = 10    /* int32 [local entries]: local column indices        */
+    GDSW_MAP_LOCAL_COL = 10,   /* int32 [local entries]: local column indices        */
+    /* the nested-dissection supernodal structure (exact_order = ND; empty
+     * otherwise): new local numbering, supernodes (children before parents),
+     * their panels, the forward-solve row gathers, the rows by height, the
+     * left-looking update lists and the assembly map */
+    GDSW_MAP_ND_PERM = 11,     /* int32 [sum_overlap_dofs]: old local row of new row p  */
+    GDSW_MAP_ND_SN_PTR = 12,   /* int64 [n_parts+1]: supernodes of each subdomain       */
+    GDSW_MAP_ND_SN = 13,       /* int32 [4 nsn]: first column, columns, panel rows, height */
+    GDSW_MAP_ND_VOFF = 14,     /* int64 [nsn+1]: panel value offsets                   */
+    GDSW_MAP_ND_ST_PTR = 15,   /* int64 [nsn+1]                                        */
+    GDSW_MAP_ND_ST_ROW = 16,   /* int32: struct rows (new local indices)                */
+    GDSW_MAP_ND_RC_PTR = 17,   /* int64 [sum_overlap_dofs+1]                            */
+    GDSW_MAP_ND_RC = 18,       /* int32 [2 nrc]: contributor supernode, panel row       */
+    GDSW_MAP_ND_LV_BASE = 19,  /* int64 [n_parts+1]: offsets into ND_LV_PTR (nlev_i+1 each) */
+    GDSW_MAP_ND_LV_PTR = 20,   /* int32: level offsets into the subdomain's rows by level */
+    GDSW_MAP_ND_LV_ROWS = 21,  /* int32 [sum_overlap_dofs]: new rows by level, subdomains
+                                  one after another (supernodes are numbered by height,
+                                  so each slice is the identity)                         */
+    GDSW_MAP_ND_UP_PTR = 22,   /* int64 [nsn+1]                                         */
+    GDSW_MAP_ND_UP = 23,       /* int64 [4 nup]: K, s0, n1, offset into ND_REL          */
+    GDSW_MAP_ND_REL = 24,      /* int32: panel rows of the update lists                 */
+    GDSW_MAP_ND_ASM = 25,      /* int64 [2 nasm]: A CSR position, panel value index     */
+    GDSW_MAP_ND_RC_W = 26,     /* int32 [nrc]: the gather entries as struct entries,
+                                  relative to the subdomain's first                     */
+    GDSW_MAP_ND_ST_SN = 27,    /* int32: supernode holding each struct entry            */
+    GDSW_MAP_ND_LV_INFO = 28   /* int32 [4 per ND_LV_PTR entry]: first struct entry of
+                                  the height's supernodes (relative), multiply-adds of
+                                  their diagonal blocks, of their struct parts, 0        */
 };
 
 /* Fills `opt` with the paper's defaults: overlap 1, GDSW coarse space,
@@ -241,8 +293,8 @@ gdsw_status gdsw_apply(gdsw_handle h, const double *r_dev, double *z_dev, void *
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * z = M^{-1} r as gdsw_apply, bit for bit, with the apply's scratch (the
  * local results, the coarse restriction partials, r_0 and z_0, the blocked
- * coarse prolongation, the sweep iterates of subdomains too large for LDS)
- * taken from a static device array of GDSW_STATIC_SCRATCH_BYTES per GPU
+ * coarse prolongation, the sweep iterates of subdomains too large for LDS,
+ * the struct products of the supernodal solves) taken from a static device array of GDSW_STATIC_SCRATCH_BYTES per GPU
  * instead of the handle's own buffers.  Allocates nothing (no hipMalloc or
  * hipFree, no allocating library call); the array is held by every GPU the
  * library runs on until the process ends.  The current device must be the

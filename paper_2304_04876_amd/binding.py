@@ -30,8 +30,15 @@ FLAG_GRAPHS = 1
 MAP_OV_PTR, MAP_OV_IDX, MAP_IS_GAMMA, MAP_COMP_OF_NODE, MAP_COMP_RANK = 0, 1, 2, 3, 4
 MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8
 MAP_LOCAL_ROWPTR, MAP_LOCAL_COL = 9, 10
+(MAP_ND_PERM, MAP_ND_SN_PTR, MAP_ND_SN, MAP_ND_VOFF, MAP_ND_ST_PTR, MAP_ND_ST_ROW, MAP_ND_RC_PTR, MAP_ND_RC,
+ MAP_ND_LV_BASE, MAP_ND_LV_PTR, MAP_ND_LV_ROWS, MAP_ND_UP_PTR, MAP_ND_UP, MAP_ND_REL, MAP_ND_ASM,
+ MAP_ND_RC_W, MAP_ND_ST_SN, MAP_ND_LV_INFO) = range(11, 29)
 _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
-              5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64, 9: np.int64, 10: np.int32}
+              5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64, 9: np.int64, 10: np.int32,
+              11: np.int32, 12: np.int64, 13: np.int32, 14: np.int64, 15: np.int64, 16: np.int32, 17: np.int64,
+              18: np.int32, 19: np.int64, 20: np.int32, 21: np.int32, 22: np.int64, 23: np.int64, 24: np.int32,
+              25: np.int64, 26: np.int32, 27: np.int32, 28: np.int32}
+ORDER_NATURAL, ORDER_ND, ORDER_AUTO = 0, 1, 2
 
 EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
             "gdsw_apply", "gdsw_apply_static", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
@@ -46,7 +53,8 @@ class Options(ctypes.Structure):
                 ("jacobi_sweeps", ctypes.c_int32), ("local_prec", ctypes.c_int32),
                 ("basis_prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
                 ("flags", ctypes.c_uint64), ("ilu_level", ctypes.c_int32),
-                ("ilu_factor_sweeps", ctypes.c_int32), ("slots", ctypes.c_int32)]
+                ("ilu_factor_sweeps", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("exact_order", ctypes.c_int32)]
 
 
 class CSR(ctypes.Structure):
@@ -71,7 +79,8 @@ class Info(ctypes.Structure):
                 ("n_problems", ctypes.c_int32), ("local_variant", ctypes.c_int32),
                 ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32),
                 ("prolong_variant", ctypes.c_int32), ("t_refactor", ctypes.c_double),
-                ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_int64)]
+                ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_int64), ("exact_order", ctypes.c_int32),
+                ("nd_subdomains", ctypes.c_int32), ("local_solve_bytes", ctypes.c_int64)]
 
 
 def lib():

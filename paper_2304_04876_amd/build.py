@@ -33,7 +33,7 @@ def build(verbose: bool = True) -> str:
     tmp = tempfile.mkdtemp(prefix="gdsw_build_")
     try:
         objs = []
-        for src in ("symbolic.cpp", "capi.cpp"):
+        for src in ("symbolic.cpp", "nd.cpp", "capi.cpp"):
             o = os.path.join(tmp, src + ".o")
             _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)

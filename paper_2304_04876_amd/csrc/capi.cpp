@@ -7,6 +7,11 @@
 
 #include "gdsw_impl.hpp"
 
+template <typename T>
+static void copy_vec(const std::vector<T> &v, void *out) {
+    if (!v.empty()) std::memcpy(out, v.data(), sizeof(T) * v.size());
+}
+
 extern "C" {
 
 void gdsw_default_options(gdsw_options *opt) {
@@ -21,6 +26,7 @@ void gdsw_default_options(gdsw_options *opt) {
     opt->hbm_budget_bytes = 0;
     opt->flags = 0;
     opt->slots = 1;
+    opt->exact_order = GDSW_ORDER_NATURAL;
 }
 
 gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts, int32_t dpn, const double *Z,
@@ -169,7 +175,8 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->phi_entries = S.blk.val_off.empty() ? 0 : S.blk.val_off.back();
     info->local_factor_entries = 0;
     if (S.opt.local == GDSW_LOCAL_EXACT)
-        info->local_factor_entries = S.band_off.empty() ? 0 : S.band_off.back();
+        info->local_factor_entries =
+            (S.nd.voff.empty() ? 0 : S.nd.voff.back()) + (S.band_off.empty() ? 0 : S.band_off.back());
     else
         info->local_factor_entries = S.lcol.size();
     info->device_bytes = gdsw::device_bytes(h);
@@ -185,6 +192,33 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->t_refactor = h->t_refactor;
     info->slots = std::max(1, S.opt.slots);
     info->slot_bytes = gdsw::slot_bytes(h);
+    info->exact_order = S.opt.exact_order;
+    info->nd_subdomains = 0;
+    for (uint8_t m : S.nd_mask) info->nd_subdomains += m;
+    {
+        const int64_t vb = S.opt.local_prec == GDSW_FP64 ? 8 : S.opt.local_prec == GDSW_FP32 ? 4 : 2;
+        const int64_t nloc = S.ov_ptr.empty() ? 0 : S.ov_ptr.back();
+        int64_t b = nloc * 20;   // restriction index, gathered r, local result
+        if (S.opt.local == GDSW_LOCAL_ILU0) {
+            const int64_t off = int64_t(S.lcol.size()) - nloc;   // off-diagonal factor entries
+            b += off * (vb + 2) + nloc * vb;
+        } else {
+            // the band twice (forward, backward); the panels' lower parts
+            // twice, their gather lists and struct rows once
+            b += 2 * vb * (S.band_off.empty() ? 0 : S.band_off.back());
+            for (int64_t J = 0; J < S.nd.nsn; ++J) {
+                const int64_t nJ = S.nd.ncol[J], ns = S.nd.nrow[J] - nJ;
+                b += 2 * vb * (nJ * (nJ + 1) / 2 + nJ * ns);
+            }
+            // the gather entries, the struct rows and their supernodes, the
+            // struct products written and read back, the inverse permutation
+            const int64_t ab = S.opt.local_prec == GDSW_FP64 ? 8 : 4;
+            b += 4 * int64_t(S.nd.rc_w.size()) + (8 + 2 * ab) * int64_t(S.nd.st_row.size());
+            for (int i = 0; i < S.np; ++i)
+                if (!S.nd_mask.empty() && S.nd_mask[i]) b += 4 * (S.ov_ptr[i + 1] - S.ov_ptr[i]);
+        }
+        info->local_solve_bytes = b;
+    }
     return GDSW_OK;
 }
 
@@ -202,6 +236,24 @@ static int64_t map_count(gdsw_handle h, int32_t map) {
         case GDSW_MAP_A0: return S.a0_off.empty() ? 0 : S.a0_off.back();
         case GDSW_MAP_LOCAL_ROWPTR: return int64_t(S.lrowptr.size());
         case GDSW_MAP_LOCAL_COL: return int64_t(S.lcol.size());
+        case GDSW_MAP_ND_PERM: return int64_t(S.nd.perm.size());
+        case GDSW_MAP_ND_SN_PTR: return int64_t(S.nd.sn_ptr.size());
+        case GDSW_MAP_ND_SN: return 4 * S.nd.nsn;
+        case GDSW_MAP_ND_VOFF: return int64_t(S.nd.voff.size());
+        case GDSW_MAP_ND_ST_PTR: return int64_t(S.nd.st_ptr.size());
+        case GDSW_MAP_ND_ST_ROW: return int64_t(S.nd.st_row.size());
+        case GDSW_MAP_ND_RC_PTR: return int64_t(S.nd.rc_ptr.size());
+        case GDSW_MAP_ND_RC: return 2 * int64_t(S.nd.rc_sn.size());
+        case GDSW_MAP_ND_LV_BASE: return int64_t(S.nd.lv_base.size());
+        case GDSW_MAP_ND_LV_PTR: return int64_t(S.nd.lv_ptr.size());
+        case GDSW_MAP_ND_LV_ROWS: return int64_t(S.nd.lv_rows.size());
+        case GDSW_MAP_ND_UP_PTR: return int64_t(S.nd.up_ptr.size());
+        case GDSW_MAP_ND_UP: return 4 * int64_t(S.nd.up_k.size());
+        case GDSW_MAP_ND_REL: return int64_t(S.nd.rel.size());
+        case GDSW_MAP_ND_ASM: return 2 * int64_t(S.nd.asm_src.size());
+        case GDSW_MAP_ND_RC_W: return int64_t(S.nd.rc_w.size());
+        case GDSW_MAP_ND_ST_SN: return int64_t(S.nd.st_sn.size());
+        case GDSW_MAP_ND_LV_INFO: return int64_t(S.nd.lv_info.size());
         default: return -1;
     }
 }
@@ -263,6 +315,56 @@ gdsw_status gdsw_copy_map(gdsw_handle h, int32_t map, void *out) {
         case GDSW_MAP_LOCAL_COL:
             std::memcpy(out, S.lcol.data(), 4 * S.lcol.size());
             return GDSW_OK;
+        case GDSW_MAP_ND_PERM: copy_vec(S.nd.perm, out); return GDSW_OK;
+        case GDSW_MAP_ND_SN_PTR: copy_vec(S.nd.sn_ptr, out); return GDSW_OK;
+        case GDSW_MAP_ND_SN: {
+            int32_t *o = static_cast<int32_t *>(out);
+            for (int64_t J = 0; J < S.nd.nsn; ++J) {
+                o[4 * J] = S.nd.first[J];
+                o[4 * J + 1] = S.nd.ncol[J];
+                o[4 * J + 2] = S.nd.nrow[J];
+                o[4 * J + 3] = S.nd.height[J];
+            }
+            return GDSW_OK;
+        }
+        case GDSW_MAP_ND_VOFF: copy_vec(S.nd.voff, out); return GDSW_OK;
+        case GDSW_MAP_ND_ST_PTR: copy_vec(S.nd.st_ptr, out); return GDSW_OK;
+        case GDSW_MAP_ND_ST_ROW: copy_vec(S.nd.st_row, out); return GDSW_OK;
+        case GDSW_MAP_ND_RC_PTR: copy_vec(S.nd.rc_ptr, out); return GDSW_OK;
+        case GDSW_MAP_ND_RC: {
+            int32_t *o = static_cast<int32_t *>(out);
+            for (size_t q = 0; q < S.nd.rc_sn.size(); ++q) {
+                o[2 * q] = S.nd.rc_sn[q];
+                o[2 * q + 1] = S.nd.rc_pos[q];
+            }
+            return GDSW_OK;
+        }
+        case GDSW_MAP_ND_LV_BASE: copy_vec(S.nd.lv_base, out); return GDSW_OK;
+        case GDSW_MAP_ND_LV_PTR: copy_vec(S.nd.lv_ptr, out); return GDSW_OK;
+        case GDSW_MAP_ND_LV_ROWS: copy_vec(S.nd.lv_rows, out); return GDSW_OK;
+        case GDSW_MAP_ND_UP_PTR: copy_vec(S.nd.up_ptr, out); return GDSW_OK;
+        case GDSW_MAP_ND_UP: {
+            int64_t *o = static_cast<int64_t *>(out);
+            for (size_t q = 0; q < S.nd.up_k.size(); ++q) {
+                o[4 * q] = S.nd.up_k[q];
+                o[4 * q + 1] = S.nd.up_s0[q];
+                o[4 * q + 2] = S.nd.up_n1[q];
+                o[4 * q + 3] = S.nd.up_rel[q];
+            }
+            return GDSW_OK;
+        }
+        case GDSW_MAP_ND_REL: copy_vec(S.nd.rel, out); return GDSW_OK;
+        case GDSW_MAP_ND_RC_W: copy_vec(S.nd.rc_w, out); return GDSW_OK;
+        case GDSW_MAP_ND_ST_SN: copy_vec(S.nd.st_sn, out); return GDSW_OK;
+        case GDSW_MAP_ND_LV_INFO: copy_vec(S.nd.lv_info, out); return GDSW_OK;
+        case GDSW_MAP_ND_ASM: {
+            int64_t *o = static_cast<int64_t *>(out);
+            for (size_t q = 0; q < S.nd.asm_src.size(); ++q) {
+                o[2 * q] = S.nd.asm_src[q];
+                o[2 * q + 1] = S.nd.asm_dst[q];
+            }
+            return GDSW_OK;
+        }
         default:
             return GDSW_ERR_INVALID_ARG;
     }

@@ -14,12 +14,14 @@
 #include "gdsw_impl.hpp"
 #include "kernels_apply.hpp"
 #include "kernels_krylov.hpp"
+#include "kernels_nd.hpp"
 #include "kernels_setup.hpp"
 
 // Scratch of the allocation-free apply (gdsw_apply_static): the local
 // results, the coarse restriction partials, r_0, z_0 and its repetitions,
-// the coarse part of the prolongation and the sweep iterates of large
-// subdomains, carved from this array instead of the handle's buffers.  Each
+// the coarse part of the prolongation, the sweep iterates of large
+// subdomains and the struct products of the supernodal solves, carved from
+// this array instead of the handle's buffers.  Each
 // GPU the library runs on holds its own copy until the process ends; host
 // code uses the address hipGetSymbolAddress returns for the current device,
 // never the array's name.
@@ -273,6 +275,21 @@ struct Device {
     Slots slots{};
     int32_t *sub_order = nullptr;   // local-solve launch order (decreasing size), or null
     int *queue = nullptr;           // work counters of the persistent band solves (QUEUE_HALF per kind)
+    // nested-dissection supernodal factor (exact local solver): subdomains
+    // with it and with a band (largest of each)
+    bool nd = false;
+    int nd_max_ni = 0, band_max_ni = 0;
+    void *ndL = nullptr;                                   // panels in the local precision
+    int32_t *nd_iperm = nullptr, *nd_first = nullptr, *nd_ncol = nullptr, *nd_nrow = nullptr;
+    int64_t *nd_voff = nullptr, *nd_st_ptr = nullptr, *nd_rc_ptr = nullptr, *nd_lv_base = nullptr;
+    int64_t *nd_sn_ptr = nullptr;
+    int32_t *nd_st_row = nullptr, *nd_st_sn = nullptr, *nd_row_sn = nullptr, *nd_lv_ptr = nullptr;
+    int32_t *nd_rc_w = nullptr;
+    int4 *nd_lv_info = nullptr;
+    // the solve's struct products (one value per struct entry and slot,
+    // accumulator precision, sized for FP64)
+    double *nd_w = nullptr;
+    int64_t nd_nst = 0;
     // size classes of the local solves: consecutive ranges of the launch
     // order whose sizes lie within a factor two of the class's largest; each
     // is launched with LDS and rows per thread for its own largest
@@ -288,7 +305,7 @@ struct Device {
 // Scratch tags of the numerical setup (Device::setup_scratch).
 enum SetupTag {
     ST_STATUS = 1, ST_LVAL, ST_FI_A, ST_FI_V, ST_BAND64, ST_BP_LOCAL, ST_BP_INT, ST_E, ST_IBAND, ST_T2, ST_T1,
-    ST_GJ_P, ST_GJ_W, ST_SUB_BLK
+    ST_GJ_P, ST_GJ_W, ST_SUB_BLK, ST_ND64
 };
 
 // Values of A in the sliced ELL layout of the Krylov SpMV (slices of SELL_C
@@ -495,11 +512,12 @@ static void check_status(Device &D, int *d_status, int count, hipStream_t s, con
 // subdomains need: bit 0 the substitution one, bit 1 the inverse one.
 static int invert_diagonal_blocks(Device &D, double *band, const int64_t *off, const int32_t *bw, const int64_t *rptr,
                                   const std::vector<int64_t> &rows_h, const std::vector<int32_t> &bw_h, int np,
-                                  int tag, hipStream_t s) {
+                                  int tag, hipStream_t s, const std::vector<int64_t> *off_h = nullptr) {
     std::vector<int64_t> bp(size_t(np) + 1, 0);
     int kinds = 0;
     for (int i = 0; i < np; ++i) {
-        const int64_t n = rows_h[i + 1] - rows_h[i];
+        // (subdomains without a band: none)
+        const int64_t n = (off_h && (*off_h)[i + 1] == (*off_h)[i]) ? 0 : rows_h[i + 1] - rows_h[i];
         const bool inv = band_inverted(bw_h[i]);
         if (n > 0) kinds |= inv ? 2 : 1;
         bp[i + 1] = bp[i] + (inv ? (n + BS_NB - 1) / BS_NB : 0);
@@ -519,6 +537,89 @@ static int invert_diagonal_blocks(Device &D, double *band, const int64_t *off, c
 // Local factors (ILU(k) in the sweep layout, or band Cholesky factors with
 // inverted diagonal blocks) from the current values of A.  Allocates the
 // factor buffers on the first call; a numeric re-setup overwrites them.
+// Nested-dissection supernodal factor: the structure maps uploaded once,
+// A_i's lower entries scattered into FP64 panels, the left-looking
+// supernodal Cholesky, the diagonal blocks inverted, then the cast to the
+// local precision.
+static void factor_nd(gdsw_handle_s *h, int *d_status, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const NDSym &N = S.nd;
+    const int prec = S.opt.local_prec;
+    const int64_t nv = N.voff[N.nsn];
+    if (!D.nd_iperm) {
+        std::vector<int32_t> iperm(N.perm.size());
+        for (int i = 0; i < S.np; ++i)
+            for (int64_t p = S.ov_ptr[i]; p < S.ov_ptr[i + 1]; ++p) iperm[S.ov_ptr[i] + N.perm[p]] = int32_t(p - S.ov_ptr[i]);
+        D.nd_iperm = D.upload(iperm, s);
+        D.nd_first = D.upload(N.first, s);
+        D.nd_ncol = D.upload(N.ncol, s);
+        D.nd_nrow = D.upload(N.nrow, s);
+        D.nd_voff = D.upload(N.voff, s);
+        D.nd_sn_ptr = D.upload(N.sn_ptr, s);
+        D.nd_st_ptr = D.upload(N.st_ptr, s);
+        D.nd_st_row = D.upload(N.st_row, s);
+        D.nd_st_sn = D.upload(N.st_sn, s);
+        D.nd_row_sn = D.upload(N.row_sn, s);
+        D.nd_rc_ptr = D.upload(N.rc_ptr, s);
+        D.nd_rc_w = D.upload(N.rc_w, s);
+        D.nd_lv_base = D.upload(N.lv_base, s);
+        D.nd_lv_ptr = D.upload(N.lv_ptr, s);
+        std::vector<int4> info(N.lv_info.size() / 4);
+        for (size_t q = 0; q < info.size(); ++q)
+            info[q] = make_int4(N.lv_info[4 * q], N.lv_info[4 * q + 1], N.lv_info[4 * q + 2], N.lv_info[4 * q + 3]);
+        D.nd_lv_info = D.upload(info, s);
+        D.nd_nst = N.st_ptr[N.nsn];
+        D.nd_w = D.alloc<double>(std::max<int64_t>(1, int64_t(D.ns) * D.nd_nst));
+        HIPCHK(hipStreamSynchronize(s));   // (the packed host copies go out of scope)
+    }
+    double *P64 = prec == GDSW_FP64 ? static_cast<double *>(D.ndL) : D.setup_scratch<double>(ST_ND64, nv);
+    if (!P64) P64 = static_cast<double *>(D.ndL = D.alloc<double>(nv));
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(nv, 256, 65536)), dim3(256), 0, s, P64, 0.0, nv);
+    int64_t *d_src = D.setup_upload(N.asm_src, s);
+    int64_t *d_dst = D.setup_upload(N.asm_dst, s);
+    const int64_t ne = int64_t(N.asm_src.size());
+    hipLaunchKernelGGL(k_gather_vals, dim3(nblocks(ne, 256, 65536)), dim3(256), 0, s, D.val, d_src, d_dst, P64, ne,
+                       D.dscale, D.arow, D.col);
+    int64_t *d_up_ptr = D.setup_upload(N.up_ptr, s);
+    int32_t *d_up_k = D.setup_upload(N.up_k, s);
+    int32_t *d_up_s0 = D.setup_upload(N.up_s0, s);
+    int32_t *d_up_n1 = D.setup_upload(N.up_n1, s);
+    int64_t *d_up_rel = D.setup_upload(N.up_rel, s);
+    int32_t *d_rel = D.setup_upload(N.rel, s);
+    hipLaunchKernelGGL(k_nd_factor<256>, dim3(S.np), dim3(256), 0, s, P64, D.nd_sn_ptr, D.nd_first, D.nd_ncol,
+                       D.nd_nrow, D.nd_voff, D.nd_st_ptr, d_up_ptr, d_up_k, d_up_s0, d_up_n1, d_up_rel, d_rel,
+                       d_status);
+    HIPCHK(hipGetLastError());
+    check_status(D, d_status, S.np, s, "supernodal Cholesky");
+    const size_t lds = sizeof(double) * size_t(std::max(N.max_ncol, 1));
+    if (lds > D.max_lds) throw DevError{GDSW_ERR_INVALID_ARG, "a supernode is too wide for LDS"};
+    hipLaunchKernelGGL(k_nd_invert<256>, dim3(S.np), dim3(256), lds, s, P64, D.nd_sn_ptr, D.nd_ncol, D.nd_nrow,
+                       D.nd_voff);
+    HIPCHK(hipGetLastError());
+    if (prec != GDSW_FP64) {
+        if (!D.ndL) D.ndL = D.raw_alloc(prec_size(prec) * size_t(nv));
+        const int gb = nblocks(nv, 256, 65536);
+        if (prec == GDSW_FP32) hipLaunchKernelGGL(k_cast<float>, dim3(gb), dim3(256), 0, s, P64, (float *)D.ndL, nv);
+        else if (prec == GDSW_BF16) hipLaunchKernelGGL(k_cast<bf16>, dim3(gb), dim3(256), 0, s, P64, (bf16 *)D.ndL, nv);
+        else hipLaunchKernelGGL(k_cast<fp16>, dim3(gb), dim3(256), 0, s, P64, (fp16 *)D.ndL, nv);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (prec != GDSW_FP64) D.setup_release(P64, sizeof(double) * size_t(nv));
+    D.setup_release(d_src, sizeof(int64_t) * N.asm_src.size());
+    D.setup_release(d_dst, sizeof(int64_t) * N.asm_dst.size());
+    D.setup_release(d_up_ptr, sizeof(int64_t) * N.up_ptr.size());
+    D.setup_release(d_up_k, sizeof(int32_t) * N.up_k.size());
+    D.setup_release(d_up_s0, sizeof(int32_t) * N.up_s0.size());
+    D.setup_release(d_up_n1, sizeof(int32_t) * N.up_n1.size());
+    D.setup_release(d_up_rel, sizeof(int64_t) * N.up_rel.size());
+    D.setup_release(d_rel, sizeof(int32_t) * N.rel.size());
+    D.nd = true;
+    D.local_entries += nv;
+}
+
+static void factor_band(gdsw_handle_s *h, int *d_status, hipStream_t s);
+
 static void factor_local(gdsw_handle_s *h, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
@@ -599,6 +700,28 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
         D.setup_release(d_lvl_ptr, sizeof(int32_t) * S.lvl_ptr.size());
         D.setup_release(d_lvl_rows, sizeof(int32_t) * S.lvl_rows.size());
     } else {
+        // supernodal subdomains, then the banded ones (either set may be empty)
+        D.nd_max_ni = D.band_max_ni = 0;
+        for (int i = 0; i < S.np; ++i) {
+            const int ni = int(S.ov_ptr[i + 1] - S.ov_ptr[i]);
+            if (S.nd_mask[i]) D.nd_max_ni = std::max(D.nd_max_ni, ni);
+            else D.band_max_ni = std::max(D.band_max_ni, ni);
+        }
+        D.local_entries = 0;
+        if (S.nd.nsn > 0) factor_nd(h, d_status, s);
+        if (S.band_off[S.np] > 0) factor_band(h, d_status, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    D.setup_release(d_status, sizeof(int) * S.np);
+}
+
+// Band Cholesky factors of the subdomains with a band (natural order), with
+// inverted diagonal blocks, in the local precision.
+static void factor_band(gdsw_handle_s *h, int *d_status, hipStream_t s) {
+    Symbolic &S = h->sym;
+    Device &D = *h->dev;
+    const int prec = S.opt.local_prec;
+    {
         const int64_t nb = S.band_off[S.np];
         // FP64 factors are the band itself; reduced precision casts a
         // scratch FP64 band into it
@@ -621,7 +744,7 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
         HIPCHK(hipGetLastError());
         check_status(D, d_status, S.np, s, "banded Cholesky");
         D.band_kinds = invert_diagonal_blocks(D, band64, D.band_off, D.bw, D.ov_ptr, S.ov_ptr, S.bw, S.np,
-                                              ST_BP_LOCAL, s);
+                                              ST_BP_LOCAL, s, &S.band_off);
         D.setup_release(d_src, sizeof(int64_t) * S.bscat_src.size());
         D.setup_release(d_dst, sizeof(int64_t) * S.bscat_dst.size());
         if (prec != GDSW_FP64) {
@@ -634,10 +757,8 @@ static void factor_local(gdsw_handle_s *h, hipStream_t s) {
             HIPCHK(hipStreamSynchronize(s));
             D.setup_release(band64, sizeof(double) * size_t(nb));
         }
-        D.local_entries = nb;
+        D.local_entries += nb;
     }
-    HIPCHK(hipStreamSynchronize(s));
-    D.setup_release(d_status, sizeof(int) * S.np);
 }
 
 // Layout of the coarse part, built once per handle: block maps, restriction
@@ -1151,17 +1272,23 @@ static bool launch_band(const Symbolic &S, Device &D, const double *r, const Ski
     return true;
 }
 
+template <typename VT, int NT>
+static bool launch_nd(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                      const Device::SizeClass &c) {
+    using AT = typename AccOf<VT>::type;
+    const size_t lds = 2 * sizeof(AT) * size_t(c.max_ni);
+    if (lds > D.max_lds) return false;
+    hipLaunchKernelGGL((k_nd_apply<NT, VT>), dim3(c.end - c.begin, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
+                       D.nd_iperm, (const VT *)D.ndL, D.nd_sn_ptr, D.nd_first, D.nd_ncol, D.nd_nrow, D.nd_voff,
+                       D.nd_st_ptr, D.nd_st_row, D.nd_st_sn, D.nd_row_sn, D.nd_rc_ptr, D.nd_rc_w, D.nd_lv_base,
+                       D.nd_lv_ptr, D.nd_lv_info, D.dscale, D.zloc, reinterpret_cast<AT *>(D.nd_w), D.nd_nst, c.max_ni,
+                       class_skip(D, sk, c));
+    return true;
+}
+
 template <typename VT>
-static bool launch_local_variant(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
-                                 hipStream_t s, const Device::SizeClass &c) {
-    if (S.opt.local == GDSW_LOCAL_ILU0) {
-        switch (v) {
-            case 0: return launch_ilu_regs<VT, 512>(S, D, r, sk, s, c);
-            case 1: return launch_ilu_regs<VT, 1024>(S, D, r, sk, s, c);
-            case 2: return launch_ilu_stream<VT, 256>(S, D, r, sk, s, c);
-            default: return launch_ilu_stream<VT, 512>(S, D, r, sk, s, c);
-        }
-    }
+static bool launch_band_variant(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
+                                hipStream_t s, const Device::SizeClass &c) {
     switch (v) {
         case 0: return launch_band<VT, 256>(S, D, r, sk, s, c, false);
         case 1: return launch_band<VT, 512>(S, D, r, sk, s, c, false);
@@ -1170,6 +1297,41 @@ static bool launch_local_variant(const Symbolic &S, Device &D, int v, const doub
         case 4: return launch_band<VT, 512>(S, D, r, sk, s, c, true);
         default: return launch_band<VT, 1024>(S, D, r, sk, s, c, true);
     }
+}
+
+template <typename VT>
+static bool launch_local_variant(const Symbolic &S, Device &D, int v, const double *r, const Skip &sk,
+                                 hipStream_t s, const Device::SizeClass &c) {
+    if (S.opt.local == GDSW_LOCAL_EXACT) {
+        // the banded subdomains in configuration v, the supernodal ones with
+        // 256, 512 or 1024 threads (v mod 3); each kernel leaves the other
+        // kind's subdomains alone
+        bool ok = true;
+        if (D.band_kinds) {
+            Device::SizeClass cb = c;
+            cb.max_ni = std::min(c.max_ni, std::max(D.band_max_ni, 1));
+            ok = launch_band_variant<VT>(S, D, v, r, sk, s, cb);
+        }
+        if (ok && D.nd) {
+            Device::SizeClass cn = c;
+            cn.max_ni = std::min(c.max_ni, std::max(D.nd_max_ni, 1));
+            switch (v % 3) {
+                case 0: ok = launch_nd<VT, 256>(S, D, r, sk, s, cn); break;
+                case 1: ok = launch_nd<VT, 512>(S, D, r, sk, s, cn); break;
+                default: ok = launch_nd<VT, 1024>(S, D, r, sk, s, cn); break;
+            }
+        }
+        return ok;
+    }
+    if (S.opt.local == GDSW_LOCAL_ILU0) {
+        switch (v) {
+            case 0: return launch_ilu_regs<VT, 512>(S, D, r, sk, s, c);
+            case 1: return launch_ilu_regs<VT, 1024>(S, D, r, sk, s, c);
+            case 2: return launch_ilu_stream<VT, 256>(S, D, r, sk, s, c);
+            default: return launch_ilu_stream<VT, 512>(S, D, r, sk, s, c);
+        }
+    }
+    return false;
 }
 
 // Every size class in the configuration tuned for it, else the handle's
@@ -1396,6 +1558,7 @@ gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *str
     const size_t o_zg = take(ns * sizeof(double) * S.blk.cols.size());
     const size_t o_zc = split_used ? take(ns * sizeof(double) * size_t(S.n)) : 0;
     const size_t o_sw = D.sweep_buf ? take(ns * D.sweep_bytes) : 0;
+    const size_t o_ndw = D.nd_w ? take(ns * sizeof(double) * size_t(D.nd_nst)) : 0;
     if (off > GDSW_STATIC_SCRATCH_BYTES) {
         h->err = "apply_static: this handle needs " + std::to_string(off) + " bytes of scratch, more than the " +
                  std::to_string(size_t(GDSW_STATIC_SCRATCH_BYTES)) + " of the static array";
@@ -1406,11 +1569,13 @@ gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *str
         Device &D;
         double *zloc, *partial, *r0, *z0, *zg, *zc;
         void *sweep;
+        double *ndw;
         ~Swap() {
             D.zloc = zloc, D.partial = partial, D.r0 = r0, D.z0 = z0, D.zg = zg, D.zc = zc;
             D.sweep_buf = sweep;
+            D.nd_w = ndw;
         }
-    } keep{D, D.zloc, D.partial, D.r0, D.z0, D.zg, D.zc, D.sweep_buf};
+    } keep{D, D.zloc, D.partial, D.r0, D.z0, D.zg, D.zc, D.sweep_buf, D.nd_w};
     D.zloc = reinterpret_cast<double *>(b + o_zloc);
     D.partial = reinterpret_cast<double *>(b + o_part);
     D.r0 = reinterpret_cast<double *>(b + o_r0);
@@ -1418,6 +1583,7 @@ gdsw_status apply_static(gdsw_handle_s *h, const double *r, double *z, void *str
     D.zg = reinterpret_cast<double *>(b + o_zg);
     if (split_used) D.zc = reinterpret_cast<double *>(b + o_zc);
     if (D.sweep_buf) D.sweep_buf = b + o_sw;
+    if (D.nd_w) D.nd_w = reinterpret_cast<double *>(b + o_ndw);
     try {
         launch_apply(h, r, z, 3, Skip(), static_cast<hipStream_t>(stream));
     } catch (const DevError &e) {
@@ -2272,7 +2438,8 @@ int64_t slot_bytes(const gdsw_handle_s *h) {
     const int64_t cols = D.zg ? D.slots.cols : 0, n0 = D.z0 ? S.n0 : 0, nkb = D.nkb / D.ns;
     return int64_t(sizeof(double)) * (6 * S.n + S.ov_ptr[S.np] + D.n_partial + 2 * n0 + cols + (D.zc ? S.n : 0) +
                                       2 * nkb) +
-           int64_t(D.sweep_bytes) + int64_t(sizeof(int32_t)) * (3 * nkb + S.nprob) +
+           int64_t(D.sweep_bytes) + int64_t(sizeof(double)) * (D.nd_w ? D.nd_nst : 0) +
+           int64_t(sizeof(int32_t)) * (3 * nkb + S.nprob) +
            int64_t(sizeof(KState) + 2 * sizeof(int)) * S.nprob;
 }
 

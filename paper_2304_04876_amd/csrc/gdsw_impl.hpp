@@ -25,6 +25,55 @@ struct PhiBlocks {
     int32_t nb = 0;
 };
 
+// Nested-dissection supernodal factor of the local matrices (exact local
+// solver with exact_order = GDSW_ORDER_ND).  Per subdomain the rows are
+// renumbered by recursive vertex-separator bisection (new local index p:
+// old local row perm[ov_ptr[i] + p]); a supernode is a leaf part or a
+// separator, columns [first, first + ncol) of the new numbering, ordered
+// children before parents.  Its panel holds L's columns first..first+ncol-1
+// on the rows first..first+ncol-1 and then on its struct rows (ascending
+// new indices, all beyond the supernode), column-major with leading
+// dimension nrow = ncol + |struct|.
+struct NDSym {
+    std::vector<int32_t> perm;        // [sum n_i]
+    std::vector<int64_t> sn_ptr;      // [np+1] supernodes of each subdomain (global ids)
+    std::vector<int32_t> first, ncol, nrow, height;   // [nsn]
+    std::vector<int64_t> voff;        // [nsn+1] panel value offsets (all subdomains)
+    std::vector<int64_t> st_ptr;      // [nsn+1] struct rows
+    std::vector<int32_t> st_row;      //   new local indices
+    std::vector<int32_t> row_sn;      // [sum n_i] supernode (global id) holding each new row
+    // forward solve: each row gathers the products of the earlier supernodes
+    // whose struct holds it (contributor K, row position in K's panel)
+    std::vector<int64_t> rc_ptr;      // [sum n_i + 1]
+    std::vector<int32_t> rc_sn, rc_pos;
+    // the same gathers as struct entries relative to the subdomain's first
+    // (the solve keeps each struct product in a vector laid out like st_row)
+    std::vector<int32_t> rc_w;
+    std::vector<int32_t> st_sn;       // [struct entries] supernode holding each
+    // rows by height of their supernode (leaves 0): per subdomain a list of
+    // level offsets into its slice of lv_rows (slice i starts at ov_ptr[i])
+    std::vector<int64_t> lv_base;     // [np+1] offsets into lv_ptr (nlev_i + 1 each)
+    std::vector<int32_t> lv_ptr;
+    std::vector<int32_t> lv_rows;     // [sum n_i] new local rows (supernodes are
+                                      // numbered by height: the identity)
+    // per lv_ptr entry: {first struct entry of the height's supernodes
+    // (relative to the subdomain's first), multiply-adds of their diagonal
+    // blocks, of their struct parts, 0}
+    std::vector<int32_t> lv_info;
+    // left-looking factor: the earlier supernodes K updating J (ascending K):
+    // struct(K) from index s0 on lies in J's panel rows (the first n1 of them
+    // in J's columns), at panel rows rel[rel_off .. + |struct(K)| - s0)
+    std::vector<int64_t> up_ptr;      // [nsn+1]
+    std::vector<int32_t> up_k, up_s0, up_n1;
+    std::vector<int64_t> up_rel;
+    std::vector<int32_t> rel;
+    // assembly: lower entries of A_i -> panel values
+    std::vector<int64_t> asm_src;     // position in A's CSR
+    std::vector<int64_t> asm_dst;     // panel value index
+    int32_t max_ncol = 0, max_levels = 0;
+    int64_t nsn = 0;
+};
+
 struct Symbolic {
     // ---- input copy -----------------------------------------------------
     int64_t n = 0, nn = 0, nnz = 0;
@@ -86,7 +135,11 @@ struct Symbolic {
     std::vector<int64_t> lrowptr;   // [sum n_i + 1]
     std::vector<int32_t> lcol;      // local column within the subdomain
     std::vector<int64_t> lgpos;     // position in A's CSR
-    // band Cholesky profiles (exact local solver)
+    // nested-dissection supernodal factors (exact local solver): the
+    // subdomains that take it (1) instead of the band (0)
+    NDSym nd;
+    std::vector<uint8_t> nd_mask;
+    // band Cholesky profiles (exact local solver, natural order)
     std::vector<int32_t> bw;        // [np] lower bandwidth b_i of A_i
     std::vector<int64_t> band_off;  // [np+1] offsets, row-major (b_i+1) per row
     std::vector<int64_t> bscat_dst; // band positions of the lower entries of A_i
@@ -167,6 +220,9 @@ gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, in
 gdsw_status analyze_batch(gdsw_handle_s *h, int32_t count, const gdsw_csr *A, const int32_t *const *part,
                           const int32_t *n_parts, int32_t dpn, const double *const *Z, int32_t n_null,
                           const gdsw_options *opt);
+// nd.cpp: the nested-dissection supernodal structure of every A_i (needs
+// the local CSR of build_local)
+void build_nd(Symbolic &s);
 // device.hip
 gdsw_status factor(gdsw_handle_s *h, void *stream);
 gdsw_status refactor(gdsw_handle_s *h, const double *val, void *stream);

@@ -331,7 +331,8 @@ __global__ __launch_bounds__(1024) void k_band_apply(
     const VT *__restrict__ band, const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
     const double *__restrict__ dscale, double *__restrict__ zloc, int maxrows, Skip sk) {
     const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
-    if (sk.sub(i, slot) || band_inverted(bw[i]) != INV) return;
+    // (subdomains without a band take the supernodal solve)
+    if (sk.sub(i, slot) || band_inverted(bw[i]) != INV || band_off[i + 1] == band_off[i]) return;
     band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
                                 zloc + slot * sk.sl.zl, maxrows);
 }
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_band_apply_pers(
         __syncthreads();   // (every thread has read the ticket before the next is drawn)
         if (t >= nitems) break;   // (the whole workgroup)
         const int i = sk.sub_at(t);
-        if (!sk.sub(i, slot) && band_inverted(bw[i]) == INV)
+        if (!sk.sub(i, slot) && band_inverted(bw[i]) == INV && band_off[i + 1] != band_off[i])
             band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
                                         zloc + slot * sk.sl.zl, maxrows);
         __syncthreads();   // (the LDS vector is free for the next subdomain)

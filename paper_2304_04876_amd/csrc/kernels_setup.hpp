@@ -219,6 +219,7 @@ __global__ __launch_bounds__(NT) void k_band_chol(double *__restrict__ band, con
                                                   const int64_t *__restrict__ rptr, int *__restrict__ status) {
     extern __shared__ double smem[];
     const int i = blockIdx.x;
+    if (off[i + 1] == off[i]) return;   // no band (empty, or a supernodal subdomain)
     const int n = int(rptr[i + 1] - rptr[i]);
     const int b = bwid[i];
     const int64_t w = b + 1;

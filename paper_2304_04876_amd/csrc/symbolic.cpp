@@ -29,6 +29,7 @@
 #include <map>
 #include <numeric>
 #include <queue>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,9 @@ void validate_and_copy(Symbolic &s, const gdsw_csr *A, const int32_t *part, int3
     if (o.ilu_factor_sweeps < 0 || o.ilu_factor_sweeps > 100) fail(GDSW_ERR_INVALID_ARG, "ilu_factor_sweeps");
     if (o.slots == 0) o.slots = 1;
     if (o.slots < 0 || o.slots > 4096) fail(GDSW_ERR_INVALID_ARG, "slots out of range");
+    if (o.exact_order != GDSW_ORDER_NATURAL && o.exact_order != GDSW_ORDER_ND && o.exact_order != GDSW_ORDER_AUTO)
+        fail(GDSW_ERR_INVALID_ARG, "exact_order");
+    if (o.local != GDSW_LOCAL_EXACT) o.exact_order = GDSW_ORDER_NATURAL;
     if (Z == nullptr && n_null > 1) fail(GDSW_ERR_INVALID_ARG, "Z == NULL needs n_null <= 1");
     if (Z != nullptr && (n_null <= 0 || n_null > 64)) fail(GDSW_ERR_INVALID_ARG, "n_null out of range");
     s.opt = o;
@@ -644,6 +648,8 @@ void build_local(Symbolic &s) {
     // diagonal positions, level schedule of the ILU(0) rows, band scatter
     s.max_bw = 0;
     for (int i = 0; i < np; ++i) s.max_bw = std::max(s.max_bw, s.bw[i]);
+    // (band profiles for the exact factor; the nested-dissection analysis
+    // drops those of the subdomains that take the supernodal factor)
     const bool exact = s.opt.local == GDSW_LOCAL_EXACT;
     s.band_off.assign(np + 1, 0);
     for (int i = 0; i < np; ++i)
@@ -1007,6 +1013,8 @@ gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, in
         build_overlap(s);
         build_interface(s);
         build_local(s);
+        s.nd_mask.assign(s.np, 0);
+        if (s.opt.local == GDSW_LOCAL_EXACT && s.opt.exact_order != GDSW_ORDER_NATURAL) build_nd(s);
         build_coarse(s);
         if (s.opt.local == GDSW_LOCAL_ILU0 && s.max_ni > 65535)
             fail(GDSW_ERR_INVALID_ARG, "ILU(0) local solver supports subdomains of at most 65535 dofs");
@@ -1016,6 +1024,9 @@ gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, in
     } catch (const std::bad_alloc &) {
         h->err = "host allocation failed in analysis";
         return GDSW_ERR_BUDGET;
+    } catch (const std::runtime_error &e) {
+        h->err = e.what();
+        return GDSW_ERR_INTERNAL;
     }
     h->sym.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->analyzed = true;
