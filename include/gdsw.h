@@ -119,13 +119,13 @@ typedef struct {
                                  GDSW_ORDER_ND (nested dissection by vertex
                                  separators, supernodal Cholesky; Sec. V-B,
                                  sparse direct factorization) for every
-                                 subdomain whose two solve vectors fit the
-                                 160 KiB of LDS (16 B per local row for FP64
-                                 factors, 8 otherwise), the band for the
-                                 others, or
+                                 subdomain whose solve fits the 160 KiB of
+                                 LDS (at most 7,964 local rows with FP64
+                                 factors, 14,332 otherwise, and 1,024
+                                 supernodes), the band for the others, or
                                  GDSW_ORDER_AUTO (per subdomain whichever of
                                  the two stores fewer factor values, when its
-                                 two solve vectors fit LDS; the choice depends
+                                 supernodal solve fits LDS; the choice depends
                                  on the subdomain alone, gdsw_info.nd_subdomains
                                  counts the supernodal ones).  Default NATURAL */
 } gdsw_options;

@@ -1276,13 +1276,13 @@ template <typename VT, int NT>
 static bool launch_nd(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
                       const Device::SizeClass &c) {
     using AT = typename AccOf<VT>::type;
-    const size_t lds = 2 * sizeof(AT) * size_t(c.max_ni);
+    const size_t lds = nd_lds_bytes(c.max_ni, S.nd.max_sn, sizeof(AT));
     if (lds > D.max_lds) return false;
     hipLaunchKernelGGL((k_nd_apply<NT, VT>), dim3(c.end - c.begin, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                        D.nd_iperm, (const VT *)D.ndL, D.nd_sn_ptr, D.nd_first, D.nd_ncol, D.nd_nrow, D.nd_voff,
                        D.nd_st_ptr, D.nd_st_row, D.nd_st_sn, D.nd_row_sn, D.nd_rc_ptr, D.nd_rc_w, D.nd_lv_base,
                        D.nd_lv_ptr, D.nd_lv_info, D.dscale, D.zloc, reinterpret_cast<AT *>(D.nd_w), D.nd_nst, c.max_ni,
-                       class_skip(D, sk, c));
+                       S.nd.max_sn, class_skip(D, sk, c));
     return true;
 }
 

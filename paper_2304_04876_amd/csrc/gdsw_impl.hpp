@@ -34,6 +34,20 @@ struct PhiBlocks {
 // on the rows first..first+ncol-1 and then on its struct rows (ascending
 // new indices, all beyond the supernode), column-major with leading
 // dimension nrow = ncol + |struct|.
+// LDS bytes of the supernodal solve (k_nd_apply) for subdomains of at most
+// `rows` rows and `nsn` supernodes with accumulators of `acc` bytes: the
+// vector and the pass results (rows each, rounded up to 4), the supernode
+// table (16 B each), the struct offsets (nsn + 1 ints) and each row's
+// supernode (16-bit).  A subdomain takes the supernodal factor only if it
+// has at most ND_MAX_SUPERNODES supernodes and nd_lds_bytes(rows,
+// ND_MAX_SUPERNODES, acc) fits a compute unit's 160 KiB, so that any set of
+// such subdomains fits one launch.
+constexpr int ND_MAX_SUPERNODES = 1024;
+inline size_t nd_lds_bytes(int rows, int nsn, size_t acc) {
+    const size_t r4 = (size_t(rows) + 3) / 4 * 4;
+    return 2 * acc * r4 + 16 * size_t(nsn) + 4 * (size_t(nsn) + 1) + 2 * r4;
+}
+
 struct NDSym {
     std::vector<int32_t> perm;        // [sum n_i]
     std::vector<int64_t> sn_ptr;      // [np+1] supernodes of each subdomain (global ids)
@@ -70,7 +84,7 @@ struct NDSym {
     // assembly: lower entries of A_i -> panel values
     std::vector<int64_t> asm_src;     // position in A's CSR
     std::vector<int64_t> asm_dst;     // panel value index
-    int32_t max_ncol = 0, max_levels = 0;
+    int32_t max_ncol = 0, max_levels = 0, max_sn = 0;
     int64_t nsn = 0;
 };
 

@@ -155,9 +155,11 @@ __device__ __forceinline__ int lanes_for(int items, int work, int gmin) {
 // Each pass gives every item a group of lanes (lanes_for, from the pass's
 // item and multiply-add counts) whose partial products are summed in a
 // fixed order; the values of one load instruction are consecutive in memory
-// across groups in (2) and (3), within a group in (4) and (5).  w: one
-// vector of struct-entry length per slot (slot stride nst).  LDS: 2 maxrows
-// accumulator values.
+// across groups in (2) and (3), within a group in (4) and (5).  The
+// subdomain's supernode table and each row's supernode are copied to LDS
+// first, so that an item's factor loads wait on one global load at most.
+// w: one vector of struct-entry length per slot (slot stride nst).  LDS:
+// nd_lds_bytes(maxrows, maxsn, accumulator size) (gdsw_impl.hpp).
 template <int NT, typename VT>
 __global__ __launch_bounds__(NT) void k_nd_apply(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
     const int32_t *__restrict__ st_sn, const int32_t *__restrict__ row_sn, const int64_t *__restrict__ rc_ptr,
     const int32_t *__restrict__ rc_w, const int64_t *__restrict__ lv_base, const int32_t *__restrict__ lv_ptr,
     const int4 *__restrict__ lv_info, const double *__restrict__ dscale, double *__restrict__ zloc,
-    typename AccOf<VT>::type *__restrict__ w, int64_t nst, int maxrows, Skip sk) {
+    typename AccOf<VT>::type *__restrict__ w, int64_t nst, int maxrows, int maxsn, Skip sk) {
     using AT = typename AccOf<VT>::type;
     const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
     // (subdomains without levels take the band solve)
@@ -175,14 +177,26 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
     r += slot * sk.sl.n;
     zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
+    const int r4 = (maxrows + 3) / 4 * 4;
     AT *y = reinterpret_cast<AT *>(smraw);
-    AT *t = y + maxrows;
+    AT *t = y + r4;
+    int4 *snt = reinterpret_cast<int4 *>(t + r4);
+    int *stp = reinterpret_cast<int *>(snt + maxsn);
+    int16_t *rsn = reinterpret_cast<int16_t *>(stp + maxsn + 1);
     const int64_t o = ov_ptr[i];
     const int ni = int(ov_ptr[i + 1] - o);
-    const int64_t sb = st_ptr[sn_ptr[i]];
+    const int64_t s0 = sn_ptr[i];
+    const int nsn = int(sn_ptr[i + 1] - s0);
+    const int64_t sb = st_ptr[s0], vb = voff[s0];
     AT *wi = w + slot * nst + sb;
+    const VT *Li = L + vb;
     const int tid = threadIdx.x;
+    for (int J = tid; J <= nsn; J += NT) {
+        stp[J] = int(st_ptr[s0 + J] - sb);
+        if (J < nsn) snt[J] = make_int4(first[s0 + J], ncol[s0 + J], nrow[s0 + J], int(voff[s0 + J] - vb));
+    }
     for (int l = tid; l < ni; l += NT) {
+        rsn[l] = int16_t(row_sn[o + l] - s0);
         const int d = ov_idx[o + l];
         double x = r[d];
         if (dscale) x *= dscale[d];
@@ -207,12 +221,12 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         {
             const int G = lanes_for(R1 - R0, a.y, 1), g = tid & (G - 1);
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
-                const int J = row_sn[o + rr];
-                const int f = first[J], ld = nrow[J], c0 = rr - f;
-                const VT *row = L + voff[J] + c0;
+                const int4 J = snt[rsn[rr]];   // first, columns, panel rows, panel offset
+                const int c0 = rr - J.x;
+                const VT *row = Li + J.w + c0;
                 AT acc = 0;
 #pragma unroll 4
-                for (int c = g; c <= c0; c += G) acc += to_acc(ld_once(&row[int64_t(c) * ld])) * t[f + c];
+                for (int c = g; c <= c0; c += G) acc += to_acc(ld_once(&row[int64_t(c) * J.z])) * t[J.x + c];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }
@@ -222,12 +236,12 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         {
             const int G = lanes_for(T1 - T0, a.z, 1), g = tid & (G - 1);
             for (int q = T0 + tid / G; q < T1; q += NT / G) {
-                const int K = st_sn[sb + q];
-                const int fK = first[K], nK = ncol[K], ld = nrow[K];
-                const VT *row = L + voff[K] + nK + (sb + q - st_ptr[K]);
+                const int k0 = int(st_sn[sb + q] - s0);
+                const int4 K = snt[k0];
+                const VT *row = Li + K.w + K.y + (q - stp[k0]);
                 AT acc = 0;
 #pragma unroll 4
-                for (int k = g; k < nK; k += G) acc += to_acc(ld_once(&row[int64_t(k) * ld])) * y[fK + k];
+                for (int k = g; k < K.y; k += G) acc += to_acc(ld_once(&row[int64_t(k) * K.z])) * y[K.x + k];
                 acc = group_sum(acc, G);
                 if (g == 0) wi[q] = acc;
             }
@@ -241,14 +255,14 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         {
             const int G = lanes_for(R1 - R0, a.z, 8), g = tid & (G - 1);
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
-                const int J = row_sn[o + rr];
-                const int f = first[J], nJ = ncol[J], ld = nrow[J];
-                const int64_t s0 = st_ptr[J];
-                const int ns = ld - nJ;
-                const VT *col = L + voff[J] + int64_t(rr - f) * ld + nJ;
+                const int j0 = rsn[rr];
+                const int4 J = snt[j0];
+                const int ns = J.z - J.y;
+                const VT *col = Li + J.w + int64_t(rr - J.x) * J.z + J.y;
+                const int32_t *srow = st_row + sb + stp[j0];
                 AT acc = 0;
 #pragma unroll 4
-                for (int q = g; q < ns; q += G) acc += to_acc(ld_once(&col[q])) * y[st_row[s0 + q]];
+                for (int q = g; q < ns; q += G) acc += to_acc(ld_once(&col[q])) * y[srow[q]];
                 acc = group_sum(acc, G);
                 if (g == 0) t[rr] = y[rr] - acc;
             }
@@ -258,12 +272,12 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         {
             const int G = lanes_for(R1 - R0, a.y, 8), g = tid & (G - 1);
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
-                const int J = row_sn[o + rr];
-                const int f = first[J], nJ = ncol[J], ld = nrow[J], c = rr - f;
-                const VT *col = L + voff[J] + int64_t(c) * ld;
+                const int4 J = snt[rsn[rr]];
+                const int c = rr - J.x;
+                const VT *col = Li + J.w + int64_t(c) * J.z;
                 AT acc = 0;
 #pragma unroll 4
-                for (int k = c + g; k < nJ; k += G) acc += to_acc(ld_once(&col[k])) * t[f + k];
+                for (int k = c + g; k < J.y; k += G) acc += to_acc(ld_once(&col[k])) * t[J.x + k];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }

@@ -248,27 +248,27 @@ void build_nd(Symbolic &s) {
         LocalGraph g{ptr.data(), s.lcol.data() + base, ni};
         if (ni > 0) subdomain_nd(g, sub[i]);
     }
-    // Which subdomains take the supernodal factor: those whose two solve
-    // vectors fit a gfx950 compute unit's 160 KiB of LDS (8-byte
-    // accumulators for FP64 factors, 4 otherwise), all of them
-    // (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose panels hold fewer
-    // values than their band (both read twice per apply); the others keep
-    // the band.  The choice depends on the subdomain alone, so a problem's
-    // results do not depend on what it is packed with.
+    // Which subdomains take the supernodal factor: those whose solve fits a
+    // gfx950 compute unit's 160 KiB of LDS (nd_lds_bytes with 8-byte
+    // accumulators for FP64 factors, 4 otherwise; at most
+    // ND_MAX_SUPERNODES supernodes; panel values of one subdomain below
+    // 2^31), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose
+    // panels hold fewer values than their band (both read twice per apply);
+    // the others keep the band.  The choice depends on the subdomain alone,
+    // so a problem's results do not depend on what it is packed with.
     const bool all_nd = s.opt.exact_order == GDSW_ORDER_ND;
     const size_t acc = s.opt.local_prec == GDSW_FP64 ? 8 : 4;
     s.nd_mask.assign(np, 0);
     for (int i = 0; i < np; ++i) {
         const int64_t ni = s.ov_ptr[i + 1] - s.ov_ptr[i];
-        if (ni == 0 || 2 * acc * size_t(ni) > size_t(160) * 1024) continue;
-        if (all_nd) {
-            s.nd_mask[i] = 1;
-            continue;
-        }
-        int64_t vals = 0;
         const SubND &u = sub[i];
+        if (ni == 0 || int(u.first.size()) > ND_MAX_SUPERNODES ||
+            nd_lds_bytes(int(ni), ND_MAX_SUPERNODES, acc) > size_t(160) * 1024)
+            continue;
+        int64_t vals = 0;
         for (size_t J = 0; J < u.first.size(); ++J) vals += int64_t(u.ncol[J]) * (u.ncol[J] + int64_t(u.st[J].size()));
-        s.nd_mask[i] = vals < ni * int64_t(s.bw[i] + 1);
+        if (vals >= (int64_t(1) << 31)) continue;
+        s.nd_mask[i] = all_nd || vals < ni * int64_t(s.bw[i] + 1);
     }
     for (int i = 0; i < np; ++i)
         if (!s.nd_mask[i]) sub[i] = SubND{};
@@ -301,6 +301,7 @@ void build_nd(Symbolic &s) {
             d.voff[g + 1] = d.voff[g] + int64_t(d.nrow[g]) * d.ncol[g];
             d.st_ptr[g + 1] = d.st_ptr[g] + int64_t(u.st[J].size());
             d.max_ncol = std::max(d.max_ncol, u.ncol[J]);
+            d.max_sn = std::max(d.max_sn, int32_t(u.first.size()));
             for (int p = u.first[J]; p < u.first[J] + u.ncol[J]; ++p) d.row_sn[o + p] = int32_t(g);
         }
     }

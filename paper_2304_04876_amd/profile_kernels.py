@@ -29,6 +29,9 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--P", type=int, default=8)
     ap.add_argument("--elasticity", action="store_true")
+    ap.add_argument("--exact-order", choices=["natural", "nd", "auto"], default="natural",
+                    help="exact local solves: band (natural order), supernodal after nested dissection, "
+                         "or per subdomain the one with fewer factor values")
     ap.add_argument("--tune", action="store_true", help="autotune the launch configurations first "
                     "(as the benchmark does), so the counters see the configuration it times")
     ap.add_argument("--setup-only", action="store_true", help="only the numerical setup (local factors, "
@@ -46,10 +49,12 @@ def main():
     else:
         pr = P.poisson3d(a.N, a.P)
         Z = None
-    print(f"[profile] setup {pr.name} local={a.local} prec={a.prec}", file=sys.stderr, flush=True)
+    print(f"[profile] setup {pr.name} local={a.local} order={a.exact_order} prec={a.prec}", file=sys.stderr,
+          flush=True)
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                local=B.LOCAL_ILU0 if a.local == "ilu0" else B.LOCAL_EXACT, local_prec=precs[a.prec],
-               basis_prec=B.FP64 if a.prec == "fp64" else B.FP32)
+               basis_prec=B.FP64 if a.prec == "fp64" else B.FP32,
+               exact_order={"natural": B.ORDER_NATURAL, "nd": B.ORDER_ND, "auto": B.ORDER_AUTO}[a.exact_order])
     torch.cuda.synchronize()
     if a.setup_only:
         g.close()

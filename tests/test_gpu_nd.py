@@ -61,9 +61,10 @@ def test_nd_apply_matches_oracle(case):
     say(f"[nd] apply {case} n={pr.n}")
     M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local="exact")
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z, **ND)
-    # every nonempty subdomain whose two FP64 solve vectors fit 160 KiB of LDS
+    # every nonempty subdomain whose FP64 solve fits 160 KiB of LDS (at most
+    # 7,964 rows; these subdomains have far fewer than 1,024 supernodes)
     ni = np.diff(B.gdsw_copy_map(g.h, B.MAP_OV_PTR))
-    fits = int(((ni > 0) & (16 * ni <= 160 * 1024)).sum())
+    fits = int(((ni > 0) & (ni <= 7964)).sum())
     assert g.info()["nd_subdomains"] == fits
     assert fits > 0 or case == "diffusion_large_subdomains"
     r = P.rhs_uniform(pr.n, 11)
