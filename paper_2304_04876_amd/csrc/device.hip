@@ -573,8 +573,9 @@ static void factor_nd(gdsw_handle_s *h, int *d_status, hipStream_t s) {
         D.nd_w = D.alloc<double>(std::max<int64_t>(1, int64_t(D.ns) * D.nd_nst));
         HIPCHK(hipStreamSynchronize(s));   // (the packed host copies go out of scope)
     }
-    double *P64 = prec == GDSW_FP64 ? static_cast<double *>(D.ndL) : D.setup_scratch<double>(ST_ND64, nv);
-    if (!P64) P64 = static_cast<double *>(D.ndL = D.alloc<double>(nv));
+    // factorization in FP64 panels (setup scratch), then the solve layout
+    // in the storage precision
+    double *P64 = D.setup_scratch<double>(ST_ND64, nv);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(nv, 256, 65536)), dim3(256), 0, s, P64, 0.0, nv);
     int64_t *d_src = D.setup_upload(N.asm_src, s);
     int64_t *d_dst = D.setup_upload(N.asm_dst, s);
@@ -597,15 +598,19 @@ static void factor_nd(gdsw_handle_s *h, int *d_status, hipStream_t s) {
     hipLaunchKernelGGL(k_nd_invert<256>, dim3(S.np), dim3(256), lds, s, P64, D.nd_sn_ptr, D.nd_ncol, D.nd_nrow,
                        D.nd_voff);
     HIPCHK(hipGetLastError());
-    if (prec != GDSW_FP64) {
-        if (!D.ndL) D.ndL = D.raw_alloc(prec_size(prec) * size_t(nv));
-        const int gb = nblocks(nv, 256, 65536);
-        if (prec == GDSW_FP32) hipLaunchKernelGGL(k_cast<float>, dim3(gb), dim3(256), 0, s, P64, (float *)D.ndL, nv);
-        else if (prec == GDSW_BF16) hipLaunchKernelGGL(k_cast<bf16>, dim3(gb), dim3(256), 0, s, P64, (bf16 *)D.ndL, nv);
-        else hipLaunchKernelGGL(k_cast<fp16>, dim3(gb), dim3(256), 0, s, P64, (fp16 *)D.ndL, nv);
-    }
+    if (!D.ndL) D.ndL = D.raw_alloc(prec_size(prec) * size_t(std::max<int64_t>(nv, 1)));
+    const dim3 gs(unsigned(N.nsn));
+    if (prec == GDSW_FP64)
+        hipLaunchKernelGGL(k_nd_split<double>, gs, dim3(256), 0, s, P64, (double *)D.ndL, D.nd_ncol, D.nd_nrow, D.nd_voff);
+    else if (prec == GDSW_FP32)
+        hipLaunchKernelGGL(k_nd_split<float>, gs, dim3(256), 0, s, P64, (float *)D.ndL, D.nd_ncol, D.nd_nrow, D.nd_voff);
+    else if (prec == GDSW_BF16)
+        hipLaunchKernelGGL(k_nd_split<bf16>, gs, dim3(256), 0, s, P64, (bf16 *)D.ndL, D.nd_ncol, D.nd_nrow, D.nd_voff);
+    else
+        hipLaunchKernelGGL(k_nd_split<fp16>, gs, dim3(256), 0, s, P64, (fp16 *)D.ndL, D.nd_ncol, D.nd_nrow, D.nd_voff);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    if (prec != GDSW_FP64) D.setup_release(P64, sizeof(double) * size_t(nv));
+    D.setup_release(P64, sizeof(double) * size_t(nv));
     D.setup_release(d_src, sizeof(int64_t) * N.asm_src.size());
     D.setup_release(d_dst, sizeof(int64_t) * N.asm_dst.size());
     D.setup_release(d_up_ptr, sizeof(int64_t) * N.up_ptr.size());

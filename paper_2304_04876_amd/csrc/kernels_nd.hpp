@@ -2,11 +2,16 @@
 // (Sec. V-B, sparse direct factorization; the symbolic structure is built on
 // the host by nd.cpp).  One workgroup per subdomain throughout.
 //
-// Panels: supernode J holds L's columns first_J .. first_J + ncol_J - 1 on
-// its own rows and then on its struct rows, column-major with leading
-// dimension nrow_J (value index voff_J + c nrow_J + row).  After the
+// Panels (factorization): supernode J holds L's columns first_J .. first_J +
+// ncol_J - 1 on its own rows and then on its struct rows, column-major with
+// leading dimension nrow_J (value index voff_J + c nrow_J + row).  After the
 // factorization each diagonal block is replaced by its inverse (lower
 // triangular), so that every diagonal step of the solves is one product.
+// Solve layout (k_nd_split): the same values of J at the same offset voff_J,
+// first the inverted diagonal block (ncol_J x ncol_J, column-major) and
+// then the struct part (ns_J x ncol_J, column-major, ns_J = nrow_J -
+// ncol_J), so that the solve's diagonal passes and struct passes read
+// disjoint cache lines.
 #pragma once
 
 #include "kernels_common.hpp"
@@ -104,6 +109,24 @@ __global__ __launch_bounds__(NT) void k_nd_invert(double *__restrict__ P, const 
     }
 }
 
+// Panels (FP64) to the solve layout in the factor's storage type, one
+// workgroup per supernode.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_split(const double *__restrict__ P, T *__restrict__ out,
+                                                  const int32_t *__restrict__ ncol, const int32_t *__restrict__ nrow,
+                                                  const int64_t *__restrict__ voff) {
+    const int64_t J = blockIdx.x;
+    const int nJ = ncol[J], ld = nrow[J], ns = ld - nJ;
+    const double *src = P + voff[J];
+    T *dst = out + voff[J];
+    const int64_t cnt = int64_t(nJ) * ld;
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+        const int c = int(e / ld), p = int(e - int64_t(c) * ld);
+        const int64_t at = p < nJ ? int64_t(c) * nJ + p : int64_t(nJ) * nJ + int64_t(c) * ns + (p - nJ);
+        dst[at] = from_double<T>(src[e]);
+    }
+}
+
 // Sum over aligned groups of G lanes (G a power of two up to 64); every lane
 // of a group gets its group's sum.  The lanes of a group must be active
 // together; the other groups of the wavefront may be inactive.
@@ -155,7 +178,9 @@ __device__ __forceinline__ int lanes_for(int items, int work, int gmin) {
 // Each pass gives every item a group of lanes (lanes_for, from the pass's
 // item and multiply-add counts) whose partial products are summed in a
 // fixed order; the values of one load instruction are consecutive in memory
-// across groups in (2) and (3), within a group in (4) and (5).  The
+// across groups in (2) and (3), within a group in (4) and (5) (the solve
+// layout above; plain loads, so that a line shared by neighbouring items
+// stays in the caches between them).  The
 // subdomain's supernode table and each row's supernode are copied to LDS
 // first, so that an item's factor loads wait on one global load at most.
 // w: one vector of struct-entry length per slot (slot stride nst).  LDS:
@@ -221,12 +246,12 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         {
             const int G = lanes_for(R1 - R0, a.y, 1), g = tid & (G - 1);
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
-                const int4 J = snt[rsn[rr]];   // first, columns, panel rows, panel offset
+                const int4 J = snt[rsn[rr]];   // first, columns, panel rows, value offset
                 const int c0 = rr - J.x;
                 const VT *row = Li + J.w + c0;
                 AT acc = 0;
 #pragma unroll 4
-                for (int c = g; c <= c0; c += G) acc += to_acc(ld_once(&row[int64_t(c) * J.z])) * t[J.x + c];
+                for (int c = g; c <= c0; c += G) acc += to_acc(row[int64_t(c) * J.y]) * t[J.x + c];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }
@@ -238,10 +263,11 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
             for (int q = T0 + tid / G; q < T1; q += NT / G) {
                 const int k0 = int(st_sn[sb + q] - s0);
                 const int4 K = snt[k0];
-                const VT *row = Li + K.w + K.y + (q - stp[k0]);
+                const int ns = K.z - K.y;
+                const VT *row = Li + K.w + int64_t(K.y) * K.y + (q - stp[k0]);
                 AT acc = 0;
 #pragma unroll 4
-                for (int k = g; k < K.y; k += G) acc += to_acc(ld_once(&row[int64_t(k) * K.z])) * y[K.x + k];
+                for (int k = g; k < K.y; k += G) acc += to_acc(row[int64_t(k) * ns]) * y[K.x + k];
                 acc = group_sum(acc, G);
                 if (g == 0) wi[q] = acc;
             }
@@ -258,11 +284,11 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
                 const int j0 = rsn[rr];
                 const int4 J = snt[j0];
                 const int ns = J.z - J.y;
-                const VT *col = Li + J.w + int64_t(rr - J.x) * J.z + J.y;
+                const VT *col = Li + J.w + int64_t(J.y) * J.y + int64_t(rr - J.x) * ns;
                 const int32_t *srow = st_row + sb + stp[j0];
                 AT acc = 0;
 #pragma unroll 4
-                for (int q = g; q < ns; q += G) acc += to_acc(ld_once(&col[q])) * y[srow[q]];
+                for (int q = g; q < ns; q += G) acc += to_acc(col[q]) * y[srow[q]];
                 acc = group_sum(acc, G);
                 if (g == 0) t[rr] = y[rr] - acc;
             }
@@ -274,10 +300,10 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
                 const int4 J = snt[rsn[rr]];
                 const int c = rr - J.x;
-                const VT *col = Li + J.w + int64_t(c) * J.z;
+                const VT *col = Li + J.w + int64_t(c) * J.y;
                 AT acc = 0;
 #pragma unroll 4
-                for (int k = c + g; k < J.y; k += G) acc += to_acc(ld_once(&col[k])) * t[J.x + k];
+                for (int k = c + g; k < J.y; k += G) acc += to_acc(col[k]) * t[J.x + k];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }
