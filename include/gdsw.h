@@ -233,9 +233,12 @@ enum {
     GDSW_MAP_ND_RC_W = 26,     /* int32 [nrc]: the gather entries as struct entries,
                                   relative to the subdomain's first                     */
     GDSW_MAP_ND_ST_SN = 27,    /* int32: supernode holding each struct entry            */
-    GDSW_MAP_ND_LV_INFO = 28   /* int32 [4 per ND_LV_PTR entry]: first struct entry of
+    GDSW_MAP_ND_LV_INFO = 28,  /* int32 [4 per ND_LV_PTR entry]: first struct entry of
                                   the height's supernodes (relative), multiply-adds of
                                   their diagonal blocks, of their struct parts, 0        */
+    GDSW_MAP_ND_CH_BASE = 29,  /* int64 [n_parts+1]: offsets into ND_CH_ROW             */
+    GDSW_MAP_ND_CH_ROW = 30    /* int32: per subdomain 0 and the end row of each chunk of
+                                  whole leaves (at most 64 rows; one wavefront each)    */
 };
 
 /* Fills `opt` with the paper's defaults: overlap 1, GDSW coarse space,

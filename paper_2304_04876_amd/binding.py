@@ -32,12 +32,12 @@ MAP_PHI_ROWPTR, MAP_PHI_COL, MAP_PHI_VAL, MAP_A0 = 5, 6, 7, 8
 MAP_LOCAL_ROWPTR, MAP_LOCAL_COL = 9, 10
 (MAP_ND_PERM, MAP_ND_SN_PTR, MAP_ND_SN, MAP_ND_VOFF, MAP_ND_ST_PTR, MAP_ND_ST_ROW, MAP_ND_RC_PTR, MAP_ND_RC,
  MAP_ND_LV_BASE, MAP_ND_LV_PTR, MAP_ND_LV_ROWS, MAP_ND_UP_PTR, MAP_ND_UP, MAP_ND_REL, MAP_ND_ASM,
- MAP_ND_RC_W, MAP_ND_ST_SN, MAP_ND_LV_INFO) = range(11, 29)
+ MAP_ND_RC_W, MAP_ND_ST_SN, MAP_ND_LV_INFO, MAP_ND_CH_BASE, MAP_ND_CH_ROW) = range(11, 31)
 _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
               5: np.int64, 6: np.int32, 7: np.float64, 8: np.float64, 9: np.int64, 10: np.int32,
               11: np.int32, 12: np.int64, 13: np.int32, 14: np.int64, 15: np.int64, 16: np.int32, 17: np.int64,
               18: np.int32, 19: np.int64, 20: np.int32, 21: np.int32, 22: np.int64, 23: np.int64, 24: np.int32,
-              25: np.int64, 26: np.int32, 27: np.int32, 28: np.int32}
+              25: np.int64, 26: np.int32, 27: np.int32, 28: np.int32, 29: np.int64, 30: np.int32}
 ORDER_NATURAL, ORDER_ND, ORDER_AUTO = 0, 1, 2
 
 EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",

@@ -254,6 +254,8 @@ static int64_t map_count(gdsw_handle h, int32_t map) {
         case GDSW_MAP_ND_RC_W: return int64_t(S.nd.rc_w.size());
         case GDSW_MAP_ND_ST_SN: return int64_t(S.nd.st_sn.size());
         case GDSW_MAP_ND_LV_INFO: return int64_t(S.nd.lv_info.size());
+        case GDSW_MAP_ND_CH_BASE: return int64_t(S.nd.ch_base.size());
+        case GDSW_MAP_ND_CH_ROW: return int64_t(S.nd.ch_row.size());
         default: return -1;
     }
 }
@@ -357,6 +359,8 @@ gdsw_status gdsw_copy_map(gdsw_handle h, int32_t map, void *out) {
         case GDSW_MAP_ND_RC_W: copy_vec(S.nd.rc_w, out); return GDSW_OK;
         case GDSW_MAP_ND_ST_SN: copy_vec(S.nd.st_sn, out); return GDSW_OK;
         case GDSW_MAP_ND_LV_INFO: copy_vec(S.nd.lv_info, out); return GDSW_OK;
+        case GDSW_MAP_ND_CH_BASE: copy_vec(S.nd.ch_base, out); return GDSW_OK;
+        case GDSW_MAP_ND_CH_ROW: copy_vec(S.nd.ch_row, out); return GDSW_OK;
         case GDSW_MAP_ND_ASM: {
             int64_t *o = static_cast<int64_t *>(out);
             for (size_t q = 0; q < S.nd.asm_src.size(); ++q) {

@@ -284,7 +284,8 @@ struct Device {
     int64_t *nd_voff = nullptr, *nd_st_ptr = nullptr, *nd_rc_ptr = nullptr, *nd_lv_base = nullptr;
     int64_t *nd_sn_ptr = nullptr;
     int32_t *nd_st_row = nullptr, *nd_st_sn = nullptr, *nd_row_sn = nullptr, *nd_lv_ptr = nullptr;
-    int32_t *nd_rc_w = nullptr;
+    int32_t *nd_rc_w = nullptr, *nd_ch_row = nullptr;
+    int64_t *nd_ch_base = nullptr;
     int4 *nd_lv_info = nullptr;
     // the solve's struct products (one value per struct entry and slot,
     // accumulator precision, sized for FP64)
@@ -569,6 +570,8 @@ static void factor_nd(gdsw_handle_s *h, int *d_status, hipStream_t s) {
         for (size_t q = 0; q < info.size(); ++q)
             info[q] = make_int4(N.lv_info[4 * q], N.lv_info[4 * q + 1], N.lv_info[4 * q + 2], N.lv_info[4 * q + 3]);
         D.nd_lv_info = D.upload(info, s);
+        D.nd_ch_base = D.upload(N.ch_base, s);
+        D.nd_ch_row = D.upload(N.ch_row, s);
         D.nd_nst = N.st_ptr[N.nsn];
         D.nd_w = D.alloc<double>(std::max<int64_t>(1, int64_t(D.ns) * D.nd_nst));
         HIPCHK(hipStreamSynchronize(s));   // (the packed host copies go out of scope)
@@ -1281,13 +1284,14 @@ template <typename VT, int NT>
 static bool launch_nd(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
                       const Device::SizeClass &c) {
     using AT = typename AccOf<VT>::type;
-    const size_t lds = nd_lds_bytes(c.max_ni, S.nd.max_sn, sizeof(AT));
+    const size_t lds = nd_lds_bytes(c.max_ni, S.nd.max_t, S.nd.max_sn, sizeof(AT));
     if (lds > D.max_lds) return false;
     hipLaunchKernelGGL((k_nd_apply<NT, VT>), dim3(c.end - c.begin, D.ns), dim3(NT), lds, s, r, D.ov_idx, D.ov_ptr,
                        D.nd_iperm, (const VT *)D.ndL, D.nd_sn_ptr, D.nd_first, D.nd_ncol, D.nd_nrow, D.nd_voff,
                        D.nd_st_ptr, D.nd_st_row, D.nd_st_sn, D.nd_row_sn, D.nd_rc_ptr, D.nd_rc_w, D.nd_lv_base,
-                       D.nd_lv_ptr, D.nd_lv_info, D.dscale, D.zloc, reinterpret_cast<AT *>(D.nd_w), D.nd_nst, c.max_ni,
-                       S.nd.max_sn, class_skip(D, sk, c));
+                       D.nd_lv_ptr, D.nd_lv_info, D.nd_ch_base, D.nd_ch_row, D.dscale, D.zloc,
+                       reinterpret_cast<AT *>(D.nd_w), D.nd_nst, c.max_ni, S.nd.max_t, S.nd.max_sn,
+                       class_skip(D, sk, c));
     return true;
 }
 

@@ -35,17 +35,19 @@ struct PhiBlocks {
 // new indices, all beyond the supernode), column-major with leading
 // dimension nrow = ncol + |struct|.
 // LDS bytes of the supernodal solve (k_nd_apply) for subdomains of at most
-// `rows` rows and `nsn` supernodes with accumulators of `acc` bytes: the
-// vector and the pass results (rows each, rounded up to 4), the supernode
-// table (16 B each), the struct offsets (nsn + 1 ints) and each row's
-// supernode (16-bit).  A subdomain takes the supernodal factor only if it
-// has at most ND_MAX_SUPERNODES supernodes and nd_lds_bytes(rows,
-// ND_MAX_SUPERNODES, acc) fits a compute unit's 160 KiB, so that any set of
-// such subdomains fits one launch.
+// `rows` rows, `trows` rows of one height above the leaves and `nsn`
+// supernodes with accumulators of `acc` bytes: the vector (rows), the pass
+// results of one height (trows; the leaves need none), each rounded up to
+// 4, the supernode table (16 B each), the struct offsets (nsn + 1 ints) and
+// each row's supernode (16-bit).  A subdomain takes the supernodal factor
+// only if it has at most ND_MAX_SUPERNODES supernodes and
+// nd_lds_bytes(rows, rows, ND_MAX_SUPERNODES, acc) fits a compute unit's
+// 160 KiB, so that any set of such subdomains fits one launch.
 constexpr int ND_MAX_SUPERNODES = 1024;
-inline size_t nd_lds_bytes(int rows, int nsn, size_t acc) {
-    const size_t r4 = (size_t(rows) + 3) / 4 * 4;
-    return 2 * acc * r4 + 16 * size_t(nsn) + 4 * (size_t(nsn) + 1) + 2 * r4;
+constexpr int ND_LEAF = 64;           // leaf parts of the dissection: at most this many rows
+inline size_t nd_lds_bytes(int rows, int trows, int nsn, size_t acc) {
+    const size_t r4 = (size_t(rows) + 3) / 4 * 4, t4 = (size_t(trows) + 3) / 4 * 4;
+    return acc * (r4 + t4) + 16 * size_t(nsn) + 4 * (size_t(nsn) + 1) + 2 * r4;
 }
 
 struct NDSym {
@@ -74,6 +76,12 @@ struct NDSym {
     // (relative to the subdomain's first), multiply-adds of their diagonal
     // blocks, of their struct parts, 0}
     std::vector<int32_t> lv_info;
+    // the leaves' rows in chunks of at most 64 rows that split no leaf (the
+    // leaves are numbered first): chunk boundaries of subdomain i at
+    // ch_row[ch_base[i] .. ch_base[i+1]) (a leading 0, then each chunk's end;
+    // an empty slice for band subdomains)
+    std::vector<int64_t> ch_base;     // [np+1]
+    std::vector<int32_t> ch_row;
     // left-looking factor: the earlier supernodes K updating J (ascending K):
     // struct(K) from index s0 on lies in J's panel rows (the first n1 of them
     // in J's columns), at panel rows rel[rel_off .. + |struct(K)| - s0)
@@ -85,6 +93,7 @@ struct NDSym {
     std::vector<int64_t> asm_src;     // position in A's CSR
     std::vector<int64_t> asm_dst;     // panel value index
     int32_t max_ncol = 0, max_levels = 0, max_sn = 0;
+    int32_t max_t = 0;                // most rows of one height above the leaves
     int64_t nsn = 0;
 };
 

@@ -180,11 +180,16 @@ __device__ __forceinline__ int lanes_for(int items, int work, int gmin) {
 // fixed order; the values of one load instruction are consecutive in memory
 // across groups in (2) and (3), within a group in (4) and (5) (the solve
 // layout above; plain loads, so that a line shared by neighbouring items
-// stays in the caches between them).  The
-// subdomain's supernode table and each row's supernode are copied to LDS
-// first, so that an item's factor loads wait on one global load at most.
-// w: one vector of struct-entry length per slot (slot stride nst).  LDS:
-// nd_lds_bytes(maxrows, maxsn, accumulator size) (gdsw_impl.hpp).
+// stays in the caches between them).  The leaves (no gathers) take (2), and
+// (4) with (5), one chunk of whole leaves per wavefront, a lane per row, in
+// place in the vector: a wavefront's LDS reads of a pass are issued before
+// its writes, and no other wavefront touches the chunk's rows, so the
+// leaves need neither the pass-result buffer nor a workgroup barrier
+// between (4) and (5).  The subdomain's supernode table and each row's
+// supernode are copied to LDS first, so that an item's factor loads wait on
+// one global load at most.  w: one vector of struct-entry length per slot
+// (slot stride nst).  LDS: nd_lds_bytes(maxrows, maxt, maxsn, accumulator
+// size) (gdsw_impl.hpp).
 template <int NT, typename VT>
 __global__ __launch_bounds__(NT) void k_nd_apply(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
@@ -193,8 +198,9 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
     const int64_t *__restrict__ voff, const int64_t *__restrict__ st_ptr, const int32_t *__restrict__ st_row,
     const int32_t *__restrict__ st_sn, const int32_t *__restrict__ row_sn, const int64_t *__restrict__ rc_ptr,
     const int32_t *__restrict__ rc_w, const int64_t *__restrict__ lv_base, const int32_t *__restrict__ lv_ptr,
-    const int4 *__restrict__ lv_info, const double *__restrict__ dscale, double *__restrict__ zloc,
-    typename AccOf<VT>::type *__restrict__ w, int64_t nst, int maxrows, int maxsn, Skip sk) {
+    const int4 *__restrict__ lv_info, const int64_t *__restrict__ ch_base, const int32_t *__restrict__ ch_row,
+    const double *__restrict__ dscale, double *__restrict__ zloc, typename AccOf<VT>::type *__restrict__ w,
+    int64_t nst, int maxrows, int maxt, int maxsn, Skip sk) {
     using AT = typename AccOf<VT>::type;
     const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
     // (subdomains without levels take the band solve)
@@ -202,10 +208,10 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
     r += slot * sk.sl.n;
     zloc += slot * sk.sl.zl;
     extern __shared__ __align__(16) unsigned char smraw[];
-    const int r4 = (maxrows + 3) / 4 * 4;
+    const int r4 = (maxrows + 3) / 4 * 4, t4 = (maxt + 3) / 4 * 4;
     AT *y = reinterpret_cast<AT *>(smraw);
     AT *t = y + r4;
-    int4 *snt = reinterpret_cast<int4 *>(t + r4);
+    int4 *snt = reinterpret_cast<int4 *>(t + t4);
     int *stp = reinterpret_cast<int *>(snt + maxsn);
     int16_t *rsn = reinterpret_cast<int16_t *>(stp + maxsn + 1);
     const int64_t o = ov_ptr[i];
@@ -215,7 +221,8 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
     const int64_t sb = st_ptr[s0], vb = voff[s0];
     AT *wi = w + slot * nst + sb;
     const VT *Li = L + vb;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = NT / 64;
     for (int J = tid; J <= nsn; J += NT) {
         stp[J] = int(st_ptr[s0 + J] - sb);
         if (J < nsn) snt[J] = make_int4(first[s0 + J], ncol[s0 + J], nrow[s0 + J], int(voff[s0 + J] - vb));
@@ -228,30 +235,46 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         y[iperm[o + l]] = AT(x);
     }
     __syncthreads();
-    const int64_t lb = lv_base[i];
-    const int nlev = int(lv_base[i + 1] - lb) - 1;
+    const int64_t lb = lv_base[i], cb = ch_base[i];
+    const int nlev = int(lv_base[i + 1] - lb) - 1, nch = int(ch_base[i + 1] - cb) - 1;
     for (int lev = 0; lev < nlev; ++lev) {
         const int R0 = lv_ptr[lb + lev], R1 = lv_ptr[lb + lev + 1];
         const int4 a = lv_info[lb + lev];
         const int T0 = a.x, T1 = lv_info[lb + lev + 1].x;
-        // (1)
-        for (int rr = R0 + tid; rr < R1; rr += NT) {
-            AT acc = y[rr];
-            const int64_t e1 = rc_ptr[o + rr + 1];
-            for (int64_t e = rc_ptr[o + rr]; e < e1; ++e) acc -= wi[rc_w[e]];
-            t[rr] = acc;
-        }
-        __syncthreads();
-        // (2)
-        {
+        if (lev == 0) {
+            // (2) on the leaves, in place
+            for (int ch = wv; ch < nch; ch += NW) {
+                const int rr = ch_row[cb + ch] + lane;
+                AT acc = 0;
+                if (rr < ch_row[cb + ch + 1]) {
+                    const int4 J = snt[rsn[rr]];
+                    const int c0 = rr - J.x;
+                    const VT *row = Li + J.w + c0;
+#pragma unroll 4
+                    for (int c = 0; c <= c0; ++c) acc += to_acc(row[int64_t(c) * J.y]) * y[J.x + c];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (rr < ch_row[cb + ch + 1]) y[rr] = acc;
+            }
+        } else {
+            // (1)
+            for (int rr = R0 + tid; rr < R1; rr += NT) {
+                AT acc = y[rr];
+                const int64_t e1 = rc_ptr[o + rr + 1];
+                for (int64_t e = rc_ptr[o + rr]; e < e1; ++e) acc -= wi[rc_w[e]];
+                t[rr - R0] = acc;
+            }
+            __syncthreads();
+            // (2)
             const int G = lanes_for(R1 - R0, a.y, 1), g = tid & (G - 1);
             for (int rr = R0 + tid / G; rr < R1; rr += NT / G) {
                 const int4 J = snt[rsn[rr]];   // first, columns, panel rows, value offset
                 const int c0 = rr - J.x;
                 const VT *row = Li + J.w + c0;
+                const AT *tJ = t + (J.x - R0);
                 AT acc = 0;
 #pragma unroll 4
-                for (int c = g; c <= c0; c += G) acc += to_acc(row[int64_t(c) * J.y]) * t[J.x + c];
+                for (int c = g; c <= c0; c += G) acc += to_acc(row[int64_t(c) * J.y]) * tJ[c];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }
@@ -274,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
         }
         __syncthreads();
     }
-    for (int lev = nlev - 1; lev >= 0; --lev) {
+    for (int lev = nlev - 1; lev >= 1; --lev) {
         const int R0 = lv_ptr[lb + lev], R1 = lv_ptr[lb + lev + 1];
         const int4 a = lv_info[lb + lev];
         // (4)
@@ -290,7 +313,7 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
 #pragma unroll 4
                 for (int q = g; q < ns; q += G) acc += to_acc(col[q]) * y[srow[q]];
                 acc = group_sum(acc, G);
-                if (g == 0) t[rr] = y[rr] - acc;
+                if (g == 0) t[rr - R0] = y[rr] - acc;
             }
         }
         __syncthreads();
@@ -301,15 +324,46 @@ __global__ __launch_bounds__(NT) void k_nd_apply(
                 const int4 J = snt[rsn[rr]];
                 const int c = rr - J.x;
                 const VT *col = Li + J.w + int64_t(c) * J.y;
+                const AT *tJ = t + (J.x - R0);
                 AT acc = 0;
 #pragma unroll 4
-                for (int k = c + g; k < J.y; k += G) acc += to_acc(col[k]) * t[J.x + k];
+                for (int k = c + g; k < J.y; k += G) acc += to_acc(col[k]) * tJ[k];
                 acc = group_sum(acc, G);
                 if (g == 0) y[rr] = acc;
             }
         }
         __syncthreads();
     }
+    // (4) and (5) on the leaves, in place
+    for (int ch = wv; ch < nch; ch += NW) {
+        const int rr = ch_row[cb + ch] + lane;
+        const bool in = rr < ch_row[cb + ch + 1];
+        int4 J = make_int4(0, 0, 0, 0);
+        AT acc = 0;
+        if (in) {
+            const int j0 = rsn[rr];
+            J = snt[j0];
+            const int ns = J.z - J.y;
+            const VT *col = Li + J.w + int64_t(J.y) * J.y + int64_t(rr - J.x) * ns;
+            const int32_t *srow = st_row + sb + stp[j0];
+#pragma unroll 4
+            for (int q = 0; q < ns; ++q) acc += to_acc(col[q]) * y[srow[q]];
+            acc = y[rr] - acc;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (in) y[rr] = acc;
+        __builtin_amdgcn_wave_barrier();
+        acc = 0;
+        if (in) {
+            const int c = rr - J.x;
+            const VT *col = Li + J.w + int64_t(c) * J.y;
+#pragma unroll 4
+            for (int k = c; k < J.y; ++k) acc += to_acc(col[k]) * y[J.x + k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (in) y[rr] = acc;
+    }
+    __syncthreads();
     for (int l = tid; l < ni; l += NT) {
         const int d = ov_idx[o + l];
         double v = double(y[iperm[o + l]]);

@@ -29,8 +29,6 @@
 namespace gdsw {
 namespace {
 
-constexpr int ND_LEAF = 64;
-
 struct LocalGraph {
     const int64_t *ptr;   // local CSR rows (diagonal included)
     const int32_t *col;
@@ -252,7 +250,8 @@ void build_nd(Symbolic &s) {
     // gfx950 compute unit's 160 KiB of LDS (nd_lds_bytes with 8-byte
     // accumulators for FP64 factors, 4 otherwise; at most
     // ND_MAX_SUPERNODES supernodes; panel values of one subdomain below
-    // 2^31), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose
+    // 2^31) and whose leaves hold at most ND_LEAF rows (a part the level
+    // search cannot split stays whole), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose
     // panels hold fewer values than their band (both read twice per apply);
     // the others keep the band.  The choice depends on the subdomain alone,
     // so a problem's results do not depend on what it is packed with.
@@ -263,11 +262,15 @@ void build_nd(Symbolic &s) {
         const int64_t ni = s.ov_ptr[i + 1] - s.ov_ptr[i];
         const SubND &u = sub[i];
         if (ni == 0 || int(u.first.size()) > ND_MAX_SUPERNODES ||
-            nd_lds_bytes(int(ni), ND_MAX_SUPERNODES, acc) > size_t(160) * 1024)
+            nd_lds_bytes(int(ni), int(ni), ND_MAX_SUPERNODES, acc) > size_t(160) * 1024)
             continue;
         int64_t vals = 0;
-        for (size_t J = 0; J < u.first.size(); ++J) vals += int64_t(u.ncol[J]) * (u.ncol[J] + int64_t(u.st[J].size()));
-        if (vals >= (int64_t(1) << 31)) continue;
+        bool small_leaves = true;
+        for (size_t J = 0; J < u.first.size(); ++J) {
+            vals += int64_t(u.ncol[J]) * (u.ncol[J] + int64_t(u.st[J].size()));
+            if (u.height[J] == 0 && u.ncol[J] > ND_LEAF) small_leaves = false;
+        }
+        if (vals >= (int64_t(1) << 31) || !small_leaves) continue;
         s.nd_mask[i] = all_nd || vals < ni * int64_t(s.bw[i] + 1);
     }
     for (int i = 0; i < np; ++i)
@@ -349,12 +352,15 @@ void build_nd(Symbolic &s) {
     // rows by height
     d.lv_base.assign(np + 1, 0);
     d.lv_rows.resize(nloc);
+    d.ch_base.assign(np + 1, 0);
+    d.ch_row.clear();
     {
         std::vector<int32_t> lp;
         for (int i = 0; i < np; ++i) {
             const int64_t o = s.ov_ptr[i];
             if (!s.nd_mask[i]) {   // a band subdomain: no levels
                 d.lv_base[i + 1] = d.lv_base[i];
+                d.ch_base[i + 1] = int64_t(d.ch_row.size());
                 for (int64_t p = o; p < s.ov_ptr[i + 1]; ++p) d.lv_rows[p] = int32_t(p - o);
                 continue;
             }
@@ -394,6 +400,20 @@ void build_nd(Symbolic &s) {
             d.lv_base[i + 1] = d.lv_base[i] + H + 1;
             lp.insert(lp.end(), ptr.begin(), ptr.end());
             d.max_levels = std::max(d.max_levels, H);
+            for (int hh = 1; hh < H; ++hh) d.max_t = std::max(d.max_t, ptr[hh + 1] - ptr[hh]);
+            // the leaves' rows (height 0, rows 0 .. ptr[1]) in chunks of at
+            // most 64 rows that split no leaf: one wavefront solves a chunk
+            d.ch_row.push_back(0);
+            int32_t b0 = 0, cur = 0;
+            for (int64_t J = d.sn_ptr[i]; J < d.sn_ptr[i + 1] && d.height[J] == 0; ++J) {
+                if (cur + d.ncol[J] - b0 > 64) {
+                    d.ch_row.push_back(cur);
+                    b0 = cur;
+                }
+                cur += d.ncol[J];
+            }
+            if (cur > b0) d.ch_row.push_back(cur);
+            d.ch_base[i + 1] = int64_t(d.ch_row.size());
         }
         d.lv_ptr = std::move(lp);
     }

@@ -23,7 +23,8 @@ def _maps(h):
                 lv_ptr=g(B.MAP_ND_LV_PTR), lv_rows=g(B.MAP_ND_LV_ROWS), up_ptr=g(B.MAP_ND_UP_PTR),
                 up=g(B.MAP_ND_UP).reshape(-1, 4), rel=g(B.MAP_ND_REL), asm=g(B.MAP_ND_ASM).reshape(-1, 2),
                 ov_ptr=g(B.MAP_OV_PTR), ov_idx=g(B.MAP_OV_IDX), rc_w=g(B.MAP_ND_RC_W), st_sn=g(B.MAP_ND_ST_SN),
-                lv_info=g(B.MAP_ND_LV_INFO).reshape(-1, 4))
+                lv_info=g(B.MAP_ND_LV_INFO).reshape(-1, 4), ch_base=g(B.MAP_ND_CH_BASE),
+                ch_row=g(B.MAP_ND_CH_ROW))
 
 
 def _factor(m, Aval):
@@ -190,6 +191,12 @@ def _check_levels(m, i):
         assert np.all(m["st_sn"][m["st_ptr"][Js[0]]:m["st_ptr"][Js[-1] + 1]] ==
                       np.repeat(Js, ns))
     assert info[nlev, 0] == m["st_ptr"][s1] - sb
+    # the leaves in chunks of at most 64 rows, each a run of whole leaves
+    ch = m["ch_row"][m["ch_base"][i]:m["ch_base"][i + 1]]
+    leaf_ends = {0} | {int(m["first"][J] + m["ncol"][J]) for J in range(s0, s1) if ht[J - s0] == 0}
+    assert ch[0] == 0 and ch[-1] == lp[1] and np.all(np.diff(ch) > 0) and np.all(np.diff(ch) <= 64)
+    assert set(ch.tolist()) <= leaf_ends
+    assert np.all(m["ncol"][s0:s1][ht == 0] <= 64)
     # gather entries: struct entry of K at row rr
     for rr in range(n):
         for q in range(m["rc_ptr"][o + rr], m["rc_ptr"][o + rr + 1]):
