@@ -45,9 +45,10 @@ ORDERS = {"natural": 0, "nd": 1, "auto": 2}
 # profiles/hbm_traffic_*.md).  A figure only applies to the kernel source it
 # was measured on: `src` is a hash of that kernel's text, checked below.
 MEASURED_TRAFFIC = {
-    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 271355003, "src": "01873f67dbb64d3a"},
-    ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14274626339, "src": "c63f9cb3b151c80b"},
-    ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1610807593, "src": "c63f9cb3b151c80b"},
+    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 270263559, "src": "04585098cbd2f750"},
+    ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14214515281, "src": "ac54f5871e9111d8"},
+    ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1606847147, "src": "ac54f5871e9111d8"},
+    ("k_nd_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 6140767346, "src": "46cb08cab31501fd"},
 }
 
 
@@ -62,6 +63,7 @@ def kernel_source_hash(kernel):
         "k_band_apply": [("kernels_setup.hpp", "constexpr int BS_NB = 64;", "// Extension, eq. (2)."),
                          ("kernels_apply.hpp", "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor",
                           "// Coarse restriction Phi^T r.")],
+        "k_nd_apply": [("kernels_nd.hpp", "// Sum over aligned groups of G lanes", "}  // namespace gdsw")],
     }
     if kernel not in segments:
         return None
@@ -377,7 +379,7 @@ def sub(d, keys=("value", "ms_per_step", "dtype", "applies_per_sec", "p50_ms", "
     out = {k: d[k] for k in keys if k in d and d[k] is not None}
     out["workload"] = d["config"]["workload"]
     out["unit"] = "solves/s"
-    out["roofline"] = {k: d["roofline"][k] for k in ("kernel", "achieved", "frac", "avg_launch_ms",
+    out["roofline"] = {k: d["roofline"][k] for k in ("kernel", "achieved", "frac", "avg_launch_ms", "traffic",
                                                      "alg_bytes_per_launch")}
     if d.get("apply_roofline"):
         out["apply_roofline_frac"] = d["apply_roofline"]["frac"]
