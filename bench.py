@@ -87,7 +87,7 @@ GOLD = os.path.join(ROOT, "tests", "golden")
 
 def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=None, gmres="single_reduce",
            ilu_level=0, factor_sweeps=0, graphs=False, steps=10, warmup=2, kernel_reps=50, autotune=True,
-           with_graph_apply=True, order="natural"):
+           with_graph_apply=True, order="natural", element_sharing=False):
     """One workload on one handle: setup, autotune, `warmup` + `steps` timed
     solves, applies/s from a graph-replayed apply, the dominant kernel timed
     where it runs, and the error against FP64 oracle samples where the
@@ -119,13 +119,15 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
+    sharing = P.element_sharing(pr) if element_sharing else None
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                        B.gdsw_default_options(local=loc, local_prec=precs[prec],
                                               basis_prec=B.FP64 if prec == "fp64" else B.FP32,
                                               ilu_level=ilu_level, ilu_factor_sweeps=factor_sweeps,
                                               coarse=B.COARSE_RGDSW if coarse_name == "rgdsw" else B.COARSE_GDSW,
                                               flags=B.FLAG_GRAPHS if graphs else 0,
-                                              exact_order=ORDERS[order]))
+                                              exact_order=ORDERS[order]),
+                       sharing=sharing)
     t_an = time.perf_counter() - t0
     log(f"[bench] analysis {t_an:.2f}s; numerical setup on the GPU")
     B.gdsw_factor(h, stream)
@@ -205,7 +207,7 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
     # ---- error against the FP64 oracle (sampled) ------------------------------------
     err = None
     xe = torch.zeros_like(r)
-    if elastic and (N, Pn) == (48, 6):
+    if elastic and (N, Pn) == (48, 6) and not element_sharing:
         gold = np.load(os.path.join(GOLD, "elasticity_oracle.npz" if coarse_name == "gdsw"
                                     else f"elasticity_{coarse_name}_oracle.npz"))
         bl = torch.from_numpy(pr.b).to(dev)
@@ -319,6 +321,7 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                    "jacobi_sweeps": 5, "ilu_level": ilu_level, "ilu_factor_sweeps": factor_sweeps,
                    "local_prec": prec, "rtol": 1e-8,
                    "exact_order": order if local == "exact" else None,
+                   "interface": "element sharing sets" if element_sharing else "node graph",
                    "nd_subdomains": info["nd_subdomains"],
                    "tuned_local_variant": info["local_variant"], "tuned_gemv_variant": info["gemv_variant"],
                    "tuned_apply_streams": info["apply_streams"], "tuned_prolong_variant": info["prolong_variant"],
@@ -411,6 +414,9 @@ def main():
     ap.add_argument("--coarse", choices=["gdsw", "rgdsw"], default=None,
                     help="coarse space: GDSW, or the reduced GDSW space of the paper's experiments "
                          "(default: rgdsw for the elasticity workload, gdsw for Poisson)")
+    ap.add_argument("--element-sharing", action="store_true",
+                    help="elasticity: the interface from the element decomposition's sharing sets (the "
+                         "geometric GDSW / rGDSW space) instead of the node graph")
     ap.add_argument("--ilu-level", type=int, default=0)
     ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--N", type=int, default=None)
@@ -434,7 +440,7 @@ def main():
         args.local = "exact" if kind == "elasticity" else "ilu0"
     d = single(kind, args.N, args.P, args.local, args.prec, args.coarse, args.gmres, args.ilu_level,
                args.factor_sweeps, args.graphs, args.steps, args.warmup, args.kernel_reps,
-               order=args.exact_order)
+               order=args.exact_order, element_sharing=args.element_sharing)
     line = {
         "metric": METRIC,
         "value": d["value"], "unit": "solves/s", "n_gpus": 1, "steps": d["steps"], "warmup": d["warmup"],

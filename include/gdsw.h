@@ -261,6 +261,27 @@ gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts
                          int32_t dpn, const double *Z, int32_t n_null,
                          const gdsw_options *opt, gdsw_handle *out);
 
+/* Phase (a) as gdsw_analyze, with the interface taken from given sharing
+ * sets instead of the node graph: the geometric interface of a
+ * decomposition into subdomains of elements (Sec. III: Gamma is the set of
+ * nodes shared by two or more subdomains, its components are grouped by the
+ * set of subdomains sharing them).
+ *   share_ptr: [n/dpn + 1] int64, share_ptr[0] = 0, ascending (host);
+ *   share_sub: [share_ptr[n/dpn]] int32 (host): for node v the subdomains
+ *              whose elements contain v, at share_sub[share_ptr[v] ..
+ *              share_ptr[v+1]) in any order (duplicates allowed).
+ * Both are read during the call only.  Every node's set must contain
+ * part[v]; a node with a set of one subdomain is interior, and each of its
+ * graph neighbours must be shared by that subdomain (A_II block diagonal,
+ * eq. (2)).  The overlapping subdomains still come from `part` and the
+ * graph.  Errors: INVALID_ARG (NULL arrays, ids out of range, a set
+ * without the node's own subdomain, an interior node coupled outside its
+ * subdomain), otherwise as gdsw_analyze. */
+gdsw_status gdsw_analyze_sharing(const gdsw_csr *A, const int32_t *part, int32_t n_parts,
+                                 int32_t dpn, const double *Z, int32_t n_null,
+                                 const int64_t *share_ptr, const int32_t *share_sub,
+                                 const gdsw_options *opt, gdsw_handle *out);
+
 /* Phase (b), numeric, on the current HIP device: uploads the maps, gathers
  * the local matrices, factors them, computes the extension Phi_I, assembles
  * A_0 and inverts it.  Synchronises `stream` before returning (so that

@@ -147,6 +147,24 @@ def interface(G: sp.csr_matrix, part: np.ndarray):
     return is_g, {k: tuple(sorted(s)) for k, s in S.items()}
 
 
+def interface_from_sharing(share_ptr: np.ndarray, share_sub: np.ndarray, part: np.ndarray):
+    """O4 for a decomposition into subdomains of elements (Sec. III): S(v) is
+    the set of subdomains whose elements contain node v, as given, and v is
+    on the interface iff S(v) holds two or more subdomains.  Every S(v) must
+    contain part(v).  Returns (is_gamma, S) as interface() does."""
+    nn = len(share_ptr) - 1
+    is_g = np.zeros(nn, dtype=bool)
+    S = {}
+    for v in range(nn):
+        sv = tuple(sorted(set(int(q) for q in share_sub[share_ptr[v]:share_ptr[v + 1]])))
+        if int(part[v]) not in sv:
+            raise ValueError(f"node {v}: its own subdomain does not share it")
+        if len(sv) >= 2:
+            is_g[v] = True
+            S[v] = sv
+    return is_g, S
+
+
 def components(G: sp.csr_matrix, is_g: np.ndarray, S: dict) -> list[np.ndarray]:
     """O5: group interface nodes by their set S, split every group into
     connected pieces of the graph restricted to the group, and order the
@@ -286,14 +304,17 @@ class GDSW:
     are exact ILU(k) factors, or with ``factor_sweeps`` > 0 the FastILU
     approximation after that many sweeps.  coarse = False drops the coarse
     term (one level); coarse_space = "rgdsw" takes the reduced GDSW interface
-    basis of O8r instead of one block per component (O8).
+    basis of O8r instead of one block per component (O8).  sharing =
+    (share_ptr, share_sub) takes the interface from the sets of subdomains
+    sharing each node (interface_from_sharing) instead of the node graph.
     """
 
     def __init__(self, A, part, dpn: int, n_parts: int, Z=None, overlap: int = 1,
                  coarse: bool = True, local: str = "exact", sweeps: int = 5,
-                 ilu_level: int = 0, factor_sweeps: int = 0, coarse_space: str = "gdsw"):
+                 ilu_level: int = 0, factor_sweeps: int = 0, coarse_space: str = "gdsw", sharing=None):
         if coarse_space not in ("gdsw", "rgdsw"):
             raise ValueError(coarse_space)
+        self.sharing = sharing
         self.coarse_space = coarse_space
         self.A = sp.csr_matrix(A, dtype=np.float64)
         self.A.sort_indices()
@@ -322,7 +343,10 @@ class GDSW:
         self.G = node_graph(self.A, self.dpn)
         self.ov_nodes = overlapping_subdomains(self.G, self.part, self.n_parts, self.overlap)
         self.R = [dofs_of(nd, self.dpn) for nd in self.ov_nodes]
-        self.is_gamma, self.S = interface(self.G, self.part)
+        if self.sharing is None:
+            self.is_gamma, self.S = interface(self.G, self.part)
+        else:
+            self.is_gamma, self.S = interface_from_sharing(self.sharing[0], self.sharing[1], self.part)
         self.comps = components(self.G, self.is_gamma, self.S)
 
     # -- O3, O11 -----------------------------------------------------------

@@ -40,8 +40,8 @@ _MAP_DTYPE = {0: np.int64, 1: np.int64, 2: np.int8, 3: np.int32, 4: np.int32,
               25: np.int64, 26: np.int32, 27: np.int32, 28: np.int32, 29: np.int64, 30: np.int32}
 ORDER_NATURAL, ORDER_ND, ORDER_AUTO = 0, 1, 2
 
-EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_factor", "gdsw_refactor", "gdsw_setup",
-            "gdsw_apply", "gdsw_apply_static", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
+EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_analyze_sharing", "gdsw_factor", "gdsw_refactor",
+            "gdsw_setup", "gdsw_apply", "gdsw_apply_static", "gdsw_apply_part", "gdsw_spmv", "gdsw_solve", "gdsw_get_info",
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
             "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch",
@@ -96,6 +96,8 @@ def lib():
         "gdsw_default_options": (None, [ctypes.POINTER(Options)]),
         "gdsw_analyze": (ctypes.c_int, [ctypes.POINTER(CSR), vp, i32, i32, vp, i32, ctypes.POINTER(Options),
                                         ctypes.POINTER(vp)]),
+        "gdsw_analyze_sharing": (ctypes.c_int, [ctypes.POINTER(CSR), vp, i32, i32, vp, i32, vp, vp,
+                                                ctypes.POINTER(Options), ctypes.POINTER(vp)]),
         "gdsw_factor": (ctypes.c_int, [vp, vp]),
         "gdsw_refactor": (ctypes.c_int, [vp, vp, vp]),
         "gdsw_setup": (ctypes.c_int, [ctypes.POINTER(CSR), vp, i32, i32, vp, i32, ctypes.POINTER(Options), vp,
@@ -176,8 +178,10 @@ def _csr_arrays(A):
     return rowptr, col, val
 
 
-def gdsw_analyze(A, part, n_parts, dpn=1, Z=None, options: Options | None = None):
-    """Symbolic phase on the host; returns a handle (int)."""
+def gdsw_analyze(A, part, n_parts, dpn=1, Z=None, options: Options | None = None, sharing=None):
+    """Symbolic phase on the host; returns a handle (int).  sharing: None
+    (the interface from the node graph) or (share_ptr, share_sub), the sets
+    of subdomains sharing each node (gdsw_analyze_sharing)."""
     rowptr, col, val = _csr_arrays(A)
     csr = CSR(A.shape[0], rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
     part = np.ascontiguousarray(part, dtype=np.int32)
@@ -188,8 +192,15 @@ def gdsw_analyze(A, part, n_parts, dpn=1, Z=None, options: Options | None = None
         Zc, zp, nz = None, None, 0
     opt = options if options is not None else gdsw_default_options()
     h = ctypes.c_void_p()
-    st = lib().gdsw_analyze(ctypes.byref(csr), part.ctypes.data, int(n_parts), int(dpn), zp, nz,
-                            ctypes.byref(opt), ctypes.byref(h))
+    if sharing is None:
+        st = lib().gdsw_analyze(ctypes.byref(csr), part.ctypes.data, int(n_parts), int(dpn), zp, nz,
+                                ctypes.byref(opt), ctypes.byref(h))
+    else:
+        sp_ = np.ascontiguousarray(sharing[0], dtype=np.int64)
+        ss_ = np.ascontiguousarray(sharing[1], dtype=np.int32)
+        st = lib().gdsw_analyze_sharing(ctypes.byref(csr), part.ctypes.data, int(n_parts), int(dpn), zp, nz,
+                                        sp_.ctypes.data, ss_.ctypes.data if ss_.size else sp_.ctypes.data,
+                                        ctypes.byref(opt), ctypes.byref(h))
     if st != GDSW_OK:
         msg = gdsw_last_error(h.value)
         gdsw_destroy(h.value)
@@ -401,8 +412,8 @@ def gdsw_last_error(h) -> str:
 class Gdsw:
     """Owning wrapper of a handle (destroyed with the object)."""
 
-    def __init__(self, A, part, n_parts, dpn=1, Z=None, factor=True, stream=None, **options):
-        self.h = gdsw_analyze(A, part, n_parts, dpn, Z, gdsw_default_options(**options))
+    def __init__(self, A, part, n_parts, dpn=1, Z=None, factor=True, stream=None, sharing=None, **options):
+        self.h = gdsw_analyze(A, part, n_parts, dpn, Z, gdsw_default_options(**options), sharing=sharing)
         self.n = A.shape[0]
         if factor:
             try:

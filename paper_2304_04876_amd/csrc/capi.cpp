@@ -40,6 +40,19 @@ gdsw_status gdsw_analyze(const gdsw_csr *A, const int32_t *part, int32_t n_parts
     return st;
 }
 
+gdsw_status gdsw_analyze_sharing(const gdsw_csr *A, const int32_t *part, int32_t n_parts, int32_t dpn,
+                                 const double *Z, int32_t n_null, const int64_t *share_ptr,
+                                 const int32_t *share_sub, const gdsw_options *opt, gdsw_handle *out) {
+    if (!out) return GDSW_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!share_ptr || !share_sub) return GDSW_ERR_INVALID_ARG;
+    gdsw_handle_s *h = new (std::nothrow) gdsw_handle_s();
+    if (!h) return GDSW_ERR_BUDGET;
+    gdsw_status st = gdsw::analyze(h, A, part, n_parts, dpn, Z, n_null, opt, share_ptr, share_sub);
+    *out = h;
+    return st;
+}
+
 gdsw_status gdsw_analyze_batch(int32_t count, const gdsw_csr *A, const int32_t *const *part, const int32_t *n_parts,
                                int32_t dpn, const double *const *Z, int32_t n_null, const gdsw_options *opt,
                                gdsw_handle *out) {

@@ -106,6 +106,10 @@ struct Symbolic {
     std::vector<int32_t> col;
     std::vector<double> val;
     std::vector<int32_t> part;      // [nn]
+    // optional sharing sets (gdsw_analyze_sharing): the subdomains whose
+    // elements hold each node; empty for the algebraic interface
+    std::vector<int64_t> share_ptr; // [nn+1]
+    std::vector<int32_t> share_sub;
     std::vector<double> Z;          // [n x n_null] column-major
     int32_t n_null = 1;
 
@@ -239,7 +243,8 @@ struct gdsw_handle_s {
 namespace gdsw {
 // symbolic.cpp
 gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, int32_t n_parts,
-                    int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt);
+                    int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt,
+                    const int64_t *share_ptr = nullptr, const int32_t *share_sub = nullptr);
 gdsw_status analyze_batch(gdsw_handle_s *h, int32_t count, const gdsw_csr *A, const int32_t *const *part,
                           const int32_t *n_parts, int32_t dpn, const double *const *Z, int32_t n_null,
                           const gdsw_options *opt);

@@ -247,28 +247,62 @@ void build_overlap(Symbolic &s) {
 }
 
 // ---------------------------------------------------------------------------
-// interface, its components and the interface basis
+// interface, its components and the interface basis.  The interface of the
+// node partition: a node with a neighbour in a lower-numbered subdomain,
+// its set the subdomains of those neighbours and its own; or, when the
+// caller gives them, the sets of subdomains whose elements hold each node
+// (the geometric interface of an element decomposition, Sec. III).
 void build_interface(Symbolic &s) {
     const int64_t nn = s.nn;
     s.is_gamma.assign(nn, 0);
     std::vector<std::vector<int32_t>> S(nn);
     int64_t ng = 0;
-    for (int64_t v = 0; v < nn; ++v) {
-        int32_t pv = s.part[v];
-        std::vector<int32_t> lower;
-        for (int64_t p = s.gptr[v]; p < s.gptr[v + 1]; ++p) {
-            int32_t pu = s.part[s.gadj[p]];
-            if (pu < pv) lower.push_back(pu);
+    if (!s.share_ptr.empty()) {
+        // sharing sets given (a decomposition into subdomains of elements):
+        // a node shared by two or more subdomains is on the interface
+        for (int64_t v = 0; v < nn; ++v) {
+            std::vector<int32_t> set(s.share_sub.begin() + s.share_ptr[v], s.share_sub.begin() + s.share_ptr[v + 1]);
+            std::sort(set.begin(), set.end());
+            set.erase(std::unique(set.begin(), set.end()), set.end());
+            if (!std::binary_search(set.begin(), set.end(), s.part[v]))
+                fail(GDSW_ERR_INVALID_ARG, "sharing sets: node " + std::to_string(v) + " is not shared by its own subdomain");
+            if (set.size() >= 2) {
+                s.is_gamma[v] = 1;
+                ++ng;
+                S[v] = std::move(set);
+            }
         }
-        if (!lower.empty()) {
-            s.is_gamma[v] = 1;
-            ++ng;
-            lower.push_back(pv);
-            std::sort(lower.begin(), lower.end());
-            lower.erase(std::unique(lower.begin(), lower.end()), lower.end());
-            S[v] = std::move(lower);
+        // the extension needs A_II block diagonal: an interior node's
+        // neighbours are all shared by its subdomain
+        for (int64_t v = 0; v < nn; ++v) {
+            if (s.is_gamma[v]) continue;
+            for (int64_t p = s.gptr[v]; p < s.gptr[v + 1]; ++p) {
+                const int32_t u = s.gadj[p];
+                const bool ok = s.is_gamma[u] ? std::binary_search(S[u].begin(), S[u].end(), s.part[v])
+                                              : s.part[u] == s.part[v];
+                if (!ok)
+                    fail(GDSW_ERR_INVALID_ARG, "sharing sets: interior node " + std::to_string(v) +
+                                                   " is coupled to node " + std::to_string(u) +
+                                                   ", which its subdomain does not share");
+            }
         }
-    }
+    } else
+        for (int64_t v = 0; v < nn; ++v) {
+            int32_t pv = s.part[v];
+            std::vector<int32_t> lower;
+            for (int64_t p = s.gptr[v]; p < s.gptr[v + 1]; ++p) {
+                int32_t pu = s.part[s.gadj[p]];
+                if (pu < pv) lower.push_back(pu);
+            }
+            if (!lower.empty()) {
+                s.is_gamma[v] = 1;
+                ++ng;
+                lower.push_back(pv);
+                std::sort(lower.begin(), lower.end());
+                lower.erase(std::unique(lower.begin(), lower.end()), lower.end());
+                S[v] = std::move(lower);
+            }
+        }
     s.n_gamma_nodes = ng;
     // group by S
     std::map<std::vector<int32_t>, int32_t> gid;
@@ -996,11 +1030,22 @@ void build_coarse(Symbolic &s) {
 }  // namespace
 
 gdsw_status analyze(gdsw_handle_s *h, const gdsw_csr *A, const int32_t *part, int32_t n_parts,
-                    int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt) {
+                    int32_t dpn, const double *Z, int32_t n_null, const gdsw_options *opt,
+                    const int64_t *share_ptr, const int32_t *share_sub) {
     auto t0 = std::chrono::steady_clock::now();
     try {
         Symbolic &s = h->sym;
         validate_and_copy(s, A, part, n_parts, dpn, Z, n_null, opt);
+        if (share_ptr || share_sub) {
+            if (!share_ptr || !share_sub) fail(GDSW_ERR_INVALID_ARG, "sharing sets: both arrays are needed");
+            if (share_ptr[0] != 0) fail(GDSW_ERR_INVALID_ARG, "sharing sets: share_ptr[0] must be 0");
+            for (int64_t v = 0; v < s.nn; ++v)
+                if (share_ptr[v + 1] < share_ptr[v]) fail(GDSW_ERR_INVALID_ARG, "sharing sets: share_ptr not ascending");
+            s.share_ptr.assign(share_ptr, share_ptr + s.nn + 1);
+            s.share_sub.assign(share_sub, share_sub + share_ptr[s.nn]);
+            for (int32_t q : s.share_sub)
+                if (q < 0 || q >= s.np) fail(GDSW_ERR_INVALID_ARG, "sharing sets: subdomain id out of range");
+        }
         if (s.prob_ptr.empty()) {
             s.nprob = 1;
             s.prob_ptr = {0, s.n};

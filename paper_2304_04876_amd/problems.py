@@ -257,6 +257,32 @@ def elasticity_q1(Ne: int, P: int | tuple = 2, E: float = 1.0, nu: float = 0.3,
                    coords, b=b, meta={"Ne": Ne, "P": P, "E": E, "nu": nu})
 
 
+def element_sharing(prob: Problem):
+    """For a Q1 mesh from elasticity_q1: the boxes of the elements around each
+    node (the element decomposition that the node boxes come from: element
+    (ex, ey, ez) lies in box (box_index(ex, P, Ne), ...)).  Returns the sets
+    as (ptr int64 [n_nodes+1], boxes int32), ascending within each node."""
+    Ne, P = prob.meta["Ne"], prob.meta["P"]
+    h = 1.0 / Ne
+    g = np.rint(prob.coords / h).astype(np.int64)            # grid index of each node
+    nn = g.shape[0]
+    cand = np.full((nn, 8), -1, dtype=np.int64)
+    for a in range(8):
+        d = np.array([a & 1, (a >> 1) & 1, (a >> 2) & 1]) - 1   # cells g-1 or g per axis
+        c = g + d[None, :]
+        ok = np.all((c >= 0) & (c <= Ne - 1), axis=1)
+        bx = [np.minimum((c[:, k] * P[k]) // Ne, P[k] - 1) for k in range(3)]
+        box = bx[0] + P[0] * (bx[1] + P[1] * bx[2])
+        cand[ok, a] = box[ok]
+    cand.sort(axis=1)
+    keep = cand >= 0
+    keep[:, 1:] &= cand[:, 1:] != cand[:, :-1]
+    counts = keep.sum(axis=1)
+    ptr = np.zeros(nn + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    return ptr, cand[keep].astype(np.int32)
+
+
 def constant_nullspace(prob: Problem) -> np.ndarray:
     """Null space of the Neumann operator of a scalar problem: one constant."""
     return np.ones((prob.n, 1))

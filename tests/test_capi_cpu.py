@@ -37,12 +37,14 @@ def test_status_strings_and_defaults():
     assert (o.overlap, o.coarse, o.local, o.jacobi_sweeps, o.local_prec) == (1, 1, 0, 5, 0)
 
 
-def _maps_equal(pr, Z=None, overlap=1, local="exact", coarse="gdsw"):
+def _maps_equal(pr, Z=None, overlap=1, local="exact", coarse="gdsw", sharing=None):
     h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                        B.gdsw_default_options(overlap=overlap, local=0 if local == "exact" else 1,
-                                              coarse=B.COARSE_RGDSW if coarse == "rgdsw" else B.COARSE_GDSW))
+                                              coarse=B.COARSE_RGDSW if coarse == "rgdsw" else B.COARSE_GDSW),
+                       sharing=sharing)
     try:
-        M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, overlap=overlap, local=local, coarse_space=coarse)
+        M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, overlap=overlap, local=local, coarse_space=coarse,
+                   sharing=sharing)
         m = M.maps()
         ov_ptr = np.concatenate([[0], np.cumsum([r.size for r in M.R])])
         assert np.array_equal(B.gdsw_copy_map(h, B.MAP_OV_PTR), ov_ptr)
@@ -250,3 +252,48 @@ def test_size_limits_and_degenerate_inputs():
     ovp = B.gdsw_copy_map(h, B.MAP_OV_PTR)
     assert info["n_parts"] == pr.n_parts + 1 and ovp[-1] == ovp[-2]
     B.gdsw_destroy(h)
+
+
+@pytest.mark.parametrize("Ne,Pn,coarse", [(6, 2, "gdsw"), (9, 3, "gdsw"), (9, 3, "rgdsw")])
+def test_maps_element_sharing(Ne, Pn, coarse):
+    """The interface from the element decomposition's sharing sets
+    (gdsw_analyze_sharing): maps equal the oracle's bit for bit."""
+    pr = P.elasticity_q1(Ne, Pn)
+    _maps_equal(pr, Z=P.rigid_body_modes(pr), coarse=coarse, sharing=P.element_sharing(pr))
+
+
+def test_sharing_sets_rejected_when_inconsistent():
+    pr = P.elasticity_q1(6, 2)
+    Z = P.rigid_body_modes(pr)
+    ptr, sub = P.element_sharing(pr)
+    # every node alone in its own subdomain: interior nodes then touch other subdomains
+    own = (np.arange(pr.n_nodes + 1, dtype=np.int64), pr.part.astype(np.int32))
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 3, Z, sharing=own)
+    assert e.value.status == 1 and "interior node" in str(e.value)
+    # a set without the node's own subdomain
+    bad = sub.copy()
+    v = int(np.argmax(np.diff(ptr) == 1))
+    bad[ptr[v]] = (pr.part[v] + 1) % pr.n_parts
+    with pytest.raises(B.GdswError) as e:
+        B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 3, Z, sharing=(ptr, bad))
+    assert e.value.status == 1 and "own subdomain" in str(e.value)
+    # an id out of range
+    bad = sub.copy()
+    bad[0] = pr.n_parts
+    with pytest.raises(B.GdswError):
+        B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 3, Z, sharing=(ptr, bad))
+
+
+def test_element_sharing_full_size_counts():
+    """The 48^3 Q1 elasticity mesh in 6^3 boxes: the element sharing sets give
+    the geometric faces, edges and vertices (n_c = 540 + 450 + 125 = 1,115,
+    n_0 = 6*540 + 5*450 + 3*125 = 5,865; the node-graph interface of R6 gives
+    1,940 / 9,240)."""
+    pr = P.elasticity_q1(48, 6)
+    h = B.gdsw_analyze(pr.A, pr.part, pr.n_parts, 3, P.rigid_body_modes(pr), sharing=P.element_sharing(pr))
+    try:
+        info = B.gdsw_get_info(h)
+        assert (info["n_components"], info["n0"]) == (1115, 5865)
+    finally:
+        B.gdsw_destroy(h)
