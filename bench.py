@@ -64,6 +64,8 @@ def kernel_source_hash(kernel):
                          ("kernels_apply.hpp", "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor",
                           "// Coarse restriction Phi^T r.")],
         "k_nd_apply": [("kernels_nd.hpp", "// Sum over aligned groups of G lanes", "}  // namespace gdsw")],
+        "k_ilu_jacobi_phased": [("kernels_apply.hpp", "// The register-resident sweeps for factors with more slots",
+                                 "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor")],
     }
     if kernel not in segments:
         return None
@@ -280,7 +282,11 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
     # restriction index (4 B), the gathered r (8 B), the local result (8 B)
     alg_bytes = info["local_solve_bytes"]
     if local == "ilu0":
-        kname = "k_ilu_jacobi" if info["local_variant"] in (0, 1) else "k_ilu_jacobi_generic"
+        if info["local_variant"] in (0, 1):
+            # (ILU(k) with fill: 6 + 6 slots, L and U entries in registers one after the other)
+            kname = "k_ilu_jacobi_phased" if ilu_level >= 1 else "k_ilu_jacobi"
+        else:
+            kname = "k_ilu_jacobi_generic"
     elif info["nd_subdomains"] == pr.n_parts:
         kname = "k_nd_apply"
     elif info["nd_subdomains"] == 0:

@@ -475,17 +475,31 @@ static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *
                      const double *d_lval, hipStream_t s) {
     Symbolic &S = h->sym;
     Device &D = *h->dev;
+    // slot counts: 3 + 3 (ILU(0) of the 7-point stencil) or 6 + 6 (ILU(1))
+    // padded for the register-resident sweeps, else the exact counts for the
+    // streaming sweeps
     const bool small = S.KL <= ILU_KL && S.KU <= ILU_KU;
-    const int KL = small ? ILU_KL : std::max(S.KL, 1), KU = small ? ILU_KU : std::max(S.KU, 1);
+    const bool mid = !small && S.KL <= ILU_KL2 && S.KU <= ILU_KU2;
+    const int KL = small ? ILU_KL : mid ? ILU_KL2 : std::max(S.KL, 1);
+    const int KU = small ? ILU_KU : mid ? ILU_KU2 : std::max(S.KU, 1);
     if (!D.Lv) {   // (a numeric re-setup writes into the same buffers)
         D.KLp = KL;
         D.KUp = KU;
-        D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows);
-        D.Uv = D.alloc<VT>(int64_t(KU) * S.ell_rows);
+        // (the 6 + 6 layout carries ILU_PAD_ROWS zeroed rows past the last
+        // slot and the last packed row, for the phased sweeps' unclamped reads)
+        const int64_t pad = mid ? ILU_PAD_ROWS : 0;
+        const int cw = (KL + KU + 1) / 2;
+        D.Lv = D.alloc<VT>(int64_t(KL) * S.ell_rows + pad);
+        D.Uv = D.alloc<VT>(int64_t(KU) * S.ell_rows + pad);
         D.dinv = D.alloc<VT>(S.ell_rows);
         D.Lc = D.alloc<uint16_t>(int64_t(KL) * S.ell_rows);
         D.Uc = D.alloc<uint16_t>(int64_t(KU) * S.ell_rows);
-        if (small) D.Cp = D.alloc<uint32_t>(int64_t(ILU_CW) * S.ell_rows);
+        if (small || mid) D.Cp = D.alloc<uint32_t>(int64_t(cw) * (S.ell_rows + pad));
+        if (mid) {
+            HIPCHK(hipMemsetAsync(D.Lv, 0, sizeof(VT) * size_t(int64_t(KL) * S.ell_rows + pad), s));
+            HIPCHK(hipMemsetAsync(D.Uv, 0, sizeof(VT) * size_t(int64_t(KU) * S.ell_rows + pad), s));
+            HIPCHK(hipMemsetAsync(D.Cp, 0, sizeof(uint32_t) * size_t(int64_t(cw) * (S.ell_rows + pad)), s));
+        }
     }
     int64_t maxpad = 0;
     for (int i = 0; i < S.np; ++i) maxpad = std::max(maxpad, S.ell_off[i + 1] - S.ell_off[i]);
@@ -1183,11 +1197,45 @@ static Skip class_skip(const Device &D, const Skip &sk, const Device::SizeClass 
     return k;
 }
 
+// The phased register-resident sweeps (ILU(k) with fill, 6 + 6 slots),
+// one right-hand-side slot; rows per thread that keep the L (then U)
+// entries in registers without spilling at this workgroup size.
+template <typename VT, int NT>
+static bool launch_ilu_phased(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                              const Device::SizeClass &c) {
+    if (D.ns > 1) return false;
+    constexpr bool f64 = std::is_same<VT, double>::value;
+    const int need = (c.max_ni + NT - 1) / NT;
+    const int nb = c.end - c.begin;
+    const Skip kc = class_skip(D, sk, c);
+    using AT = typename AccOf<VT>::type;
+#define GDSW_ILU_CASE(RR)                                                                                    \
+    if (need <= RR) {                                                                                        \
+        const size_t lds = (2 * sizeof(AT) + (f64 ? 0 : sizeof(double))) * NT * RR;                          \
+        if (lds > D.max_lds) return false;                                                                   \
+        hipLaunchKernelGGL((k_ilu_jacobi_phased<NT, RR, ILU_KL2, ILU_KU2, VT>), dim3(nb), dim3(NT), lds, s,  \
+                           r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, (const VT *)D.Uv,  \
+                           D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, kc);              \
+        return true;                                                                                         \
+    }
+    GDSW_ILU_CASE(2)
+    GDSW_ILU_CASE(4)
+    if constexpr (!(f64 && NT == 1024)) {
+        GDSW_ILU_CASE(6)
+        GDSW_ILU_CASE(8)
+    }
+    if constexpr (NT == 512) { GDSW_ILU_CASE(11) }
+#undef GDSW_ILU_CASE
+    return false;
+}
+
 template <typename VT, int NT>
 static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
                             const Device::SizeClass &c) {
     // (one sweep per triangle needs no factor entries: the streaming kernel)
-    if (D.KLp != ILU_KL || D.KUp != ILU_KU || !D.Cp || S.opt.jacobi_sweeps < 2) return false;
+    if (!D.Cp || S.opt.jacobi_sweeps < 2) return false;
+    if (D.KLp == ILU_KL2 && D.KUp == ILU_KU2) return launch_ilu_phased<VT, NT>(S, D, r, sk, s, c);
+    if (D.KLp != ILU_KL || D.KUp != ILU_KU) return false;
     constexpr bool f64 = std::is_same<VT, double>::value;
     const int need = (c.max_ni + NT - 1) / NT;
     const int nb = c.end - c.begin;

@@ -265,6 +265,166 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     }
 }
 
+// The register-resident sweeps for factors with more slots per row (ILU(k)
+// with fill: KL = KU = 6 for ILU(1) of the 7-point stencil), whose L and U
+// entries do not fit the registers together: the L entries and columns are
+// held in registers for the L sweeps, then the same registers take the U
+// entries and columns, loaded after the L sweeps, for the U sweeps.  Each
+// factor entry is still read once per apply.  One right-hand-side slot;
+// the same LDS layout, rows per thread and order of operations as
+// k_ilu_jacobi.  Columns: CW words per row, the KL (even) L columns in the
+// first KL/2 words, the U columns after them.
+template <int NT, int R, int KL, int KU, typename VT>
+__global__ __launch_bounds__(NT) void k_ilu_jacobi_phased(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
+    const VT *__restrict__ Uv, const uint32_t *__restrict__ Cp, const VT *__restrict__ dinv,
+    const double *__restrict__ dscale, int sweeps, double *__restrict__ zloc, Skip sk) {
+    using AT = typename AccOf<VT>::type;
+    static_assert(KL % 2 == 0, "the L columns end on a word boundary");
+    constexpr int CW = (KL + KU + 1) / 2, CL = KL / 2, CU = CW - CL;
+    constexpr bool scaled = !std::is_same<VT, double>::value;
+    constexpr int SG = 2;   // rows whose LDS reads of a sweep are issued together
+    const int i = sk.sub_at(blockIdx.x);
+    if (sk.sub(i, 0)) return;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    AT *bufA = reinterpret_cast<AT *>(smraw);
+    AT *bufB = bufA + NT * R;
+    double *sscale = reinterpret_cast<double *>(bufB + NT * R);   // used with dscale only
+    const int64_t o = ov_ptr[i];
+    const int ni = int(ov_ptr[i + 1] - o);
+    const int64_t eo = ell_off[i];
+    const int npad = int(ell_off[i + 1] - eo);
+    const int tid = threadIdx.x;
+    if (ni == 0) return;   // (the whole workgroup)
+    __builtin_assume(sweeps >= 2);
+    const int last_r = ni - 1;
+    (void)npad;
+    AT rr[R];
+    AT *cur = bufA, *nxt = bufB;
+    {
+        int dof[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) dof[m] = ov_idx[o + min(tid + m * NT, last_r)];
+        AT lv[R][KL];
+        uint32_t cw[R][CL];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int64_t e = eo + tid + m * NT;
+#pragma unroll
+            for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(ld_once(&Lv[s * ell_rows + e]));
+#pragma unroll
+            for (int w = 0; w < CL; ++w) cw[m][w] = ld_once(&Cp[e * CW + w]);
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            double x = r[dof[m]];
+            if (scaled && dscale) {
+                const double sc = dscale[dof[m]];
+                x *= sc;
+                sscale[tid + m * NT] = sc;
+            }
+            rr[m] = AT(x);
+        }
+        // first L sweep from zero: y^1 = r
+#pragma unroll
+        for (int m = 0; m < R; ++m) cur[tid + m * NT] = rr[m];
+        __syncthreads();
+        for (int k = 1; k < sweeps; ++k) {
+            // (the packed columns are unpacked anew every sweep: an empty
+            // asm statement marks them as changed, so that the compiler
+            // does not keep all LDS addresses live across the sweeps)
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+#pragma unroll
+                for (int w = 0; w < CL; ++w) asm volatile("" : "+v"(cw[m][w]));
+#pragma unroll
+            for (int m0 = 0; m0 < R; m0 += SG) {
+                AT v[SG][KL];
+#pragma unroll
+                for (int g = 0; g < SG; ++g)
+#pragma unroll
+                    for (int s = 0; s < KL; ++s)
+                        if (m0 + g < R) v[g][s] = cur[(cw[m0 + g][s >> 1] >> (16 * (s & 1))) & 0xffffu];
+#pragma unroll
+                for (int g = 0; g < SG; ++g)
+                    if (m0 + g < R) {
+                        AT acc = rr[m0 + g];
+#pragma unroll
+                        for (int s = 0; s < KL; ++s) acc -= lv[m0 + g][s] * v[g][s];
+                        nxt[tid + (m0 + g) * NT] = acc;
+                    }
+            }
+            __syncthreads();
+            AT *t = cur; cur = nxt; nxt = t;
+        }
+    }
+    // c = D^{-1} y^K (kept in rr; the pivots loaded only now, to keep the
+    // registers for the L entries), first U sweep from zero: w^1 = c
+    {
+        AT dv[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) dv[m] = to_acc(ld_once(&dinv[eo + min(tid + m * NT, last_r)]));
+#pragma unroll
+        for (int m = 0; m < R; ++m) rr[m] = dv[m] * cur[tid + m * NT];
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) nxt[tid + m * NT] = rr[m];
+    {
+        // (the row index passes through an empty asm statement after the L
+        // sweeps, so that the U loads cannot be hoisted above them and hold
+        // registers during the L phase)
+        int tu = tid;
+        asm volatile("" : "+v"(tu));
+        AT uv[R][KU];
+        uint32_t cu[R][CU];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int64_t e = eo + tu + m * NT;
+#pragma unroll
+            for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(ld_once(&Uv[s * ell_rows + e]));
+#pragma unroll
+            for (int w = 0; w < CU; ++w) cu[m][w] = ld_once(&Cp[e * CW + CL + w]);
+        }
+        __syncthreads();
+        { AT *t = cur; cur = nxt; nxt = t; }
+        for (int k = 1; k < sweeps; ++k) {
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+#pragma unroll
+                for (int w = 0; w < CU; ++w) asm volatile("" : "+v"(cu[m][w]));
+#pragma unroll
+            for (int m0 = 0; m0 < R; m0 += SG) {
+                AT v[SG][KU];
+#pragma unroll
+                for (int g = 0; g < SG; ++g)
+#pragma unroll
+                    for (int s = 0; s < KU; ++s)
+                        if (m0 + g < R) v[g][s] = cur[(cu[m0 + g][s >> 1] >> (16 * (s & 1))) & 0xffffu];
+#pragma unroll
+                for (int g = 0; g < SG; ++g)
+                    if (m0 + g < R) {
+                        AT acc = rr[m0 + g];
+#pragma unroll
+                        for (int s = 0; s < KU; ++s) acc -= uv[m0 + g][s] * v[g][s];
+                        nxt[tid + (m0 + g) * NT] = acc;
+                    }
+            }
+            __syncthreads();
+            AT *t = cur; cur = nxt; nxt = t;
+        }
+    }
+    double out[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        out[m] = double(cur[tid + m * NT]);
+        if (scaled && dscale) out[m] *= sscale[tid + m * NT];
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+        if (tid + m * NT < ni) zloc[o + tid + m * NT] = out[m];
+}
+
 // ---------------------------------------------------------------------------
 // Exact local solve A_i^{-1} r_i with the banded Cholesky factor, one
 // workgroup per subdomain, vector in LDS, gather and scatter fused.

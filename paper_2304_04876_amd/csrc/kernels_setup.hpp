@@ -144,6 +144,12 @@ __global__ void k_ilu0_factor(const int64_t *__restrict__ ov_ptr, const int64_t 
 // Slots of the register-resident ILU(0) sweeps: three L and three U entries
 // per row; their local columns packed two per 32-bit word.
 constexpr int ILU_KL = 3, ILU_KU = 3, ILU_CW = (ILU_KL + ILU_KU + 1) / 2;
+// slot counts of the register-resident sweeps with phased L and U loads
+// (ILU(k) with fill)
+constexpr int ILU_KL2 = 6, ILU_KU2 = 6, ILU_CW2 = (ILU_KL2 + ILU_KU2 + 1) / 2;
+// zeroed factor rows past the last subdomain's (the phased sweeps read up
+// to workgroup size x rows per thread rows from a subdomain's first)
+constexpr int64_t ILU_PAD_ROWS = 8192;
 
 template <typename VT>
 __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__restrict__ ell_off,
@@ -188,16 +194,18 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
         Uc[su * ell_rows + R] = 0;
     }
     // Cp != nullptr: the row's L then U columns again, two per 32-bit word
-    // (low half first), ILU_CW words per row, for the register-resident sweeps
+    // (low half first), (KL + KU + 1) / 2 words per row, for the
+    // register-resident sweeps
     if (Cp) {
-        for (int w = 0; w < ILU_CW; ++w) {
+        const int cw = (KL + KU + 1) / 2;
+        for (int w = 0; w < cw; ++w) {
             uint32_t v = 0;
             for (int h = 0; h < 2; ++h) {
                 const int k = 2 * w + h;
                 const uint32_t c = k < KL ? Lc[k * ell_rows + R] : (k < KL + KU ? Uc[(k - KL) * ell_rows + R] : 0u);
                 v |= c << (16 * h);
             }
-            Cp[R * ILU_CW + w] = v;
+            Cp[R * cw + w] = v;
         }
     }
 }

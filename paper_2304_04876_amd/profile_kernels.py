@@ -29,6 +29,8 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--P", type=int, default=8)
     ap.add_argument("--elasticity", action="store_true")
+    ap.add_argument("--ilu-level", type=int, default=0)
+    ap.add_argument("--factor-sweeps", type=int, default=0)
     ap.add_argument("--exact-order", choices=["natural", "nd", "auto"], default="natural",
                     help="exact local solves: band (natural order), supernodal after nested dissection, "
                          "or per subdomain the one with fewer factor values")
@@ -53,7 +55,8 @@ def main():
           flush=True)
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z,
                local=B.LOCAL_ILU0 if a.local == "ilu0" else B.LOCAL_EXACT, local_prec=precs[a.prec],
-               basis_prec=B.FP64 if a.prec == "fp64" else B.FP32,
+               basis_prec=B.FP64 if a.prec == "fp64" else B.FP32, ilu_level=a.ilu_level,
+               ilu_factor_sweeps=a.factor_sweeps,
                exact_order={"natural": B.ORDER_NATURAL, "nd": B.ORDER_ND, "auto": B.ORDER_AUTO}[a.exact_order])
     torch.cuda.synchronize()
     if a.setup_only:
