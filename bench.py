@@ -49,6 +49,8 @@ MEASURED_TRAFFIC = {
     ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14214515281, "src": "ac54f5871e9111d8"},
     ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1606847147, "src": "ac54f5871e9111d8"},
     ("k_nd_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 6140767346, "src": "46cb08cab31501fd"},
+    # ILU(1) factors from 3 FastILU sweeps (the traffic does not depend on how the factors were computed)
+    ("k_ilu_jacobi_phased", "poisson128^3_P8^3", "fp64"): {"bytes": 449873130, "src": "4e1cfa6c27b7f1c8"},
 }
 
 
@@ -302,7 +304,7 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                    + nloc * 12 + n * 20)
     traffic = None
     meas = None
-    if ilu_level == 0 and factor_sweeps == 0:
+    if (ilu_level == 0 and factor_sweeps == 0) or (kname == "k_ilu_jacobi_phased" and ilu_level == 1):
         meas = MEASURED_TRAFFIC.get((kname, f"poisson{N}^3_P{Pn}^3" if not elastic else f"elasticity{N}^3", prec))
     if meas and kernel_source_hash(kname) == meas["src"]:
         traffic = int(meas["bytes"])
@@ -464,6 +466,8 @@ def main():
         line["mixed_precision_fp16"]["vs_fp64_solves_per_s"] = round(fp16["value"] / d["value"], 3)
         # exact local solves: the supernodal factor after nested dissection
         # (the faster form on these 16^3 boxes) and the band beside it
+        line["iluk_fastilu"] = sub(single("poisson", args.N, args.P, "ilu0", "fp64", None, "single_reduce", 1, 3,
+                                          steps=3, warmup=1, kernel_reps=10))
         line["exact_local"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
                                          kernel_reps=10, order="nd"))
         line["exact_local_band"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,

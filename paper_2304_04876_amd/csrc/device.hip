@@ -505,7 +505,8 @@ static void pack_ilu(gdsw_handle_s *h, const int64_t *d_lrowptr, const int32_t *
     for (int i = 0; i < S.np; ++i) maxpad = std::max(maxpad, S.ell_off[i + 1] - S.ell_off[i]);
     dim3 grid(nblocks(maxpad, 256), S.np);
     hipLaunchKernelGGL(k_ilu_pack<VT>, grid, dim3(256), 0, s, D.ov_ptr, D.ell_off, d_lrowptr, d_lcol, d_ldiag,
-                       d_lval, S.ell_rows, KL, KU, (VT *)D.Lv, D.Lc, (VT *)D.Uv, D.Uc, (VT *)D.dinv, D.Cp);
+                       d_lval, S.ell_rows, KL, KU, (VT *)D.Lv, D.Lc, (VT *)D.Uv, D.Uc, (VT *)D.dinv, D.Cp,
+                       mid ? S.ell_rows + ILU_PAD_ROWS : int64_t(0));
     HIPCHK(hipGetLastError());
     D.local_entries = int64_t(KL + KU + 1) * S.ell_rows;
 }
@@ -1215,7 +1216,8 @@ static bool launch_ilu_phased(const Symbolic &S, Device &D, const double *r, con
         if (lds > D.max_lds) return false;                                                                   \
         hipLaunchKernelGGL((k_ilu_jacobi_phased<NT, RR, ILU_KL2, ILU_KU2, VT>), dim3(nb), dim3(NT), lds, s,  \
                            r, D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, (const VT *)D.Lv, (const VT *)D.Uv,  \
-                           D.Cp, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps, D.zloc, kc);              \
+                           D.Cp, S.ell_rows + ILU_PAD_ROWS, (const VT *)D.dinv, D.dscale, S.opt.jacobi_sweeps,  \
+                           D.zloc, kc);                                                                       \
         return true;                                                                                         \
     }
     GDSW_ILU_CASE(2)

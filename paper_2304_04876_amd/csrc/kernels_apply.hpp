@@ -271,14 +271,22 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
 // held in registers for the L sweeps, then the same registers take the U
 // entries and columns, loaded after the L sweeps, for the U sweeps.  Each
 // factor entry is still read once per apply.  One right-hand-side slot;
-// the same LDS layout, rows per thread and order of operations as
-// k_ilu_jacobi.  Columns: CW words per row, the KL (even) L columns in the
-// first KL/2 words, the U columns after them.
+// the same rows per thread and order of operations as k_ilu_jacobi, so
+// the same results as the streaming sweeps bit for bit.  Columns: CW words
+// per row, the KL (even) L columns in the first KL/2 words, the U columns
+// after them, word w of row e at Cp[w * cps + e] (each phase reads only its
+// own words).  The factor rows of a thread are read at fixed strides from
+// one base, without clamping: rows past a subdomain's padded rows are the
+// next subdomain's, and the arrays carry ILU_PAD_ROWS zeroed rows past the
+// last one, so every read is in bounds and every column points inside the
+// LDS vectors; those rows' results are never read or stored.  LDS: the two
+// iterates (and the scales of reduced-precision factors); the pivots are
+// read from memory when the U phase starts.
 template <int NT, int R, int KL, int KU, typename VT>
 __global__ __launch_bounds__(NT) void k_ilu_jacobi_phased(
     const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
     const int64_t *__restrict__ ell_off, int64_t ell_rows, const VT *__restrict__ Lv,
-    const VT *__restrict__ Uv, const uint32_t *__restrict__ Cp, const VT *__restrict__ dinv,
+    const VT *__restrict__ Uv, const uint32_t *__restrict__ Cp, int64_t cps, const VT *__restrict__ dinv,
     const double *__restrict__ dscale, int sweeps, double *__restrict__ zloc, Skip sk) {
     using AT = typename AccOf<VT>::type;
     static_assert(KL % 2 == 0, "the L columns end on a word boundary");
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_phased(
 #pragma unroll
             for (int s = 0; s < KL; ++s) lv[m][s] = to_acc(ld_once(&Lv[s * ell_rows + e]));
 #pragma unroll
-            for (int w = 0; w < CL; ++w) cw[m][w] = ld_once(&Cp[e * CW + w]);
+            for (int w = 0; w < CL; ++w) cw[m][w] = ld_once(&Cp[w * cps + e]);
         }
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_phased(
 #pragma unroll
             for (int s = 0; s < KU; ++s) uv[m][s] = to_acc(ld_once(&Uv[s * ell_rows + e]));
 #pragma unroll
-            for (int w = 0; w < CU; ++w) cu[m][w] = ld_once(&Cp[e * CW + CL + w]);
+            for (int w = 0; w < CU; ++w) cu[m][w] = ld_once(&Cp[(CL + w) * cps + e]);
         }
         __syncthreads();
         { AT *t = cur; cur = nxt; nxt = t; }

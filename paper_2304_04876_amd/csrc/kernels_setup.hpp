@@ -157,7 +157,7 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
                            const int32_t *__restrict__ ldiag, const double *__restrict__ lval,
                            int64_t ell_rows, int KL, int KU, VT *__restrict__ Lv,
                            uint16_t *__restrict__ Lc, VT *__restrict__ Uv, uint16_t *__restrict__ Uc,
-                           VT *__restrict__ dinv, uint32_t *__restrict__ Cp) {
+                           VT *__restrict__ dinv, uint32_t *__restrict__ Cp, int64_t cp_stride) {
     const int i = blockIdx.y;
     const int64_t o = ov_ptr[i], ni = ov_ptr[i + 1] - o;
     const int64_t npad = ell_off[i + 1] - ell_off[i];
@@ -195,7 +195,9 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
     }
     // Cp != nullptr: the row's L then U columns again, two per 32-bit word
     // (low half first), (KL + KU + 1) / 2 words per row, for the
-    // register-resident sweeps
+    // register-resident sweeps: the words of a row together (cp_stride 0),
+    // or word w of every row at w * cp_stride (each phase of the phased
+    // sweeps then reads only its own words)
     if (Cp) {
         const int cw = (KL + KU + 1) / 2;
         for (int w = 0; w < cw; ++w) {
@@ -205,7 +207,7 @@ __global__ void k_ilu_pack(const int64_t *__restrict__ ov_ptr, const int64_t *__
                 const uint32_t c = k < KL ? Lc[k * ell_rows + R] : (k < KL + KU ? Uc[(k - KL) * ell_rows + R] : 0u);
                 v |= c << (16 * h);
             }
-            Cp[R * cw + w] = v;
+            Cp[cp_stride ? w * cp_stride + R : R * cw + w] = v;
         }
     }
 }
