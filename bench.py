@@ -411,6 +411,9 @@ def main():
     ap.add_argument("--workload", choices=["all", "poisson", "elasticity", "batch", "serve"], default="all",
                     help="all (default): the headline line with the other workloads as sub-records")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-exact-order", choices=["natural", "nd", "auto"], default="nd",
+                    help="batch workload: ordering of the exact local factors (the supernodal factor after "
+                         "nested dissection by default, the experiments' choice for exact solvers)")
     ap.add_argument("--batch-seq-stride", type=int, default=1,
                     help="batch workload: time the sequential FP64 reference on every k-th problem")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -512,7 +515,7 @@ def bench_batch(args, sequential_stride=1):
                               options=B.gdsw_default_options(local=B.LOCAL_EXACT, local_prec=B.FP32,
                                                              basis_prec=B.FP32,
                                                              flags=B.FLAG_GRAPHS if args.graphs else 0,
-                                                             exact_order=ORDERS[args.exact_order]))
+                                                             exact_order=ORDERS[args.batch_exact_order]))
     t_an = time.perf_counter() - t0
     B.gdsw_factor(hb)
     tune = B.gdsw_autotune(hb, reps=3)
@@ -549,7 +552,7 @@ def bench_batch(args, sequential_stride=1):
     seq, seq_res, nseq = 0.0, 0.0, 0
     for k in range(0, len(probs), sequential_stride):
         p = probs[k]
-        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_EXACT, exact_order=ORDERS[args.exact_order])
+        g = B.Gdsw(p.A, p.part, p.n_parts, 1, local=B.LOCAL_EXACT, exact_order=ORDERS[args.batch_exact_order])
         bk = b[int(offs[k]):int(offs[k + 1])].clone()
         xk = torch.zeros_like(bk)
         g.solve(bk, xk, rtol=1e-8, maxit=2000)
@@ -569,8 +572,9 @@ def bench_batch(args, sequential_stride=1):
         "dtype": "f64+fp32", "data": "synthetic",
         "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact_fp32_gdsw_cg",
                    "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8,
-                   "graphs": bool(args.graphs), "exact_order": args.exact_order,
-                   "nd_subdomains": int(info["nd_subdomains"])},
+                   "graphs": bool(args.graphs), "exact_order": args.batch_exact_order,
+                   "nd_subdomains": int(info["nd_subdomains"]),
+                   "local_classes": int(info["local_classes"])},
         "iterations_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
         "rel_res_true_max": res,
         "sequential_fp64_solves_per_s": round(seq_rate, 2),

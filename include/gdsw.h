@@ -120,9 +120,10 @@ typedef struct {
                                  separators, supernodal Cholesky; Sec. V-B,
                                  sparse direct factorization) for every
                                  subdomain whose solve fits the 160 KiB of
-                                 LDS (at most 7,964 local rows with FP64
-                                 factors, 14,332 otherwise, and 1,024
-                                 supernodes), the band for the others, or
+                                 LDS (at most 10,648 local rows with FP64
+                                 factors, 19,112 otherwise, 2,048 supernodes
+                                 and 2,048 rows of one height above the
+                                 leaves), the band for the others, or
                                  GDSW_ORDER_AUTO (per subdomain whichever of
                                  the two stores fewer factor values, when its
                                  supernodal solve fits LDS; the choice depends
@@ -184,6 +185,9 @@ typedef struct {
     int32_t exact_order;      /* options.exact_order                              */
     int32_t nd_subdomains;    /* subdomains with the supernodal (nested-dissection)
                                  exact factor; the others keep the band       */
+    int32_t local_classes;    /* size classes the local solves run in (1, or
+                                 more when gdsw_autotune found the split by
+                                 size faster)                                 */
     int64_t local_solve_bytes;/* algorithmic bytes of one launch of the local
                                  solves (every stored factor value read once
                                  per pass, the index data once, per local row
@@ -421,8 +425,11 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
  * host, 16 floats) receives the average milliseconds per launch (-1 for
  * configurations that do not fit): [0..7] local variants (ILU(0): 0..3,
  * exact: 0..5), [8..9] GEMV variants, [10..11] apply in one stream / two
- * streams, [12..13] apply with the prolongation per dof / by blocks.
- * Synchronises `stream`. */
+ * streams, [12..13] apply with the prolongation per dof / by blocks,
+ * [14..15] the local solves as one launch in size order / split into size
+ * classes (subdomain sizes within a factor four, at most four classes,
+ * each with its own tuned configuration, launched at once on streams of
+ * their own; -1 when the sizes form one class).  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);
 
 /* Pins the launch configurations gdsw_autotune chooses from, for callers

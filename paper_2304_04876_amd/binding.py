@@ -80,7 +80,8 @@ class Info(ctypes.Structure):
                 ("gemv_variant", ctypes.c_int32), ("apply_streams", ctypes.c_int32),
                 ("prolong_variant", ctypes.c_int32), ("t_refactor", ctypes.c_double),
                 ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_int64), ("exact_order", ctypes.c_int32),
-                ("nd_subdomains", ctypes.c_int32), ("local_solve_bytes", ctypes.c_int64)]
+                ("nd_subdomains", ctypes.c_int32), ("local_classes", ctypes.c_int32),
+                ("local_solve_bytes", ctypes.c_int64)]
 
 
 def lib():

@@ -206,6 +206,7 @@ gdsw_status gdsw_get_info(gdsw_handle h, gdsw_info *info) {
     info->slots = std::max(1, S.opt.slots);
     info->slot_bytes = gdsw::slot_bytes(h);
     info->exact_order = S.opt.exact_order;
+    info->local_classes = h->dev ? gdsw::tuned_variant(h, 4) : 1;
     info->nd_subdomains = 0;
     for (uint8_t m : S.nd_mask) info->nd_subdomains += m;
     {

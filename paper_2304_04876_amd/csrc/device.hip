@@ -185,6 +185,11 @@ struct Device {
         for (auto &g : cg_graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap) (void)hipStreamDestroy(cap);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_cfork) (void)hipEventDestroy(ev_cfork);
+        for (int k = 0; k < MAX_CLASSES - 1; ++k) {
+            if (ev_cjoin[k]) (void)hipEventDestroy(ev_cjoin[k]);
+            if (cstream[k]) (void)hipStreamDestroy(cstream[k]);
+        }
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
         for (void *p : allocs) (void)hipFree(p);
@@ -296,9 +301,15 @@ struct Device {
     // is launched with LDS and rows per thread for its own largest
     // subdomain, in the launch configuration tuned for it (-1: the handle's)
     struct SizeClass {
-        int begin, end, max_ni, variant;
+        int begin, end, max_ni, variant, idx;
     };
-    std::vector<SizeClass> cls;
+    std::vector<SizeClass> cls;                 // the classes in use
+    std::vector<SizeClass> cls_one, cls_split;  // one class; split by size (autotuned choice)
+    // classes after the first run on their own streams beside it (fork and
+    // join by events), created with the default priority
+    static constexpr int MAX_CLASSES = 4;
+    hipStream_t cstream[MAX_CLASSES - 1] = {};
+    hipEvent_t ev_cfork = nullptr, ev_cjoin[MAX_CLASSES - 1] = {};
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
     int gemv_variant = -1;        // coarse GEMV: 0 wavefront per row, 1 workgroup per row
 };
@@ -448,12 +459,37 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         bool uniform = true;
         for (int i = 1; i < S.np && uniform; ++i) uniform = sz(i) == sz(0);
         if (!uniform) D.sub_order = D.upload(ord, s);
-        // one class: separate launches per size class run one after another
-        // on the stream, each with its own tail of idle compute units, and
-        // were slower than one launch in size order (256-problem diffusion
-        // batch: 688 against 827 solves/s)
-        D.cls.clear();
-        D.cls.push_back({0, S.np, int(S.max_ni), -1});
+        // size classes: consecutive ranges of that order whose sizes lie
+        // within a factor four of the class's largest (at most
+        // MAX_CLASSES, the last takes the rest), each launched with LDS and
+        // rows per thread for its own largest subdomain and, from the
+        // second on, on a stream of its own beside the first, so that the
+        // small subdomains run many workgroups per compute unit next to the
+        // large ones.  Whether this beats one launch in size order depends
+        // on the local solver (256-problem diffusion batch: supernodal
+        // solves 888 -> 967 solves/s, band solves 877 -> 830), so the
+        // autotuner times both.  (Launched one after another on one stream,
+        // classes were slower still: 688 against 827 for the band.)
+        D.cls_split.clear();
+        int b = 0;
+        while (b < S.np) {
+            const int64_t top = std::max<int64_t>(sz(ord[b]), 1);
+            int e = b + 1;
+            if (int(D.cls_split.size()) == Device::MAX_CLASSES - 1) e = S.np;
+            else
+                while (e < S.np && 4 * sz(ord[e]) > top) ++e;
+            D.cls_split.push_back({b, e, int(top), -1, int(D.cls_split.size())});
+            b = e;
+        }
+        D.cls_one.assign(1, {0, S.np, int(std::max<int64_t>(S.max_ni, 1)), -1, 0});
+        for (size_t k = 1; k < D.cls_split.size(); ++k) {
+            if (!D.cstream[k - 1]) HIPCHK(hipStreamCreateWithFlags(&D.cstream[k - 1], hipStreamNonBlocking));
+            if (!D.ev_cjoin[k - 1]) HIPCHK(hipEventCreateWithFlags(&D.ev_cjoin[k - 1], hipEventDisableTiming));
+        }
+        if (D.cls_split.size() > 1 && !D.ev_cfork)
+            HIPCHK(hipEventCreateWithFlags(&D.ev_cfork, hipEventDisableTiming));
+        // one class until the autotuner finds the split faster
+        D.cls = D.cls_one;
         HIPCHK(hipStreamSynchronize(s));
     }
     {
@@ -1308,7 +1344,9 @@ static bool launch_band(const Symbolic &S, Device &D, const double *r, const Ski
         for (int kind = 0; kind < 2; ++kind) {
             const bool inv = kind == 0;
             if (!(D.band_kinds & (inv ? 2 : 1))) continue;
-            int *q = D.queue + (inv ? 0 : QUEUE_HALF);
+            // (one counter per slot and size class: the classes may run at once)
+            if ((c.idx + 1) * D.ns > QUEUE_HALF) return false;
+            int *q = D.queue + (inv ? 0 : QUEUE_HALF) + c.idx * D.ns;
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, q, 0, D.ns);
             if (inv)
                 hipLaunchKernelGGL((k_band_apply_pers<NT, VT, true>), dim3(g, D.ns), dim3(NT), lds, s, r, D.ov_idx,
@@ -1414,7 +1452,19 @@ static void launch_local_class(const Symbolic &S, Device &D, const double *r, co
 
 template <typename VT>
 static void launch_local(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s) {
-    for (const Device::SizeClass &c : D.cls) launch_local_class<VT>(S, D, r, sk, s, c);
+    if (D.cls.size() == 1) {
+        launch_local_class<VT>(S, D, r, sk, s, D.cls[0]);
+        return;
+    }
+    // the first (largest) class on `s`, the others beside it, joined back
+    HIPCHK(hipEventRecord(D.ev_cfork, s));
+    for (size_t k = 1; k < D.cls.size(); ++k) {
+        HIPCHK(hipStreamWaitEvent(D.cstream[k - 1], D.ev_cfork, 0));
+        launch_local_class<VT>(S, D, r, sk, D.cstream[k - 1], D.cls[k]);
+        HIPCHK(hipEventRecord(D.ev_cjoin[k - 1], D.cstream[k - 1]));
+    }
+    launch_local_class<VT>(S, D, r, sk, s, D.cls[0]);
+    for (size_t k = 1; k < D.cls.size(); ++k) HIPCHK(hipStreamWaitEvent(s, D.ev_cjoin[k - 1], 0));
 }
 
 // One launch configuration for every size class (false: it does not fit
@@ -2288,11 +2338,37 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
         HIPCHK(hipEventCreate(&e1));
         hipLaunchKernelGGL(k_fill, dim3(nblocks(D.nv, 256, 65536)), dim3(256), 0, s, D.kr, 1.0, D.nv);
         // every size class of the local solves on its own: the fastest
-        // configuration per class (times[v]: the sum over the classes, -1
-        // where v does not fit a class)
+        // configuration per class (times[v]: the sum over the classes of one
+        // launch, -1 where v does not fit a class); then the whole local
+        // solve with the classes split by size (at once, on their streams)
+        // against one class, the faster kept
         const int nv = S.opt.local == GDSW_LOCAL_ILU0 ? N_ILU_VARIANTS : N_BAND_VARIANTS;
         if (times)
             for (int v = 0; v < nv; ++v) times[v] = 0.0f;
+        const bool split = D.cls_split.size() > 1;
+        if (split) {
+            D.cls = D.cls_split;
+            for (Device::SizeClass &c : D.cls) {
+                float best = -1.0f;
+                int bv = -1;
+                for (int v = 0; v < nv; ++v) {
+                    float t;
+                    switch (S.opt.local_prec) {
+                        case GDSW_FP64: t = time_local<double>(h, v, c, reps, s, e0, e1); break;
+                        case GDSW_FP32: t = time_local<float>(h, v, c, reps, s, e0, e1); break;
+                        case GDSW_BF16: t = time_local<bf16>(h, v, c, reps, s, e0, e1); break;
+                        default: t = time_local<fp16>(h, v, c, reps, s, e0, e1); break;
+                    }
+                    if (t > 0.0f && (best < 0.0f || t < best)) {
+                        best = t;
+                        bv = v;
+                    }
+                }
+                c.variant = bv;
+            }
+            D.cls_split = D.cls;
+            D.cls = D.cls_one;
+        }
         for (size_t ci = 0; ci < D.cls.size(); ++ci) {
             Device::SizeClass &c = D.cls[ci];
             float best = -1.0f;
@@ -2312,6 +2388,33 @@ gdsw_status autotune(gdsw_handle_s *h, int reps, float *times, void *stream) {
                 }
             }
             c.variant = bv;
+        }
+        D.cls_one = D.cls;
+        if (split) {
+            float tl[2];
+            for (int k = 0; k < 2; ++k) {
+                D.cls = k == 0 ? D.cls_one : D.cls_split;
+                Skip none;
+                none.sl = D.slots;
+                switch (S.opt.local_prec) {
+                    case GDSW_FP64: launch_local<double>(S, D, D.kr, none, s); break;
+                    case GDSW_FP32: launch_local<float>(S, D, D.kr, none, s); break;
+                    case GDSW_BF16: launch_local<bf16>(S, D, D.kr, none, s); break;
+                    default: launch_local<fp16>(S, D, D.kr, none, s); break;
+                }
+                HIPCHK(hipEventRecord(e0, s));
+                for (int q = 0; q < reps; ++q) switch (S.opt.local_prec) {
+                        case GDSW_FP64: launch_local<double>(S, D, D.kr, none, s); break;
+                        case GDSW_FP32: launch_local<float>(S, D, D.kr, none, s); break;
+                        case GDSW_BF16: launch_local<bf16>(S, D, D.kr, none, s); break;
+                        default: launch_local<fp16>(S, D, D.kr, none, s); break;
+                    }
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&tl[k], e0, e1));
+            }
+            D.cls = tl[1] < tl[0] ? D.cls_split : D.cls_one;
+            if (times) times[14] = tl[0] / reps, times[15] = tl[1] / reps;
         }
         // reported: the configuration of the largest subdomains
         D.local_variant = D.cls.empty() ? -1 : D.cls[0].variant;
@@ -2474,7 +2577,8 @@ int tuned_variant(const gdsw_handle_s *h, int which) {
     return which == 0 ? h->dev->local_variant
          : which == 1 ? h->dev->gemv_variant
          : which == 2 ? h->dev->apply_streams
-                      : h->dev->prolong_split;
+         : which == 3 ? h->dev->prolong_split
+                      : int(h->dev->cls.size());
 }
 
 void destroy_device(gdsw_handle_s *h) {

@@ -40,10 +40,13 @@ struct PhiBlocks {
 // results of one height (trows; the leaves need none), each rounded up to
 // 4, the supernode table (16 B each), the struct offsets (nsn + 1 ints) and
 // each row's supernode (16-bit).  A subdomain takes the supernodal factor
-// only if it has at most ND_MAX_SUPERNODES supernodes and
-// nd_lds_bytes(rows, rows, ND_MAX_SUPERNODES, acc) fits a compute unit's
-// 160 KiB, so that any set of such subdomains fits one launch.
-constexpr int ND_MAX_SUPERNODES = 1024;
+// only if it has at most ND_MAX_SUPERNODES supernodes, at most ND_MAX_TROWS
+// rows of one height above the leaves and nd_lds_bytes(rows, ND_MAX_TROWS,
+// ND_MAX_SUPERNODES, acc) fits a compute unit's 160 KiB, so that any set of
+// such subdomains fits one launch (FP64 accumulators: up to 10,648 rows;
+// FP32: up to 19,112).
+constexpr int ND_MAX_SUPERNODES = 2048;
+constexpr int ND_MAX_TROWS = 2048;
 constexpr int ND_LEAF = 64;           // leaf parts of the dissection: at most this many rows
 inline size_t nd_lds_bytes(int rows, int trows, int nsn, size_t acc) {
     const size_t r4 = (size_t(rows) + 3) / 4 * 4, t4 = (size_t(trows) + 3) / 4 * 4;

@@ -249,8 +249,8 @@ void build_nd(Symbolic &s) {
     // Which subdomains take the supernodal factor: those whose solve fits a
     // gfx950 compute unit's 160 KiB of LDS (nd_lds_bytes with 8-byte
     // accumulators for FP64 factors, 4 otherwise; at most
-    // ND_MAX_SUPERNODES supernodes; panel values of one subdomain below
-    // 2^31) and whose leaves hold at most ND_LEAF rows (a part the level
+    // ND_MAX_SUPERNODES supernodes and ND_MAX_TROWS rows of one height above
+    // the leaves; panel values of one subdomain below 2^31) and whose leaves hold at most ND_LEAF rows (a part the level
     // search cannot split stays whole), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose
     // panels hold fewer values than their band (both read twice per apply);
     // the others keep the band.  The choice depends on the subdomain alone,
@@ -262,8 +262,18 @@ void build_nd(Symbolic &s) {
         const int64_t ni = s.ov_ptr[i + 1] - s.ov_ptr[i];
         const SubND &u = sub[i];
         if (ni == 0 || int(u.first.size()) > ND_MAX_SUPERNODES ||
-            nd_lds_bytes(int(ni), int(ni), ND_MAX_SUPERNODES, acc) > size_t(160) * 1024)
+            nd_lds_bytes(int(ni), ND_MAX_TROWS, ND_MAX_SUPERNODES, acc) > size_t(160) * 1024)
             continue;
+        {   // rows of one height above the leaves
+            std::vector<int64_t> rows_at;
+            for (size_t J = 0; J < u.first.size(); ++J) {
+                if (size_t(u.height[J]) >= rows_at.size()) rows_at.resize(u.height[J] + 1, 0);
+                rows_at[u.height[J]] += u.ncol[J];
+            }
+            bool ok = true;
+            for (size_t hh = 1; hh < rows_at.size(); ++hh) ok &= rows_at[hh] <= ND_MAX_TROWS;
+            if (!ok) continue;
+        }
         int64_t vals = 0;
         bool small_leaves = true;
         for (size_t J = 0; J < u.first.size(); ++J) {

@@ -186,3 +186,37 @@ def test_batch_workload_samples_match_oracle():
                 assert abs(it - oit) <= 3
                 assert xerr <= 1e-6, (ks[j], xerr)
         B.gdsw_destroy(hb)
+
+
+@pytest.mark.parametrize("order", [B.ORDER_NATURAL, B.ORDER_ND])
+def test_autotuned_size_classes_keep_results(order):
+    """Problems whose subdomains differ in size by more than a factor four
+    form several size classes; the autotuner may run them as separate
+    launches at once on their own streams.  Every subdomain's solve is the
+    same computation either way, so the apply equals, bit for bit, that of
+    an untuned handle pinned to the same coarse GEMV, prolongation and
+    stream choices (the only choices that change the order of sums)."""
+    rng = np.random.default_rng(8)
+    probs = [P.diffusion3d(20, np.exp(rng.standard_normal(21 ** 3)), 2), P.poisson3d(6, 2), P.poisson3d(12, 3)]
+    say(f"[batch] size classes order={order}")
+    opts = B.gdsw_default_options(local=B.LOCAL_EXACT, local_prec=B.FP32, basis_prec=B.FP32, exact_order=order)
+    ha = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs], options=opts)
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs], options=opts)
+    B.gdsw_factor(ha)
+    B.gdsw_factor(hb)
+    times = B.gdsw_autotune(ha, reps=2)
+    assert times[14] > 0 and times[15] > 0     # both forms were timed: the sizes span several classes
+    ia = B.gdsw_get_info(ha)
+    assert ia["local_classes"] >= 1
+    B.gdsw_set_launch(hb, -1, ia["gemv_variant"], ia["apply_streams"], ia["prolong_variant"])
+    assert B.gdsw_get_info(hb)["local_classes"] == 1
+    r = torch.from_numpy(np.concatenate([P.rhs_uniform(p.n, 30 + k) for k, p in enumerate(probs)])).cuda()
+    za, zb = torch.zeros_like(r), torch.zeros_like(r)
+    B.gdsw_apply(ha, r, za)
+    B.gdsw_apply(hb, r, zb)
+    assert torch.equal(za, zb), ia["local_classes"]
+    x = torch.zeros_like(r)
+    infos = B.gdsw_solve_batch(ha, r, x, rtol=1e-8)
+    assert all(i["converged"] for i in infos)
+    B.gdsw_destroy(ha)
+    B.gdsw_destroy(hb)

@@ -49,7 +49,7 @@ CASES = {
     "poisson10_P231": lambda: (P.poisson3d(10, (2, 3, 1)), None),
     "diffusion20_P3": lambda: (P.diffusion3d(20, np.exp(np.random.default_rng(9).standard_normal(21 ** 3)), 3),
                                None),
-    # 12,100-row subdomains: too large for LDS, they keep the band
+    # 12,100-row subdomains: too large for LDS with FP64 factors, they keep the band
     "diffusion_large_subdomains": lambda: (P.batch_diffusion_problem(P.batch_diffusion_specs(2)[1]), None),
     "elasticity6_P2": lambda: ((lambda p: (p, P.rigid_body_modes(p)))(P.elasticity_q1(6, 2))),
 }
@@ -62,9 +62,10 @@ def test_nd_apply_matches_oracle(case):
     M = O.GDSW(pr.A, pr.part, pr.dpn, pr.n_parts, Z=Z, local="exact")
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, pr.dpn, Z, **ND)
     # every nonempty subdomain whose FP64 solve fits 160 KiB of LDS (at most
-    # 7,964 rows; these subdomains have far fewer than 1,024 supernodes)
+    # 10,648 rows; these subdomains have far fewer than 2,048 supernodes and
+    # 2,048 rows of one height above the leaves)
     ni = np.diff(B.gdsw_copy_map(g.h, B.MAP_OV_PTR))
-    fits = int(((ni > 0) & (ni <= 7964)).sum())
+    fits = int(((ni > 0) & (ni <= 10648)).sum())
     assert g.info()["nd_subdomains"] == fits
     assert fits > 0 or case == "diffusion_large_subdomains"
     r = P.rhs_uniform(pr.n, 11)
