@@ -570,7 +570,9 @@ def bench_batch(args, sequential_stride=1):
         "value": round(len(probs) / wall, 2), "unit": "solves/s", "n_gpus": 1, "steps": reps, "warmup": 1,
         "ms_per_step": round(1e3 * wall, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+fp32", "data": "synthetic",
-        "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact_fp32_gdsw_cg",
+        "config": {"workload": f"batch{len(probs)}_diffusion_N16-48_P2-4_exact"
+                               f"{'' if args.batch_exact_order == 'natural' else '_' + args.batch_exact_order}"
+                               "_fp32_gdsw_cg",
                    "n": int(info["n"]), "n_parts": int(info["n_parts"]), "rtol": 1e-8,
                    "graphs": bool(args.graphs), "exact_order": args.batch_exact_order,
                    "nd_subdomains": int(info["nd_subdomains"]),

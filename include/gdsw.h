@@ -427,7 +427,7 @@ gdsw_status gdsw_slot_finish(gdsw_handle h, int32_t slot, gdsw_solve_info *info,
  * exact: 0..5), [8..9] GEMV variants, [10..11] apply in one stream / two
  * streams, [12..13] apply with the prolongation per dof / by blocks,
  * [14..15] the local solves as one launch in size order / split into size
- * classes (subdomain sizes within a factor four, at most four classes,
+ * classes (subdomain sizes within a factor two, at most six classes,
  * each with its own tuned configuration, launched at once on streams of
  * their own; -1 when the sizes form one class).  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *stream);

@@ -307,7 +307,7 @@ struct Device {
     std::vector<SizeClass> cls_one, cls_split;  // one class; split by size (autotuned choice)
     // classes after the first run on their own streams beside it (fork and
     // join by events), created with the default priority
-    static constexpr int MAX_CLASSES = 4;
+    static constexpr int MAX_CLASSES = 6;
     hipStream_t cstream[MAX_CLASSES - 1] = {};
     hipEvent_t ev_cfork = nullptr, ev_cjoin[MAX_CLASSES - 1] = {};
     int local_variant = -1;       // launch configuration of the local solves (-1: fixed rule)
@@ -460,16 +460,17 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         for (int i = 1; i < S.np && uniform; ++i) uniform = sz(i) == sz(0);
         if (!uniform) D.sub_order = D.upload(ord, s);
         // size classes: consecutive ranges of that order whose sizes lie
-        // within a factor four of the class's largest (at most
-        // MAX_CLASSES, the last takes the rest), each launched with LDS and
-        // rows per thread for its own largest subdomain and, from the
-        // second on, on a stream of its own beside the first, so that the
-        // small subdomains run many workgroups per compute unit next to the
-        // large ones.  Whether this beats one launch in size order depends
-        // on the local solver (256-problem diffusion batch: supernodal
-        // solves 888 -> 967 solves/s, band solves 877 -> 830), so the
-        // autotuner times both.  (Launched one after another on one stream,
-        // classes were slower still: 688 against 827 for the band.)
+        // within a factor two of the class's largest (at most MAX_CLASSES,
+        // the last takes the rest), each launched with LDS and rows per
+        // thread for its own largest subdomain and, from the second on, on
+        // a stream of its own beside the first, so that the smaller
+        // subdomains run more workgroups per compute unit next to the large
+        // ones.  Whether this beats one launch in size order depends on the
+        // local solver (256-problem diffusion batch: supernodal solves 888
+        // -> 1,001 solves/s, with classes within a factor four 967; band
+        // solves 877 -> 830), so the autotuner times both.  (Launched one
+        // after another on one stream, classes were slower still: 688
+        // against 827 for the band.)
         D.cls_split.clear();
         int b = 0;
         while (b < S.np) {
@@ -477,7 +478,7 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
             int e = b + 1;
             if (int(D.cls_split.size()) == Device::MAX_CLASSES - 1) e = S.np;
             else
-                while (e < S.np && 4 * sz(ord[e]) > top) ++e;
+                while (e < S.np && 2 * sz(ord[e]) > top) ++e;
             D.cls_split.push_back({b, e, int(top), -1, int(D.cls_split.size())});
             b = e;
         }

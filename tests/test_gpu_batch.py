@@ -190,7 +190,7 @@ def test_batch_workload_samples_match_oracle():
 
 @pytest.mark.parametrize("order", [B.ORDER_NATURAL, B.ORDER_ND])
 def test_autotuned_size_classes_keep_results(order):
-    """Problems whose subdomains differ in size by more than a factor four
+    """Problems whose subdomains differ in size by more than a factor two
     form several size classes; the autotuner may run them as separate
     launches at once on their own streams.  Every subdomain's solve is the
     same computation either way, so the apply equals, bit for bit, that of
