@@ -467,7 +467,7 @@ static void upload_all(gdsw_handle_s *h, hipStream_t s) {
         // subdomains run more workgroups per compute unit next to the large
         // ones.  Whether this beats one launch in size order depends on the
         // local solver (256-problem diffusion batch: supernodal solves 888
-        // -> 1,001 solves/s, with classes within a factor four 967; band
+        // -> 1,037 solves/s, with classes within a factor four 967; band
         // solves 877 -> 830), so the autotuner times both.  (Launched one
         // after another on one stream, classes were slower still: 688
         // against 827 for the band.)
@@ -1457,14 +1457,16 @@ static void launch_local(const Symbolic &S, Device &D, const double *r, const Sk
         launch_local_class<VT>(S, D, r, sk, s, D.cls[0]);
         return;
     }
-    // the first (largest) class on `s`, the others beside it, joined back
+    // the first (largest) class on `s`, queued first so that its long
+    // workgroups take the compute units first, the others beside it, joined
+    // back
     HIPCHK(hipEventRecord(D.ev_cfork, s));
+    launch_local_class<VT>(S, D, r, sk, s, D.cls[0]);
     for (size_t k = 1; k < D.cls.size(); ++k) {
         HIPCHK(hipStreamWaitEvent(D.cstream[k - 1], D.ev_cfork, 0));
         launch_local_class<VT>(S, D, r, sk, D.cstream[k - 1], D.cls[k]);
         HIPCHK(hipEventRecord(D.ev_cjoin[k - 1], D.cstream[k - 1]));
     }
-    launch_local_class<VT>(S, D, r, sk, s, D.cls[0]);
     for (size_t k = 1; k < D.cls.size(); ++k) HIPCHK(hipStreamWaitEvent(s, D.ev_cjoin[k - 1], 0));
 }
 
