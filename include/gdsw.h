@@ -452,6 +452,17 @@ gdsw_status gdsw_autotune(gdsw_handle h, int32_t reps, float *times_ms, void *st
 gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_variant,
                             int32_t apply_streams, int32_t prolong_variant, void *stream);
 
+/* Pins the other choice gdsw_autotune makes for the local solves: split = 0
+ * runs them as one launch in size order (the default), split = 1 as one
+ * launch per size class (subdomain sizes within a factor two, at most six
+ * classes, the largest first), all at once on streams of their own, each
+ * class with its tuned configuration (or the handle's).  Each subdomain's
+ * solve is the same computation either way (the results do not change).
+ * A handle whose subdomain sizes form one class ignores split = 1 and
+ * reports one class in gdsw_info.local_classes.  Errors: STATE (not
+ * factored), INVALID_ARG. */
+gdsw_status gdsw_set_size_classes(gdsw_handle h, int32_t split);
+
 /* Timing of the local solves where they run (Sec. VII times the local-solver
  * phase of the apply on its own).  With enable != 0 every later apply of the
  * handle, those inside the solvers included, records a pair of HIP events on

@@ -45,7 +45,7 @@ EXPORTED = ("gdsw_default_options", "gdsw_analyze", "gdsw_analyze_sharing", "gds
             "gdsw_map_size", "gdsw_copy_map", "gdsw_destroy", "gdsw_status_string", "gdsw_last_error",
             "gdsw_analyze_batch", "gdsw_solve_batch", "gdsw_slots_begin", "gdsw_slot_start",
             "gdsw_slots_step", "gdsw_slot_finish", "gdsw_problem_offsets", "gdsw_autotune", "gdsw_set_launch",
-            "gdsw_profile_local", "gdsw_profile_read")
+            "gdsw_set_size_classes", "gdsw_profile_local", "gdsw_profile_read")
 
 
 class Options(ctypes.Structure):
@@ -124,6 +124,7 @@ def lib():
         "gdsw_problem_offsets": (ctypes.c_int, [vp, vp]),
         "gdsw_autotune": (ctypes.c_int, [vp, i32, vp, vp]),
         "gdsw_set_launch": (ctypes.c_int, [vp, i32, i32, i32, i32, vp]),
+        "gdsw_set_size_classes": (ctypes.c_int, [vp, i32]),
         "gdsw_profile_local": (ctypes.c_int, [vp, i32]),
         "gdsw_profile_read": (ctypes.c_int, [vp, vp, i32, vp]),
         "gdsw_last_error": (ctypes.c_char_p, [vp]),
@@ -349,6 +350,10 @@ def gdsw_autotune(h, reps=10, stream=None) -> list:
     times = np.full(16, -1.0, dtype=np.float32)
     _check(h, lib().gdsw_autotune(h, int(reps), times.ctypes.data, _stream(stream)))
     return times.tolist()
+
+
+def gdsw_set_size_classes(h, split):
+    _check(h, lib().gdsw_set_size_classes(h, int(split)))
 
 
 def gdsw_set_launch(h, local_variant=-1, gemv_variant=-1, apply_streams=-1, prolong_variant=-1, stream=None):

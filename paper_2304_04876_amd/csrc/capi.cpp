@@ -104,6 +104,11 @@ gdsw_status gdsw_set_launch(gdsw_handle h, int32_t local_variant, int32_t gemv_v
     return gdsw::set_launch(h, local_variant, gemv_variant, apply_streams, prolong_variant, stream);
 }
 
+gdsw_status gdsw_set_size_classes(gdsw_handle h, int32_t split) {
+    if (!h || split < 0 || split > 1) return GDSW_ERR_INVALID_ARG;
+    return gdsw::set_size_classes(h, split);
+}
+
 gdsw_status gdsw_profile_local(gdsw_handle h, int32_t enable) {
     if (!h) return GDSW_ERR_INVALID_ARG;
     return gdsw::profile_local(h, enable);

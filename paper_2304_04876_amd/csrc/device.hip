@@ -2568,10 +2568,22 @@ gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, in
         }
     }
     D.local_variant = local_variant;
-    for (Device::SizeClass &c : D.cls) c.variant = -1;   // one configuration for every class
+    // one configuration for every class, in both class layouts
+    for (auto *v : {&D.cls, &D.cls_one, &D.cls_split})
+        for (Device::SizeClass &c : *v) c.variant = -1;
     D.gemv_variant = gemv_variant;
     D.apply_streams = apply_streams;
     D.prolong_split = prolong_variant;
+    return GDSW_OK;
+}
+
+gdsw_status set_size_classes(gdsw_handle_s *h, int split) {
+    if (!h->factored || !h->dev) {
+        h->err = "set_size_classes before factor";
+        return GDSW_ERR_STATE;
+    }
+    Device &D = *h->dev;
+    D.cls = split && D.cls_split.size() > 1 ? D.cls_split : D.cls_one;
     return GDSW_OK;
 }
 

@@ -273,6 +273,7 @@ gdsw_status profile_read(gdsw_handle_s *h, float *ms, int max, int *count);
 gdsw_status set_launch(gdsw_handle_s *h, int local_variant, int gemv_variant, int apply_streams, int prolong_variant,
                        void *stream);
 int tuned_variant(const gdsw_handle_s *h, int which);
+gdsw_status set_size_classes(gdsw_handle_s *h, int split);
 void destroy_device(gdsw_handle_s *h);
 int64_t device_bytes(const gdsw_handle_s *h);
 gdsw_status copy_device_map(gdsw_handle_s *h, int map, void *out);

@@ -220,3 +220,40 @@ def test_autotuned_size_classes_keep_results(order):
     assert all(i["converged"] for i in infos)
     B.gdsw_destroy(ha)
     B.gdsw_destroy(hb)
+
+
+def test_size_classes_pinned_and_graph_captured():
+    """The local solves split into size classes (pinned with
+    gdsw_set_size_classes), launched at once on their own streams, inside
+    captured CG graphs: the batch solve equals, bit for bit, the one-launch
+    eager solve (the same computations, only the launches differ)."""
+    rng = np.random.default_rng(8)
+    probs = [P.diffusion3d(20, np.exp(rng.standard_normal(21 ** 3)), 2), P.poisson3d(6, 2), P.poisson3d(12, 3)]
+    say("[batch] size classes pinned, graphs")
+    opts = dict(local=B.LOCAL_EXACT, local_prec=B.FP32, basis_prec=B.FP32, exact_order=B.ORDER_ND)
+    ha = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs],
+                              options=B.gdsw_default_options(flags=B.FLAG_GRAPHS, **opts))
+    hb = B.gdsw_analyze_batch([(p.A, p.part, p.n_parts) for p in probs], options=B.gdsw_default_options(**opts))
+    B.gdsw_factor(ha)
+    B.gdsw_factor(hb)
+    B.gdsw_set_size_classes(ha, 1)
+    assert B.gdsw_get_info(ha)["local_classes"] > 1
+    assert B.gdsw_get_info(hb)["local_classes"] == 1
+    r = torch.from_numpy(np.concatenate([P.rhs_uniform(p.n, 40 + k) for k, p in enumerate(probs)])).cuda()
+    za, zb = torch.zeros_like(r), torch.zeros_like(r)
+    B.gdsw_apply(ha, r, za)
+    B.gdsw_apply(hb, r, zb)
+    assert torch.equal(za, zb)
+    for rep in range(3):
+        xa, xb = torch.zeros_like(r), torch.zeros_like(r)
+        ia = B.gdsw_solve_batch(ha, r, xa, rtol=1e-8)
+        torch.cuda.synchronize()
+        ib = B.gdsw_solve_batch(hb, r, xb, rtol=1e-8)
+        assert [i["iterations"] for i in ia] == [i["iterations"] for i in ib]
+        assert torch.equal(xa, xb), rep
+    B.gdsw_set_size_classes(ha, 0)
+    assert B.gdsw_get_info(ha)["local_classes"] == 1
+    with pytest.raises(B.GdswError):
+        B.gdsw_set_size_classes(ha, 2)
+    B.gdsw_destroy(ha)
+    B.gdsw_destroy(hb)
