@@ -47,7 +47,11 @@ struct PhiBlocks {
 // FP32: up to 19,112).
 constexpr int ND_MAX_SUPERNODES = 2048;
 constexpr int ND_MAX_TROWS = 2048;
-constexpr int ND_LEAF = 64;           // leaf parts of the dissection: at most this many rows
+// leaf parts of the dissection: at most this many rows (at most 64, one
+// wavefront's rows; on the 128^3 workload leaves of 32, 40, 48, 56 and 64
+// rows gave 1.85, 1.32, 1.33, 1.38 and 1.44 ms per launch inside the apply,
+// and 48 the most applies/s and batch solves/s)
+constexpr int ND_LEAF = 48;
 inline size_t nd_lds_bytes(int rows, int trows, int nsn, size_t acc) {
     const size_t r4 = (size_t(rows) + 3) / 4 * 4, t4 = (size_t(trows) + 3) / 4 * 4;
     return acc * (r4 + t4) + 16 * size_t(nsn) + 4 * (size_t(nsn) + 1) + 2 * r4;

@@ -250,11 +250,13 @@ void build_nd(Symbolic &s) {
     // gfx950 compute unit's 160 KiB of LDS (nd_lds_bytes with 8-byte
     // accumulators for FP64 factors, 4 otherwise; at most
     // ND_MAX_SUPERNODES supernodes and ND_MAX_TROWS rows of one height above
-    // the leaves; panel values of one subdomain below 2^31) and whose leaves hold at most ND_LEAF rows (a part the level
-    // search cannot split stays whole), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those whose
-    // panels hold fewer values than their band (both read twice per apply);
-    // the others keep the band.  The choice depends on the subdomain alone,
-    // so a problem's results do not depend on what it is packed with.
+    // the leaves; panel values of one subdomain below 2^31) and whose
+    // leaves hold at most ND_LEAF rows (a part the level search cannot split
+    // stays whole), all of them (GDSW_ORDER_ND) or (GDSW_ORDER_AUTO) those
+    // whose panels hold fewer values than their band (both read twice per
+    // apply); the others keep the band.  The choice depends on the
+    // subdomain alone, so a problem's results do not depend on what it is
+    // packed with.
     const bool all_nd = s.opt.exact_order == GDSW_ORDER_ND;
     const size_t acc = s.opt.local_prec == GDSW_FP64 ? 8 : 4;
     s.nd_mask.assign(np, 0);

@@ -198,8 +198,8 @@ def test_large_exact_local_solves_match_oracle(order):
     # [12 sin^2(pi/38), 12), so condition numbers below 147, and
     # half-bandwidth 320; a local solve's forward error is at most about
     # 147 * 320 * 1.1e-16 = 5e-12 of its size.  The supernodal factor's rows
-    # hold up to 1,061 entries (counted from the analysis maps of an interior
-    # box), so there 147 * 1061 * 1.1e-16 = 1.7e-11.
+    # hold up to 995 entries (counted from the analysis maps of an interior
+    # box), so there 147 * 995 * 1.1e-16 = 1.6e-11.
     assert err <= (5e-12 if order == "band" else 2e-11), err
     g.apply_part(r, z, 2)
     zc = z.cpu().numpy()[ref["idx"]]
