@@ -475,6 +475,11 @@ def main():
                                          kernel_reps=10, order="nd"))
         line["exact_local_band"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
                                               kernel_reps=10, order="natural"))
+        # mixed precision on the exact form: FP16 supernodal factors (FP32
+        # accumulation), FP64 CG
+        ex16 = single("poisson", args.N, args.P, "exact", "fp16", steps=3, warmup=1, kernel_reps=10, order="nd")
+        line["exact_local_fp16"] = sub(ex16)
+        line["exact_local_fp16"]["vs_fp64_solves_per_s"] = round(ex16["value"] / line["exact_local"]["value"], 3)
         line["elasticity"] = sub(single("elasticity", None, None, "exact", "fp32", None, "single_reduce",
                                         steps=3, warmup=1, kernel_reps=10))
         bargs = argparse.Namespace(**vars(args))
