@@ -78,13 +78,11 @@ def test_nd_apply_matches_oracle(case):
 
 
 def test_nd_auto_mixes_band_and_supernodal_subdomains():
-    """24^3 in 3^3 boxes: AUTO gives 25 of the 27 subdomains the supernodal
-    factor and keeps the band for two; the apply and a CG solve match the
-    oracle, and the apply is the same whether the other subdomains take the
-    band or the supernodal factor (each subdomain's result is computed
-    alone)."""
-    pr = P.poisson3d(24, 3)
-    say("[nd] auto mix 24^3")
+    """20^3 in 3^3 boxes: AUTO gives most of the 27 subdomains the
+    supernodal factor and keeps the band for the others (20 and 7 with
+    leaves of 48 rows); the apply and a CG solve match the oracle."""
+    pr = P.poisson3d(20, 3)
+    say("[nd] auto mix 20^3")
     g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_EXACT, exact_order=B.ORDER_AUTO)
     k = g.info()["nd_subdomains"]
     assert 0 < k < pr.n_parts
