@@ -436,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_phased(
 // ---------------------------------------------------------------------------
 // Exact local solve A_i^{-1} r_i with the banded Cholesky factor, one
 // workgroup per subdomain, vector in LDS, gather and scatter fused.
-template <int NT, typename VT, bool INV>
+template <int NT, typename VT, bool INV, bool AHEAD>
 __device__ __forceinline__ void band_apply_one(int i, const double *__restrict__ r, const int32_t *__restrict__ ov_idx,
                                                const int64_t *__restrict__ ov_ptr, const VT *__restrict__ band,
                                                const int64_t *__restrict__ band_off, const int32_t *__restrict__ bw,
@@ -470,7 +470,7 @@ __device__ __forceinline__ void band_apply_one(int i, const double *__restrict__
             if (l0 + b * NT < ni) y[l0 + b * NT] = AT(x[b]);
     }
     __syncthreads();
-    band_llt_solve<VT, AT, NT, INV>(band + band_off[i], ni, bw[i], y, sT);
+    band_llt_solve<VT, AT, NT, INV, AHEAD>(band + band_off[i], ni, bw[i], y, sT);
     for (int l0 = threadIdx.x; l0 < ni; l0 += GB * NT) {
         double v[GB];
 #pragma unroll
@@ -501,8 +501,8 @@ __global__ __launch_bounds__(1024) void k_band_apply(
     const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
     // (subdomains without a band take the supernodal solve)
     if (sk.sub(i, slot) || band_inverted(bw[i]) != INV || band_off[i + 1] == band_off[i]) return;
-    band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
-                                zloc + slot * sk.sl.zl, maxrows);
+    band_apply_one<NT, VT, INV, true>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
+                                      zloc + slot * sk.sl.zl, maxrows);
 }
 
 // The same as a persistent loop: gridDim.x workgroups per slot take the
@@ -525,8 +525,8 @@ __global__ __launch_bounds__(1024) void k_band_apply_pers(
         if (t >= nitems) break;   // (the whole workgroup)
         const int i = sk.sub_at(t);
         if (!sk.sub(i, slot) && band_inverted(bw[i]) == INV && band_off[i + 1] != band_off[i])
-            band_apply_one<NT, VT, INV>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
-                                        zloc + slot * sk.sl.zl, maxrows);
+            band_apply_one<NT, VT, INV, false>(i, r + slot * sk.sl.n, ov_idx, ov_ptr, band, band_off, bw, dscale,
+                                               zloc + slot * sk.sl.zl, maxrows);
         __syncthreads();   // (the LDS vector is free for the next subdomain)
     }
 }

@@ -502,9 +502,192 @@ __device__ __forceinline__ void band_store_triangle(const AT (&tv)[tri_per_threa
     }
 }
 
+// The solve with its band loads one block step ahead (1024 threads).  A
+// step first uses the entries loaded during the step before (the rows below
+// the solved block, forward; the thread's column above it, backward),
+// then issues the next step's entries and triangle into the same registers,
+// so that those loads are in flight across the triangle solve and its two
+// barriers instead of being waited for at the start of the next step.  Rows
+// (columns) past the held ones are loaded in the step itself.  Every sum is
+// formed in the same order as in the plain form below, so both give the
+// same bits.
+template <typename VT, typename AT, int NT, bool INV>
+__device__ void band_llt_solve_ahead(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
+    constexpr bool F64 = sizeof(AT) == 8;
+    constexpr int LPR = 16, RPI = NT / LPR, QN = BS_NB / LPR;
+    static_assert(LPR == 16, "the row sums use rows of 16 lanes");
+    constexpr int PF = F64 ? 4 : 6;      // forward: row groups of RPI rows held per step
+    constexpr int RB = F64 ? 2 : 4;      // forward: row groups per pass past the held ones
+    constexpr int BPF = F64 ? 16 : 32;   // backward: rows of the thread's first column held
+    constexpr int G = F64 ? 8 : 32;      // backward: loads per group past the held rows
+    const int64_t w = b + 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int sub = tid & (LPR - 1), rg = tid / LPR;
+    const int nblk = (n + BS_NB - 1) / BS_NB;
+    AT tv[tri_per_thread<NT>()];
+    // ---- forward
+    // v[it][q] = L(r, k0 + sub + 16 q) for the row r = k0 + 64 + it RPI + rg
+    // below the block at k0 (zero outside the band and past the subdomain)
+    AT v[PF][QN];
+    auto load_rows = [&](int k0) {
+        const int k1 = k0 + BS_NB, rend = min(n, k1 + b);
+#pragma unroll
+        for (int it = 0; it < PF; ++it) {
+            const int r = k1 + it * RPI + rg;
+            const int s0 = max(0, r - b - k0);
+            const VT *row = L + int64_t(r) * w + (k0 - r + b);
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                const int s = sub + q * LPR;
+                v[it][q] = (r < rend && s >= s0) ? to_acc(band_ld(&row[s])) : AT(0);
+            }
+        }
+    };
+    band_stage_triangle<VT, AT, NT>(L, w, b, 0, min(BS_NB, n), sT);
+    __syncthreads();
+    if (tid < 64) {
+        if constexpr (INV) band_block_fwd_inv(sT, y, 0, min(BS_NB, n), lane);
+        else band_block_fwd(sT, y, 0, min(BS_NB, n), lane);
+    }
+    if (nblk > 1) {
+        load_rows(0);
+        band_load_triangle<VT, AT, NT>(L, w, b, BS_NB, min(BS_NB, n - BS_NB), tv);
+    }
+    __syncthreads();
+    for (int blk = 0; blk + 1 < nblk; ++blk) {
+        const int k0 = blk * BS_NB, k1 = k0 + BS_NB, kb1 = min(BS_NB, n - k1);
+        const int rend = min(n, k1 + b);
+        AT yq[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) yq[q] = y[k0 + sub + q * LPR];
+#pragma unroll
+        for (int it = 0; it < PF; ++it) {
+            const int r = k1 + it * RPI + rg;
+            AT acc = 0;
+#pragma unroll
+            for (int q = 0; q < QN; ++q) acc += v[it][q] * yq[q];
+            acc = row16_sum(acc);
+            if (r < rend && sub == 0) y[r] -= acc;
+        }
+        for (int r0 = k1 + PF * RPI; r0 < rend; r0 += RB * RPI) {
+            AT u[RB][QN];
+#pragma unroll
+            for (int it = 0; it < RB; ++it) {
+                const int r = r0 + it * RPI + rg;
+                const int s0 = max(0, r - b - k0);
+                const VT *row = L + int64_t(r) * w + (k0 - r + b);
+#pragma unroll
+                for (int q = 0; q < QN; ++q) {
+                    const int s = sub + q * LPR;
+                    u[it][q] = (r < rend && s >= s0) ? to_acc(band_ld(&row[s])) : AT(0);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < RB; ++it) {
+                const int r = r0 + it * RPI + rg;
+                AT acc = 0;
+#pragma unroll
+                for (int q = 0; q < QN; ++q) acc += u[it][q] * yq[q];
+                acc = row16_sum(acc);
+                if (r < rend && sub == 0) y[r] -= acc;
+            }
+        }
+        band_store_triangle<AT, NT>(tv, sT);
+        if (blk + 2 < nblk) {   // the next step's rows and triangle
+            load_rows(k1);
+            band_load_triangle<VT, AT, NT>(L, w, b, k1 + BS_NB, min(BS_NB, n - k1 - BS_NB), tv);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            if constexpr (INV) band_block_fwd_inv(sT, y, k1, kb1, lane);
+            else band_block_fwd(sT, y, k1, kb1, lane);
+        }
+        __syncthreads();
+    }
+    // ---- backward
+    // cv[s] = L(k0 + s, j) for the thread's first column j = max(0, k0 - b) + tid
+    // above the block at k0 (zero outside the band)
+    AT cv[BPF];
+    auto load_col = [&](int k0) {
+        const int kb = min(BS_NB, n - k0), j = max(0, k0 - b) + tid;
+        const int smax = min(kb, j + b - k0 + 1);
+        const VT *col = L + int64_t(k0) * w + (j - k0 + b);
+#pragma unroll
+        for (int s = 0; s < BPF; ++s) cv[s] = (j < k0 && s < smax) ? to_acc(band_ld(&col[int64_t(s) * (w - 1)])) : AT(0);
+    };
+    {
+        const int k0 = (nblk - 1) * BS_NB, kb = n - k0;
+        band_stage_triangle<VT, AT, NT>(L, w, b, k0, kb, sT);
+        __syncthreads();
+        if (tid < 64) {
+            if constexpr (INV) band_block_bwd_inv(sT, y, k0, kb, lane);
+            else band_block_bwd(sT, y, k0, kb, lane);
+        }
+        if (nblk > 1) {
+            load_col(k0);
+            band_load_triangle<VT, AT, NT>(L, w, b, k0 - BS_NB, BS_NB, tv);
+        }
+        __syncthreads();
+    }
+    for (int blk = nblk - 1; blk > 0; --blk) {
+        const int k0 = blk * BS_NB, kb = min(BS_NB, n - k0);
+        const int p0 = k0 - BS_NB;
+        const int jbeg = max(0, k0 - b);
+        {
+            const int j = jbeg + tid;
+            if (j < k0) {
+                const int smax = min(kb, j + b - k0 + 1);
+                const VT *col = L + int64_t(k0) * w + (j - k0 + b);
+                AT acc = 0;
+#pragma unroll
+                for (int s = 0; s < BPF; ++s) acc += cv[s] * y[k0 + min(s, kb - 1)];
+#pragma unroll 1
+                for (int g = BPF; g < BS_NB; g += G) {
+                    AT u[G];
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        u[q] = (g + q < smax) ? to_acc(band_ld(&col[int64_t(g + q) * (w - 1)])) : AT(0);
+#pragma unroll
+                    for (int q = 0; q < G; ++q) acc += u[q] * y[k0 + min(g + q, kb - 1)];
+                }
+                y[j] -= acc;
+            }
+        }
+        // columns past the first NT (bands wider than the workgroup)
+        for (int j = jbeg + tid + NT; j < k0; j += NT) {
+            const int smax = min(kb, j + b - k0 + 1);
+            const VT *col = L + int64_t(k0) * w + (j - k0 + b);
+            AT acc = 0;
+#pragma unroll 1
+            for (int g = 0; g < BS_NB; g += G) {
+                AT u[G];
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+                    u[q] = (g + q < smax) ? to_acc(band_ld(&col[int64_t(g + q) * (w - 1)])) : AT(0);
+#pragma unroll
+                for (int q = 0; q < G; ++q) acc += u[q] * y[k0 + min(g + q, kb - 1)];
+            }
+            y[j] -= acc;
+        }
+        band_store_triangle<AT, NT>(tv, sT);
+        if (blk > 1) {   // the next step's column and triangle
+            load_col(p0);
+            band_load_triangle<VT, AT, NT>(L, w, b, p0 - BS_NB, BS_NB, tv);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            if constexpr (INV) band_block_bwd_inv(sT, y, p0, BS_NB, lane);
+            else band_block_bwd(sT, y, p0, BS_NB, lane);
+        }
+        __syncthreads();
+    }
+}
+
 // INV: the diagonal blocks hold their inverses (band_inverted(b)), so each
 // triangle solve is one product with the staged block.
-template <typename VT, typename AT, int NT, bool INV>
+// AHEAD: the form with the loads one step ahead (1024 threads: that
+// register budget holds the extra entries without spills).
+template <typename VT, typename AT, int NT, bool INV, bool AHEAD = false>
 __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT *sT) {
     if (n <= 0) return;   // an empty subdomain or interior (uniform over the workgroup)
     constexpr bool F64 = sizeof(AT) == 8;
@@ -513,6 +696,10 @@ __device__ void band_llt_solve(const VT *__restrict__ L, int n, int b, AT *y, AT
     // triangle loads overlapped with the updates where the register budget
     // holds the extra values (FP32 accumulation from 512 threads, FP64 at 1024)
     constexpr bool PREF = F64 ? NT >= 1024 : NT >= 512;
+    if constexpr (AHEAD && PREF && NT >= 1024) {
+        band_llt_solve_ahead<VT, AT, NT, INV>(L, n, b, y, sT);
+        return;
+    }
     const int64_t w = b + 1;
     const int tid = threadIdx.x, lane = tid & 63;
     const int nblk = (n + BS_NB - 1) / BS_NB;
