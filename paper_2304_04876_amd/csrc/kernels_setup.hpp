@@ -426,20 +426,41 @@ __device__ __forceinline__ void band_stage_triangle(const VT *__restrict__ L, in
 // least BS_NB - 1): lane t forms row t of X y (forward) or of X^T y
 // (backward) in one pass of products; entries outside the triangle are zero
 // in the staging, and the clamp keeps the reads inside the block.
+// For a whole block (kb = 64, every block but a subdomain's last) the
+// vector entries sit at fixed offsets from a 16-byte aligned address (the
+// solve's LDS vector starts 16-byte aligned and blocks start at multiples of
+// 64 entries), so their broadcast reads merge into wide LDS reads.
+template <typename AT>
+__device__ __forceinline__ const AT *band_block_vec(const AT *y, int k0) {
+    return static_cast<const AT *>(__builtin_assume_aligned(y + k0, 16));
+}
+
 template <typename AT>
 __device__ __forceinline__ void band_block_fwd_inv(const AT *sT, AT *y, int k0, int kb, int lane) {
     const AT *row = sT + lane * BS_LD;
     AT acc = 0;
+    if (kb == BS_NB) {
+        const AT *yb = band_block_vec(y, k0);
 #pragma unroll 8
-    for (int s = 0; s < BS_NB; ++s) acc += row[s] * y[k0 + min(s, kb - 1)];
+        for (int s = 0; s < BS_NB; ++s) acc += row[s] * yb[s];
+    } else {
+#pragma unroll 8
+        for (int s = 0; s < BS_NB; ++s) acc += row[s] * y[k0 + min(s, kb - 1)];
+    }
     if (lane < kb) y[k0 + lane] = acc;
 }
 
 template <typename AT>
 __device__ __forceinline__ void band_block_bwd_inv(const AT *sT, AT *y, int k0, int kb, int lane) {
     AT acc = 0;
+    if (kb == BS_NB) {
+        const AT *yb = band_block_vec(y, k0);
 #pragma unroll 8
-    for (int s = 0; s < BS_NB; ++s) acc += sT[s * BS_LD + lane] * y[k0 + min(s, kb - 1)];
+        for (int s = 0; s < BS_NB; ++s) acc += sT[s * BS_LD + lane] * yb[s];
+    } else {
+#pragma unroll 8
+        for (int s = 0; s < BS_NB; ++s) acc += sT[s * BS_LD + lane] * y[k0 + min(s, kb - 1)];
+    }
     if (lane < kb) y[k0 + lane] = acc;
 }
 
@@ -638,19 +659,26 @@ __device__ void band_llt_solve_ahead(const VT *__restrict__ L, int n, int b, AT 
             if (j < k0) {
                 const int smax = min(kb, j + b - k0 + 1);
                 const VT *col = L + int64_t(k0) * w + (j - k0 + b);
-                AT acc = 0;
+                // (the block's vector entries: at fixed offsets for a whole
+                // block, clamped to the last row for the last one)
+                auto col_sum = [&](auto yat) {
+                    AT acc = 0;
 #pragma unroll
-                for (int s = 0; s < BPF; ++s) acc += cv[s] * y[k0 + min(s, kb - 1)];
+                    for (int s = 0; s < BPF; ++s) acc += cv[s] * yat(s);
 #pragma unroll 1
-                for (int g = BPF; g < BS_NB; g += G) {
-                    AT u[G];
+                    for (int g = BPF; g < BS_NB; g += G) {
+                        AT u[G];
 #pragma unroll
-                    for (int q = 0; q < G; ++q)
-                        u[q] = (g + q < smax) ? to_acc(band_ld(&col[int64_t(g + q) * (w - 1)])) : AT(0);
+                        for (int q = 0; q < G; ++q)
+                            u[q] = (g + q < smax) ? to_acc(band_ld(&col[int64_t(g + q) * (w - 1)])) : AT(0);
 #pragma unroll
-                    for (int q = 0; q < G; ++q) acc += u[q] * y[k0 + min(g + q, kb - 1)];
-                }
-                y[j] -= acc;
+                        for (int q = 0; q < G; ++q) acc += u[q] * yat(g + q);
+                    }
+                    return acc;
+                };
+                const AT *yb = band_block_vec(y, k0);
+                y[j] -= kb == BS_NB ? col_sum([&](int s) { return yb[s]; })
+                                    : col_sum([&](int s) { return y[k0 + min(s, kb - 1)]; });
             }
         }
         // columns past the first NT (bands wider than the workgroup)
@@ -845,7 +873,8 @@ __global__ __launch_bounds__(1024) void k_ext_solve(const double *__restrict__ i
                                                   const int32_t *__restrict__ sub_blk,
                                                   const int64_t *__restrict__ blk_val_off,
                                                   double *__restrict__ phi) {
-    extern __shared__ double smem[];
+    extern __shared__ __align__(16) double sxs[];   // (16-byte aligned: the band solve's block reads)
+    double *smem = sxs;
     const int i = blockIdx.x;
     const int n = int(int_ptr[i + 1] - int_ptr[i]);
     const int k = int(scol_ptr[i + 1] - scol_ptr[i]);
