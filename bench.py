@@ -471,6 +471,10 @@ def main():
         # (the faster form on these 16^3 boxes) and the band beside it
         line["iluk_fastilu"] = sub(single("poisson", args.N, args.P, "ilu0", "fp64", None, "single_reduce", 1, 3,
                                           steps=3, warmup=1, kernel_reps=10))
+        # ILU(2): 11 + 11 factor entries per row, more than registers and LDS
+        # hold, so the streaming sweeps read the factors on every sweep
+        line["iluk2_fastilu"] = sub(single("poisson", args.N, args.P, "ilu0", "fp64", None, "single_reduce", 2, 3,
+                                           steps=2, warmup=1, kernel_reps=10))
         line["exact_local"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
                                          kernel_reps=10, order="nd"))
         line["exact_local_band"] = sub(single("poisson", args.N, args.P, "exact", "fp64", steps=3, warmup=1,
