@@ -232,13 +232,48 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
         cur[l] = AT(x);
     }
     __syncthreads();
-    for (int k = 1; k < sweeps; ++k) {
-        for (int l = threadIdx.x; l < ni; l += NT) {
-            AT acc = rb[l];
-            for (int s = 0; s < KL; ++s)
-                acc -= to_acc(Lv[s * ell_rows + eo + l]) * cur[Lc[s * ell_rows + eo + l]];
-            nxt[l] = acc;
+    // One sweep: nxt = rb - N cur over the K slots of V / C.  Each thread
+    // takes its rows RB at a time and the slots SC at a time: the entries and
+    // columns of a chunk are loaded together, then the chunk's iterate
+    // entries, then the products, each row's in slot order (the order of
+    // one row at a time, so the same bits).  Slots past K are neither loaded
+    // nor used; rows past the subdomain load its last row and are not
+    // written.
+    constexpr int RB = 2, SC = 4;   // (measured: 2 x 4 rows x slots ahead of 4 x 4, 4 x 2, 2 x 2 and larger)
+    auto sweep = [&](const VT *__restrict__ V, const uint16_t *__restrict__ C, int K) {
+        for (int l0 = threadIdx.x; l0 < ni; l0 += NT * RB) {
+            AT acc[RB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) acc[b] = rb[min(l0 + b * NT, ni - 1)];
+            for (int s0 = 0; s0 < K; s0 += SC) {
+                AT v[RB][SC];
+                int c[RB][SC];
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int j = 0; j < SC; ++j) {
+                        const int64_t e = int64_t(min(s0 + j, K - 1)) * ell_rows + eo + min(l0 + b * NT, ni - 1);
+                        v[b][j] = to_acc(V[e]);
+                        c[b][j] = C[e];
+                    }
+                AT g[RB][SC];
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int j = 0; j < SC; ++j) g[b][j] = cur[c[b][j]];
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int j = 0; j < SC; ++j)
+                        if (s0 + j < K) acc[b] -= v[b][j] * g[b][j];
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                if (l0 + b * NT < ni) nxt[l0 + b * NT] = acc[b];
         }
+    };
+    for (int k = 1; k < sweeps; ++k) {
+        sweep(Lv, Lc, KL);
         __syncthreads();
         AT *t = cur; cur = nxt; nxt = t;
     }
@@ -249,12 +284,7 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     __syncthreads();
     { AT *t = cur; cur = nxt; nxt = t; }
     for (int k = 1; k < sweeps; ++k) {
-        for (int l = threadIdx.x; l < ni; l += NT) {
-            AT acc = rb[l];
-            for (int s = 0; s < KU; ++s)
-                acc -= to_acc(Uv[s * ell_rows + eo + l]) * cur[Uc[s * ell_rows + eo + l]];
-            nxt[l] = acc;
-        }
+        sweep(Uv, Uc, KU);
         __syncthreads();
         AT *t = cur; cur = nxt; nxt = t;
     }
