@@ -61,8 +61,10 @@ int oracle_ilu0(int64_t n, const int64_t *rowptr, const int32_t *col, double *va
 
 /* Level-of-fill pattern of ILU(p) for a matrix with sorted rows that all hold
  * their diagonal.  Writes out_rowptr[n+1], out_col[nnz], out_lev[nnz] (rows
- * sorted) and returns nnz, or -(needed capacity lower bound) if cap is too
- * small, or -2 on allocation failure. */
+ * sorted) and returns nnz; if a row does not fit in cap entries it stops
+ * there (the rows after it would read the rows not stored) and returns
+ * -(a larger capacity to try: at least the entries up to that row, at least
+ * twice cap); -2 on allocation failure. */
 int64_t oracle_iluk_pattern(int64_t n, const int64_t *rowptr, const int32_t *col, int p,
                             int64_t *out_rowptr, int32_t *out_col, int32_t *out_lev, int64_t cap)
 {
@@ -103,11 +105,17 @@ int64_t oracle_iluk_pattern(int64_t n, const int64_t *rowptr, const int32_t *col
                 if (j > prev) prev = j;
             }
         }
+        int64_t len = 0;
+        for (int64_t c = head; c < n; c = nxt[c]) ++len;
+        if (nnz + len > cap) {
+            const int64_t need = nnz + len > 2 * cap ? nnz + len : 2 * cap;
+            free(nxt);
+            free(lev);
+            return -need;
+        }
         for (int64_t c = head; c < n; c = nxt[c]) {
-            if (nnz < cap) {
-                out_col[nnz] = (int32_t)c;
-                out_lev[nnz] = lev[c];
-            }
+            out_col[nnz] = (int32_t)c;
+            out_lev[nnz] = lev[c];
             ++nnz;
             lev[c] = INT_MAX;
         }
@@ -115,5 +123,5 @@ int64_t oracle_iluk_pattern(int64_t n, const int64_t *rowptr, const int32_t *col
     }
     free(nxt);
     free(lev);
-    return nnz <= cap ? nnz : -nnz;
+    return nnz;
 }

@@ -54,6 +54,20 @@ def test_level_of_fill_matches_dense_rule(p, seed):
     assert np.array_equal(got, ref)
 
 
+def test_ilu3_pattern_of_the_7point_stencil_past_the_first_capacity():
+    """ILU(3) of the 7-point stencil on a 6^3 grid: more pattern entries than
+    the first capacity (4 nnz(A)), so the pattern is computed again with more
+    room; it equals the dense level-of-fill rule."""
+    A = P.poisson3d(6, 1).A.tocsr()
+    Pm, lev = O.iluk_pattern(A, 3)
+    assert Pm.nnz > 4 * A.nnz
+    ref = dense_levels(A.toarray(), 3)
+    got = np.full(A.shape, 10 ** 9)
+    Pm = Pm.tocoo()
+    got[Pm.row, Pm.col] = lev
+    assert np.array_equal(got, ref)
+
+
 def test_ilu1_fill_of_the_7point_stencil():
     """On an N^3 grid in natural order, eliminating the three lower neighbours
     i-1, i-N, i-N^2 of an interior row creates exactly the six couplings
