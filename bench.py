@@ -285,8 +285,10 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
     alg_bytes = info["local_solve_bytes"]
     if local == "ilu0":
         if info["local_variant"] in (0, 1):
-            # (ILU(k) with fill: 6 + 6 slots, L and U entries in registers one after the other)
-            kname = "k_ilu_jacobi_phased" if ilu_level >= 1 else "k_ilu_jacobi"
+            # ILU(0): every entry in registers; ILU(1) (6 + 6 slots): L and
+            # U entries in registers one after the other; ILU(2) and up: the
+            # first slots of each row held, the others read on every sweep
+            kname = {0: "k_ilu_jacobi", 1: "k_ilu_jacobi_phased"}.get(ilu_level, "k_ilu_jacobi_hold")
         else:
             kname = "k_ilu_jacobi_generic"
     elif info["nd_subdomains"] == pr.n_parts:

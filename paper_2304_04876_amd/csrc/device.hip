@@ -1268,9 +1268,46 @@ static bool launch_ilu_phased(const Symbolic &S, Device &D, const double *r, con
     return false;
 }
 
+// ILU(k) factors with more slots than the register-resident kernels take:
+// the first 6 slots of each row held in registers (4 with FP64 entries at
+// 11 rows a thread, the register budget), the rest streamed (512 threads,
+// up to 11 rows each)
+template <typename VT, int NT>
+static bool launch_ilu_hold(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
+                            const Device::SizeClass &c) {
+    if constexpr (NT != 512) {
+        return false;
+    } else {
+        if (S.opt.jacobi_sweeps < 2 || !D.Lc || !D.Uc || D.KLp < 2 || D.KUp < 2) return false;
+        using AT = typename AccOf<VT>::type;
+        constexpr bool f64 = std::is_same<VT, double>::value;
+        const size_t lds = 3 * sizeof(AT) * size_t(std::max(c.max_ni, 1));
+        if (lds > D.max_lds) return false;
+        const int need = (c.max_ni + NT - 1) / NT;
+        const int nb = c.end - c.begin;
+        const Skip kc = class_skip(D, sk, c);
+#define GDSW_ILU_HOLD(RR)                                                                                     \
+        if (need <= RR) {                                                                                     \
+            hipLaunchKernelGGL((k_ilu_jacobi_hold<NT, RR, (f64 && RR > 8) ? 4 : 6, VT>), dim3(nb, D.ns),      \
+                               dim3(NT), lds, s, r,                                                           \
+                               D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv,     \
+                               D.Lc, (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale,                    \
+                               S.opt.jacobi_sweeps, D.zloc, c.max_ni, kc);                                    \
+            return true;                                                                                      \
+        }
+        GDSW_ILU_HOLD(4)
+        GDSW_ILU_HOLD(8)
+        GDSW_ILU_HOLD(11)
+#undef GDSW_ILU_HOLD
+        return false;
+    }
+}
+
 template <typename VT, int NT>
 static bool launch_ilu_regs(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
                             const Device::SizeClass &c) {
+    // more slots than the phased kernel holds: the first ones held
+    if (D.KLp > ILU_KL2 || D.KUp > ILU_KU2) return launch_ilu_hold<VT, NT>(S, D, r, sk, s, c);
     // (one sweep per triangle needs no factor entries: the streaming kernel)
     if (!D.Cp || S.opt.jacobi_sweeps < 2) return false;
     if (D.KLp == ILU_KL2 && D.KUp == ILU_KU2) return launch_ilu_phased<VT, NT>(S, D, r, sk, s, c);

@@ -295,6 +295,135 @@ __global__ __launch_bounds__(NT) void k_ilu_jacobi_generic(
     }
 }
 
+// ILU(k) factors with more slots per row than the registers hold beside
+// the sweeps (ILU(2) and ILU(3) of the 7-point stencil: 11 + 11 and 21 + 21
+// slots): the first H slots of each of the thread's R rows stay in registers
+// across the sweeps of a triangle (the L slots for the L sweeps, then the U
+// slots in the same registers), so that only the slots past them are read
+// again on every sweep (two rows and four slots at a time, as in
+// k_ilu_jacobi_generic).  Each row's products in slot order: the same bits
+// as the streaming sweeps.  Rows t, t + NT, ... of thread t (ni <= NT R and
+// the vectors in LDS, checked by the launcher); right-hand-side slot
+// blockIdx.y.
+template <int NT, int R, int H, typename VT>
+__global__ __launch_bounds__(NT) void k_ilu_jacobi_hold(
+    const double *__restrict__ r, const int32_t *__restrict__ ov_idx, const int64_t *__restrict__ ov_ptr,
+    const int64_t *__restrict__ ell_off, int64_t ell_rows, int KL, int KU, const VT *__restrict__ Lv,
+    const uint16_t *__restrict__ Lc, const VT *__restrict__ Uv, const uint16_t *__restrict__ Uc,
+    const VT *__restrict__ dinv, const double *__restrict__ dscale, int sweeps,
+    double *__restrict__ zloc, int maxrows, Skip sk) {
+    using AT = typename AccOf<VT>::type;
+    static_assert(H % 2 == 0, "held columns two to a word");
+    const int slot = blockIdx.y, i = sk.sub_at(blockIdx.x);
+    if (sk.sub(i, slot)) return;
+    r += slot * sk.sl.n;
+    zloc += slot * sk.sl.zl;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    const int64_t o = ov_ptr[i];
+    const int ni = int(ov_ptr[i + 1] - o);
+    if (ni == 0) return;   // (the whole workgroup)
+    AT *rb = reinterpret_cast<AT *>(smraw);
+    AT *cur = rb + maxrows, *nxt = cur + maxrows;
+    const int64_t eo = ell_off[i];
+    const int tid = threadIdx.x;
+    for (int l = tid; l < ni; l += NT) {
+        const int d = ov_idx[o + l];
+        double x = r[d];
+        if (dscale) x *= dscale[d];
+        rb[l] = AT(x);
+        cur[l] = AT(x);
+    }
+    // the held slots of the thread's rows (rows past the subdomain read its
+    // last row and are never written)
+    AT hv[R][H];
+    uint32_t hc[R][H / 2];   // columns of slots j and j + 1 in one word
+    auto hold = [&](const VT *__restrict__ V, const uint16_t *__restrict__ C, int K) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int64_t e0 = eo + min(tid + m * NT, ni - 1);
+#pragma unroll
+            for (int j = 0; j < H; j += 2) {
+                const int64_t ea = int64_t(min(j, K - 1)) * ell_rows + e0;
+                const int64_t eb = int64_t(min(j + 1, K - 1)) * ell_rows + e0;
+                hv[m][j] = to_acc(V[ea]);
+                hv[m][j + 1] = to_acc(V[eb]);
+                hc[m][j / 2] = uint32_t(C[ea]) | (uint32_t(C[eb]) << 16);
+            }
+        }
+    };
+    constexpr int SC = 4;
+    auto sweep = [&](const VT *__restrict__ V, const uint16_t *__restrict__ C, int K) {
+#pragma unroll
+        for (int m0 = 0; m0 < R; m0 += 2) {
+            AT acc[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                if (m0 + b < R) acc[b] = rb[min(tid + (m0 + b) * NT, ni - 1)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                if (m0 + b < R) {
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+                        if (j < K) acc[b] -= hv[m0 + b][j] * cur[(hc[m0 + b][j / 2] >> (16 * (j & 1))) & 0xffffu];
+                }
+            for (int s0 = H; s0 < K; s0 += SC) {
+                AT v[2][SC];
+                int c[2][SC];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int j = 0; j < SC; ++j) {
+                        const int64_t e = int64_t(min(s0 + j, K - 1)) * ell_rows + eo +
+                                          min(tid + min(m0 + b, R - 1) * NT, ni - 1);
+                        v[b][j] = to_acc(V[e]);
+                        c[b][j] = C[e];
+                    }
+                AT g[2][SC];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int j = 0; j < SC; ++j) g[b][j] = cur[c[b][j]];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (m0 + b < R) {
+#pragma unroll
+                        for (int j = 0; j < SC; ++j)
+                            if (s0 + j < K) acc[b] -= v[b][j] * g[b][j];
+                    }
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int l = tid + (m0 + b) * NT;
+                if (m0 + b < R && l < ni) nxt[l] = acc[b];
+            }
+        }
+    };
+    hold(Lv, Lc, KL);
+    __syncthreads();
+    for (int k = 1; k < sweeps; ++k) {
+        sweep(Lv, Lc, KL);
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+    for (int l = tid; l < ni; l += NT) {
+        rb[l] = to_acc(dinv[eo + l]) * cur[l];
+        nxt[l] = rb[l];
+    }
+    hold(Uv, Uc, KU);
+    __syncthreads();
+    { AT *t = cur; cur = nxt; nxt = t; }
+    for (int k = 1; k < sweeps; ++k) {
+        sweep(Uv, Uc, KU);
+        __syncthreads();
+        AT *t = cur; cur = nxt; nxt = t;
+    }
+    for (int l = tid; l < ni; l += NT) {
+        double v = double(cur[l]);
+        if (dscale) v *= dscale[ov_idx[o + l]];
+        zloc[o + l] = v;
+    }
+}
+
 // The register-resident sweeps for factors with more slots per row (ILU(k)
 // with fill: KL = KU = 6 for ILU(1) of the 7-point stencil), whose L and U
 // entries do not fit the registers together: the L entries and columns are

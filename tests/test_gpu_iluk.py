@@ -73,29 +73,39 @@ def test_iluk_reduced_precision_and_batch():
     B.gdsw_destroy(hb)
 
 
+@pytest.mark.parametrize("level", [1, 2, 3])
 @pytest.mark.parametrize("prec", [B.FP64, B.FP32, B.FP16])
-def test_iluk1_launch_forms_bitwise(prec):
-    """ILU(1) (6 + 6 slots per row on the 7-point stencil): the phased
-    register-resident sweeps (L entries in registers for the L sweeps, then
-    U) and the streaming sweeps compute every row in the same order, so all
-    launch configurations give the same bits; FP64 is within the apply
-    tolerance of the oracle."""
+def test_iluk_launch_forms_bitwise(prec, level):
+    """ILU(k) with fill (6 + 6, 11 + 11 and 21 + 21 slots per row on the
+    7-point stencil): the register-resident sweeps (ILU(1): L entries in
+    registers for the L sweeps, then U; ILU(2), ILU(3): the first slots of
+    each row held, the others read on every sweep) and the streaming sweeps
+    compute every row in the same order, so every launch configuration that
+    fits gives the same bits; FP64 is within the apply tolerance of the
+    oracle."""
     pr = P.poisson3d(20, 2)
-    say(f"[iluk] ILU(1) launch forms prec={prec}")
-    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0, ilu_level=1, ilu_factor_sweeps=3,
+    say(f"[iluk] ILU({level}) launch forms prec={prec}")
+    g = B.Gdsw(pr.A, pr.part, pr.n_parts, 1, local=B.LOCAL_ILU0, ilu_level=level, ilu_factor_sweeps=3,
                local_prec=prec, basis_prec=B.FP64 if prec == B.FP64 else B.FP32)
     r_h = P.rhs_uniform(pr.n, 5)
     r = torch.from_numpy(r_h).cuda()
     first = None
+    ran = 0
     for v in range(4):
-        B.gdsw_set_launch(g.h, v, 0, 1, 0)
+        try:
+            B.gdsw_set_launch(g.h, v, 0, 1, 0)
+        except B.GdswError as e:   # (the 1024-thread register form holds ILU(1) at most)
+            assert e.status == 1 and "fit" in str(e) and level > 1 and v == 1, (v, e)
+            continue
         z = torch.zeros_like(r)
         g.apply(r, z)
         if first is None:
             first = z
         assert torch.equal(z, first), v
+        ran += 1
+    assert ran >= 3
     if prec == B.FP64:
-        M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local="ilu0", ilu_level=1, factor_sweeps=3)
+        M = O.GDSW(pr.A, pr.part, 1, pr.n_parts, local="ilu0", ilu_level=level, factor_sweeps=3)
         zo = M.apply(r_h)
         assert np.abs(first.cpu().numpy() - zo).max() <= 1e-12 * np.abs(zo).max()
     g.close()
