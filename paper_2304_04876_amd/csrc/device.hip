@@ -1269,13 +1269,13 @@ static bool launch_ilu_phased(const Symbolic &S, Device &D, const double *r, con
 }
 
 // ILU(k) factors with more slots than the register-resident kernels take:
-// the first 6 slots of each row held in registers (4 with FP64 entries at
-// 11 rows a thread, the register budget), the rest streamed (512 threads,
-// up to 11 rows each)
+// the first 6 slots of each row held in registers (4 with FP64 entries for
+// more than 4,096 rows a workgroup, the register budget), the rest streamed
+// (512 threads with up to 11 rows each, or 1024 with up to 6, 4 for FP64)
 template <typename VT, int NT>
 static bool launch_ilu_hold(const Symbolic &S, Device &D, const double *r, const Skip &sk, hipStream_t s,
                             const Device::SizeClass &c) {
-    if constexpr (NT != 512) {
+    if constexpr (NT != 512 && NT != 1024) {
         return false;
     } else {
         if (S.opt.jacobi_sweeps < 2 || !D.Lc || !D.Uc || D.KLp < 2 || D.KUp < 2) return false;
@@ -1288,16 +1288,22 @@ static bool launch_ilu_hold(const Symbolic &S, Device &D, const double *r, const
         const Skip kc = class_skip(D, sk, c);
 #define GDSW_ILU_HOLD(RR)                                                                                     \
         if (need <= RR) {                                                                                     \
-            hipLaunchKernelGGL((k_ilu_jacobi_hold<NT, RR, (f64 && RR > 8) ? 4 : 6, VT>), dim3(nb, D.ns),      \
+            hipLaunchKernelGGL((k_ilu_jacobi_hold<NT, RR, (f64 && RR * NT > 4096) ? 4 : 6, VT>), dim3(nb, D.ns), \
                                dim3(NT), lds, s, r,                                                           \
                                D.ov_idx, D.ov_ptr, D.ell_off, S.ell_rows, D.KLp, D.KUp, (const VT *)D.Lv,     \
                                D.Lc, (const VT *)D.Uv, D.Uc, (const VT *)D.dinv, D.dscale,                    \
                                S.opt.jacobi_sweeps, D.zloc, c.max_ni, kc);                                    \
             return true;                                                                                      \
         }
-        GDSW_ILU_HOLD(4)
-        GDSW_ILU_HOLD(8)
-        GDSW_ILU_HOLD(11)
+        if constexpr (NT == 512) {
+            GDSW_ILU_HOLD(4)
+            GDSW_ILU_HOLD(8)
+            GDSW_ILU_HOLD(11)
+        } else {
+            GDSW_ILU_HOLD(2)
+            GDSW_ILU_HOLD(4)
+            if constexpr (!f64) { GDSW_ILU_HOLD(6) }   // (FP64 at 6 rows a thread spills)
+        }
 #undef GDSW_ILU_HOLD
         return false;
     }
