@@ -51,6 +51,8 @@ MEASURED_TRAFFIC = {
     ("k_nd_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 5574150050, "src": "a6f6d04cf1931195"},
     # ILU(1) factors from 3 FastILU sweeps (the traffic does not depend on how the factors were computed)
     ("k_ilu_jacobi_phased", "poisson128^3_P8^3", "fp64"): {"bytes": 449873130, "src": "4e1cfa6c27b7f1c8"},
+    # ILU(2) factors from 3 FastILU sweeps (the entry holds for ILU(2) only)
+    ("k_ilu_jacobi_hold", "poisson128^3_P8^3", "fp64"): {"bytes": 1887125645, "src": "e771500e6d544bfb"},
 }
 
 
@@ -68,6 +70,8 @@ def kernel_source_hash(kernel):
         "k_nd_apply": [("kernels_nd.hpp", "// Sum over aligned groups of G lanes", "}  // namespace gdsw")],
         "k_ilu_jacobi_phased": [("kernels_apply.hpp", "// The register-resident sweeps for factors with more slots",
                                  "// Exact local solve A_i^{-1} r_i with the banded Cholesky factor")],
+        "k_ilu_jacobi_hold": [("kernels_apply.hpp", "// ILU(k) factors with more slots per row than the registers hold",
+                               "// The register-resident sweeps for factors with more slots")],
     }
     if kernel not in segments:
         return None
@@ -306,7 +310,8 @@ def single(kind="poisson", N=None, Pn=None, local="ilu0", prec="fp64", coarse=No
                    + nloc * 12 + n * 20)
     traffic = None
     meas = None
-    if (ilu_level == 0 and factor_sweeps == 0) or (kname == "k_ilu_jacobi_phased" and ilu_level == 1):
+    if ((ilu_level == 0 and factor_sweeps == 0) or (kname == "k_ilu_jacobi_phased" and ilu_level == 1)
+            or (kname == "k_ilu_jacobi_hold" and ilu_level == 2)):
         meas = MEASURED_TRAFFIC.get((kname, f"poisson{N}^3_P{Pn}^3" if not elastic else f"elasticity{N}^3", prec))
     if meas and kernel_source_hash(kname) == meas["src"]:
         traffic = int(meas["bytes"])
