@@ -49,6 +49,7 @@ MEASURED_TRAFFIC = {
     ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14214170851, "src": "af0e9d368f9e553e"},
     ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1623322957, "src": "af0e9d368f9e553e"},
     ("k_nd_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 5574150050, "src": "a6f6d04cf1931195"},
+    ("k_nd_apply", "poisson128^3_P8^3", "fp16"): {"bytes": 1744098215, "src": "a6f6d04cf1931195"},
     # ILU(1) factors from 3 FastILU sweeps (the traffic does not depend on how the factors were computed)
     ("k_ilu_jacobi_phased", "poisson128^3_P8^3", "fp64"): {"bytes": 449873130, "src": "4e1cfa6c27b7f1c8"},
     # ILU(2) factors from 3 FastILU sweeps (the entry holds for ILU(2) only)
