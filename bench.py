@@ -46,6 +46,7 @@ ORDERS = {"natural": 0, "nd": 1, "auto": 2}
 # was measured on: `src` is a hash of that kernel's text, checked below.
 MEASURED_TRAFFIC = {
     ("k_ilu_jacobi", "poisson128^3_P8^3", "fp64"): {"bytes": 270263559, "src": "04585098cbd2f750"},
+    ("k_ilu_jacobi", "poisson128^3_P8^3", "fp16"): {"bytes": 203127279, "src": "04585098cbd2f750"},
     ("k_band_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 14214170851, "src": "af0e9d368f9e553e"},
     ("k_band_apply", "elasticity48^3", "fp32"): {"bytes": 1623322957, "src": "af0e9d368f9e553e"},
     ("k_nd_apply", "poisson128^3_P8^3", "fp64"): {"bytes": 5574150050, "src": "a6f6d04cf1931195"},
